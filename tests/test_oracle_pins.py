@@ -1,0 +1,308 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check below is independent of the oracle's own code: a brute-force
+elimination game, dense LAPACK Cholesky, closed forms, invariants of
+elimination trees, and the worked example of Sec. 3, Fig. 1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_09288_amd import workloads as W
+from tests.bruteforce import dense_lower, elimination_game, permuted_dense
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def lower_from_dense_pattern(P, values=None):
+    n = P.shape[0]
+    r, c = np.nonzero(np.tril(P))
+    v = values[r, c] if values is not None else np.ones(r.size)
+    return W.lower_csc(n, r, c, v)
+
+
+def random_cases():
+    for n, dens, seed in [(1, 0.5, 0), (2, 1.0, 1), (7, 0.3, 2), (16, 0.15, 3), (33, 0.08, 4),
+                          (48, 0.05, 5), (64, 0.04, 6), (64, 0.2, 7), (40, 0.0, 8)]:
+        colptr, rowidx, values = W.random_spd_pattern(n, dens, seed)
+        perm = np.arange(n, dtype=np.int32)[::-1].copy() if seed % 2 else np.arange(n, dtype=np.int32)
+        yield f"rand{n}_{seed}", n, colptr, rowidx, values, perm
+    for dims in [(3, 3), (5, 4), (8, 8), (4, 4, 4), (5, 3, 6), (8, 8, 8)]:
+        s = W.laplacian(dims, "5pt" if len(dims) == 2 else "7pt", 77, 0, unit=False, shift=1e-2, nrhs=1)
+        yield s.name, s.n, s.colptr, s.rowidx, s.values, s.perm
+
+
+CASES = list(random_cases())
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("z", [-1.0, 0.0, 0.05, 0.3])
+def test_structure_vs_elimination_game(case, z):
+    _, n, colptr, rowidx, values, perm = case
+    S = oracle.Symbolic(colptr, rowidx, perm, z)
+    G = permuted_dense(n, colptr, rowidx, np.ones(colptr[-1]), S.perm) != 0
+    parent, cols = elimination_game(G)
+    assert np.array_equal(S.parent, parent)
+    assert np.array_equal(S.colcount, np.array([c.size + 1 for c in cols]))
+    Lp, Li = S.Lp, S.Li
+    for j in range(n):
+        assert np.array_equal(Li[Lp[j]:Lp[j + 1]], cols[j])
+    assert S.sizes["nnzL"] == sum(c.size + 1 for c in cols)
+    assert S.sizes["flops"] == sum((c.size + 1) ** 2 for c in cols)
+    # final order is a permutation; parent(j) > j; subtrees are contiguous
+    assert np.array_equal(np.sort(S.perm), np.arange(n))
+    assert np.all((parent == -1) | (parent > np.arange(n)))
+    size = np.ones(n, dtype=int)
+    for j in range(n):
+        if parent[j] != -1:
+            size[parent[j]] += size[j]
+    for j in range(n):
+        lo = j - size[j] + 1
+        for k in range(lo, j):
+            a = k
+            while a != -1 and a < j:
+                a = parent[a]
+            assert a == j, "postorder: subtree of j must be [j-size+1, j]"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("z", [-1.0, 0.0, 0.05, 0.3])
+def test_supernode_invariants(case, z):
+    _, n, colptr, rowidx, values, perm = case
+    S = oracle.Symbolic(colptr, rowidx, perm, z)
+    sp, rp, rows, par = S.super_ptr, S.rptr, S.rows, S.parent
+    cc = S.colcount
+    Lp, Li = S.Lp, S.Li
+    snode = np.repeat(np.arange(S.nsuper), np.diff(sp))
+    fp = S.fund_ptr
+    # fundamental supernodes: columns j, j+1 together iff the textbook rule
+    for j in range(n - 1):
+        together = snode_of(fp, j) == snode_of(fp, j + 1)
+        rule = par[j] == j + 1 and np.sum(par == j + 1) == 1 and cc[j] == cc[j + 1] + 1
+        assert together == rule
+    # every final supernode is a union of consecutive fundamental ones
+    assert set(sp.tolist()) <= set(fp.tolist())
+    zeros_total = 0
+    for s in range(S.nsuper):
+        R = rows[rp[s]:rp[s + 1]]
+        f, l = sp[s], sp[s + 1] - 1
+        w, m = l - f + 1, R.size
+        assert np.all(np.diff(R) > 0)
+        assert np.array_equal(R[:w], np.arange(f, l + 1))
+        stored = 0
+        exact = 0
+        for j in range(f, l + 1):
+            col = Li[Lp[j]:Lp[j + 1]]
+            assert np.all(np.isin(col, R)), "pattern of L inside R_s"
+            stored += m - (j - f)
+            exact += col.size + 1
+        zeros_total += stored - exact
+        assert float(stored - exact) <= max(z, 0.0) * float(stored)
+    assert zeros_total == S.sizes["zeros"]
+    # U_s is the set of d < s with R_d meeting cols(s); R_d below f_s inside R_s
+    U = {s: S.ulist[S.uptr[s]:S.uptr[s + 1]] for s in range(S.nsuper)}
+    for s in range(S.nsuper):
+        f, l = sp[s], sp[s + 1] - 1
+        want = [d for d in range(s) if np.any((rows[rp[d]:rp[d + 1]] >= f) & (rows[rp[d]:rp[d + 1]] <= l))]
+        assert U[s].tolist() == want
+        Rs = set(rows[rp[s]:rp[s + 1]].tolist())
+        for d in want:
+            Rd = rows[rp[d]:rp[d + 1]]
+            assert set(Rd[Rd >= f].tolist()) <= Rs
+    # levels: 0 at leaves, else 1 + max over children
+    sparent = S.sparent
+    lev = np.zeros(S.nsuper, dtype=int)
+    for s in range(S.nsuper):
+        if sparent[s] != -1:
+            lev[sparent[s]] = max(lev[sparent[s]], lev[s] + 1)
+            assert sparent[s] == snode[par[sp[s + 1] - 1]]
+    assert np.array_equal(S.level, lev)
+
+
+def snode_of(ptr, j):
+    return int(np.searchsorted(ptr, j, side="right") - 1)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_factor_vs_dense_cholesky(case):
+    _, n, colptr, rowidx, values, perm = case
+    S = oracle.Symbolic(colptr, rowidx, perm, 0.05)
+    Lx = S.factor(values)
+    Ah = permuted_dense(n, colptr, rowidx, values, S.perm)
+    Lref = np.linalg.cholesky(Ah)
+    L = S.to_dense_L(Lx)
+    assert np.linalg.norm(L - Lref) <= 1e-13 * np.linalg.norm(Lref)
+    assert np.linalg.norm(Ah - L @ L.T) <= 4 * n * 2.2e-16 * np.linalg.norm(Ah)
+    # explicit zeros of amalgamated supernodes stay exactly zero
+    mask = S.lower_mask()
+    stored = np.zeros((n, n), dtype=bool)
+    for s in range(S.nsuper):
+        R = S.rows[S.rptr[s]:S.rptr[s + 1]]
+        for c in range(S.super_ptr[s + 1] - S.super_ptr[s]):
+            stored[R[c:], S.super_ptr[s] + c] = True
+    exact = np.zeros((n, n), dtype=bool)
+    for j in range(n):
+        exact[j, j] = True
+        exact[S.Li[S.Lp[j]:S.Lp[j + 1]], j] = True
+    assert np.all(L[stored & ~exact] == 0.0)
+    assert mask.sum() == S.sizes["panel_entries"] - sum(
+        (w * (w - 1)) // 2 for w in np.diff(S.super_ptr))
+
+
+def test_scaling_gives_sqrt_alpha():
+    s = W.laplacian((6, 5), "5pt", 77, 3, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    L1 = S.factor(s.values)
+    L4 = S.factor(4.0 * s.values)
+    assert np.array_equal(L4, 2.0 * L1)  # scaling by 4 is exact in binary
+
+
+def test_closed_form_diagonal():
+    n = 9
+    colptr, rowidx, values = W.lower_csc(n, np.arange(n), np.arange(n), np.arange(1, n + 1, dtype=float))
+    S = oracle.Symbolic(colptr, rowidx, np.arange(n, dtype=np.int32), 0.05)
+    assert np.all(S.parent == -1)
+    assert np.all(S.colcount == 1)
+    assert S.nsuper == n and S.sizes["nlevels"] == 1
+    Lx = S.factor(values)
+    assert np.allclose(np.sort(Lx), np.sqrt(np.arange(1, n + 1)), rtol=0, atol=1e-15)
+
+
+def test_closed_form_tridiagonal():
+    n = 12
+    r = np.concatenate([np.arange(n), np.arange(1, n)])
+    c = np.concatenate([np.arange(n), np.arange(n - 1)])
+    v = np.concatenate([np.full(n, 2.0), np.full(n - 1, -1.0)])
+    colptr, rowidx, values = W.lower_csc(n, r, c, v)
+    S = oracle.Symbolic(colptr, rowidx, np.arange(n, dtype=np.int32), 0.05)
+    assert np.array_equal(S.parent, np.append(np.arange(1, n), -1))
+    assert np.array_equal(S.colcount, np.append(np.full(n - 1, 2), 1))
+    assert S.sizes["nfund"] == n - 1
+    L = S.to_dense_L(S.factor(values))
+    j = np.arange(n)
+    assert np.allclose(np.diag(L), np.sqrt((j + 2) / (j + 1)), rtol=1e-15, atol=0)
+    assert np.allclose(np.diag(L, -1), -np.sqrt((j[:-1] + 1) / (j[:-1] + 2)), rtol=1e-15, atol=0)
+
+
+def test_closed_form_dense():
+    n = 20
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    colptr, rowidx, values = lower_from_dense_pattern(np.ones((n, n), bool), A)
+    S = oracle.Symbolic(colptr, rowidx, np.arange(n, dtype=np.int32), 0.05)
+    assert S.nsuper == 1
+    assert np.array_equal(S.colcount, n - np.arange(n))
+    assert S.sizes["flops"] == n * (n + 1) * (2 * n + 1) // 6
+    L = S.to_dense_L(S.factor(values))
+    assert np.allclose(L, np.linalg.cholesky(A), rtol=0, atol=1e-13 * np.abs(A).max())
+
+
+def test_closed_form_arrow():
+    n = 10
+    r = np.concatenate([np.arange(n), np.full(n - 1, n - 1)])
+    c = np.concatenate([np.arange(n), np.arange(n - 1)])
+    v = np.concatenate([np.full(n, float(n)), np.full(n - 1, -1.0)])
+    colptr, rowidx, values = W.lower_csc(n, r, c, v)
+    S = oracle.Symbolic(colptr, rowidx, np.arange(n, dtype=np.int32), 0.0)
+    assert np.array_equal(S.parent, np.append(np.full(n - 1, n - 1), -1))  # a star
+    assert np.array_equal(S.colcount, np.append(np.full(n - 1, 2), 1))
+    assert S.sizes["nlevels"] == 2
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 7, 9])
+def test_closed_form_lexicographic_grid(k):
+    """k x k 5-point grid in lexicographic order fills its band."""
+    s = W.laplacian((k, k), "5pt", 77, 0, unit=True, shift=1e-2, nrhs=1)
+    n = k * k
+    S = oracle.Symbolic(s.colptr, s.rowidx, np.arange(n, dtype=np.int32), 0.0)
+    j = np.arange(n)
+    want = np.where(j <= k - 2, j + 3, np.minimum(k, n - 1 - j) + 1)
+    assert np.array_equal(S.colcount, want)
+
+
+def test_fig1_schedule_golden():
+    """Levels reproduce the schedule printed for Fig. 1 (Sec. 3)."""
+    txt = open(os.path.join(HERE, "golden", "fig1_tree.txt")).read().splitlines()
+    edges = [tuple(int(x) for x in e.split("->")) for e in
+             next(l for l in txt if l.startswith("edges:")).split(":", 1)[1].split()]
+    sched = [set(int(x) for x in g.split()) for g in
+             next(l for l in txt if l.startswith("schedule:")).split(":", 1)[1].split("|")]
+    n = 6
+    r = [p - 1 for (_, p) in edges]; c = [ch - 1 for (ch, _) in edges]
+    colptr, rowidx, values = W.lower_csc(n, np.concatenate([np.arange(n), r]),
+                                         np.concatenate([np.arange(n), c]),
+                                         np.concatenate([np.full(n, 4.0), -np.ones(len(r))]))
+    # z < 0 turns amalgamation off: the six supernodes of the figure stay apart
+    S = oracle.Symbolic(colptr, rowidx, np.arange(n, dtype=np.int32), -1.0)
+    assert S.nsuper == n
+    groups = {}
+    for k in range(n):  # supernode k holds pivot k = original column perm[k]
+        groups.setdefault(int(S.level[k]), set()).add(int(S.perm[k]) + 1)
+    assert [groups[l] for l in sorted(groups)] == sched
+
+
+@pytest.mark.parametrize("dims", [(8, 8), (12, 9), (5, 5, 5)])
+def test_solve_backward_error_and_manufactured(dims):
+    s = W.laplacian(dims, "5pt" if len(dims) == 2 else "7pt", 77, 1, unit=False, shift=1e-2, nrhs=3)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lx = S.factor(s.values)
+    X = S.solve(Lx, s.B)
+    assert oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X, s.B) < 1e-15
+    # manufactured: b = A x* with integer x*
+    A = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values)
+    xs = np.arange(s.n, dtype=float) % 7 - 3
+    x = S.solve(Lx, A @ xs)
+    cond = np.linalg.cond(A.toarray())
+    assert np.max(np.abs(x - xs)) <= 10 * cond * 2.2e-16 * np.max(np.abs(xs))
+    # a different ordering gives the same solution within kappa * u
+    S2 = oracle.Symbolic(s.colptr, s.rowidx, np.arange(s.n, dtype=np.int32), 0.0)
+    X2 = S2.solve(S2.factor(s.values), s.B)
+    assert np.max(np.abs(X2 - X)) <= 10 * cond * 2.2e-16 * np.max(np.abs(X))
+
+
+def test_not_spd_reports_pivot():
+    s = W.laplacian((7, 6), "5pt", 77, 2, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    iperm = np.argsort(S.perm)
+    for r in (0, 17, s.n - 1):
+        v = s.values.copy()
+        diag_pos = s.colptr[r]  # rows sorted, diagonal first in its column
+        assert s.rowidx[diag_pos] == r
+        v[diag_pos] = -v[diag_pos]
+        with pytest.raises(oracle.NotSPD) as e:
+            S.factor(v)
+        assert e.value.column == iperm[r]
+    v = s.values.copy(); v[s.colptr[5]] = np.nan
+    with pytest.raises(oracle.NotSPD) as e:
+        S.factor(v)
+    assert e.value.column == iperm[5]
+
+
+def test_workload_sizes_2d64():
+    """The 64x64 5-point workload: n = 4096, 20,224 stored entries in full."""
+    s = W.grid2d_unit()
+    assert s.n == 4096 and 2 * s.nnz - s.n == 20224
+    A = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values)
+    d = A.diagonal()
+    off = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(d)
+    assert np.allclose(d - off, 1e-2, rtol=0, atol=1e-12)
+
+
+def test_subtree_factor_matches_full():
+    s = W.laplacian((9, 9, 9), "7pt", 77, 4, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lx = S.factor(s.values)
+    for lev in (1, 3):
+        root = int(np.nonzero(S.level == lev)[0][-1])
+        Ls, first = S.factor_subtree(s.values, root)
+        sl = slice(S.lptr[first], S.lptr[root + 1])
+        assert np.array_equal(Ls[sl], Lx[sl])
+        anc = root
+        for k in range(first, root + 1):  # every supernode in range descends from root
+            a = k
+            while a != -1 and a < root:
+                a = S.sparent[a]
+            assert a == root
