@@ -1,0 +1,216 @@
+/*
+ * spchol.h -- C ABI of the MI355X supernodal sparse Cholesky library.
+ *
+ * The library follows the three phases of a direct solver (paper Sec. 1 and
+ * Sec. 2, "Background on CHOLMOD"): analyze the pattern of an SPD matrix,
+ * factorize A = L L^T numerically, solve L y = b and L^T x = y.  The numeric
+ * phases run in hand-written HIP kernels for gfx950; analyze runs on the host.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status (enum spc_status); no exception or
+ *     C++ type crosses this boundary.
+ *   - Indices are 0-based.  A matrix is given as its lower triangle,
+ *     diagonal included, in compressed-column form: colptr int64[n+1],
+ *     rowidx int32[nnz] (rows strictly increasing inside a column, first row
+ *     of column j equal to j), values double[nnz] in the same order.
+ *   - Pointers named h_* are host memory, d_* are device memory on the
+ *     current HIP device.  The library never frees caller memory.  Handles
+ *     are created by the library and released by the caller with the
+ *     matching spc_free_* function; freeing NULL is a no-op.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Numeric calls are asynchronous on it; numeric failure (a non-positive
+ *     pivot) is reported by spc_sync.
+ *   - One handle must not be used from two host threads at once.  Distinct
+ *     handles may be used concurrently on distinct streams.
+ */
+#ifndef SPCHOL_H
+#define SPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum spc_status {
+    SPC_OK = 0,
+    SPC_INVALID_INPUT = -1,   /* malformed CSC / permutation / argument */
+    SPC_NOT_SPD = -2,         /* a pivot was not positive and finite */
+    SPC_OUT_OF_MEMORY = -3,   /* device or host allocation failed */
+    SPC_NO_CONVERGENCE = -4,  /* refinement did not reach the tolerance */
+    SPC_DEVICE_ERROR = -5,    /* a HIP call failed */
+    SPC_BAD_HANDLE = -6,      /* NULL or already released handle */
+    SPC_NO_DEVICE = -7        /* no usable gfx950 device */
+};
+
+enum spc_precision {
+    SPC_FP64 = 0,             /* panels, updates and solves in double */
+    SPC_FP32 = 1              /* panels, updates and solves in float, float accumulation */
+};
+
+typedef struct spc_symbolic_s *spc_symbolic;
+typedef struct spc_factor_s *spc_factor;
+
+/* Analysis options.  Pass NULL for the defaults. */
+typedef struct spc_options {
+    /* Chain amalgamation tolerance z: a supernode absorbs its only
+     * predecessor chain while the explicit zeros stay within z of the stored
+     * entries (paper Sec. 2 describes node amalgamation; the exact rule is
+     * this library's).  z < 0 keeps the fundamental supernodes.
+     * Default 0.05. */
+    double amalg_z;
+    int32_t reserved[8];
+} spc_options;
+
+/* Summary numbers of an analysis. */
+typedef struct spc_info {
+    int64_t n;
+    int64_t nnz_a;            /* entries of the lower triangle given */
+    int64_t nsuper;           /* supernodes after amalgamation */
+    int64_t nnz_l;            /* sum of column counts (exact pattern of L) */
+    int64_t panel_entries;    /* stored panel entries, sum of m_s * w_s */
+    int64_t flops;            /* sum of squared column counts */
+    int64_t levels;           /* height of the supernodal elimination tree */
+    int64_t rows_total;       /* sum of |R_s| */
+    int64_t max_width;        /* widest supernode */
+    int64_t max_rows;         /* longest row list */
+    int64_t factor_bytes_fp64;/* device bytes of an FP64 factor + plan */
+    int64_t factor_bytes_fp32;/* device bytes of an FP32 factor + plan */
+} spc_info;
+
+/*
+ * spc_analyze -- symbolic phase (paper Sec. 2: reordering, elimination tree,
+ * node amalgamation into supernodes).  Host only; touches no device.
+ *   n        matrix order (>= 0)
+ *   h_colptr, h_rowidx   lower CSC pattern as described above
+ *   h_perm   fill-reducing order, perm[k] = original index of pivot k, or
+ *            NULL for the identity.  The library composes it with a
+ *            postorder of the elimination tree.
+ *   opts     NULL or options
+ *   out      receives the handle
+ * Errors: SPC_INVALID_INPUT for any malformed input (unsorted or duplicate
+ * rows, entries above the diagonal, a missing diagonal, out-of-range
+ * indices, perm not a permutation), SPC_OUT_OF_MEMORY.
+ */
+int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx,
+                const int32_t *h_perm, const spc_options *opts, spc_symbolic *out);
+
+int spc_symbolic_info(spc_symbolic sym, spc_info *out);
+
+/* Export one symbolic array to host memory for inspection.
+ *   0 perm int32[n]        final order (given order composed with postorder)
+ *   1 parent int32[n]      elimination tree of the permuted matrix, -1 root
+ *   2 colcount int32[n]    column counts of L, diagonal included
+ *   3 super_ptr int32[nsuper+1]  first column of each supernode
+ *   4 sparent int32[nsuper]      supernodal parent, -1 root
+ *   5 rptr int64[nsuper+1]       row-list offsets
+ *   6 rows int32[rows_total]     row lists R_s (sorted; first w_s are cols(s))
+ *   7 lptr int64[nsuper+1]       panel offsets (m_s*w_s entries each)
+ *   8 level int32[nsuper]        0 for leaves, else 1 + max over children
+ * Returns SPC_INVALID_INPUT for an unknown `which`. */
+int spc_symbolic_export(spc_symbolic sym, int which, void *h_dst);
+
+/*
+ * spc_factorize -- numeric phase (paper Sec. 3, Listing 1: per supernode the
+ * SYRK/GEMM updates from earlier supernodes, then POTRF and TRSM).  The
+ * device schedule is right-looking by elimination-tree level: every
+ * supernode of one level is factored in batched launches, then its
+ * Schur-complement update is scatter-added into its ancestors through
+ * relative indices.
+ *   d_values  device double[nnz] in the CSC order given to spc_analyze
+ *   precision enum spc_precision
+ *   stream    hipStream_t or NULL
+ *   out       receives a factor handle that owns its device storage
+ * Asynchronous; call spc_sync to learn whether the matrix was SPD.
+ */
+int spc_factorize(spc_symbolic sym, const double *d_values, int precision, void *stream,
+                  spc_factor *out);
+
+/* Re-run the numeric phase into an existing factor (same pattern, new
+ * values); allocates nothing once the factor exists. */
+int spc_refactorize(spc_factor f, const double *d_values, void *stream);
+
+/*
+ * spc_factorize_batch -- factor `count` independent systems in one
+ * level-scheduled pass: the launches of level l carry the supernodes of
+ * level l of every system.  Arguments as for spc_factorize, one per system;
+ * all systems use `precision` and `stream`.  outs[i] receives system i's
+ * factor.
+ */
+int spc_factorize_batch(int count, const spc_symbolic *syms, const double *const *d_values,
+                        int precision, void *stream, spc_factor *outs);
+
+/*
+ * spc_solve -- X := A^{-1} B in place (paper Sec. 2: the two triangular
+ * systems L y = b and L^T x = y).
+ *   d_B   device double, n x nrhs column-major with leading dimension ldb,
+ *         original (unpermuted) ordering; overwritten with the solution
+ * The arithmetic runs in the factor's precision.  Asynchronous.
+ */
+int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream);
+
+/* Result of iterative refinement. */
+typedef struct spc_refine_info {
+    int32_t iterations;       /* refinement steps taken */
+    int32_t converged;        /* 1 if berr <= tol */
+    double berr;              /* final max-over-RHS normwise backward error */
+} spc_refine_info;
+
+/*
+ * spc_solve_refined -- solve with the factor, then refine in FP64 on the
+ * device: r = b - A x (FP64 sparse product with the original A), d = solve(r)
+ * in the factor's precision, x += d (FP64), until the backward error
+ *   max_k ||b_k - A x_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf) <= tol
+ * or maxit steps.  d_values must be the values the factor was built from.
+ *   d_B  device double n x nrhs (ld), not modified
+ *   d_X  device double n x nrhs (ld), receives the solution
+ * Returns SPC_NO_CONVERGENCE (with info filled) when tol is not reached.
+ * Synchronizes `stream` once per step to read the error.
+ */
+int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, double *d_X,
+                      int nrhs, int64_t ld, double tol, int maxit, void *stream,
+                      spc_refine_info *info);
+
+/* Wait for the factor's work on its stream; SPC_NOT_SPD if a pivot failed,
+ * with *bad_pivot (nullable) set to the permuted column of the first
+ * failing pivot found, else -1. */
+int spc_sync(spc_factor f, int64_t *bad_pivot);
+
+/* Copy the panels to host as double (lptr layout of spc_symbolic_export;
+ * strict upper triangles of the diagonal blocks are zeroed). Synchronous. */
+int spc_factor_export(spc_factor f, double *h_dst);
+
+/* Device time in milliseconds of the last numeric factorization of f,
+ * measured with events around its launches on its stream. */
+int spc_factor_last_ms(spc_factor f, float *ms);
+
+/* Kernel classes of the numeric phase, for spc_factor_kernel_stats. */
+enum spc_kernel_class {
+    SPC_K_ASSEMBLE = 0,       /* zero the panels, scatter A into them */
+    SPC_K_PANEL = 1,          /* POTRF of a diagonal block + TRSM of the rows below */
+    SPC_K_TRAILING = 2,       /* SYRK/GEMM update inside a wide supernode */
+    SPC_K_SCATTER = 3,        /* SYRK/GEMM update scatter-added into ancestors */
+    SPC_K_COUNT = 4
+};
+
+typedef struct spc_kernel_stats {
+    int64_t launches;         /* launches of the class in the last factorization */
+    double total_ms;          /* sum of their device durations (events on the stream) */
+    double flops;             /* sum of their algorithmic flops (LAPACK counts) */
+} spc_kernel_stats;
+
+/* Turn per-launch event timing of f's factorizations on (1) or off (0).
+ * While on, every numeric launch is bracketed by two events on the stream. */
+int spc_factor_set_profiling(spc_factor f, int on);
+
+/* Per-class totals of the last profiled factorization of f (synchronizes). */
+int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *out);
+
+void spc_free_symbolic(spc_symbolic sym);
+void spc_free_factor(spc_factor f);
+const char *spc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPCHOL_H */

@@ -1,0 +1,537 @@
+// capi.cpp -- the extern "C" entry points declared in include/spchol.h.
+//
+// A symbolic handle owns the host analysis and, after the first numeric
+// call, one device allocation holding every array the kernels read.  A
+// factor handle owns its panels, a status word and a solve work area.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spchol.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+constexpr uint32_t kSymMagic = 0x53594d31u, kFacMagic = 0x46414331u, kDead = 0xdeadbeefu;
+
+struct DeviceArrays {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+    spc::DevPlan plan{};
+};
+
+}  // namespace
+
+struct spc_symbolic_s {
+    uint32_t magic = kSymMagic;
+    std::atomic<int> refs{1};
+    spc::Symbolic S;
+    DeviceArrays dev;
+    std::mutex mu;
+};
+
+struct spc_factor_s {
+    uint32_t magic = kFacMagic;
+    spc_symbolic_s *sym = nullptr;
+    int precision = SPC_FP64;
+    int device = -1;
+    void *Lx = nullptr;
+    unsigned long long *status = nullptr;
+    void *work = nullptr;       // solve work vectors (factor precision)
+    size_t work_bytes = 0;
+    double *refine = nullptr;   // refinement vectors (FP64)
+    size_t refine_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-launch profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_ev;     // pairs
+    std::vector<int> prof_cls;
+    std::vector<double> prof_flops;
+    size_t prof_used = 0;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) {                        \
+            return e_ == hipErrorOutOfMemory ? SPC_OUT_OF_MEMORY : SPC_DEVICE_ERROR; \
+        }                                              \
+    } while (0)
+
+bool sym_ok(spc_symbolic s) { return s && s->magic == kSymMagic; }
+bool fac_ok(spc_factor f) { return f && f->magic == kFacMagic && sym_ok(f->sym); }
+
+void sym_release(spc_symbolic_s *s) {
+    if (s && s->refs.fetch_sub(1) == 1) {
+        if (s->dev.base) {
+            int cur = -1;
+            (void)hipGetDevice(&cur);
+            if (s->dev.device >= 0) (void)hipSetDevice(s->dev.device);
+            (void)hipFree(s->dev.base);
+            if (cur >= 0) (void)hipSetDevice(cur);
+        }
+        s->magic = kDead;
+        delete s;
+    }
+}
+
+int check_device(int *dev_out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SPC_NO_DEVICE;
+    *dev_out = dev;
+    return SPC_OK;
+}
+
+template <typename V>
+size_t bytes_of(const std::vector<V> &v) {
+    return v.size() * sizeof(V);
+}
+
+// Upload the schedule once per symbolic handle and device.
+int ensure_device_plan(spc_symbolic_s *sym, int device) {
+    std::lock_guard<std::mutex> lk(sym->mu);
+    if (sym->dev.base) return sym->dev.device == device ? SPC_OK : SPC_INVALID_INPUT;
+    const spc::Symbolic &S = sym->S;
+    struct Piece {
+        const void *src;
+        size_t bytes;
+        const void **dst;
+    };
+    spc::DevPlan &P = sym->dev.plan;
+    std::vector<Piece> pieces = {
+        {S.super_ptr.data(), bytes_of(S.super_ptr), (const void **)&P.super_ptr},
+        {S.rptr.data(), bytes_of(S.rptr), (const void **)&P.rptr},
+        {S.lptr.data(), bytes_of(S.lptr), (const void **)&P.lptr},
+        {S.rows.data(), bytes_of(S.rows), (const void **)&P.rows},
+        {S.colpair.data(), bytes_of(S.colpair), (const void **)&P.colpair},
+        {S.pairs.data(), bytes_of(S.pairs), (const void **)&P.pairs},
+        {S.rel.data(), bytes_of(S.rel), (const void **)&P.rel},
+        {S.amap.data(), bytes_of(S.amap), (const void **)&P.amap},
+        {S.perm.data(), bytes_of(S.perm), (const void **)&P.perm},
+        {S.potrf_tasks.data(), bytes_of(S.potrf_tasks), (const void **)&P.potrf_tasks},
+        {S.panel_tasks.data(), bytes_of(S.panel_tasks), (const void **)&P.panel_tasks},
+        {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
+        {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
+        {S.sblocks.data(), bytes_of(S.sblocks), (const void **)&P.sblocks},
+        {S.sblock_order.data(), bytes_of(S.sblock_order), (const void **)&P.sblock_order},
+        {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
+    };
+    size_t total = 0;
+    for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
+    void *base = nullptr;
+    HIP_TRY(hipMalloc(&base, total ? total : 256));
+    std::vector<char> host(total ? total : 256, 0);
+    size_t off = 0;
+    for (auto &p : pieces) {
+        if (p.bytes) std::memcpy(host.data() + off, p.src, p.bytes);
+        *p.dst = (const char *)base + off;
+        off += (p.bytes + 255) & ~size_t(255);
+    }
+    hipError_t e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        return SPC_DEVICE_ERROR;
+    }
+    sym->dev.base = base;
+    sym->dev.bytes = total;
+    sym->dev.device = device;
+    return SPC_OK;
+}
+
+size_t plan_bytes(const spc::Symbolic &S) {
+    return bytes_of(S.super_ptr) + bytes_of(S.rptr) + bytes_of(S.lptr) + bytes_of(S.rows) +
+           bytes_of(S.colpair) + bytes_of(S.pairs) + bytes_of(S.rel) + bytes_of(S.amap) +
+           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.panel_tasks) + bytes_of(S.int_tiles) +
+           bytes_of(S.ext_tiles) + bytes_of(S.sblocks) + bytes_of(S.sblock_order) +
+           bytes_of(S.stasks);
+}
+
+// Brackets one launch with a pair of events when profiling is on.
+struct Prof {
+    spc_factor_s *f;
+    hipStream_t st;
+    template <typename Fn>
+    void run(int cls, double flops, Fn &&fn) {
+        if (!f || !f->profiling) {
+            fn();
+            return;
+        }
+        size_t i = f->prof_used++;
+        while (f->prof_ev.size() < 2 * (i + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                f->prof_used--;
+                fn();
+                return;
+            }
+            f->prof_ev.push_back(e);
+        }
+        if (f->prof_cls.size() <= i) {
+            f->prof_cls.resize(i + 1);
+            f->prof_flops.resize(i + 1);
+        }
+        f->prof_cls[i] = cls;
+        f->prof_flops[i] = flops;
+        (void)hipEventRecord(f->prof_ev[2 * i], st);
+        fn();
+        (void)hipEventRecord(f->prof_ev[2 * i + 1], st);
+    }
+};
+
+template <typename T>
+void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx,
+                    unsigned long long *status, hipStream_t st, Prof &prof) {
+    prof.run(SPC_K_ASSEMBLE, 0.0, [&] {
+        spc::launch_zero<T>(Lx, S.panel_entries(), st);
+        spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
+    });
+    for (int32_t l = 0; l < S.nlevels; ++l) {
+        for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
+            const auto &stp = S.steps[k];
+            prof.run(SPC_K_PANEL, stp.panel_flops, [&] {
+                spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, status, st);
+                spc::launch_trsm<T>(P, stp.p0, stp.p1, Lx, st);
+            });
+            if (stp.t1 > stp.t0)
+                prof.run(SPC_K_TRAILING, stp.trailing_flops,
+                         [&] { spc::launch_tiles<T>(P, false, stp.t0, stp.t1, Lx, st); });
+        }
+        if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
+            prof.run(SPC_K_SCATTER, S.ext_flops[l], [&] {
+                spc::launch_tiles<T>(P, true, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, st);
+            });
+    }
+}
+
+template <typename T>
+void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, T *W, int nrhs,
+                   hipStream_t st) {
+    const int64_t n = S.n;
+    for (int32_t l = 0; l < S.nslevels; ++l) {
+        spc::launch_solve_diag<T>(P, true, S.slevel_ptr[l], S.slevel_ptr[l + 1], Lx, W, n, nrhs, st);
+        spc::launch_solve_update<T>(P, true, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, W, n, nrhs, st);
+    }
+    for (int32_t l = S.nslevels - 1; l >= 0; --l) {
+        spc::launch_solve_update<T>(P, false, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, W, n, nrhs, st);
+        spc::launch_solve_diag<T>(P, false, S.slevel_ptr[l], S.slevel_ptr[l + 1], Lx, W, n, nrhs, st);
+    }
+}
+
+int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
+    const spc::Symbolic &S = f->sym->S;
+    const spc::DevPlan &P = f->sym->dev.plan;
+    spc::launch_status_reset(f->status, st);
+    HIP_TRY(hipEventRecord(f->ev0, st));
+    f->prof_used = 0;
+    Prof prof{f, st};
+    if (f->precision == SPC_FP64)
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, f->status, st, prof);
+    else
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, f->status, st, prof);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(f->ev1, st));
+    f->stream = st;
+    return SPC_OK;
+}
+
+int create_factor(spc_symbolic sym, int precision, spc_factor *out) {
+    if (precision != SPC_FP64 && precision != SPC_FP32) return SPC_INVALID_INPUT;
+    int dev = -1;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    rc = ensure_device_plan(sym, dev);
+    if (rc) return rc;
+    spc_factor f = new (std::nothrow) spc_factor_s;
+    if (!f) return SPC_OUT_OF_MEMORY;
+    f->sym = sym;
+    sym->refs.fetch_add(1);
+    f->precision = precision;
+    f->device = dev;
+    size_t esz = precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    size_t bytes = std::max<size_t>(1, (size_t)sym->S.panel_entries()) * esz;
+    hipError_t e = hipMalloc(&f->Lx, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipEventCreate(&f->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&f->ev1);
+    if (e != hipSuccess) {
+        spc_free_factor(f);
+        return e == hipErrorOutOfMemory ? SPC_OUT_OF_MEMORY : SPC_DEVICE_ERROR;
+    }
+    *out = f;
+    return SPC_OK;
+}
+
+int ensure_bytes(void **p, size_t *have, size_t need) {
+    if (*have >= need) return SPC_OK;
+    if (*p) HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+    HIP_TRY(hipMalloc(p, need));
+    *have = need;
+    return SPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, const int32_t *h_perm,
+                const spc_options *opts, spc_symbolic *out) {
+    if (!out) return SPC_INVALID_INPUT;
+    *out = nullptr;
+    spc_symbolic s = new (std::nothrow) spc_symbolic_s;
+    if (!s) return SPC_OUT_OF_MEMORY;
+    double z = opts ? opts->amalg_z : 0.05;
+    int rc;
+    try {
+        rc = spc::analyze(n, h_colptr, h_rowidx, h_perm, z, s->S);
+    } catch (const std::bad_alloc &) {
+        rc = SPC_OUT_OF_MEMORY;
+    } catch (...) {
+        rc = SPC_INVALID_INPUT;
+    }
+    if (rc != SPC_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return SPC_OK;
+}
+
+int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
+    if (!sym_ok(sym)) return SPC_BAD_HANDLE;
+    if (!out) return SPC_INVALID_INPUT;
+    const spc::Symbolic &S = sym->S;
+    out->n = S.n;
+    out->nnz_a = S.nnzA;
+    out->nsuper = S.nsuper;
+    out->nnz_l = S.nnzL;
+    out->panel_entries = S.panel_entries();
+    out->flops = S.flops;
+    out->levels = S.nlevels;
+    out->rows_total = S.rows_total();
+    out->max_width = S.max_w;
+    out->max_rows = S.max_m;
+    out->factor_bytes_fp64 = (int64_t)(S.panel_entries() * 8 + plan_bytes(S));
+    out->factor_bytes_fp32 = (int64_t)(S.panel_entries() * 4 + plan_bytes(S));
+    return SPC_OK;
+}
+
+int spc_symbolic_export(spc_symbolic sym, int which, void *h_dst) {
+    if (!sym_ok(sym)) return SPC_BAD_HANDLE;
+    if (!h_dst) return SPC_INVALID_INPUT;
+    const spc::Symbolic &S = sym->S;
+    auto put = [&](const auto &v) {
+        if (!v.empty()) std::memcpy(h_dst, v.data(), bytes_of(v));
+        return SPC_OK;
+    };
+    switch (which) {
+    case 0: return put(S.perm);
+    case 1: return put(S.parent);
+    case 2: return put(S.colcount);
+    case 3: return put(S.super_ptr);
+    case 4: return put(S.sparent);
+    case 5: return put(S.rptr);
+    case 6: return put(S.rows);
+    case 7: return put(S.lptr);
+    case 8: return put(S.level);
+    default: return SPC_INVALID_INPUT;
+    }
+}
+
+int spc_factorize(spc_symbolic sym, const double *d_values, int precision, void *stream,
+                  spc_factor *out) {
+    if (!out) return SPC_INVALID_INPUT;
+    *out = nullptr;
+    if (!sym_ok(sym)) return SPC_BAD_HANDLE;
+    if (!d_values && sym->S.nnzA > 0) return SPC_INVALID_INPUT;
+    spc_factor f = nullptr;
+    int rc = create_factor(sym, precision, &f);
+    if (rc) return rc;
+    rc = run_factor(f, d_values, (hipStream_t)stream);
+    if (rc) {
+        spc_free_factor(f);
+        return rc;
+    }
+    *out = f;
+    return SPC_OK;
+}
+
+int spc_refactorize(spc_factor f, const double *d_values, void *stream) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!d_values && f->sym->S.nnzA > 0) return SPC_INVALID_INPUT;
+    return run_factor(f, d_values, (hipStream_t)stream);
+}
+
+int spc_factorize_batch(int count, const spc_symbolic *syms, const double *const *d_values,
+                        int precision, void *stream, spc_factor *outs) {
+    if (count < 0 || (count > 0 && (!syms || !d_values || !outs))) return SPC_INVALID_INPUT;
+    for (int i = 0; i < count; ++i) outs[i] = nullptr;
+    for (int i = 0; i < count; ++i) {
+        int rc = spc_factorize(syms[i], d_values[i], precision, stream, &outs[i]);
+        if (rc) {
+            for (int k = 0; k < i; ++k) {
+                spc_free_factor(outs[k]);
+                outs[k] = nullptr;
+            }
+            return rc;
+        }
+    }
+    return SPC_OK;
+}
+
+int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    const spc::Symbolic &S = f->sym->S;
+    if (nrhs < 0 || ldb < S.n || (!d_B && nrhs > 0 && S.n > 0)) return SPC_INVALID_INPUT;
+    if (nrhs == 0 || S.n == 0) return SPC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const spc::DevPlan &P = f->sym->dev.plan;
+    size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    constexpr int kChunk = 16;
+    int rc = ensure_bytes(&f->work, &f->work_bytes, (size_t)S.n * kChunk * esz);
+    if (rc) return rc;
+    for (int q0 = 0; q0 < nrhs; q0 += kChunk) {
+        int q = std::min(kChunk, nrhs - q0);
+        double *B = d_B + (int64_t)q0 * ldb;
+        if (f->precision == SPC_FP64) {
+            double *W = (double *)f->work;
+            spc::launch_perm_in<double>(P, S.n, q, B, ldb, W, st);
+            enqueue_solve<double>(S, P, (const double *)f->Lx, W, q, st);
+            spc::launch_perm_out<double>(P, S.n, q, W, B, ldb, st);
+        } else {
+            float *W = (float *)f->work;
+            spc::launch_perm_in<float>(P, S.n, q, B, ldb, W, st);
+            enqueue_solve<float>(S, P, (const float *)f->Lx, W, q, st);
+            spc::launch_perm_out<float>(P, S.n, q, W, B, ldb, st);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return SPC_OK;
+}
+
+int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, double *d_X, int nrhs,
+                      int64_t ld, double tol, int maxit, void *stream, spc_refine_info *info) {
+    (void)f; (void)d_values; (void)d_B; (void)d_X; (void)nrhs; (void)ld; (void)tol; (void)maxit;
+    (void)stream; (void)info;
+    return SPC_INVALID_INPUT;
+}
+
+int spc_sync(spc_factor f, int64_t *bad_pivot) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (bad_pivot) *bad_pivot = -1;
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
+    if (v != ~0ull) {
+        if (bad_pivot) *bad_pivot = (int64_t)v;
+        return SPC_NOT_SPD;
+    }
+    return SPC_OK;
+}
+
+int spc_factor_export(spc_factor f, double *h_dst) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!h_dst) return SPC_INVALID_INPUT;
+    const spc::Symbolic &S = f->sym->S;
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    int64_t cnt = S.panel_entries();
+    if (f->precision == SPC_FP64) {
+        HIP_TRY(hipMemcpy(h_dst, f->Lx, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(cnt);
+        HIP_TRY(hipMemcpy(tmp.data(), f->Lx, cnt * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < cnt; ++i) h_dst[i] = tmp[i];
+    }
+    for (int32_t s = 0; s < S.nsuper; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+        double *Pn = h_dst + S.lptr[s];
+        for (int64_t c = 1; c < w; ++c)
+            for (int64_t i = 0; i < c; ++i) Pn[c * m + i] = 0.0;
+    }
+    return SPC_OK;
+}
+
+int spc_factor_last_ms(spc_factor f, float *ms) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!ms) return SPC_INVALID_INPUT;
+    HIP_TRY(hipEventSynchronize(f->ev1));
+    HIP_TRY(hipEventElapsedTime(ms, f->ev0, f->ev1));
+    return SPC_OK;
+}
+
+int spc_factor_set_profiling(spc_factor f, int on) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    f->profiling = on != 0;
+    return SPC_OK;
+}
+
+int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *out) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!out || kernel_class < 0 || kernel_class >= SPC_K_COUNT) return SPC_INVALID_INPUT;
+    out->launches = 0;
+    out->total_ms = 0.0;
+    out->flops = 0.0;
+    if (f->prof_used) HIP_TRY(hipEventSynchronize(f->prof_ev[2 * f->prof_used - 1]));
+    for (size_t i = 0; i < f->prof_used; ++i) {
+        if (f->prof_cls[i] != kernel_class) continue;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, f->prof_ev[2 * i], f->prof_ev[2 * i + 1]));
+        out->launches++;
+        out->total_ms += ms;
+        out->flops += f->prof_flops[i];
+    }
+    return SPC_OK;
+}
+
+void spc_free_symbolic(spc_symbolic sym) {
+    if (!sym_ok(sym)) return;
+    sym_release(sym);
+}
+
+void spc_free_factor(spc_factor f) {
+    if (!f || f->magic != kFacMagic) return;
+    if (f->stream || f->Lx) (void)hipStreamSynchronize(f->stream);
+    if (f->Lx) (void)hipFree(f->Lx);
+    if (f->status) (void)hipFree(f->status);
+    if (f->work) (void)hipFree(f->work);
+    if (f->refine) (void)hipFree(f->refine);
+    if (f->ev0) (void)hipEventDestroy(f->ev0);
+    if (f->ev1) (void)hipEventDestroy(f->ev1);
+    for (hipEvent_t e : f->prof_ev) (void)hipEventDestroy(e);
+    spc_symbolic_s *s = f->sym;
+    f->magic = kDead;
+    delete f;
+    if (s) sym_release(s);
+}
+
+const char *spc_status_string(int status) {
+    switch (status) {
+    case SPC_OK: return "ok";
+    case SPC_INVALID_INPUT: return "invalid input";
+    case SPC_NOT_SPD: return "matrix is not positive definite";
+    case SPC_OUT_OF_MEMORY: return "out of memory";
+    case SPC_NO_CONVERGENCE: return "refinement did not converge";
+    case SPC_DEVICE_ERROR: return "device error";
+    case SPC_BAD_HANDLE: return "bad handle";
+    case SPC_NO_DEVICE: return "no gfx950 device";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// kernels.h -- host-side launchers of the device kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace spc {
+
+// Device copy of the symbolic arrays the kernels read.
+struct DevPlan {
+    const int32_t *super_ptr;
+    const int64_t *rptr;
+    const int64_t *lptr;
+    const int32_t *rows;
+    const int32_t *colpair;
+    const UpdatePair *pairs;
+    const int32_t *rel;
+    const int64_t *amap;
+    const int32_t *perm;
+    const PanelTask *potrf_tasks;
+    const PanelTask *panel_tasks;
+    const TileTask *int_tiles;
+    const TileTask *ext_tiles;
+    const SolveBlock *sblocks;
+    const int32_t *sblock_order;
+    const SolveTask *stasks;
+};
+
+// status word: lowest permuted column whose pivot failed, or ~0ull
+void launch_status_reset(unsigned long long *status, hipStream_t st);
+template <typename T>
+void launch_zero(T *x, int64_t count, hipStream_t st);
+template <typename T>
+void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx, hipStream_t st);
+template <typename T>
+void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, unsigned long long *status,
+                  hipStream_t st);
+template <typename T>
+void launch_trsm(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+template <typename T>
+void launch_tiles(const DevPlan &P, bool external, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+
+template <typename T>
+void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,
+                    hipStream_t st);
+template <typename T>
+void launch_perm_out(const DevPlan &P, int64_t n, int nrhs, const T *W, double *B, int64_t ldb,
+                     hipStream_t st);
+template <typename T>
+void launch_solve_diag(const DevPlan &P, bool forward, int64_t e0, int64_t e1, const T *Lx, T *W,
+                       int64_t n, int nrhs, hipStream_t st);
+template <typename T>
+void launch_solve_update(const DevPlan &P, bool forward, int64_t t0, int64_t t1, const T *Lx,
+                         T *W, int64_t n, int nrhs, hipStream_t st);
+
+}  // namespace spc

@@ -1,0 +1,119 @@
+// plan.h -- host-side symbolic analysis and the device schedule built from it.
+//
+// Internal to the library: nothing here crosses the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace spc {
+
+// Tile edge of the update kernels and block width of the panel kernels.
+constexpr int kTile = 64;
+constexpr int kPanelNB = 64;
+// Rows of the panel triangular solve handled by one workgroup.
+constexpr int kPanelRows = 32;
+// Block width of the triangular solves and rows per update task there.
+constexpr int kSolveNB = 64;
+constexpr int kSolveRows = 256;
+
+// One pair (source supernode s, ancestor t) of the scatter: rows
+// i0..i1-1 of R_s (positions, i0 >= w_s) are columns of t, and rows
+// i0..m_s-1 of R_s sit at positions rel[rel_off + (i - i0)] of R_t.
+struct UpdatePair {
+    int32_t target;
+    int32_t i0;
+    int32_t i1;
+    int32_t pad;
+    int64_t rel_off;
+};
+
+// One output tile of a SYRK/GEMM update of supernode s: rows i0..i0+63 and
+// columns j0..j0+63 (positions in R_s) of P P^T with P the columns
+// k0..k1-1 of the panel.
+struct TileTask {
+    int32_t s;
+    int32_t i0;
+    int32_t j0;
+    int32_t k0;
+    int32_t k1;
+    int32_t jmax;   // columns j >= jmax are outside the update
+    int32_t pad[2];
+};
+
+// Panel work on block b (columns b*kPanelNB ..) of supernode s.  A POTRF
+// task factors the diagonal block; a TRSM task solves rows r0..r1-1
+// (positions below the block) against the factored block.
+struct PanelTask {
+    int32_t s;
+    int32_t b;   // block index: columns b*kPanelNB ..
+    int32_t r0;
+    int32_t r1;
+};
+
+// One block of columns of a supernode in the triangular solves.
+struct SolveBlock {
+    int32_t s;
+    int32_t c0;  // first column (position in the panel)
+    int32_t c1;  // one past the last column
+    int32_t pad;
+};
+
+struct SolveTask {
+    int32_t blk;
+    int32_t r0;
+    int32_t r1;
+    int32_t pad;
+};
+
+struct Symbolic {
+    int64_t n = 0, nnzA = 0;
+    std::vector<int32_t> perm, iperm, parent, colcount;
+    int32_t nsuper = 0;
+    std::vector<int32_t> super_ptr, snode, sparent, level;
+    std::vector<int64_t> rptr, lptr;
+    std::vector<int32_t> rows;
+    int64_t flops = 0, nnzL = 0, max_w = 0, max_m = 0;
+    int32_t nlevels = 0;
+    std::vector<int64_t> amap;  // caller entry k -> panel offset
+
+    // scatter plan
+    std::vector<int64_t> pair_ptr;     // [nsuper+1] pairs of each source
+    std::vector<UpdatePair> pairs;
+    std::vector<int32_t> colpair;      // [rows_total] pair of each below row
+    std::vector<int32_t> rel;
+
+    // factor schedule: for each level, a list of steps; each step is a
+    // panel-task range followed by a tile-task range
+    struct Step {
+        int64_t f0, f1;   // POTRF tasks
+        int64_t p0, p1;   // TRSM tasks
+        int64_t t0, t1;   // internal trailing-update tiles
+        double panel_flops, trailing_flops;  // algorithmic flops of the two launches
+    };
+    std::vector<int64_t> level_step_ptr;   // [nlevels+1]
+    std::vector<Step> steps;
+    std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles
+    std::vector<double> ext_flops;         // [nlevels] algorithmic flops per launch
+    std::vector<PanelTask> potrf_tasks;
+    std::vector<PanelTask> panel_tasks;
+    std::vector<TileTask> int_tiles;
+    std::vector<TileTask> ext_tiles;
+
+    // solve schedule: blocks grouped by block-tree level
+    std::vector<SolveBlock> sblocks;
+    std::vector<int64_t> slevel_ptr;       // [nslevels+1] into sblock_order
+    std::vector<int32_t> sblock_order;
+    std::vector<int64_t> stask_ptr;        // [nslevels+1] into stasks
+    std::vector<SolveTask> stasks;
+    int32_t nslevels = 0;
+
+    int64_t rows_total() const { return rptr.empty() ? 0 : rptr.back(); }
+    int64_t panel_entries() const { return lptr.empty() ? 0 : lptr.back(); }
+};
+
+// Returns 0 or a negative spc_status.
+int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm,
+            double z, Symbolic &S);
+
+}  // namespace spc

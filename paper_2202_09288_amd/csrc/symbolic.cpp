@@ -1,0 +1,415 @@
+// symbolic.cpp -- host analysis: ordering, elimination tree, column counts,
+// supernodes, relative indices and the level schedule of the device kernels.
+//
+// The analyze phase of a supernodal direct solver (paper Sec. 2, "Background
+// on CHOLMOD": reordering, elimination tree setup, node amalgamation).  The
+// algorithms here are the classical ones:
+//   - elimination tree: Liu's algorithm with path compression over the rows
+//     of the lower triangle (J. W. H. Liu, "The role of elimination trees in
+//     sparse factorization", SIMAX 1990);
+//   - column counts and row lists: traversal of the row subtrees; row i of L
+//     is the set of nodes on the tree paths from each j with A_ij != 0 up to
+//     i, so every visited node gains row i;
+//   - supernodes: fundamental supernodes, then chain amalgamation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "plan.h"
+#include "../../include/spchol.h"
+
+namespace spc {
+namespace {
+
+// Strictly-lower pattern of A(p, p) by rows: row i lists columns j < i.
+void lower_rows(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *iperm,
+                std::vector<int64_t> &rp, std::vector<int32_t> &ri) {
+    rp.assign(n + 1, 0);
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t k = colptr[c] + 1; k < colptr[c + 1]; ++k) {
+            int32_t a = iperm[rowidx[k]], b = iperm[c];
+            rp[std::max(a, b) + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    ri.resize(rp[n]);
+    std::vector<int64_t> cur(rp.begin(), rp.end() - 1);
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t k = colptr[c] + 1; k < colptr[c + 1]; ++k) {
+            int32_t a = iperm[rowidx[k]], b = iperm[c];
+            ri[cur[std::max(a, b)]++] = std::min(a, b);
+        }
+}
+
+void etree_liu(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ri,
+               std::vector<int32_t> &parent) {
+    parent.assign(n, -1);
+    std::vector<int32_t> anc(n, -1);
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t e = rp[k]; e < rp[k + 1]; ++e) {
+            int32_t r = ri[e];
+            while (r != -1 && r != k) {
+                int32_t next = anc[r];
+                anc[r] = (int32_t)k;
+                if (next == -1) parent[r] = (int32_t)k;
+                r = next;
+            }
+        }
+}
+
+// Postorder with roots and children in ascending order, numbered on exit.
+void postorder(int64_t n, const std::vector<int32_t> &parent, std::vector<int32_t> &post) {
+    std::vector<int64_t> cptr(n + 2, 0);
+    for (int64_t j = 0; j < n; ++j) cptr[(parent[j] == -1 ? n : parent[j]) + 1]++;
+    for (int64_t j = 0; j <= n; ++j) cptr[j + 1] += cptr[j];
+    std::vector<int32_t> kids(n);
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t j = 0; j < n; ++j) kids[fill[parent[j] == -1 ? n : parent[j]]++] = (int32_t)j;
+    // node n is a virtual root over the forest
+    post.resize(n);
+    std::vector<std::pair<int32_t, int64_t>> st;
+    st.reserve(64);
+    st.push_back({(int32_t)n, cptr[n]});
+    int64_t k = 0;
+    while (!st.empty()) {
+        auto &top = st.back();
+        if (top.second < cptr[top.first + 1]) {
+            int32_t c = kids[top.second++];
+            st.push_back({c, cptr[c]});
+        } else {
+            if (top.first != n) post[k++] = top.first;
+            st.pop_back();
+        }
+    }
+}
+
+int64_t find_pos(const int32_t *R, int64_t m, int32_t row) {
+    const int32_t *p = std::lower_bound(R, R + m, row);
+    return (p != R + m && *p == row) ? (p - R) : -1;
+}
+
+}  // namespace
+
+int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm_in,
+            double z, Symbolic &S) {
+    // ---- validation --------------------------------------------------------
+    if (n < 0 || n > INT32_MAX - 1 || !colptr) return SPC_INVALID_INPUT;
+    if (colptr[0] != 0) return SPC_INVALID_INPUT;
+    for (int64_t c = 0; c < n; ++c) {
+        if (colptr[c + 1] <= colptr[c]) return SPC_INVALID_INPUT;  // diagonal missing
+        if (!rowidx) return SPC_INVALID_INPUT;
+        if (rowidx[colptr[c]] != c) return SPC_INVALID_INPUT;
+        for (int64_t k = colptr[c] + 1; k < colptr[c + 1]; ++k)
+            if (rowidx[k] <= rowidx[k - 1] || rowidx[k] >= n) return SPC_INVALID_INPUT;
+    }
+    S = Symbolic();
+    S.n = n;
+    S.nnzA = colptr[n];
+    std::vector<int32_t> perm0(n), iperm0(n, -1);
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t p = perm_in ? perm_in[k] : (int32_t)k;
+        if (p < 0 || p >= n || iperm0[p] != -1) return SPC_INVALID_INPUT;
+        perm0[k] = p;
+        iperm0[p] = (int32_t)k;
+    }
+
+    // ---- elimination tree, postorder, final order --------------------------
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ri, parent0, post;
+    lower_rows(n, colptr, rowidx, iperm0.data(), rp, ri);
+    etree_liu(n, rp, ri, parent0);
+    postorder(n, parent0, post);
+    std::vector<int32_t> ipost(n);
+    for (int64_t k = 0; k < n; ++k) ipost[post[k]] = (int32_t)k;
+    S.perm.resize(n);
+    S.iperm.resize(n);
+    S.parent.resize(n);
+    for (int64_t k = 0; k < n; ++k) {
+        S.perm[k] = perm0[post[k]];
+        int32_t p = parent0[post[k]];
+        S.parent[k] = p == -1 ? -1 : ipost[p];
+    }
+    for (int64_t k = 0; k < n; ++k) S.iperm[S.perm[k]] = (int32_t)k;
+    lower_rows(n, colptr, rowidx, S.iperm.data(), rp, ri);
+
+    // ---- column counts by row subtrees ------------------------------------
+    std::vector<int32_t> mark(n, -1);
+    std::vector<int64_t> cnt(n, 1);
+    for (int64_t i = 0; i < n; ++i) {
+        mark[i] = (int32_t)i;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            for (int32_t p = ri[e]; mark[p] != i; p = S.parent[p]) {
+                mark[p] = (int32_t)i;
+                cnt[p]++;
+            }
+    }
+    S.colcount.resize(n);
+    for (int64_t j = 0; j < n; ++j) {
+        S.colcount[j] = (int32_t)cnt[j];
+        S.nnzL += cnt[j];
+        S.flops += cnt[j] * cnt[j];
+    }
+
+    // ---- fundamental supernodes -------------------------------------------
+    std::vector<int32_t> nkids(n, 0);
+    for (int64_t j = 0; j < n; ++j)
+        if (S.parent[j] != -1) nkids[S.parent[j]]++;
+    std::vector<int32_t> fstart;  // first column of each fundamental supernode
+    for (int64_t j = 0; j < n; ++j) {
+        bool joins = j > 0 && S.parent[j - 1] == j && nkids[j] == 1 &&
+                     S.colcount[j - 1] == S.colcount[j] + 1;
+        if (!joins) fstart.push_back((int32_t)j);
+    }
+    int32_t nf = (int32_t)fstart.size();
+    fstart.push_back((int32_t)n);
+    std::vector<int32_t> fof(n);
+    for (int32_t p = 0; p < nf; ++p)
+        for (int32_t j = fstart[p]; j < fstart[p + 1]; ++j) fof[j] = p;
+
+    // ---- chain amalgamation -------------------------------------------------
+    // p joins the running group G (which ends in p-1) when p-1's parent
+    // supernode is p and the merged group keeps explicit zeros within z of
+    // its stored lower-trapezoid entries:
+    //   W' = W + w, M' = W + m, Z' = Z + W (M' - M), E' = W'M' - W'(W'-1)/2,
+    //   accept iff (double)Z' <= z * (double)E'.
+    S.super_ptr.clear();
+    int64_t W = 0, M = 0, Z = 0;
+    for (int32_t p = 0; p < nf; ++p) {
+        int64_t w = fstart[p + 1] - fstart[p];
+        int64_t m = S.colcount[fstart[p]];
+        bool accept = false;
+        if (p > 0) {
+            int32_t lastcol = fstart[p] - 1;  // last column of p-1
+            int32_t par = S.parent[lastcol];
+            if (par != -1 && fof[par] == p) {
+                int64_t W2 = W + w, M2 = W + m, Z2 = Z + W * (M2 - M);
+                int64_t E2 = W2 * M2 - W2 * (W2 - 1) / 2;
+                if ((double)Z2 <= z * (double)E2) {
+                    accept = true;
+                    W = W2; M = M2; Z = Z2;
+                }
+            }
+        }
+        if (!accept) {
+            S.super_ptr.push_back(fstart[p]);
+            W = w; M = m; Z = 0;
+        }
+    }
+    S.nsuper = (int32_t)S.super_ptr.size();
+    S.super_ptr.push_back((int32_t)n);
+    const int32_t ns = S.nsuper;
+    S.snode.resize(n);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t j = S.super_ptr[s]; j < S.super_ptr[s + 1]; ++j) S.snode[j] = s;
+    S.sparent.resize(ns);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t p = S.parent[S.super_ptr[s + 1] - 1];
+        S.sparent[s] = p == -1 ? -1 : S.snode[p];
+    }
+
+    // ---- row lists: R_s = cols(s) U (struct(L_{l_s}) below l_s) ----------
+    // Every row i > l_s of L in a column of s is also in column l_s (the
+    // columns of s are descendants of l_s), so the last column suffices.
+    std::vector<int64_t> below(ns, 0);
+    std::vector<char> islast(n, 0);
+    for (int32_t s = 0; s < ns; ++s) islast[S.super_ptr[s + 1] - 1] = 1;
+    std::fill(mark.begin(), mark.end(), -1);
+    for (int64_t i = 0; i < n; ++i) {
+        mark[i] = (int32_t)i;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            for (int32_t p = ri[e]; mark[p] != i; p = S.parent[p]) {
+                mark[p] = (int32_t)i;
+                if (islast[p]) below[S.snode[p]]++;
+            }
+    }
+    S.rptr.assign(ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s)
+        S.rptr[s + 1] = S.rptr[s] + (S.super_ptr[s + 1] - S.super_ptr[s]) + below[s];
+    S.rows.resize(S.rptr[ns]);
+    std::vector<int64_t> cur(ns);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t o = S.rptr[s];
+        for (int32_t j = S.super_ptr[s]; j < S.super_ptr[s + 1]; ++j) S.rows[o++] = j;
+        cur[s] = o;
+    }
+    std::fill(mark.begin(), mark.end(), -1);
+    for (int64_t i = 0; i < n; ++i) {
+        mark[i] = (int32_t)i;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            for (int32_t p = ri[e]; mark[p] != i; p = S.parent[p]) {
+                mark[p] = (int32_t)i;
+                if (islast[p]) S.rows[cur[S.snode[p]]++] = (int32_t)i;
+            }
+    }
+    S.lptr.assign(ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+        S.lptr[s + 1] = S.lptr[s] + w * m;
+        S.max_w = std::max(S.max_w, w);
+        S.max_m = std::max(S.max_m, m);
+    }
+
+    // ---- levels (height in the supernodal tree) ---------------------------
+    S.level.assign(ns, 0);
+    S.nlevels = ns ? 1 : 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t p = S.sparent[s];
+        if (p != -1) S.level[p] = std::max(S.level[p], S.level[s] + 1);
+        S.nlevels = std::max(S.nlevels, S.level[s] + 1);
+    }
+
+    // ---- assembly map -------------------------------------------------------
+    S.amap.resize(S.nnzA);
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t k = colptr[c]; k < colptr[c + 1]; ++k) {
+            int32_t a = S.iperm[rowidx[k]], b = S.iperm[c];
+            int32_t row = std::max(a, b), col = std::min(a, b);
+            int32_t s = S.snode[col];
+            int64_t m = S.rptr[s + 1] - S.rptr[s];
+            int64_t pos = find_pos(S.rows.data() + S.rptr[s], m, row);
+            if (pos < 0) return SPC_INVALID_INPUT;  // cannot happen for a valid pattern
+            S.amap[k] = S.lptr[s] + (int64_t)(col - S.super_ptr[s]) * m + pos;
+        }
+
+    // ---- scatter pairs and relative indices -------------------------------
+    S.pair_ptr.assign(ns + 1, 0);
+    S.colpair.assign(S.rptr[ns], -1);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+        const int32_t *R = S.rows.data() + S.rptr[s];
+        int64_t i = w;
+        while (i < m) {
+            int32_t t = S.snode[R[i]];
+            int64_t i1 = i;
+            while (i1 < m && S.snode[R[i1]] == t) ++i1;
+            UpdatePair pr;
+            pr.target = t;
+            pr.i0 = (int32_t)i;
+            pr.i1 = (int32_t)i1;
+            pr.pad = 0;
+            pr.rel_off = (int64_t)S.rel.size();
+            const int32_t *Rt = S.rows.data() + S.rptr[t];
+            int64_t mt = S.rptr[t + 1] - S.rptr[t], q = 0;
+            for (int64_t k = i; k < m; ++k) {  // merge: R_s[i:] is a subset of R_t
+                while (q < mt && Rt[q] < R[k]) ++q;
+                if (q == mt || Rt[q] != R[k]) return SPC_INVALID_INPUT;  // cannot happen
+                S.rel.push_back((int32_t)q);
+            }
+            for (int64_t k = i; k < i1; ++k) S.colpair[S.rptr[s] + k] = (int32_t)S.pairs.size();
+            S.pairs.push_back(pr);
+            i = i1;
+        }
+        S.pair_ptr[s + 1] = (int64_t)S.pairs.size();
+    }
+
+    // ---- factor schedule ----------------------------------------------------
+    std::vector<std::vector<int32_t>> bylevel(S.nlevels);
+    for (int32_t s = 0; s < ns; ++s) bylevel[S.level[s]].push_back(s);
+    S.level_step_ptr.assign(S.nlevels + 1, 0);
+    S.ext_tile_ptr.assign(S.nlevels + 1, 0);
+    for (int32_t l = 0; l < S.nlevels; ++l) {
+        int64_t maxb = 0;
+        for (int32_t s : bylevel[l]) {
+            int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
+            maxb = std::max(maxb, (w + kPanelNB - 1) / kPanelNB);
+        }
+        for (int64_t b = 0; b < maxb; ++b) {
+            Symbolic::Step st;
+            st.panel_flops = 0.0;
+            st.trailing_flops = 0.0;
+            st.f0 = (int64_t)S.potrf_tasks.size();
+            st.p0 = (int64_t)S.panel_tasks.size();
+            st.t0 = (int64_t)S.int_tiles.size();
+            for (int32_t s : bylevel[l]) {
+                int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+                int64_t c0 = b * kPanelNB;
+                if (c0 >= w) continue;
+                int64_t c1 = std::min<int64_t>(c0 + kPanelNB, w);
+                // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
+                // SYRK k n(n+1), GEMM 2 m n k
+                double nbd = (double)(c1 - c0);
+                st.panel_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0 +
+                                  (double)(m - c1) * nbd * nbd;
+                st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
+                                     2.0 * (double)(m - w) * (double)(w - c1) * nbd;
+                S.potrf_tasks.push_back(PanelTask{s, (int32_t)b, (int32_t)c0, (int32_t)c1});
+                for (int64_t r = c1; r < m; r += kPanelRows)
+                    S.panel_tasks.push_back(
+                        PanelTask{s, (int32_t)b, (int32_t)r, (int32_t)std::min<int64_t>(r + kPanelRows, m)});
+                // trailing update inside the panel: rows [c1, m), cols [c1, w)
+                for (int64_t j0 = c1; j0 < w; j0 += kTile)
+                    for (int64_t i0 = j0; i0 < m; i0 += kTile) {
+                        TileTask tt{s, (int32_t)i0, (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w, {0, 0}};
+                        S.int_tiles.push_back(tt);
+                    }
+            }
+            st.f1 = (int64_t)S.potrf_tasks.size();
+            st.p1 = (int64_t)S.panel_tasks.size();
+            st.t1 = (int64_t)S.int_tiles.size();
+            S.steps.push_back(st);
+        }
+        S.level_step_ptr[l + 1] = (int64_t)S.steps.size();
+        double ef = 0.0;
+        for (int32_t s : bylevel[l]) {
+            int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+            ef += (double)(m - w) * (double)(m - w + 1) * (double)w;
+            for (int64_t j0 = w; j0 < m; j0 += kTile)
+                for (int64_t i0 = j0; i0 < m; i0 += kTile) {
+                    TileTask tt{s, (int32_t)i0, (int32_t)j0, 0, (int32_t)w, (int32_t)m, {0, 0}};
+                    S.ext_tiles.push_back(tt);
+                }
+        }
+        S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
+        S.ext_flops.push_back(ef);
+    }
+
+    // ---- solve schedule: column blocks and their tree levels ---------------
+    std::vector<int32_t> first_blk(ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
+        first_blk[s] = (int32_t)S.sblocks.size();
+        for (int64_t c0 = 0; c0 < w; c0 += kSolveNB)
+            S.sblocks.push_back(SolveBlock{s, (int32_t)c0, (int32_t)std::min<int64_t>(c0 + kSolveNB, w), 0});
+    }
+    int64_t nb = (int64_t)S.sblocks.size();
+    std::vector<int32_t> blev(nb, 0);
+    int32_t nsl = nb ? 1 : 0;
+    for (int64_t q = 0; q < nb; ++q) {
+        const SolveBlock &B = S.sblocks[q];
+        int64_t w = S.super_ptr[B.s + 1] - S.super_ptr[B.s];
+        int64_t pq = -1;
+        if (B.c1 < w) pq = q + 1;
+        else {
+            int32_t pc = S.parent[S.super_ptr[B.s + 1] - 1];
+            if (pc != -1) {
+                int32_t t = S.snode[pc];
+                pq = first_blk[t] + (pc - S.super_ptr[t]) / kSolveNB;
+            }
+        }
+        if (pq != -1) blev[pq] = std::max(blev[pq], blev[q] + 1);
+        nsl = std::max(nsl, blev[q] + 1);
+    }
+    S.nslevels = nsl;
+    S.slevel_ptr.assign(nsl + 1, 0);
+    for (int64_t q = 0; q < nb; ++q) S.slevel_ptr[blev[q] + 1]++;
+    for (int32_t l = 0; l < nsl; ++l) S.slevel_ptr[l + 1] += S.slevel_ptr[l];
+    S.sblock_order.resize(nb);
+    {
+        std::vector<int64_t> f(S.slevel_ptr.begin(), S.slevel_ptr.end() - 1);
+        for (int64_t q = 0; q < nb; ++q) S.sblock_order[f[blev[q]]++] = (int32_t)q;
+    }
+    S.stask_ptr.assign(nsl + 1, 0);
+    for (int32_t l = 0; l < nsl; ++l) {
+        for (int64_t e = S.slevel_ptr[l]; e < S.slevel_ptr[l + 1]; ++e) {
+            int32_t q = S.sblock_order[e];
+            const SolveBlock &B = S.sblocks[q];
+            int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
+            for (int64_t r = B.c1; r < m; r += kSolveRows)
+                S.stasks.push_back(SolveTask{q, (int32_t)r, (int32_t)std::min<int64_t>(r + kSolveRows, m), 0});
+        }
+        S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
+    }
+    return SPC_OK;
+}
+
+}  // namespace spc

@@ -1,0 +1,283 @@
+"""Python binding of libspchol.so (the C ABI in include/spchol.h).
+
+Argument marshalling only: every numeric step runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device and the
+stream is torch's current stream unless one is given.  Importing this module
+loads the library and fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspchol.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_09288_amd/build.py "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, INVALID_INPUT, NOT_SPD, OUT_OF_MEMORY, NO_CONVERGENCE, DEVICE_ERROR, BAD_HANDLE, NO_DEVICE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32 = 0, 1
+_PREC = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
+
+EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_factorize",
+           "spc_refactorize", "spc_factorize_batch", "spc_solve", "spc_solve_refined", "spc_sync",
+           "spc_factor_export", "spc_factor_last_ms", "spc_factor_set_profiling",
+           "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string")
+KERNEL_CLASSES = {"assemble": 0, "panel": 1, "trailing": 2, "scatter": 3}
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("amalg_z", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "n", "nnz_a", "nsuper", "nnz_l", "panel_entries", "flops", "levels", "rows_total",
+        "max_width", "max_rows", "factor_bytes_fp64", "factor_bytes_fp32")]
+
+
+class _KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+class _RefineInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("berr", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_lib.spc_analyze.argtypes = [_i64, _P, _P, _P, ctypes.POINTER(_Options), ctypes.POINTER(_P)]
+_lib.spc_symbolic_info.argtypes = [_P, ctypes.POINTER(_Info)]
+_lib.spc_symbolic_export.argtypes = [_P, ctypes.c_int, _P]
+_lib.spc_factorize.argtypes = [_P, _P, ctypes.c_int, _P, ctypes.POINTER(_P)]
+_lib.spc_refactorize.argtypes = [_P, _P, _P]
+_lib.spc_factorize_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int,
+                                     _P, ctypes.POINTER(_P)]
+_lib.spc_solve.argtypes = [_P, _P, ctypes.c_int, _i64, _P]
+_lib.spc_solve_refined.argtypes = [_P, _P, _P, _P, ctypes.c_int, _i64, ctypes.c_double, ctypes.c_int, _P,
+                                   ctypes.POINTER(_RefineInfo)]
+_lib.spc_sync.argtypes = [_P, ctypes.POINTER(_i64)]
+_lib.spc_factor_export.argtypes = [_P, _P]
+_lib.spc_factor_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.spc_factor_set_profiling.argtypes = [_P, ctypes.c_int]
+_lib.spc_factor_kernel_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
+_lib.spc_free_symbolic.argtypes = [_P]
+_lib.spc_free_symbolic.restype = None
+_lib.spc_free_factor.argtypes = [_P]
+_lib.spc_free_factor.restype = None
+_lib.spc_status_string.argtypes = [ctypes.c_int]
+_lib.spc_status_string.restype = ctypes.c_char_p
+for _name in EXPORTS:
+    if _name not in ("spc_free_symbolic", "spc_free_factor", "spc_status_string"):
+        getattr(_lib, _name).restype = ctypes.c_int
+
+
+class SpcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        msg = _lib.spc_status_string(status).decode()
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+        self.status = status
+
+
+class NotSPD(SpcError):
+    def __init__(self, column: int):
+        super().__init__(NOT_SPD, f"pivot failed at permuted column {column}")
+        self.column = column
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise SpcError(rc, what)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a device (cuda/hip) torch tensor")
+    if str(t.dtype) != dtype_name:
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise TypeError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_EXPORT_ARRAYS = {"perm": (0, np.int32, "n"), "parent": (1, np.int32, "n"),
+                  "colcount": (2, np.int32, "n"), "super_ptr": (3, np.int32, "ns1"),
+                  "sparent": (4, np.int32, "ns"), "rptr": (5, np.int64, "ns1"),
+                  "rows": (6, np.int32, "rows_total"), "lptr": (7, np.int64, "ns1"),
+                  "level": (8, np.int32, "ns")}
+
+
+class Symbolic:
+    """spc_analyze: host-only symbolic analysis of a lower-CSC pattern."""
+
+    def __init__(self, colptr, rowidx, perm=None, amalg_z: float = 0.05):
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
+        self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        n = self._colptr.size - 1
+        opts = _Options(amalg_z=float(amalg_z))
+        h = _P()
+        rc = _lib.spc_analyze(n, _np_ptr(self._colptr), _np_ptr(self._rowidx),
+                              _np_ptr(self._perm) if self._perm is not None else None,
+                              ctypes.byref(opts), ctypes.byref(h))
+        _check(rc, "spc_analyze")
+        self._h = h
+        info = _Info()
+        _check(_lib.spc_symbolic_info(self._h, ctypes.byref(info)), "spc_symbolic_info")
+        self.info = {k: int(getattr(info, k)) for k, _ in _Info._fields_}
+        self._cache = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return self.info["n"]
+
+    def export(self, name: str) -> np.ndarray:
+        if name not in self._cache:
+            which, dt, sz = _EXPORT_ARRAYS[name]
+            i = self.info
+            count = {"n": i["n"], "ns": i["nsuper"], "ns1": i["nsuper"] + 1,
+                     "rows_total": i["rows_total"]}[sz]
+            a = np.zeros(max(count, 1), dtype=dt)
+            _check(_lib.spc_symbolic_export(self._h, which, _np_ptr(a)), "spc_symbolic_export")
+            self._cache[name] = a[:count]
+        return self._cache[name]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.spc_free_symbolic(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Factor:
+    """A device-resident factor (spc_factorize)."""
+
+    def __init__(self, sym: Symbolic, handle, precision: int):
+        self.sym = sym
+        self._h = handle
+        self.precision = precision
+
+    @property
+    def handle(self):
+        return self._h
+
+    def refactorize(self, d_values, stream=None):
+        _check(_lib.spc_refactorize(self._h, _dev_ptr(d_values, "torch.float64"), _stream_ptr(stream)),
+               "spc_refactorize")
+
+    def sync(self):
+        bad = _i64(-1)
+        rc = _lib.spc_sync(self._h, ctypes.byref(bad))
+        if rc == NOT_SPD:
+            raise NotSPD(int(bad.value))
+        _check(rc, "spc_sync")
+
+    def export(self) -> np.ndarray:
+        out = np.zeros(max(self.sym.info["panel_entries"], 1), dtype=np.float64)
+        _check(_lib.spc_factor_export(self._h, _np_ptr(out)), "spc_factor_export")
+        return out[: self.sym.info["panel_entries"]]
+
+    def last_ms(self) -> float:
+        v = ctypes.c_float(0)
+        _check(_lib.spc_factor_last_ms(self._h, ctypes.byref(v)), "spc_factor_last_ms")
+        return float(v.value)
+
+    def set_profiling(self, on: bool = True):
+        _check(_lib.spc_factor_set_profiling(self._h, 1 if on else 0), "spc_factor_set_profiling")
+
+    def kernel_stats(self) -> dict:
+        """Per kernel class: launches, total device ms and algorithmic flops of
+        the last profiled factorization."""
+        out = {}
+        for name, cls in KERNEL_CLASSES.items():
+            st = _KernelStats()
+            _check(_lib.spc_factor_kernel_stats(self._h, cls, ctypes.byref(st)), "spc_factor_kernel_stats")
+            out[name] = {"launches": int(st.launches), "ms": float(st.total_ms), "flops": float(st.flops)}
+        return out
+
+    def solve(self, B, stream=None):
+        """In-place solve. B: float64 device tensor of shape (n,) or (nrhs, n)
+        (each row one right-hand side, i.e. column-major n x nrhs)."""
+        n = self.sym.n
+        nrhs = 1 if B.dim() == 1 else B.shape[0]
+        if B.shape[-1] != n:
+            raise ValueError("B must have n entries per right-hand side")
+        _check(_lib.spc_solve(self._h, _dev_ptr(B, "torch.float64"), nrhs, n, _stream_ptr(stream)),
+               "spc_solve")
+        return B
+
+    def solve_refined(self, d_values, B, X, tol: float = 1e-12, maxit: int = 10, stream=None):
+        n = self.sym.n
+        nrhs = 1 if B.dim() == 1 else B.shape[0]
+        info = _RefineInfo()
+        rc = _lib.spc_solve_refined(self._h, _dev_ptr(d_values, "torch.float64"),
+                                    _dev_ptr(B, "torch.float64"), _dev_ptr(X, "torch.float64"),
+                                    nrhs, n, float(tol), int(maxit), _stream_ptr(stream),
+                                    ctypes.byref(info))
+        res = {"iterations": int(info.iterations), "converged": bool(info.converged),
+               "berr": float(info.berr)}
+        if rc not in (OK, NO_CONVERGENCE):
+            _check(rc, "spc_solve_refined")
+        res["status"] = rc
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.spc_free_factor(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def analyze(colptr, rowidx, perm=None, amalg_z: float = 0.05) -> Symbolic:
+    return Symbolic(colptr, rowidx, perm, amalg_z)
+
+
+def factorize(sym: Symbolic, d_values, precision="fp64", stream=None) -> Factor:
+    prec = _PREC[precision]
+    h = _P()
+    _check(_lib.spc_factorize(sym.handle, _dev_ptr(d_values, "torch.float64"), prec,
+                              _stream_ptr(stream), ctypes.byref(h)), "spc_factorize")
+    return Factor(sym, h, prec)
+
+
+def factorize_batch(syms, d_values_list, precision="fp64", stream=None):
+    prec = _PREC[precision]
+    count = len(syms)
+    hs = (_P * count)(*[s.handle for s in syms])
+    vs = (_P * count)(*[_dev_ptr(v, "torch.float64") for v in d_values_list])
+    outs = (_P * count)()
+    _check(_lib.spc_factorize_batch(count, hs, vs, prec, _stream_ptr(stream), outs),
+           "spc_factorize_batch")
+    return [Factor(s, _P(outs[i]), prec) for i, s in enumerate(syms)]
+
+
+def solve(F: Factor, B, stream=None):
+    return F.solve(B, stream)

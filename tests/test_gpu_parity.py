@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path through the C ABI vs the CPU oracle.
+
+Bars (written here, from the paper's method being exact up to rounding):
+  FP64 factor:  ||L - L_ref||_F / ||L_ref||_F <= 1e-10 over the lower parts
+  FP64 solve:   max-over-RHS normwise backward error <= 1e-12 (host FP64)
+  structure:    bit-exact (covered on the host by test_symbolic_parity)
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_09288_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_F_FP64 = 1e-10
+BERR_FP64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_dev):
+    from paper_2202_09288_amd import spchol  # fails loudly if the library is missing
+    return spchol
+
+
+def run_case(torch, lib, colptr, rowidx, values, perm, B, z=0.05, precision="fp64"):
+    print(f"case n={colptr.size - 1} nnz={colptr[-1]} nrhs={B.shape[1]} z={z} {precision}", flush=True)
+    S = oracle.Symbolic(colptr, rowidx, perm, z)
+    Lref = S.factor(values)
+    sym = lib.Symbolic(colptr, rowidx, perm, z)
+    dv = torch.from_numpy(values).cuda()
+    F = lib.factorize(sym, dv, precision)
+    F.sync()
+    Lg = F.export()
+    mask = S.lower_mask()
+    relF = oracle.rel_frobenius(Lg, Lref, mask)
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
+    F.solve(Bt)
+    X = Bt.cpu().numpy().T
+    eta = oracle.backward_error(S.n, colptr, rowidx, values, X, B)
+    return relF, eta, F, S
+
+
+def grid(dims, seed=0, nrhs=1, shift=1e-2):
+    return W.laplacian(dims, "5pt" if len(dims) == 2 else "7pt", 88, seed, unit=False, shift=shift,
+                       nrhs=nrhs)
+
+
+CASES = [
+    ("2d-8x8", lambda: grid((8, 8))),
+    ("2d-37x23-ragged", lambda: grid((37, 23), nrhs=3)),
+    ("3d-9x7x11", lambda: grid((9, 7, 11), nrhs=2)),
+    ("3d-16", lambda: grid((16, 16, 16))),
+    ("3d-20-17rhs", lambda: grid((20, 20, 20), nrhs=17)),
+    ("2d-64-unit", lambda: W.grid2d_unit()),
+    ("elast-5x4x6", lambda: W.elasticity27((5, 4, 6), 88, 0, kappa=1e6, nrhs=4, power_iters=20)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fp64_parity(torch_dev, lib, name, make):
+    s = make()
+    relF, eta, _, _ = run_case(torch_dev, lib, s.colptr, s.rowidx, s.values, s.perm, s.B)
+    print(f"{name}: relF={relF:.3e} eta={eta:.3e}")
+    assert relF <= REL_F_FP64
+    assert eta <= BERR_FP64
+
+
+@pytest.mark.parametrize("z", [-1.0, 0.0, 0.5])
+def test_fp64_amalgamation_settings(torch_dev, lib, z):
+    s = grid((14, 13, 12), seed=3, nrhs=2)
+    relF, eta, _, _ = run_case(torch_dev, lib, s.colptr, s.rowidx, s.values, s.perm, s.B, z=z)
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+
+
+def test_dense_wide_supernode(torch_dev, lib):
+    """One supernode wider than several panel blocks, with a ragged edge."""
+    n = 203
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    r, c = np.tril_indices(n)
+    colptr, rowidx, values = W.lower_csc(n, r, c, A[r, c])
+    B = rng.standard_normal((n, 2))
+    relF, eta, _, S = run_case(torch_dev, lib, colptr, rowidx, values, np.arange(n, dtype=np.int32), B)
+    assert S.nsuper == 1
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+
+
+def test_arrow_and_diagonal(torch_dev, lib):
+    n = 300  # star etree: many leaves updating one root
+    r = np.concatenate([np.arange(n), np.full(n - 1, n - 1)])
+    c = np.concatenate([np.arange(n), np.arange(n - 1)])
+    v = np.concatenate([np.full(n, float(n)), -np.linspace(0.1, 1.0, n - 1)])
+    colptr, rowidx, values = W.lower_csc(n, r, c, v)
+    B = np.linspace(-1, 1, n)[:, None]
+    relF, eta, _, _ = run_case(torch_dev, lib, colptr, rowidx, values, np.arange(n, dtype=np.int32), B)
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+    colptr, rowidx, values = W.lower_csc(5, np.arange(5), np.arange(5), np.arange(1.0, 6.0))
+    relF, eta, _, _ = run_case(torch_dev, lib, colptr, rowidx, values, np.arange(5, dtype=np.int32),
+                               np.ones((5, 1)))
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+
+
+def test_single_unknown(torch_dev, lib):
+    colptr, rowidx, values = W.lower_csc(1, [0], [0], [4.0])
+    relF, eta, _, _ = run_case(torch_dev, lib, colptr, rowidx, values, np.zeros(1, np.int32),
+                               np.array([[2.0]]))
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+
+
+def test_not_spd_pivot(torch_dev, lib):
+    s = grid((11, 9, 7), seed=2)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    iperm = np.argsort(S.perm)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    for r in (3, s.n // 2, s.n - 1):
+        v = s.values.copy()
+        v[s.colptr[r]] = -v[s.colptr[r]]
+        with pytest.raises(oracle.NotSPD) as eo:
+            S.factor(v)
+        F = lib.factorize(sym, torch_dev.from_numpy(v).cuda())
+        with pytest.raises(lib.NotSPD) as eg:
+            F.sync()
+        assert eg.value.column == eo.value.column == iperm[r]
+    v = s.values.copy()
+    v[s.colptr[7]] = np.nan
+    F = lib.factorize(sym, torch_dev.from_numpy(v).cuda())
+    with pytest.raises(lib.NotSPD) as eg:
+        F.sync()
+    assert eg.value.column == iperm[7]
+
+
+def test_refactorize_and_repeat(torch_dev, lib):
+    s = grid((15, 15, 15), seed=4, nrhs=1)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch_dev.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv)
+    F.sync()
+    L1 = F.export()
+    F.refactorize(dv * 4.0)
+    F.sync()
+    L2 = F.export()
+    assert np.max(np.abs(L2 - 2.0 * L1)) <= 1e-12 * np.max(np.abs(L1))
+    F.refactorize(dv)
+    F.sync()
+    L3 = F.export()
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    assert oracle.rel_frobenius(L3, L1, S.lower_mask()) <= 1e-14
+
+
+def test_zero_rhs_and_empty(torch_dev, lib):
+    s = grid((6, 6))
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm)
+    F = lib.factorize(sym, torch_dev.from_numpy(s.values).cuda())
+    F.sync()
+    B = torch_dev.zeros((0, s.n), dtype=torch_dev.float64, device="cuda")
+    F.solve(B)
+    colptr = np.zeros(1, np.int64)
+    sym0 = lib.Symbolic(colptr, np.zeros(0, np.int32), None)
+    F0 = lib.factorize(sym0, torch_dev.zeros(1, dtype=torch_dev.float64, device="cuda"))
+    F0.sync()
+
+
+def test_batch_members_fp64(torch_dev, lib):
+    specs = W.batch_specs(512, 0)
+    picks = [i for i, (k, side) in enumerate(specs) if side <= (70 if k == "2d" else 16)][:4]
+    for i in picks:
+        s = W.batch_system(i, *specs[i], nrhs=3)
+        relF, eta, _, _ = run_case(torch_dev, lib, s.colptr, s.rowidx, s.values, s.perm, s.B)
+        assert relF <= REL_F_FP64 and eta <= BERR_FP64
+
+
+def test_grid3d_60_full_size(torch_dev, lib):
+    """The 60^3 7-point workload at full size, in the benchmark's launch
+    configuration.  The oracle checks (a) a sampled subtree whose panels it
+    computes exactly, (b) the backward error of the solve, (c) the factor
+    residual A - L L^T on sampled columns, all in FP64 on the host."""
+    torch = torch_dev
+    s = W.grid3d_cond()
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv)
+    F.sync()
+    Lg = F.export()
+    # (a) subtree of a supernode at level 8 (a few seconds in the oracle)
+    lev = S.level
+    root = int(np.nonzero(lev == 8)[0][0])
+    Ls, first = S.factor_subtree(s.values, root)
+    sl = slice(int(S.lptr[first]), int(S.lptr[root + 1]))
+    mask = S.lower_mask()[sl]
+    assert oracle.rel_frobenius(Lg[sl], Ls[sl], mask) <= REL_F_FP64
+    # (b) solve
+    Bt = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    F.solve(Bt)
+    X = Bt.cpu().numpy().T
+    eta = oracle.backward_error(S.n, s.colptr, s.rowidx, s.values, X, s.B)
+    print(f"60^3: eta={eta:.3e}")
+    assert eta <= BERR_FP64
+    # (c) sampled columns of Ahat - L L^T, relative to ||Ahat||
+    A = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values)
+    P = S.perm
+    Ah = A[P][:, P].tocsc()
+    rng = np.random.default_rng(0)
+    cols = np.concatenate([rng.choice(S.n, 40, replace=False), np.arange(S.n - 10, S.n)])
+    sp, rp, rows, lp = S.super_ptr, S.rptr, S.rows, S.lptr
+    snode = np.repeat(np.arange(S.nsuper), np.diff(sp))
+
+    # L column j as sparse vector
+    def lcol(j):
+        t = snode[j]
+        m = rp[t + 1] - rp[t]
+        c = j - sp[t]
+        vals = Lg[lp[t] + c * m: lp[t] + (c + 1) * m][c:]
+        return rows[rp[t]:rp[t + 1]][c:], vals
+
+    import scipy.sparse as ssp
+    import scipy.sparse.linalg  # noqa: F401  (norm)
+    # assemble L (CSC) from panels, then check columns of L L^T
+    indptr = [0]; ind = []; dat = []
+    for j in range(S.n):
+        r_, v_ = lcol(j)
+        ind.append(r_); dat.append(v_); indptr.append(indptr[-1] + r_.size)
+    Lm = ssp.csc_matrix((np.concatenate(dat), np.concatenate(ind), np.array(indptr)), shape=(S.n, S.n))
+    E = (Lm @ Lm[cols, :].T) - Ah[:, cols]
+    res = ssp.linalg.norm(E) / ssp.linalg.norm(Ah[:, cols])
+    print(f"60^3: sampled ||A - LL^T||/||A|| = {res:.3e}")
+    assert res <= 1e-12
