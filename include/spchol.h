@@ -210,6 +210,10 @@ void spc_free_symbolic(spc_symbolic sym);
 void spc_free_factor(spc_factor f);
 const char *spc_status_string(int status);
 
+/* Text of the last HIP failure seen by this host thread (error string, the
+ * failing call and its place), or "" if none.  Owned by the library. */
+const char *spc_last_error_message(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,8 +45,9 @@ struct spc_factor_s {
     int precision = SPC_FP64;
     int device = -1;
     void *Lx = nullptr;
+    void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
-    void *work = nullptr;       // solve work vectors (factor precision)
+    void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
     size_t refine_bytes = 0;
@@ -62,12 +63,17 @@ struct spc_factor_s {
 
 namespace {
 
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) {                        \
-            return e_ == hipErrorOutOfMemory ? SPC_OUT_OF_MEMORY : SPC_DEVICE_ERROR; \
-        }                                              \
+thread_local char g_last_error[256] = "";
+
+int record_error(hipError_t e, const char *what, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%s) at capi.cpp:%d", hipGetErrorString(e), what, line);
+    return e == hipErrorOutOfMemory ? SPC_OUT_OF_MEMORY : SPC_DEVICE_ERROR;
+}
+
+#define HIP_TRY(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return record_error(e_, #expr, __LINE__); \
     } while (0)
 
 bool sym_ok(spc_symbolic s) { return s && s->magic == kSymMagic; }
@@ -124,10 +130,13 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.amap.data(), bytes_of(S.amap), (const void **)&P.amap},
         {S.perm.data(), bytes_of(S.perm), (const void **)&P.perm},
         {S.potrf_tasks.data(), bytes_of(S.potrf_tasks), (const void **)&P.potrf_tasks},
-        {S.panel_tasks.data(), bytes_of(S.panel_tasks), (const void **)&P.panel_tasks},
+        {S.trsm_tiles.data(), bytes_of(S.trsm_tiles), (const void **)&P.trsm_tiles},
         {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
+        {S.int_tiles_big.data(), bytes_of(S.int_tiles_big), (const void **)&P.int_tiles_big},
+        {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
         {S.sblocks.data(), bytes_of(S.sblocks), (const void **)&P.sblocks},
+        {S.inv_off.data(), bytes_of(S.inv_off), (const void **)&P.inv_off},
         {S.sblock_order.data(), bytes_of(S.sblock_order), (const void **)&P.sblock_order},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
     };
@@ -145,7 +154,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
     hipError_t e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
-        return SPC_DEVICE_ERROR;
+        return record_error(e, "plan upload", __LINE__);
     }
     sym->dev.base = base;
     sym->dev.bytes = total;
@@ -156,8 +165,8 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.super_ptr) + bytes_of(S.rptr) + bytes_of(S.lptr) + bytes_of(S.rows) +
            bytes_of(S.colpair) + bytes_of(S.pairs) + bytes_of(S.rel) + bytes_of(S.amap) +
-           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.panel_tasks) + bytes_of(S.int_tiles) +
-           bytes_of(S.ext_tiles) + bytes_of(S.sblocks) + bytes_of(S.sblock_order) +
+           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.trsm_tiles) + bytes_of(S.int_tiles) +
+           bytes_of(S.ext_tiles) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) + bytes_of(S.sblocks) + bytes_of(S.inv_off) + bytes_of(S.sblock_order) +
            bytes_of(S.stasks);
 }
 
@@ -194,7 +203,7 @@ struct Prof {
 };
 
 template <typename T>
-void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx,
+void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
                     unsigned long long *status, hipStream_t st, Prof &prof) {
     prof.run(SPC_K_ASSEMBLE, 0.0, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
@@ -204,45 +213,50 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
             prof.run(SPC_K_PANEL, stp.panel_flops, [&] {
-                spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, status, st);
-                spc::launch_trsm<T>(P, stp.p0, stp.p1, Lx, st);
+                spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st);
+                spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, st);
             });
-            if (stp.t1 > stp.t0)
-                prof.run(SPC_K_TRAILING, stp.trailing_flops,
-                         [&] { spc::launch_tiles<T>(P, false, stp.t0, stp.t1, Lx, st); });
+            if (stp.t1 > stp.t0 || stp.u1 > stp.u0)
+                prof.run(SPC_K_TRAILING, stp.trailing_flops, [&] {
+                    spc::launch_tiles128<T>(P, spc::kTilesTrailing, stp.u0, stp.u1, Lx, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, st);
+                });
         }
-        if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
+        if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l] || S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], [&] {
-                spc::launch_tiles<T>(P, true, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, st);
+                spc::launch_tiles128<T>(P, spc::kTilesScatter, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, st);
+                spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
+                                     st);
             });
     }
 }
 
+// Y holds the permuted right-hand sides on entry; X receives the solution.
 template <typename T>
-void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, T *W, int nrhs,
-                   hipStream_t st) {
+void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, const T *Linv, T *Y, T *X,
+                   T *Acc, int32_t *counters, int nrhs, hipStream_t st) {
     const int64_t n = S.n;
-    for (int32_t l = 0; l < S.nslevels; ++l) {
-        spc::launch_solve_diag<T>(P, true, S.slevel_ptr[l], S.slevel_ptr[l + 1], Lx, W, n, nrhs, st);
-        spc::launch_solve_update<T>(P, true, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, W, n, nrhs, st);
-    }
-    for (int32_t l = S.nslevels - 1; l >= 0; --l) {
-        spc::launch_solve_update<T>(P, false, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, W, n, nrhs, st);
-        spc::launch_solve_diag<T>(P, false, S.slevel_ptr[l], S.slevel_ptr[l + 1], Lx, W, n, nrhs, st);
-    }
+    spc::launch_zero<T>(Acc, n * nrhs, st);
+    spc::launch_zero<int32_t>(counters, (int64_t)S.sblocks.size(), st);
+    for (int32_t l = 0; l < S.nslevels; ++l)
+        spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, st);
+    for (int32_t l = S.nslevels - 1; l >= 0; --l)
+        spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, counters, n, nrhs,
+                                 st);
 }
 
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
+    (void)hipGetLastError();  // judge only the launches below
     spc::launch_status_reset(f->status, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
     Prof prof{f, st};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, f->status, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, f->status, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -265,12 +279,14 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out) {
     size_t esz = precision == SPC_FP64 ? sizeof(double) : sizeof(float);
     size_t bytes = std::max<size_t>(1, (size_t)sym->S.panel_entries()) * esz;
     hipError_t e = hipMalloc(&f->Lx, bytes);
+    size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
+    if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
     if (e != hipSuccess) {
         spc_free_factor(f);
-        return e == hipErrorOutOfMemory ? SPC_OUT_OF_MEMORY : SPC_DEVICE_ERROR;
+        return record_error(e, "factor allocation", __LINE__);
     }
     *out = f;
     return SPC_OK;
@@ -327,8 +343,9 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     out->rows_total = S.rows_total();
     out->max_width = S.max_w;
     out->max_rows = S.max_m;
-    out->factor_bytes_fp64 = (int64_t)(S.panel_entries() * 8 + plan_bytes(S));
-    out->factor_bytes_fp32 = (int64_t)(S.panel_entries() * 4 + plan_bytes(S));
+    const int64_t entries = S.panel_entries() + (S.inv_off.empty() ? 0 : S.inv_off.back());
+    out->factor_bytes_fp64 = (int64_t)(entries * 8 + plan_bytes(S));
+    out->factor_bytes_fp32 = (int64_t)(entries * 4 + plan_bytes(S));
     return SPC_OK;
 }
 
@@ -403,22 +420,27 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const spc::DevPlan &P = f->sym->dev.plan;
     size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    (void)hipGetLastError();  // judge only the launches below
     constexpr int kChunk = 16;
-    int rc = ensure_bytes(&f->work, &f->work_bytes, (size_t)S.n * kChunk * esz);
+    const size_t vec = (size_t)S.n * kChunk * esz;
+    const size_t cnt_off = (3 * vec + 255) & ~size_t(255);
+    int rc = ensure_bytes(&f->work, &f->work_bytes, cnt_off + sizeof(int32_t) * (S.sblocks.size() + 1));
     if (rc) return rc;
+    char *base = (char *)f->work;
+    int32_t *counters = (int32_t *)(base + cnt_off);
     for (int q0 = 0; q0 < nrhs; q0 += kChunk) {
         int q = std::min(kChunk, nrhs - q0);
         double *B = d_B + (int64_t)q0 * ldb;
         if (f->precision == SPC_FP64) {
-            double *W = (double *)f->work;
-            spc::launch_perm_in<double>(P, S.n, q, B, ldb, W, st);
-            enqueue_solve<double>(S, P, (const double *)f->Lx, W, q, st);
-            spc::launch_perm_out<double>(P, S.n, q, W, B, ldb, st);
+            double *Y = (double *)base, *X = (double *)(base + vec), *Acc = (double *)(base + 2 * vec);
+            spc::launch_perm_in<double>(P, S.n, q, B, ldb, Y, st);
+            enqueue_solve<double>(S, P, (const double *)f->Lx, (const double *)f->Linv, Y, X, Acc, counters, q, st);
+            spc::launch_perm_out<double>(P, S.n, q, X, B, ldb, st);
         } else {
-            float *W = (float *)f->work;
-            spc::launch_perm_in<float>(P, S.n, q, B, ldb, W, st);
-            enqueue_solve<float>(S, P, (const float *)f->Lx, W, q, st);
-            spc::launch_perm_out<float>(P, S.n, q, W, B, ldb, st);
+            float *Y = (float *)base, *X = (float *)(base + vec), *Acc = (float *)(base + 2 * vec);
+            spc::launch_perm_in<float>(P, S.n, q, B, ldb, Y, st);
+            enqueue_solve<float>(S, P, (const float *)f->Lx, (const float *)f->Linv, Y, X, Acc, counters, q, st);
+            spc::launch_perm_out<float>(P, S.n, q, X, B, ldb, st);
         }
     }
     HIP_TRY(hipGetLastError());
@@ -508,6 +530,7 @@ void spc_free_factor(spc_factor f) {
     if (!f || f->magic != kFacMagic) return;
     if (f->stream || f->Lx) (void)hipStreamSynchronize(f->stream);
     if (f->Lx) (void)hipFree(f->Lx);
+    if (f->Linv) (void)hipFree(f->Linv);
     if (f->status) (void)hipFree(f->status);
     if (f->work) (void)hipFree(f->work);
     if (f->refine) (void)hipFree(f->refine);
@@ -519,6 +542,8 @@ void spc_free_factor(spc_factor f) {
     delete f;
     if (s) sym_release(s);
 }
+
+const char *spc_last_error_message(void) { return g_last_error; }
 
 const char *spc_status_string(int status) {
     switch (status) {

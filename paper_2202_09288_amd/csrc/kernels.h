@@ -19,13 +19,18 @@ struct DevPlan {
     const int64_t *amap;
     const int32_t *perm;
     const PanelTask *potrf_tasks;
-    const PanelTask *panel_tasks;
+    const TileTask *trsm_tiles;
     const TileTask *int_tiles;
     const TileTask *ext_tiles;
+    const TileTask *int_tiles_big;
+    const TileTask *ext_tiles_big;
     const SolveBlock *sblocks;
+    const int64_t *inv_off;
     const int32_t *sblock_order;
     const SolveTask *stasks;
 };
+
+enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
 // status word: lowest permuted column whose pivot failed, or ~0ull
 void launch_status_reset(unsigned long long *status, hipStream_t st);
@@ -34,12 +39,13 @@ void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
 void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx, hipStream_t st);
 template <typename T>
-void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, unsigned long long *status,
+void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);
 template <typename T>
-void launch_trsm(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st);
+
 template <typename T>
-void launch_tiles(const DevPlan &P, bool external, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+void launch_tiles128(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
 
 template <typename T>
 void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,
@@ -48,10 +54,10 @@ template <typename T>
 void launch_perm_out(const DevPlan &P, int64_t n, int nrhs, const T *W, double *B, int64_t ldb,
                      hipStream_t st);
 template <typename T>
-void launch_solve_diag(const DevPlan &P, bool forward, int64_t e0, int64_t e1, const T *Lx, T *W,
-                       int64_t n, int nrhs, hipStream_t st);
+void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
+                      int64_t n, int nrhs, hipStream_t st);
 template <typename T>
-void launch_solve_update(const DevPlan &P, bool forward, int64_t t0, int64_t t1, const T *Lx,
-                         T *W, int64_t n, int nrhs, hipStream_t st);
+void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
+                      int32_t *counters, int64_t n, int nrhs, hipStream_t st);
 
 }  // namespace spc

@@ -8,13 +8,19 @@
 
 namespace spc {
 
-// Tile edge of the update kernels and block width of the panel kernels.
+// Tile edges of the update kernels; scatter updates of dimension >=
+// kBigMin with a contraction of at least kBigMinK use the large tiles.
 constexpr int kTile = 64;
-constexpr int kPanelNB = 64;
-// Rows of the panel triangular solve handled by one workgroup.
-constexpr int kPanelRows = 32;
-// Block width of the triangular solves and rows per update task there.
-constexpr int kSolveNB = 64;
+constexpr int kTileBig = 128;
+constexpr int kBigMin = 256;
+constexpr int kBigMinK = 128;
+// Width of the column blocks a supernode is cut into, for the panel
+// factorization and for the triangular solves alike; each block's diagonal
+// triangle gets an explicit inverse in the inverse store.
+constexpr int kNB = 64;
+constexpr int kPanelNB = kNB;
+constexpr int kSolveNB = kNB;
+// Rows of one solve-update task.
 constexpr int kSolveRows = 256;
 
 // One pair (source supernode s, ancestor t) of the scatter: rows
@@ -30,7 +36,8 @@ struct UpdatePair {
 
 // One output tile of a SYRK/GEMM update of supernode s: rows i0..i0+63 and
 // columns j0..j0+63 (positions in R_s) of P P^T with P the columns
-// k0..k1-1 of the panel.
+// k0..k1-1 of the panel.  A TRSM tile is rows i0..i0+63 of block `blk`
+// (columns k0..k1-1) multiplied by the transposed block inverse.
 struct TileTask {
     int32_t s;
     int32_t i0;
@@ -38,25 +45,27 @@ struct TileTask {
     int32_t k0;
     int32_t k1;
     int32_t jmax;   // columns j >= jmax are outside the update
-    int32_t pad[2];
+    int32_t blk;    // TRSM tiles: block id
+    int32_t pad;
 };
 
-// Panel work on block b (columns b*kPanelNB ..) of supernode s.  A POTRF
-// task factors the diagonal block; a TRSM task solves rows r0..r1-1
-// (positions below the block) against the factored block.
+// POTRF of block b (columns c0..c1-1, c0 = b*kNB) of supernode s: factor
+// the diagonal triangle and write its inverse at inv_off[blk].
 struct PanelTask {
     int32_t s;
-    int32_t b;   // block index: columns b*kPanelNB ..
-    int32_t r0;
-    int32_t r1;
+    int32_t b;
+    int32_t c0;
+    int32_t c1;
+    int32_t blk;  // global block id (index into the block list)
+    int32_t pad;
 };
 
-// One block of columns of a supernode in the triangular solves.
+// One column block of a supernode (solves and inverse store).
 struct SolveBlock {
     int32_t s;
-    int32_t c0;  // first column (position in the panel)
-    int32_t c1;  // one past the last column
-    int32_t pad;
+    int32_t c0;      // first column (position in the panel)
+    int32_t c1;      // one past the last column
+    int32_t ntasks;  // solve-update tasks of this block (>= 1)
 };
 
 struct SolveTask {
@@ -87,21 +96,27 @@ struct Symbolic {
     // panel-task range followed by a tile-task range
     struct Step {
         int64_t f0, f1;   // POTRF tasks
-        int64_t p0, p1;   // TRSM tasks
-        int64_t t0, t1;   // internal trailing-update tiles
+        int64_t p0, p1;   // TRSM tiles
+        int64_t t0, t1;   // internal trailing-update tiles (64)
+        int64_t u0, u1;   // internal trailing-update tiles (128)
         double panel_flops, trailing_flops;  // algorithmic flops of the two launches
     };
     std::vector<int64_t> level_step_ptr;   // [nlevels+1]
     std::vector<Step> steps;
-    std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles
+    std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles (64)
+    std::vector<int64_t> ext_big_ptr;      // [nlevels+1] external tiles (128)
     std::vector<double> ext_flops;         // [nlevels] algorithmic flops per launch
     std::vector<PanelTask> potrf_tasks;
-    std::vector<PanelTask> panel_tasks;
+    std::vector<TileTask> trsm_tiles;
     std::vector<TileTask> int_tiles;
     std::vector<TileTask> ext_tiles;
+    std::vector<TileTask> int_tiles_big;
+    std::vector<TileTask> ext_tiles_big;
 
-    // solve schedule: blocks grouped by block-tree level
+    // column blocks, their inverse-store offsets, and the solve schedule
+    // (blocks grouped by block-tree level)
     std::vector<SolveBlock> sblocks;
+    std::vector<int64_t> inv_off;          // [nblocks+1]
     std::vector<int64_t> slevel_ptr;       // [nslevels+1] into sblock_order
     std::vector<int32_t> sblock_order;
     std::vector<int64_t> stask_ptr;        // [nslevels+1] into stasks

@@ -302,29 +302,51 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
         S.pair_ptr[s + 1] = (int64_t)S.pairs.size();
     }
 
+    // ---- column blocks and the inverse store ------------------------------
+    std::vector<int32_t> first_blk(ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
+        first_blk[s] = (int32_t)S.sblocks.size();
+        for (int64_t c0 = 0; c0 < w; c0 += kNB)
+            S.sblocks.push_back(SolveBlock{s, (int32_t)c0, (int32_t)std::min<int64_t>(c0 + kNB, w), 0});
+    }
+    first_blk[ns] = (int32_t)S.sblocks.size();
+    const int64_t nb = (int64_t)S.sblocks.size();
+    S.inv_off.assign(nb + 1, 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        int64_t d = S.sblocks[q].c1 - S.sblocks[q].c0;
+        S.inv_off[q + 1] = S.inv_off[q] + d * d;
+    }
+
     // ---- factor schedule ----------------------------------------------------
+    // level l: for each block index b, POTRF of block b of every supernode
+    // of the level that has it, TRSM tiles of the rows below, trailing SYRK
+    // tiles inside the supernode; then the scatter tiles of the level.
     std::vector<std::vector<int32_t>> bylevel(S.nlevels);
     for (int32_t s = 0; s < ns; ++s) bylevel[S.level[s]].push_back(s);
     S.level_step_ptr.assign(S.nlevels + 1, 0);
     S.ext_tile_ptr.assign(S.nlevels + 1, 0);
+    S.ext_big_ptr.assign(S.nlevels + 1, 0);
     for (int32_t l = 0; l < S.nlevels; ++l) {
         int64_t maxb = 0;
         for (int32_t s : bylevel[l]) {
             int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
-            maxb = std::max(maxb, (w + kPanelNB - 1) / kPanelNB);
+            maxb = std::max(maxb, (w + kNB - 1) / kNB);
         }
         for (int64_t b = 0; b < maxb; ++b) {
             Symbolic::Step st;
             st.panel_flops = 0.0;
             st.trailing_flops = 0.0;
             st.f0 = (int64_t)S.potrf_tasks.size();
-            st.p0 = (int64_t)S.panel_tasks.size();
+            st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
+            st.u0 = (int64_t)S.int_tiles_big.size();
             for (int32_t s : bylevel[l]) {
                 int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
-                int64_t c0 = b * kPanelNB;
+                int64_t c0 = b * kNB;
                 if (c0 >= w) continue;
-                int64_t c1 = std::min<int64_t>(c0 + kPanelNB, w);
+                int64_t c1 = std::min<int64_t>(c0 + kNB, w);
+                int32_t blk = first_blk[s] + (int32_t)b;
                 // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                 // SYRK k n(n+1), GEMM 2 m n k
                 double nbd = (double)(c1 - c0);
@@ -332,20 +354,24 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
                                   (double)(m - c1) * nbd * nbd;
                 st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
                                      2.0 * (double)(m - w) * (double)(w - c1) * nbd;
-                S.potrf_tasks.push_back(PanelTask{s, (int32_t)b, (int32_t)c0, (int32_t)c1});
-                for (int64_t r = c1; r < m; r += kPanelRows)
-                    S.panel_tasks.push_back(
-                        PanelTask{s, (int32_t)b, (int32_t)r, (int32_t)std::min<int64_t>(r + kPanelRows, m)});
+                S.potrf_tasks.push_back(PanelTask{s, (int32_t)b, (int32_t)c0, (int32_t)c1, blk, 0});
+                for (int64_t r = c1; r < m; r += kTile)
+                    S.trsm_tiles.push_back(TileTask{s, (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
+                                                    (int32_t)c1, blk, 0});
                 // trailing update inside the panel: rows [c1, m), cols [c1, w)
-                for (int64_t j0 = c1; j0 < w; j0 += kTile)
-                    for (int64_t i0 = j0; i0 < m; i0 += kTile) {
-                        TileTask tt{s, (int32_t)i0, (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w, {0, 0}};
-                        S.int_tiles.push_back(tt);
-                    }
+                // K is one block (<= 64) here: the small tiles do better
+                const bool big = false;
+                const int64_t tsz = kTile;
+                for (int64_t j0 = c1; j0 < w; j0 += tsz)
+                    for (int64_t i0 = j0; i0 < m; i0 += tsz)
+                        (big ? S.int_tiles_big : S.int_tiles)
+                            .push_back(TileTask{s, (int32_t)i0, (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w,
+                                                -1, 0});
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
-            st.p1 = (int64_t)S.panel_tasks.size();
+            st.p1 = (int64_t)S.trsm_tiles.size();
             st.t1 = (int64_t)S.int_tiles.size();
+            st.u1 = (int64_t)S.int_tiles_big.size();
             S.steps.push_back(st);
         }
         S.level_step_ptr[l + 1] = (int64_t)S.steps.size();
@@ -353,25 +379,21 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
         for (int32_t s : bylevel[l]) {
             int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
             ef += (double)(m - w) * (double)(m - w + 1) * (double)w;
-            for (int64_t j0 = w; j0 < m; j0 += kTile)
-                for (int64_t i0 = j0; i0 < m; i0 += kTile) {
-                    TileTask tt{s, (int32_t)i0, (int32_t)j0, 0, (int32_t)w, (int32_t)m, {0, 0}};
-                    S.ext_tiles.push_back(tt);
-                }
+            const bool big = m - w >= kBigMin && w >= kBigMinK;
+            const int64_t tsz = big ? kTileBig : kTile;
+            for (int64_t j0 = w; j0 < m; j0 += tsz)
+                for (int64_t i0 = j0; i0 < m; i0 += tsz)
+                    (big ? S.ext_tiles_big : S.ext_tiles)
+                        .push_back(TileTask{s, (int32_t)i0, (int32_t)j0, 0, (int32_t)w, (int32_t)m, -1, 0});
         }
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
+        S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();
         S.ext_flops.push_back(ef);
     }
 
-    // ---- solve schedule: column blocks and their tree levels ---------------
-    std::vector<int32_t> first_blk(ns + 1, 0);
-    for (int32_t s = 0; s < ns; ++s) {
-        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
-        first_blk[s] = (int32_t)S.sblocks.size();
-        for (int64_t c0 = 0; c0 < w; c0 += kSolveNB)
-            S.sblocks.push_back(SolveBlock{s, (int32_t)c0, (int32_t)std::min<int64_t>(c0 + kSolveNB, w), 0});
-    }
-    int64_t nb = (int64_t)S.sblocks.size();
+    // ---- solve schedule: block-tree levels ---------------------------------
+    // parent of block q: the next block of its supernode, else the block of
+    // the parent supernode holding the parent column of the last column
     std::vector<int32_t> blev(nb, 0);
     int32_t nsl = nb ? 1 : 0;
     for (int64_t q = 0; q < nb; ++q) {
@@ -383,7 +405,7 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
             int32_t pc = S.parent[S.super_ptr[B.s + 1] - 1];
             if (pc != -1) {
                 int32_t t = S.snode[pc];
-                pq = first_blk[t] + (pc - S.super_ptr[t]) / kSolveNB;
+                pq = first_blk[t] + (pc - S.super_ptr[t]) / kNB;
             }
         }
         if (pq != -1) blev[pq] = std::max(blev[pq], blev[q] + 1);
@@ -398,14 +420,23 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
         std::vector<int64_t> f(S.slevel_ptr.begin(), S.slevel_ptr.end() - 1);
         for (int64_t q = 0; q < nb; ++q) S.sblock_order[f[blev[q]]++] = (int32_t)q;
     }
+    // one task per chunk of rows below the block; a block with no rows
+    // below still gets one (empty) task, which does its diagonal part
     S.stask_ptr.assign(nsl + 1, 0);
     for (int32_t l = 0; l < nsl; ++l) {
         for (int64_t e = S.slevel_ptr[l]; e < S.slevel_ptr[l + 1]; ++e) {
             int32_t q = S.sblock_order[e];
-            const SolveBlock &B = S.sblocks[q];
+            SolveBlock &B = S.sblocks[q];
             int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
-            for (int64_t r = B.c1; r < m; r += kSolveRows)
-                S.stasks.push_back(SolveTask{q, (int32_t)r, (int32_t)std::min<int64_t>(r + kSolveRows, m), 0});
+            int32_t cnt = 0;
+            int64_t r = B.c1;
+            do {
+                int64_t r1 = std::min<int64_t>(r + kSolveRows, m);
+                S.stasks.push_back(SolveTask{q, (int32_t)r, (int32_t)r1, 0});
+                ++cnt;
+                r = r1;
+            } while (r < m);
+            B.ntasks = cnt;
         }
         S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
     }

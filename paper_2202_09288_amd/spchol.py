@@ -19,6 +19,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_09288_amd/build.py "
                       "(or __graft_entry__.build())")
 
+# torch ships its own HIP runtime and refers to it by a name the loader does
+# not match against an already loaded /opt/rocm copy; loading torch first
+# makes libspchol.so bind to torch's runtime, so the process holds one HIP
+# runtime and both see the device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, INVALID_INPUT, NOT_SPD, OUT_OF_MEMORY, NO_CONVERGENCE, DEVICE_ERROR, BAD_HANDLE, NO_DEVICE = \
@@ -29,7 +35,8 @@ _PREC = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
 EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_factorize",
            "spc_refactorize", "spc_factorize_batch", "spc_solve", "spc_solve_refined", "spc_sync",
            "spc_factor_export", "spc_factor_last_ms", "spc_factor_set_profiling",
-           "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string")
+           "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string",
+           "spc_last_error_message")
 KERNEL_CLASSES = {"assemble": 0, "panel": 1, "trailing": 2, "scatter": 3}
 
 
@@ -75,14 +82,20 @@ _lib.spc_free_factor.argtypes = [_P]
 _lib.spc_free_factor.restype = None
 _lib.spc_status_string.argtypes = [ctypes.c_int]
 _lib.spc_status_string.restype = ctypes.c_char_p
+_lib.spc_last_error_message.argtypes = []
+_lib.spc_last_error_message.restype = ctypes.c_char_p
 for _name in EXPORTS:
-    if _name not in ("spc_free_symbolic", "spc_free_factor", "spc_status_string"):
+    if _name not in ("spc_free_symbolic", "spc_free_factor", "spc_status_string", "spc_last_error_message"):
         getattr(_lib, _name).restype = ctypes.c_int
 
 
 class SpcError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         msg = _lib.spc_status_string(status).decode()
+        if status in (DEVICE_ERROR, OUT_OF_MEMORY):
+            detail = _lib.spc_last_error_message().decode()
+            if detail:
+                msg += f" [{detail}]"
         super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
         self.status = status
 
