@@ -36,6 +36,10 @@ struct spc_symbolic_s {
     std::atomic<int> refs{1};
     spc::Symbolic S;
     DeviceArrays dev;
+    // full-A CSR for refinement, uploaded on first use
+    void *csr_base = nullptr;
+    const int64_t *d_csr_ptr = nullptr, *d_csr_val = nullptr;
+    const int32_t *d_csr_col = nullptr;
     std::mutex mu;
 };
 
@@ -81,11 +85,12 @@ bool fac_ok(spc_factor f) { return f && f->magic == kFacMagic && sym_ok(f->sym);
 
 void sym_release(spc_symbolic_s *s) {
     if (s && s->refs.fetch_sub(1) == 1) {
-        if (s->dev.base) {
+        if (s->dev.base || s->csr_base) {
             int cur = -1;
             (void)hipGetDevice(&cur);
             if (s->dev.device >= 0) (void)hipSetDevice(s->dev.device);
-            (void)hipFree(s->dev.base);
+            if (s->dev.base) (void)hipFree(s->dev.base);
+            if (s->csr_base) (void)hipFree(s->csr_base);
             if (cur >= 0) (void)hipSetDevice(cur);
         }
         s->magic = kDead;
@@ -302,6 +307,171 @@ int ensure_bytes(void **p, size_t *have, size_t need) {
     return SPC_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Iterative refinement (FP64 on the device).
+// ---------------------------------------------------------------------------
+constexpr int kRefineChunk = 16;
+
+int ensure_csr(spc_symbolic_s *sym) {
+    std::lock_guard<std::mutex> lk(sym->mu);
+    if (sym->csr_base) return SPC_OK;
+    const spc::Symbolic &S = sym->S;
+    const size_t b0 = (bytes_of(S.csr_ptr) + 255) & ~size_t(255);
+    const size_t b1 = (bytes_of(S.csr_val) + 255) & ~size_t(255);
+    const size_t b2 = (bytes_of(S.csr_col) + 255) & ~size_t(255);
+    void *base = nullptr;
+    HIP_TRY(hipMalloc(&base, b0 + b1 + b2 + 256));
+    char *c = (char *)base;
+    hipError_t e = hipMemcpy(c, S.csr_ptr.data(), bytes_of(S.csr_ptr), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !S.csr_val.empty())
+        e = hipMemcpy(c + b0, S.csr_val.data(), bytes_of(S.csr_val), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !S.csr_col.empty())
+        e = hipMemcpy(c + b0 + b1, S.csr_col.data(), bytes_of(S.csr_col), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        return record_error(e, "csr upload", __LINE__);
+    }
+    sym->csr_base = base;
+    sym->d_csr_ptr = (const int64_t *)c;
+    sym->d_csr_val = (const int64_t *)(c + b0);
+    sym->d_csr_col = (const int32_t *)(c + b0 + b1);
+    return SPC_OK;
+}
+
+struct RefineResult {
+    int iterations = 0;
+    bool converged = false;
+    double berr = 0.0;
+};
+
+double bits_to_double(unsigned long long b) {
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+// One chunk of q <= kRefineChunk right-hand sides.  x0 = low-precision
+// solve; then each step computes r = b - A x in FP64 and the backward error
+//   eta_k = ||r_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf).
+// Classical refinement (x += solve(r)) runs while eta at least halves every
+// two steps; after that, conjugate gradients in FP64 preconditioned by the
+// factor (M^{-1} = solve) continue from the current x.  Stops at
+// max_k eta_k <= tol or after maxit steps of either kind.
+int refine_chunk(spc_factor f, const double *d_values, const double *B, double *X, int q, int64_t ld, double tol,
+                 int maxit, hipStream_t st, RefineResult *res) {
+    const spc::Symbolic &S = f->sym->S;
+    const int64_t n = S.n;
+    constexpr int C = kRefineChunk;
+    // workspace: 7 vectors of n x C (leading dimension n), then scalars
+    const size_t vec = ((size_t)n * C * sizeof(double) + 255) & ~size_t(255);
+    const size_t scal = 16 * C * sizeof(double);
+    int rc = ensure_bytes((void **)&f->refine, &f->refine_bytes, 7 * vec + scal);
+    if (rc) return rc;
+    char *base = (char *)f->refine;
+    double *Bw = (double *)base, *Xw = (double *)(base + vec), *Tv = (double *)(base + 2 * vec),
+           *Rv = (double *)(base + 3 * vec), *Zv = (double *)(base + 4 * vec), *Pv = (double *)(base + 5 * vec),
+           *Qv = (double *)(base + 6 * vec);
+    unsigned long long *umax = (unsigned long long *)(base + 7 * vec);  // r[C], x[C], b[C], |A|
+    double *dots = (double *)(umax + 4 * C);                               // [C]
+    double *coef = dots + C;                                               // alpha[C], -alpha[C], beta[C]
+    const int64_t *rp = f->sym->d_csr_ptr, *vm = f->sym->d_csr_val;
+    const int32_t *ci = f->sym->d_csr_col;
+
+    spc::launch_copy_cols(B, ld, Bw, n, n, q, st);
+    spc::launch_copy_cols(Bw, n, Xw, n, n, q, st);
+    rc = spc_solve(f, Xw, q, n, st);
+    if (rc) return rc;
+    spc::launch_zero<unsigned long long>(umax, 4 * C, st);
+    spc::launch_norm_inf_A(rp, vm, d_values, n, umax + 3 * C, st);
+    spc::launch_colmax(Bw, n, q, n, umax + 2 * C, st);
+
+    std::vector<unsigned long long> hb(4 * C);
+    std::vector<double> hdot(C), hcoef(3 * C);
+    std::vector<double> eta_hist, rho(C, 0.0);
+    std::vector<char> frozen(C, 0);
+    bool cg = false, cg_started = false;
+    int it = 0;
+    auto dot = [&](const double *U, const double *V) -> int {
+        HIP_TRY(hipMemsetAsync(dots, 0, C * sizeof(double), st));
+        spc::launch_coldot(U, V, n, q, n, dots, st);
+        HIP_TRY(hipMemcpyAsync(hdot.data(), dots, C * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SPC_OK;
+    };
+    for (;;) {
+        spc::launch_spmv(rp, ci, vm, d_values, Xw, Bw, Tv, n, q, n, st);  // T = b - A x
+        spc::launch_zero<unsigned long long>(umax, 2 * C, st);
+        spc::launch_colmax(Tv, n, q, n, umax, st);
+        spc::launch_colmax(Xw, n, q, n, umax + C, st);
+        HIP_TRY(hipMemcpyAsync(hb.data(), umax, 4 * C * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double normA = bits_to_double(hb[3 * C]);
+        double eta = 0.0;
+        for (int k = 0; k < q; ++k) {
+            const double rn = bits_to_double(hb[k]), xn = bits_to_double(hb[C + k]), bn = bits_to_double(hb[2 * C + k]);
+            const double den = normA * xn + bn;
+            double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (std::isnan(e)) e = INFINITY;
+            frozen[k] = e <= tol;
+            eta = std::max(eta, e);
+        }
+        eta_hist.push_back(eta);
+        res->berr = eta;
+        res->iterations = it;
+        if (eta <= tol) {
+            res->converged = true;
+            break;
+        }
+        if (it >= maxit) break;
+        const size_t h = eta_hist.size();
+        if (!cg && h >= 3 && !(eta_hist[h - 1] <= 0.5 * eta_hist[h - 3])) cg = true;
+        ++it;
+        if (!cg) {
+            spc::launch_copy_cols(Tv, n, Zv, n, n, q, st);
+            rc = spc_solve(f, Zv, q, n, st);  // d = M^{-1} r
+            if (rc) return rc;
+            spc::launch_axpby(nullptr, 1.0, Zv, nullptr, 1.0, Xw, n, q, n, st);  // x += d
+            continue;
+        }
+        if (!cg_started) {
+            // r = b - A x, z = M^{-1} r, p = z, rho = r.z
+            spc::launch_copy_cols(Tv, n, Rv, n, n, q, st);
+            spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
+            rc = spc_solve(f, Zv, q, n, st);
+            if (rc) return rc;
+            spc::launch_copy_cols(Zv, n, Pv, n, n, q, st);
+            if ((rc = dot(Rv, Zv))) return rc;
+            for (int k = 0; k < q; ++k) rho[k] = hdot[k];
+            cg_started = true;
+        }
+        spc::launch_spmv(rp, ci, vm, d_values, Pv, nullptr, Qv, n, q, n, st);  // q = A p
+        if ((rc = dot(Pv, Qv))) return rc;
+        for (int k = 0; k < q; ++k) {
+            const double a = (!frozen[k] && hdot[k] > 0.0 && std::isfinite(rho[k] / hdot[k])) ? rho[k] / hdot[k] : 0.0;
+            hcoef[k] = a;
+            hcoef[C + k] = -a;
+        }
+        HIP_TRY(hipMemcpyAsync(coef, hcoef.data(), 2 * C * sizeof(double), hipMemcpyHostToDevice, st));
+        spc::launch_axpby(coef, 0.0, Pv, nullptr, 1.0, Xw, n, q, n, st);      // x += alpha p
+        spc::launch_axpby(coef + C, 0.0, Qv, nullptr, 1.0, Rv, n, q, n, st);  // r -= alpha q
+        spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
+        rc = spc_solve(f, Zv, q, n, st);  // z = M^{-1} r
+        if (rc) return rc;
+        if ((rc = dot(Rv, Zv))) return rc;
+        for (int k = 0; k < q; ++k) {
+            const double b = (rho[k] != 0.0 && std::isfinite(hdot[k] / rho[k])) ? hdot[k] / rho[k] : 0.0;
+            hcoef[2 * C + k] = frozen[k] ? 0.0 : b;
+            if (!frozen[k]) rho[k] = hdot[k];
+        }
+        HIP_TRY(hipMemcpyAsync(coef + 2 * C, hcoef.data() + 2 * C, C * sizeof(double), hipMemcpyHostToDevice, st));
+        spc::launch_axpby(nullptr, 1.0, Zv, coef + 2 * C, 0.0, Pv, n, q, n, st);  // p = z + beta p
+    }
+    spc::launch_copy_cols(Xw, n, X, ld, n, q, st);
+    HIP_TRY(hipGetLastError());
+    return SPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -449,9 +619,38 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
 
 int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, double *d_X, int nrhs,
                       int64_t ld, double tol, int maxit, void *stream, spc_refine_info *info) {
-    (void)f; (void)d_values; (void)d_B; (void)d_X; (void)nrhs; (void)ld; (void)tol; (void)maxit;
-    (void)stream; (void)info;
-    return SPC_INVALID_INPUT;
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    const spc::Symbolic &S = f->sym->S;
+    const int64_t n = S.n;
+    if (nrhs < 0 || ld < n || maxit < 0 || !(tol >= 0.0) || (n > 0 && nrhs > 0 && (!d_values || !d_B || !d_X)))
+        return SPC_INVALID_INPUT;
+    if (info) {
+        info->iterations = 0;
+        info->converged = 1;
+        info->berr = 0.0;
+    }
+    if (n == 0 || nrhs == 0) return SPC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_csr(f->sym);
+    if (rc) return rc;
+    int worst = 0;
+    double worst_berr = 0.0;
+    bool all_conv = true;
+    for (int q0 = 0; q0 < nrhs; q0 += kRefineChunk) {
+        const int q = std::min(kRefineChunk, nrhs - q0);
+        RefineResult res;
+        rc = refine_chunk(f, d_values, d_B + (int64_t)q0 * ld, d_X + (int64_t)q0 * ld, q, ld, tol, maxit, st, &res);
+        if (rc) return rc;
+        worst = std::max(worst, res.iterations);
+        worst_berr = std::max(worst_berr, res.berr);
+        all_conv = all_conv && res.converged;
+    }
+    if (info) {
+        info->iterations = worst;
+        info->converged = all_conv ? 1 : 0;
+        info->berr = worst_berr;
+    }
+    return all_conv ? SPC_OK : SPC_NO_CONVERGENCE;
 }
 
 int spc_sync(spc_factor f, int64_t *bad_pivot) {

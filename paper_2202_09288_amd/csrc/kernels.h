@@ -60,4 +60,15 @@ template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
                       int32_t *counters, int64_t n, int nrhs, hipStream_t st);
 
+// refinement (FP64)
+void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
+                 const double *X, const double *B, double *Y, int64_t n, int nrhs, int64_t ld, hipStream_t st);
+void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
+                       unsigned long long *out, hipStream_t st);
+void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned long long *out, hipStream_t st);
+void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st);
+void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
+                  int nrhs, int64_t ld, hipStream_t st);
+void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st);
+
 }  // namespace spc

@@ -646,6 +646,79 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 kernels of iterative refinement.  A is applied in full through a CSR
+// of the symmetric pattern whose entries point into the caller's lower-CSC
+// values (valmap), so refinement always uses the values given.  Vectors are
+// n x nrhs column-major with leading dimension ld.
+// ---------------------------------------------------------------------------
+// Y = B - A X (beta = -1, with B) or Y = A X (B == nullptr)
+__global__ void k_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap,
+                       const double *values, const double *X, const double *B, double *Y, int64_t n,
+                       int nrhs, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const double a = values[valmap[e]];
+        const int64_t c = colidx[e];
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (q < nrhs) acc[q] += a * X[c + q * ld];
+    }
+    for (int q = 0; q < nrhs; ++q) Y[i + q * ld] = B ? B[i + q * ld] - acc[q] : acc[q];
+}
+
+// out = max_i sum_j |a_ij| (as the bit pattern of a non-negative double)
+__global__ void k_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
+                             unsigned long long *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sum = 0.0;
+    if (i < n)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) sum += fabs(values[valmap[e]]);
+    for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sum));
+}
+
+// out[q] = max_i |V[i, q]| (bit patterns), grid.y = q
+__global__ void k_colmax(const double *V, int64_t n, int64_t ld, unsigned long long *out) {
+    const int q = blockIdx.y;
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mx = fmax(mx, fabs(V[i + q * ld]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(&out[q], (unsigned long long)__double_as_longlong(mx));
+}
+
+// out[q] += sum_i U[i, q] V[i, q], grid.y = q
+__global__ void k_coldot(const double *U, const double *V, int64_t n, int64_t ld, double *out) {
+    const int q = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += U[i + q * ld] * V[i + q * ld];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&out[q], acc);
+}
+
+// Y[:, q] = a_q X[:, q] + b_q Y[:, q]; a_q = a[q] (device) or a0 when a is
+// null, likewise b_q; b_q = 0 does not read Y.
+__global__ void k_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y,
+                        int64_t n, int64_t ld) {
+    const int q = blockIdx.y;
+    const double aq = a ? a[q] : a0, bq = b ? b[q] : b0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        Y[i + q * ld] = (bq == 0.0) ? aq * X[i + q * ld] : aq * X[i + q * ld] + bq * Y[i + q * ld];
+}
+
+// copy n x q between leading dimensions
+__global__ void k_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n) {
+    const int q = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        Y[i + q * ldy] = X[i + q * ldx];
+}
+
 inline unsigned grid1(int64_t count, int block) {
     int64_t g = (count + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
@@ -738,7 +811,41 @@ void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
                        P.super_ptr, P.rptr, P.lptr, P.rows, Lx, Linv, P.inv_off, X, Acc, counters, n, nrhs);
 }
 
+
+void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
+                 const double *X, const double *B, double *Y, int64_t n, int nrhs, int64_t ld, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_spmv, dim3(grid1(n, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values, X, B, Y, n,
+                       nrhs, ld);
+}
+void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
+                       unsigned long long *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_norm_inf_A, dim3(grid1(n, 256)), dim3(256), 0, st, rowptr, valmap, values, n, out);
+}
+static unsigned red_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned long long *out, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_colmax, dim3(red_grid(n), nrhs), dim3(256), 0, st, V, n, ld, out);
+}
+void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_coldot, dim3(red_grid(n), nrhs), dim3(256), 0, st, U, V, n, ld, out);
+}
+void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
+                  int nrhs, int64_t ld, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3(red_grid(n), nrhs), dim3(256), 0, st, a, a0, X, b, b0, Y, n, ld);
+}
+void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_copy_cols, dim3(red_grid(n), nrhs), dim3(256), 0, st, X, ldx, Y, ldy, n);
+}
 template void launch_zero<int32_t>(int32_t *, int64_t, hipStream_t);
+template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hipStream_t);
 
 #define SPC_INSTANTIATE(T)                                                                                  \
     template void launch_zero<T>(T *, int64_t, hipStream_t);                                                \

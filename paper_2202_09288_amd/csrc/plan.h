@@ -85,6 +85,10 @@ struct Symbolic {
     int64_t flops = 0, nnzL = 0, max_w = 0, max_m = 0;
     int32_t nlevels = 0;
     std::vector<int64_t> amap;  // caller entry k -> panel offset
+    // full symmetric A in the caller's ordering (CSR), entries pointing into
+    // the caller's lower-CSC values; used by iterative refinement
+    std::vector<int64_t> csr_ptr, csr_val;
+    std::vector<int32_t> csr_col;
 
     // scatter plan
     std::vector<int64_t> pair_ptr;     // [nsuper+1] pairs of each source

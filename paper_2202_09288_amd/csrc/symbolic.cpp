@@ -271,6 +271,30 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
             S.amap[k] = S.lptr[s] + (int64_t)(col - S.super_ptr[s]) * m + pos;
         }
 
+    // ---- full symmetric CSR (caller's ordering) for refinement -------------
+    S.csr_ptr.assign(n + 1, 0);
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t k = colptr[c]; k < colptr[c + 1]; ++k) {
+            S.csr_ptr[rowidx[k] + 1]++;
+            if (rowidx[k] != c) S.csr_ptr[c + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) S.csr_ptr[i + 1] += S.csr_ptr[i];
+    S.csr_col.resize(S.csr_ptr[n]);
+    S.csr_val.resize(S.csr_ptr[n]);
+    {
+        std::vector<int64_t> fill(S.csr_ptr.begin(), S.csr_ptr.end() - 1);
+        for (int64_t c = 0; c < n; ++c)
+            for (int64_t k = colptr[c]; k < colptr[c + 1]; ++k) {
+                int32_t r = rowidx[k];
+                S.csr_col[fill[r]] = (int32_t)c;
+                S.csr_val[fill[r]++] = k;
+                if (r != c) {
+                    S.csr_col[fill[c]] = r;
+                    S.csr_val[fill[c]++] = k;
+                }
+            }
+    }
+
     // ---- scatter pairs and relative indices -------------------------------
     S.pair_ptr.assign(ns + 1, 0);
     S.colpair.assign(S.rptr[ns], -1);

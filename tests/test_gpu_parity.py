@@ -234,3 +234,55 @@ def test_grid3d_60_full_size(torch_dev, lib):
     res = ssp.linalg.norm(E) / ssp.linalg.norm(Ah[:, cols])
     print(f"60^3: sampled ||A - LL^T||/||A|| = {res:.3e}")
     assert res <= 1e-12
+
+
+# ---- FP32 factorization and FP64 refinement ---------------------------------
+
+def refined(torch, lib, s, precision, tol=1e-12, maxit=50, z=0.05):
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, z)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv, precision)
+    F.sync()
+    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    X = torch.zeros_like(B)
+    info = F.solve_refined(dv, B, X, tol=tol, maxit=maxit)
+    Xh = X.cpu().numpy().T
+    eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Xh, s.B)
+    print(f"refine {precision}: {info}, host eta={eta:.3e}", flush=True)
+    return info, eta, F
+
+
+def test_fp32_factor_error_vs_oracle(torch_dev, lib):
+    """FP32 panels: the error against the FP64 oracle is reported; for this
+    well-conditioned grid it must be of the order of FP32 rounding."""
+    s = grid((18, 17, 16), seed=5, nrhs=2)
+    relF, eta, _, _ = run_case(torch_dev, lib, s.colptr, s.rowidx, s.values, s.perm, s.B, precision="fp32")
+    print(f"fp32 relF={relF:.3e} eta={eta:.3e}")
+    assert relF <= 1e-4
+    assert eta <= 1e-5
+
+
+def test_fp32_refined_to_1e12(torch_dev, lib):
+    s = grid((20, 19, 18), seed=6, nrhs=3)
+    info, eta, _ = refined(torch_dev, lib, s, "fp32")
+    assert info["converged"] and info["status"] == lib.OK
+    assert eta <= 1e-12 and info["berr"] <= 1e-12
+
+
+def test_fp32_refined_ill_conditioned_elasticity(torch_dev, lib):
+    """27-point 3-dof operator with kappa = 1e8: kappa * u_fp32 > 1, so the
+    classical steps stall and the FP64 CG phase must finish the job."""
+    s = W.elasticity27((7, 6, 5), 88, 1, kappa=1e8, nrhs=4, power_iters=50)
+    info, eta, _ = refined(torch_dev, lib, s, "fp32", maxit=200)
+    assert info["converged"], info
+    assert eta <= 1e-12
+
+
+def test_fp64_refined_and_no_convergence_status(torch_dev, lib):
+    s = grid((12, 12, 12), seed=7, nrhs=2)
+    info, eta, F = refined(torch_dev, lib, s, "fp64")
+    assert info["converged"] and eta <= 1e-12 and info["iterations"] <= 1
+    s2 = W.elasticity27((6, 5, 5), 88, 2, kappa=1e8, nrhs=1, power_iters=50)
+    info2, eta2, _ = refined(torch_dev, lib, s2, "fp32", tol=1e-15, maxit=0)
+    assert info2["status"] == lib.NO_CONVERGENCE and not info2["converged"]
+    assert info2["iterations"] == 0 and info2["berr"] > 0
