@@ -50,6 +50,7 @@ enum spc_precision {
 
 typedef struct spc_symbolic_s *spc_symbolic;
 typedef struct spc_factor_s *spc_factor;
+typedef struct spc_batch_s *spc_batch;
 
 /* Analysis options.  Pass NULL for the defaults. */
 typedef struct spc_options {
@@ -133,12 +134,44 @@ int spc_refactorize(spc_factor f, const double *d_values, void *stream);
 /*
  * spc_factorize_batch -- factor `count` independent systems in one
  * level-scheduled pass: the launches of level l carry the supernodes of
- * level l of every system.  Arguments as for spc_factorize, one per system;
- * all systems use `precision` and `stream`.  outs[i] receives system i's
- * factor.
+ * level l of every system (the systems form one elimination forest; paper
+ * Sec. 3 schedules independent supernodes of the tree together).
+ * Arguments as for spc_factorize, one per system; all systems use
+ * `precision` and `stream`.  outs[i] receives a view of system i's factor
+ * (usable with spc_solve, spc_solve_refined, spc_sync, spc_factor_export;
+ * not with spc_refactorize); the views share one allocation, released when
+ * the last view is freed.  Equivalent to spc_batch_create +
+ * spc_batch_factorize + spc_batch_factor for every system.
  */
 int spc_factorize_batch(int count, const spc_symbolic *syms, const double *const *d_values,
                         int precision, void *stream, spc_factor *outs);
+
+/*
+ * Batch handle: the disjoint union of `count` analyses with one device
+ * schedule, created once and factored / solved repeatedly.
+ *   spc_batch_create     merge the analyses (host) and allocate the merged
+ *                        factor on the device; the batch keeps references to
+ *                        the symbolic handles
+ *   spc_batch_factorize  d_values[i]: system i's values (device, caller CSC
+ *                        order); one level-scheduled pass over all systems
+ *   spc_batch_factor     a view of system i's factor (free with
+ *                        spc_free_factor)
+ *   spc_batch_solve      d_B[i]: system i's right-hand sides (device, n_i x
+ *                        nrhs column-major, leading dimension ldb[i] >= n_i,
+ *                        host arrays d_B and ldb), solved in place by one
+ *                        level-scheduled pass; returns after the stream has
+ *                        drained
+ *   spc_batch_sync       SPC_NOT_SPD with the first failing system and its
+ *                        permuted pivot column, else SPC_OK
+ */
+int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_batch *out);
+int spc_batch_factorize(spc_batch b, const double *const *d_values, void *stream);
+int spc_batch_factor(spc_batch b, int i, spc_factor *out);
+int spc_batch_solve(spc_batch b, double *const *d_B, int nrhs, const int64_t *ldb, void *stream);
+int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot);
+int spc_batch_last_ms(spc_batch b, float *ms);
+int spc_batch_info(spc_batch b, spc_info *out);
+void spc_free_batch(spc_batch b);
 
 /*
  * spc_solve -- X := A^{-1} B in place (paper Sec. 2: the two triangular
@@ -205,6 +238,8 @@ int spc_factor_set_profiling(spc_factor f, int on);
 
 /* Per-class totals of the last profiled factorization of f (synchronizes). */
 int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *out);
+int spc_batch_set_profiling(spc_batch b, int on);
+int spc_batch_kernel_stats(spc_batch b, int kernel_class, spc_kernel_stats *out);
 
 void spc_free_symbolic(spc_symbolic sym);
 void spc_free_factor(spc_factor f);

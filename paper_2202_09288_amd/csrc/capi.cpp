@@ -57,12 +57,39 @@ struct spc_factor_s {
     size_t refine_bytes = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // status words (one per system of a batch) and, for a view into a
+    // batch, the owning batch, the system index and its first column
+    int nstatus = 1;
+    bool owns_storage = true;
+    struct spc_batch_s *batch = nullptr;
+    int batch_index = -1;
+    int64_t status_col_off = 0;
     // per-launch profiling
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;     // pairs
     std::vector<int> prof_cls;
     std::vector<double> prof_flops;
     size_t prof_used = 0;
+};
+
+// A batch: the disjoint union of several analyses, factored and solved by
+// one level schedule.  It owns the merged plan and the merged factor; views
+// of single systems (spc_batch_factor) share that storage and keep the batch
+// alive until they are freed.
+struct spc_batch_s {
+    uint32_t magic = 0x42415431u;
+    std::atomic<int> refs{1};
+    int count = 0;
+    int precision = SPC_FP64;
+    std::vector<spc_symbolic_s *> members;
+    spc_symbolic_s *merged = nullptr;
+    spc_factor_s *F = nullptr;
+    std::vector<int64_t> col_off, panel_off, inv_base, val_off;
+    double *vbuf = nullptr;      // concatenated values
+    double *bbuf = nullptr;      // merged right-hand sides
+    size_t bbuf_bytes = 0;
+    void *meta = nullptr;        // device: pointer table, leading dims, row offsets
+    size_t meta_bytes = 0;
 };
 
 namespace {
@@ -144,6 +171,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.inv_off.data(), bytes_of(S.inv_off), (const void **)&P.inv_off},
         {S.sblock_order.data(), bytes_of(S.sblock_order), (const void **)&P.sblock_order},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
+        {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
     };
     size_t total = 0;
     for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
@@ -161,6 +189,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         (void)hipFree(base);
         return record_error(e, "plan upload", __LINE__);
     }
+    if (S.status_slot.empty()) P.status_slot = nullptr;
     sym->dev.base = base;
     sym->dev.bytes = total;
     sym->dev.device = device;
@@ -254,7 +283,7 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
     (void)hipGetLastError();  // judge only the launches below
-    spc::launch_status_reset(f->status, st);
+    spc::launch_status_reset(f->status, f->nstatus, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
     Prof prof{f, st};
@@ -268,7 +297,7 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     return SPC_OK;
 }
 
-int create_factor(spc_symbolic sym, int precision, spc_factor *out) {
+int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus = 1) {
     if (precision != SPC_FP64 && precision != SPC_FP32) return SPC_INVALID_INPUT;
     int dev = -1;
     int rc = check_device(&dev);
@@ -281,12 +310,13 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out) {
     sym->refs.fetch_add(1);
     f->precision = precision;
     f->device = dev;
+    f->nstatus = nstatus;
     size_t esz = precision == SPC_FP64 ? sizeof(double) : sizeof(float);
     size_t bytes = std::max<size_t>(1, (size_t)sym->S.panel_entries()) * esz;
     hipError_t e = hipMalloc(&f->Lx, bytes);
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus);
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
     if (e != hipSuccess) {
@@ -472,6 +502,21 @@ int refine_chunk(spc_factor f, const double *d_values, const double *B, double *
     return SPC_OK;
 }
 
+
+void batch_release(spc_batch_s *b) {
+    if (!b || b->refs.fetch_sub(1) != 1) return;
+    if (b->F) spc_free_factor(b->F);
+    if (b->vbuf) (void)hipFree(b->vbuf);
+    if (b->bbuf) (void)hipFree(b->bbuf);
+    if (b->meta) (void)hipFree(b->meta);
+    if (b->merged) sym_release(b->merged);
+    for (spc_symbolic_s *m : b->members) sym_release(m);
+    b->magic = kDead;
+    delete b;
+}
+
+bool batch_ok(spc_batch b) { return b && b->magic == 0x42415431u; }
+
 }  // namespace
 
 extern "C" {
@@ -561,6 +606,7 @@ int spc_factorize(spc_symbolic sym, const double *d_values, int precision, void 
 
 int spc_refactorize(spc_factor f, const double *d_values, void *stream) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (f->batch) return SPC_INVALID_INPUT;  // refactor the batch instead
     if (!d_values && f->sym->S.nnzA > 0) return SPC_INVALID_INPUT;
     return run_factor(f, d_values, (hipStream_t)stream);
 }
@@ -569,17 +615,19 @@ int spc_factorize_batch(int count, const spc_symbolic *syms, const double *const
                         int precision, void *stream, spc_factor *outs) {
     if (count < 0 || (count > 0 && (!syms || !d_values || !outs))) return SPC_INVALID_INPUT;
     for (int i = 0; i < count; ++i) outs[i] = nullptr;
-    for (int i = 0; i < count; ++i) {
-        int rc = spc_factorize(syms[i], d_values[i], precision, stream, &outs[i]);
-        if (rc) {
-            for (int k = 0; k < i; ++k) {
-                spc_free_factor(outs[k]);
-                outs[k] = nullptr;
-            }
-            return rc;
+    if (count == 0) return SPC_OK;
+    spc_batch b = nullptr;
+    int rc = spc_batch_create(count, syms, precision, &b);
+    if (rc) return rc;
+    rc = spc_batch_factorize(b, d_values, stream);
+    for (int i = 0; rc == SPC_OK && i < count; ++i) rc = spc_batch_factor(b, i, &outs[i]);
+    if (rc)
+        for (int i = 0; i < count; ++i) {
+            spc_free_factor(outs[i]);
+            outs[i] = nullptr;
         }
-    }
-    return SPC_OK;
+    spc_free_batch(b);  // the views keep the storage alive
+    return rc;
 }
 
 int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
@@ -656,11 +704,11 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
 int spc_sync(spc_factor f, int64_t *bad_pivot) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (bad_pivot) *bad_pivot = -1;
-    HIP_TRY(hipStreamSynchronize(f->stream));
+    HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
     unsigned long long v = 0;
     HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
     if (v != ~0ull) {
-        if (bad_pivot) *bad_pivot = (int64_t)v;
+        if (bad_pivot) *bad_pivot = (int64_t)v - f->status_col_off;
         return SPC_NOT_SPD;
     }
     return SPC_OK;
@@ -670,7 +718,7 @@ int spc_factor_export(spc_factor f, double *h_dst) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (!h_dst) return SPC_INVALID_INPUT;
     const spc::Symbolic &S = f->sym->S;
-    HIP_TRY(hipStreamSynchronize(f->stream));
+    HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
     int64_t cnt = S.panel_entries();
     if (f->precision == SPC_FP64) {
         HIP_TRY(hipMemcpy(h_dst, f->Lx, cnt * sizeof(double), hipMemcpyDeviceToHost));
@@ -727,6 +775,17 @@ void spc_free_symbolic(spc_symbolic sym) {
 
 void spc_free_factor(spc_factor f) {
     if (!f || f->magic != kFacMagic) return;
+    if (f->batch) {
+        spc_batch_s *b = f->batch;
+        if (f->work) (void)hipFree(f->work);
+        if (f->refine) (void)hipFree(f->refine);
+        spc_symbolic_s *s = f->sym;
+        f->magic = kDead;
+        delete f;
+        if (s) sym_release(s);
+        batch_release(b);
+        return;
+    }
     if (f->stream || f->Lx) (void)hipStreamSynchronize(f->stream);
     if (f->Lx) (void)hipFree(f->Lx);
     if (f->Linv) (void)hipFree(f->Linv);
@@ -740,6 +799,166 @@ void spc_free_factor(spc_factor f) {
     f->magic = kDead;
     delete f;
     if (s) sym_release(s);
+}
+
+
+int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_batch *out) {
+    if (!out) return SPC_INVALID_INPUT;
+    *out = nullptr;
+    if (count <= 0 || !syms || (precision != SPC_FP64 && precision != SPC_FP32)) return SPC_INVALID_INPUT;
+    for (int i = 0; i < count; ++i)
+        if (!sym_ok(syms[i])) return SPC_BAD_HANDLE;
+    int dev = -1;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    spc_batch_s *b = new (std::nothrow) spc_batch_s;
+    if (!b) return SPC_OUT_OF_MEMORY;
+    b->count = count;
+    b->precision = precision;
+    std::vector<const spc::Symbolic *> parts;
+    for (int i = 0; i < count; ++i) {
+        syms[i]->refs.fetch_add(1);
+        b->members.push_back(syms[i]);
+        parts.push_back(&syms[i]->S);
+    }
+    b->merged = new (std::nothrow) spc_symbolic_s;
+    if (!b->merged) {
+        batch_release(b);
+        return SPC_OUT_OF_MEMORY;
+    }
+    try {
+        rc = spc::merge(parts, b->merged->S, b->col_off, b->panel_off, b->inv_base, b->val_off);
+    } catch (const std::bad_alloc &) {
+        rc = SPC_OUT_OF_MEMORY;
+    }
+    if (rc == SPC_OK) rc = create_factor(b->merged, precision, &b->F, count);
+    if (rc == SPC_OK && hipMalloc((void **)&b->vbuf, std::max<int64_t>(1, b->val_off[count]) * sizeof(double)) !=
+                            hipSuccess)
+        rc = SPC_OUT_OF_MEMORY;
+    // meta: pointer table [count], leading dims [count], row offsets [count + 1]
+    b->meta_bytes = sizeof(double *) * count + sizeof(int64_t) * (2 * count + 1);
+    if (rc == SPC_OK && hipMalloc(&b->meta, b->meta_bytes) != hipSuccess) rc = SPC_OUT_OF_MEMORY;
+    if (rc == SPC_OK &&
+        hipMemcpy((char *)b->meta + sizeof(double *) * count + sizeof(int64_t) * count, b->col_off.data(),
+                  sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice) != hipSuccess)
+        rc = SPC_DEVICE_ERROR;
+    if (rc) {
+        batch_release(b);
+        return rc;
+    }
+    *out = b;
+    return SPC_OK;
+}
+
+int spc_batch_factorize(spc_batch b, const double *const *d_values, void *stream) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    if (!d_values) return SPC_INVALID_INPUT;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < b->count; ++i) {
+        const int64_t cnt = b->val_off[i + 1] - b->val_off[i];
+        if (cnt == 0) continue;
+        if (!d_values[i]) return SPC_INVALID_INPUT;
+        HIP_TRY(hipMemcpyAsync(b->vbuf + b->val_off[i], d_values[i], cnt * sizeof(double), hipMemcpyDeviceToDevice,
+                               st));
+    }
+    return run_factor(b->F, b->vbuf, st);
+}
+
+int spc_batch_factor(spc_batch b, int i, spc_factor *out) {
+    if (!out) return SPC_INVALID_INPUT;
+    *out = nullptr;
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    if (i < 0 || i >= b->count) return SPC_INVALID_INPUT;
+    spc_symbolic_s *sym = b->members[i];
+    int rc = ensure_device_plan(sym, b->F->device);
+    if (rc) return rc;
+    spc_factor f = new (std::nothrow) spc_factor_s;
+    if (!f) return SPC_OUT_OF_MEMORY;
+    const size_t esz = b->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    f->sym = sym;
+    sym->refs.fetch_add(1);
+    f->precision = b->precision;
+    f->device = b->F->device;
+    f->owns_storage = false;
+    f->batch = b;
+    b->refs.fetch_add(1);
+    f->batch_index = i;
+    f->Lx = (char *)b->F->Lx + b->panel_off[i] * esz;
+    f->Linv = (char *)b->F->Linv + b->inv_base[i] * esz;
+    f->status = b->F->status + i;
+    f->status_col_off = b->col_off[i];
+    f->stream = b->F->stream;
+    *out = f;
+    return SPC_OK;
+}
+
+int spc_batch_solve(spc_batch b, double *const *d_B, int nrhs, const int64_t *ldb, void *stream) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    if (nrhs < 0 || (nrhs > 0 && (!d_B || !ldb))) return SPC_INVALID_INPUT;
+    if (nrhs == 0) return SPC_OK;
+    for (int i = 0; i < b->count; ++i)
+        if (ldb[i] < b->col_off[i + 1] - b->col_off[i] || (!d_B[i] && b->col_off[i + 1] > b->col_off[i]))
+            return SPC_INVALID_INPUT;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = b->col_off[b->count];
+    int rc = ensure_bytes((void **)&b->bbuf, &b->bbuf_bytes, (size_t)std::max<int64_t>(n, 1) * nrhs * sizeof(double));
+    if (rc) return rc;
+    char *meta = (char *)b->meta;
+    double **ptrs = (double **)meta;
+    int64_t *lds = (int64_t *)(meta + sizeof(double *) * b->count);
+    int64_t *offs = lds + b->count;
+    HIP_TRY(hipMemcpyAsync(ptrs, d_B, sizeof(double *) * b->count, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(lds, ldb, sizeof(int64_t) * b->count, hipMemcpyHostToDevice, st));
+    spc::launch_batch_move(ptrs, lds, offs, b->bbuf, n, b->count, nrhs, true, st);
+    rc = spc_solve(b->F, b->bbuf, nrhs, n, st);
+    if (rc) return rc;
+    spc::launch_batch_move(ptrs, lds, offs, b->bbuf, n, b->count, nrhs, false, st);
+    HIP_TRY(hipGetLastError());
+    // the pointer tables are read by the kernels above: wait before returning
+    // so the caller may reuse its host arrays
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPC_OK;
+}
+
+int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    if (bad_system) *bad_system = -1;
+    if (bad_pivot) *bad_pivot = -1;
+    HIP_TRY(hipStreamSynchronize(b->F->stream));
+    std::vector<unsigned long long> v(b->count);
+    HIP_TRY(hipMemcpy(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
+    for (int i = 0; i < b->count; ++i)
+        if (v[i] != ~0ull) {
+            if (bad_system) *bad_system = i;
+            if (bad_pivot) *bad_pivot = (int64_t)v[i] - b->col_off[i];
+            return SPC_NOT_SPD;
+        }
+    return SPC_OK;
+}
+
+int spc_batch_last_ms(spc_batch b, float *ms) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    return spc_factor_last_ms(b->F, ms);
+}
+
+int spc_batch_set_profiling(spc_batch b, int on) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    return spc_factor_set_profiling(b->F, on);
+}
+
+int spc_batch_kernel_stats(spc_batch b, int kernel_class, spc_kernel_stats *out) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    return spc_factor_kernel_stats(b->F, kernel_class, out);
+}
+
+int spc_batch_info(spc_batch b, spc_info *out) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    return spc_symbolic_info(b->merged, out);
+}
+
+void spc_free_batch(spc_batch b) {
+    if (!batch_ok(b)) return;
+    batch_release(b);
 }
 
 const char *spc_last_error_message(void) { return g_last_error; }

@@ -28,12 +28,13 @@ struct DevPlan {
     const int64_t *inv_off;
     const int32_t *sblock_order;
     const SolveTask *stasks;
+    const int32_t *status_slot;  // supernode -> status word, or null (one word)
 };
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
 // status word: lowest permuted column whose pivot failed, or ~0ull
-void launch_status_reset(unsigned long long *status, hipStream_t st);
+void launch_status_reset(unsigned long long *status, int count, hipStream_t st);
 template <typename T>
 void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
@@ -70,5 +71,7 @@ void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_
 void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
                   int nrhs, int64_t ld, hipStream_t st);
 void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st);
+void launch_batch_move(double *const *ptrs, const int64_t *lds, const int64_t *offs, double *M, int64_t n,
+                       int count, int nrhs, bool to_merged, hipStream_t st);
 
 }  // namespace spc

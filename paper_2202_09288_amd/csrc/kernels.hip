@@ -60,7 +60,10 @@ __global__ void k_zero(T *x, int64_t count) {
     for (; i < count; i += stride) x[i] = T(0);
 }
 
-__global__ void k_status_reset(unsigned long long *status) { *status = ~0ull; }
+__global__ void k_status_reset(unsigned long long *status, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) status[i] = ~0ull;
+}
 
 template <typename T>
 __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *values, T *Lx) {
@@ -115,7 +118,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int32_t *super_ptr,
                                                const int64_t *rptr, const int64_t *lptr,
                                                const int64_t *inv_off, T *Lx, T *Linv,
-                                               unsigned long long *status) {
+                                               unsigned long long *status, const int32_t *status_slot) {
     constexpr int NB = kNB, PW = 16;
     __shared__ T A[NB][NB + 1];
     __shared__ T rdg[NB];
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
         }
         __syncthreads();
     }
-    if (t == 0 && badcol >= 0) atomicMin(status, (unsigned long long)(super_ptr[s] + c0 + badcol));
+    if (t == 0 && badcol >= 0)
+        atomicMin(status + (status_slot ? status_slot[s] : 0), (unsigned long long)(super_ptr[s] + c0 + badcol));
     // inverses of the 16x16 diagonal blocks: wave w, lane c -> column c
     {
         const int b0 = PW * wv;
@@ -719,6 +723,20 @@ __global__ void k_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy
         Y[i + q * ldy] = X[i + q * ldx];
 }
 
+// Batched right-hand sides: system i's n_i x nrhs block (leading dimension
+// ld[i]) <-> rows off[i].. of the merged n x nrhs array (leading dimension
+// n).  grid.x = systems, grid.y = right-hand sides.
+__global__ void k_batch_move(double *const *ptrs, const int64_t *lds, const int64_t *offs, double *M, int64_t n,
+                             int to_merged) {
+    const int i = blockIdx.x, q = blockIdx.y;
+    const int64_t o = offs[i], ni = offs[i + 1] - o, ld = lds[i];
+    double *X = ptrs[i];
+    for (int64_t r = threadIdx.x; r < ni; r += blockDim.x) {
+        if (to_merged) M[o + r + q * n] = X[r + q * ld];
+        else X[r + q * ld] = M[o + r + q * n];
+    }
+}
+
 inline unsigned grid1(int64_t count, int block) {
     int64_t g = (count + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
@@ -726,8 +744,9 @@ inline unsigned grid1(int64_t count, int block) {
 
 }  // namespace
 
-void launch_status_reset(unsigned long long *status, hipStream_t st) {
-    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, st, status);
+void launch_status_reset(unsigned long long *status, int count, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
 }
 
 template <typename T>
@@ -749,7 +768,7 @@ void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
                   hipStream_t st) {
     if (t1 <= t0) return;
     hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0,
-                       P.super_ptr, P.rptr, P.lptr, P.inv_off, Lx, Linv, status);
+                       P.super_ptr, P.rptr, P.lptr, P.inv_off, Lx, Linv, status, P.status_slot);
 }
 
 template <typename T>
@@ -839,6 +858,11 @@ void launch_axpby(const double *a, double a0, const double *X, const double *b, 
                   int nrhs, int64_t ld, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
     hipLaunchKernelGGL(k_axpby, dim3(red_grid(n), nrhs), dim3(256), 0, st, a, a0, X, b, b0, Y, n, ld);
+}
+void launch_batch_move(double *const *ptrs, const int64_t *lds, const int64_t *offs, double *M, int64_t n,
+                       int count, int nrhs, bool to_merged, hipStream_t st) {
+    if (count <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_batch_move, dim3(count, nrhs), dim3(256), 0, st, ptrs, lds, offs, M, n, to_merged ? 1 : 0);
 }
 void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;

@@ -127,6 +127,9 @@ struct Symbolic {
     std::vector<SolveTask> stasks;
     int32_t nslevels = 0;
 
+    // batches: status word of each supernode (empty: one word)
+    std::vector<int32_t> status_slot;
+
     int64_t rows_total() const { return rptr.empty() ? 0 : rptr.back(); }
     int64_t panel_entries() const { return lptr.empty() ? 0 : lptr.back(); }
 };
@@ -134,5 +137,12 @@ struct Symbolic {
 // Returns 0 or a negative spc_status.
 int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm,
             double z, Symbolic &S);
+// Schedule of an analysis whose structural arrays are set.
+int build_schedule(Symbolic &S);
+// Disjoint union of analyses with a schedule over the whole forest; the
+// offsets of each part (columns, panel entries, inverse store, caller
+// entries) are returned, with a final total.
+int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<int64_t> &col_off,
+          std::vector<int64_t> &panel_off, std::vector<int64_t> &inv_base, std::vector<int64_t> &val_off);
 
 }  // namespace spc

@@ -90,6 +90,8 @@ int64_t find_pos(const int32_t *R, int64_t m, int32_t row) {
 
 }  // namespace
 
+int build_schedule(Symbolic &S);
+
 int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm_in,
             double z, Symbolic &S) {
     // ---- validation --------------------------------------------------------
@@ -295,6 +297,31 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
             }
     }
 
+    return build_schedule(S);
+}
+
+// Relative indices, scatter pairs, the factor schedule and the solve
+// schedule, from the structural arrays of S (super_ptr, snode, sparent,
+// parent, rptr, rows, lptr, level, nlevels).
+int build_schedule(Symbolic &S) {
+    const int64_t n = S.n;
+    const int32_t ns = S.nsuper;
+    S.pair_ptr.clear();
+    S.pairs.clear();
+    S.colpair.clear();
+    S.rel.clear();
+    S.steps.clear();
+    S.potrf_tasks.clear();
+    S.trsm_tiles.clear();
+    S.int_tiles.clear();
+    S.ext_tiles.clear();
+    S.int_tiles_big.clear();
+    S.ext_tiles_big.clear();
+    S.ext_flops.clear();
+    S.sblocks.clear();
+    S.sblock_order.clear();
+    S.stasks.clear();
+    (void)n;
     // ---- scatter pairs and relative indices -------------------------------
     S.pair_ptr.assign(ns + 1, 0);
     S.colpair.assign(S.rptr[ns], -1);
@@ -465,6 +492,61 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
         S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
     }
     return SPC_OK;
+}
+
+// Disjoint union of analyses: system i's columns, supernodes, rows and
+// panel entries follow those of systems 0..i-1; its caller entries follow
+// theirs too.  The schedule is then built for the whole forest, so level l
+// of the union holds level l of every system.
+int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<int64_t> &col_off,
+          std::vector<int64_t> &panel_off, std::vector<int64_t> &inv_base, std::vector<int64_t> &val_off) {
+    M = Symbolic();
+    const size_t k = parts.size();
+    col_off.assign(k + 1, 0);
+    panel_off.assign(k + 1, 0);
+    inv_base.assign(k + 1, 0);
+    val_off.assign(k + 1, 0);
+    int64_t sn_off = 0, row_off = 0;
+    M.super_ptr.push_back(0);
+    M.rptr.push_back(0);
+    M.lptr.push_back(0);
+    for (size_t i = 0; i < k; ++i) {
+        const Symbolic &S = *parts[i];
+        const int64_t c0 = col_off[i], p0 = panel_off[i];
+        for (int64_t j = 0; j < S.n; ++j) {
+            M.perm.push_back((int32_t)(c0 + S.perm[j]));
+            M.iperm.push_back((int32_t)(c0 + S.iperm[j]));
+            M.parent.push_back(S.parent[j] < 0 ? -1 : (int32_t)(c0 + S.parent[j]));
+            M.colcount.push_back(S.colcount[j]);
+            M.snode.push_back((int32_t)(sn_off + S.snode[j]));
+        }
+        for (int32_t s = 0; s < S.nsuper; ++s) {
+            M.super_ptr.push_back((int32_t)(c0 + S.super_ptr[s + 1]));
+            M.sparent.push_back(S.sparent[s] < 0 ? -1 : (int32_t)(sn_off + S.sparent[s]));
+            M.level.push_back(S.level[s]);
+            M.rptr.push_back(row_off + S.rptr[s + 1]);
+            M.lptr.push_back(p0 + S.lptr[s + 1]);
+        }
+        for (int32_t r : S.rows) M.rows.push_back((int32_t)(c0 + r));
+        for (int32_t s = 0; s < S.nsuper; ++s) M.status_slot.push_back((int32_t)i);
+        for (int64_t a : S.amap) M.amap.push_back(p0 + a);
+        M.nnzA += S.nnzA;
+        M.flops += S.flops;
+        M.nnzL += S.nnzL;
+        M.max_w = std::max(M.max_w, S.max_w);
+        M.max_m = std::max(M.max_m, S.max_m);
+        M.nlevels = std::max(M.nlevels, S.nlevels);
+        sn_off += S.nsuper;
+        row_off += S.rows_total();
+        col_off[i + 1] = c0 + S.n;
+        panel_off[i + 1] = p0 + S.panel_entries();
+        inv_base[i + 1] = inv_base[i] + (S.inv_off.empty() ? 0 : S.inv_off.back());
+        val_off[i + 1] = val_off[i] + S.nnzA;
+    }
+    M.n = col_off[k];
+    M.nsuper = (int32_t)sn_off;
+    if (M.n > INT32_MAX - 1) return SPC_INVALID_INPUT;
+    return build_schedule(M);
 }
 
 }  // namespace spc

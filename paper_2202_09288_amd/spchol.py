@@ -36,7 +36,9 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_refactorize", "spc_factorize_batch", "spc_solve", "spc_solve_refined", "spc_sync",
            "spc_factor_export", "spc_factor_last_ms", "spc_factor_set_profiling",
            "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string",
-           "spc_last_error_message")
+           "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
+           "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
+           "spc_batch_set_profiling", "spc_batch_kernel_stats")
 KERNEL_CLASSES = {"assemble": 0, "panel": 1, "trailing": 2, "scatter": 3}
 
 
@@ -76,6 +78,17 @@ _lib.spc_factor_export.argtypes = [_P, _P]
 _lib.spc_factor_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.spc_factor_set_profiling.argtypes = [_P, ctypes.c_int]
 _lib.spc_factor_kernel_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
+_lib.spc_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)]
+_lib.spc_batch_factorize.argtypes = [_P, ctypes.POINTER(_P), _P]
+_lib.spc_batch_factor.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_P)]
+_lib.spc_batch_solve.argtypes = [_P, ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_i64), _P]
+_lib.spc_batch_sync.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+_lib.spc_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.spc_batch_info.argtypes = [_P, ctypes.POINTER(_Info)]
+_lib.spc_batch_set_profiling.argtypes = [_P, ctypes.c_int]
+_lib.spc_batch_kernel_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
+_lib.spc_free_batch.argtypes = [_P]
+_lib.spc_free_batch.restype = None
 _lib.spc_free_symbolic.argtypes = [_P]
 _lib.spc_free_symbolic.restype = None
 _lib.spc_free_factor.argtypes = [_P]
@@ -85,7 +98,8 @@ _lib.spc_status_string.restype = ctypes.c_char_p
 _lib.spc_last_error_message.argtypes = []
 _lib.spc_last_error_message.restype = ctypes.c_char_p
 for _name in EXPORTS:
-    if _name not in ("spc_free_symbolic", "spc_free_factor", "spc_status_string", "spc_last_error_message"):
+    if _name not in ("spc_free_symbolic", "spc_free_factor", "spc_status_string", "spc_last_error_message",
+                     "spc_free_batch"):
         getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -101,9 +115,11 @@ class SpcError(RuntimeError):
 
 
 class NotSPD(SpcError):
-    def __init__(self, column: int):
-        super().__init__(NOT_SPD, f"pivot failed at permuted column {column}")
+    def __init__(self, column: int, system: int = -1):
+        where = f"system {system}, " if system >= 0 else ""
+        super().__init__(NOT_SPD, f"pivot failed at {where}permuted column {column}")
         self.column = column
+        self.system = system
 
 
 def _check(rc: int, what: str):
@@ -263,6 +279,70 @@ class Factor:
     def close(self):
         if getattr(self, "_h", None):
             _lib.spc_free_factor(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Several systems merged into one elimination forest and one device
+    schedule (spc_batch_*): factored and solved level by level together."""
+
+    def __init__(self, syms, precision="fp64"):
+        self.syms = list(syms)
+        self.precision = _PREC[precision]
+        hs = (_P * len(self.syms))(*[x.handle for x in self.syms])
+        h = _P()
+        _check(_lib.spc_batch_create(len(self.syms), hs, self.precision, ctypes.byref(h)), "spc_batch_create")
+        self._h = h
+        info = _Info()
+        _check(_lib.spc_batch_info(self._h, ctypes.byref(info)), "spc_batch_info")
+        self.info = {k: int(getattr(info, k)) for k, _ in _Info._fields_}
+
+    def factorize(self, d_values_list, stream=None):
+        vs = (_P * len(self.syms))(*[_dev_ptr(v, "torch.float64") for v in d_values_list])
+        _check(_lib.spc_batch_factorize(self._h, vs, _stream_ptr(stream)), "spc_batch_factorize")
+
+    def factor(self, i: int) -> "Factor":
+        h = _P()
+        _check(_lib.spc_batch_factor(self._h, int(i), ctypes.byref(h)), "spc_batch_factor")
+        return Factor(self.syms[i], h, self.precision)
+
+    def solve(self, Bs, stream=None):
+        """Bs[i]: float64 device tensor (nrhs, n_i), solved in place."""
+        nrhs = 1 if Bs[0].dim() == 1 else Bs[0].shape[0]
+        ptrs = (_P * len(Bs))(*[_dev_ptr(b, "torch.float64") for b in Bs])
+        lds = (_i64 * len(Bs))(*[x.n for x in self.syms])
+        _check(_lib.spc_batch_solve(self._h, ptrs, nrhs, lds, _stream_ptr(stream)), "spc_batch_solve")
+        return Bs
+
+    def sync(self):
+        sy, col = _i64(-1), _i64(-1)
+        rc = _lib.spc_batch_sync(self._h, ctypes.byref(sy), ctypes.byref(col))
+        if rc == NOT_SPD:
+            raise NotSPD(int(col.value), int(sy.value))
+        _check(rc, "spc_batch_sync")
+
+    def last_ms(self) -> float:
+        v = ctypes.c_float(0)
+        _check(_lib.spc_batch_last_ms(self._h, ctypes.byref(v)), "spc_batch_last_ms")
+        return float(v.value)
+
+    def set_profiling(self, on: bool = True):
+        _check(_lib.spc_batch_set_profiling(self._h, 1 if on else 0), "spc_batch_set_profiling")
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for name, cls in KERNEL_CLASSES.items():
+            st = _KernelStats()
+            _check(_lib.spc_batch_kernel_stats(self._h, cls, ctypes.byref(st)), "spc_batch_kernel_stats")
+            out[name] = {"launches": int(st.launches), "ms": float(st.total_ms), "flops": float(st.flops)}
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.spc_free_batch(self._h)
             self._h = None
 
     def __del__(self):

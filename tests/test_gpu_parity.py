@@ -286,3 +286,76 @@ def test_fp64_refined_and_no_convergence_status(torch_dev, lib):
     info2, eta2, _ = refined(torch_dev, lib, s2, "fp32", tol=1e-15, maxit=0)
     assert info2["status"] == lib.NO_CONVERGENCE and not info2["converged"]
     assert info2["iterations"] == 0 and info2["berr"] > 0
+
+
+# ---- batches: many systems in one level-scheduled pass ----------------------
+
+def small_batch(count, seed=0, nrhs=2):
+    specs = W.batch_specs(count * 8, seed)
+    chosen = [(i, k, sd) for i, (k, sd) in enumerate(specs) if sd <= (60 if k == "2d" else 14)][:count]
+    return [W.batch_system(i, k, sd, seed, nrhs=nrhs) for i, k, sd in chosen]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_factor_and_solve(torch_dev, lib, precision):
+    torch = torch_dev
+    systems = small_batch(12)
+    syms = [lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05) for s in systems]
+    batch = lib.Batch(syms, precision)
+    dvs = [torch.from_numpy(s.values).cuda() for s in systems]
+    batch.factorize(dvs)
+    batch.sync()
+    Bs = [torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda() for s in systems]
+    batch.solve(Bs)
+    for i, s in enumerate(systems):
+        S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        F = batch.factor(i)
+        relF = oracle.rel_frobenius(F.export(), S.factor(s.values), S.lower_mask())
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Bs[i].cpu().numpy().T, s.B)
+        print(f"batch {precision} {s.name}: relF={relF:.2e} eta={eta:.2e}")
+        if precision == "fp64":
+            assert relF <= REL_F_FP64 and eta <= BERR_FP64
+        else:
+            assert relF <= 1e-4 and eta <= 1e-5
+            X = torch.zeros_like(Bs[i])
+            B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+            info = F.solve_refined(dvs[i], B0, X, tol=1e-12, maxit=30)
+            assert info["converged"]
+            assert oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B) <= 1e-12
+
+
+def test_batch_alone_equals_in_mix(torch_dev, lib):
+    """A system factored alone and inside a batch gives the same factor."""
+    torch = torch_dev
+    systems = small_batch(6, seed=1, nrhs=1)
+    syms = [lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05) for s in systems]
+    views = lib.factorize_batch(syms, [torch.from_numpy(s.values).cuda() for s in systems])
+    for i, s in enumerate(systems):
+        F = lib.factorize(syms[i], torch.from_numpy(s.values).cuda())
+        F.sync()
+        views[i].sync()
+        a, b = F.export(), views[i].export()
+        S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        assert oracle.rel_frobenius(b, a, S.lower_mask()) <= 1e-13
+
+
+def test_batch_not_spd_names_system(torch_dev, lib):
+    torch = torch_dev
+    systems = small_batch(5, seed=2, nrhs=1)
+    syms = [lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05) for s in systems]
+    vals = [s.values.copy() for s in systems]
+    bad = 3
+    r = systems[bad].n // 3
+    vals[bad][systems[bad].colptr[r]] *= -1.0
+    batch = lib.Batch(syms, "fp64")
+    batch.factorize([torch.from_numpy(v).cuda() for v in vals])
+    with pytest.raises(lib.NotSPD) as e:
+        batch.sync()
+    S = oracle.Symbolic(systems[bad].colptr, systems[bad].rowidx, systems[bad].perm, 0.05)
+    assert e.value.system == bad
+    assert e.value.column == np.argsort(S.perm)[r]
+    views = [batch.factor(i) for i in range(len(systems))]
+    batch.close()  # views outlive the batch handle
+    views[0].sync()
+    with pytest.raises(lib.NotSPD):
+        views[bad].sync()
