@@ -359,3 +359,59 @@ def test_batch_not_spd_names_system(torch_dev, lib):
     views[0].sync()
     with pytest.raises(lib.NotSPD):
         views[bad].sync()
+
+
+# ---- serving: continuous batching -------------------------------------------
+
+def test_serving_alone_equals_in_mix(torch_dev, lib):
+    """Each request's solution is the same served alone (one slot) and in
+    the mix (four slots, overlapping on the device), and every one reaches
+    the 1e-12 backward error."""
+    from paper_2202_09288_amd import serving as SV
+    reqs_a = SV.make_requests(24, 200.0, 3, max_side={"2d": 48, "3d": 12})
+    reqs_b = SV.make_requests(24, 200.0, 3, max_side={"2d": 48, "3d": 12})
+    alone = SV.Server(slots=1, keep_solutions=True).run(reqs_a, time_scale=1.0)
+    mix = SV.Server(slots=4, keep_solutions=True).run(reqs_b, time_scale=1.0)
+    assert [r.rid for r in alone] == [r.rid for r in mix]
+    systems = {r.rid: r.system for r in alone if r.kind == "factor"}
+    scales = {r.rid: r.values_scale for r in alone if r.kind == "factor"}
+    kappas = {}
+    for a, b in zip(alone, mix):
+        assert a.status == "ok" and b.status == "ok", (a.status, b.status)
+        assert a.berr <= 1e-12 and b.berr <= 1e-12
+        s = systems[a.rid if a.kind == "factor" else a.target]
+        sc = scales[a.rid if a.kind == "factor" else a.target]
+        Bh = SV.Server.rhs(a, s).T if a.kind == "resolve" else s.B[:, :a.nrhs]
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values * sc, b.X, Bh)
+        assert eta <= 1e-12
+        # two solutions with backward error <= 1e-12 differ by at most
+        # about 2 kappa(A) 1e-12 relatively (kappa in the infinity norm)
+        key = a.rid if a.kind == "factor" else a.target
+        if key not in kappas:
+            Ad = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values * sc).toarray()
+            kappas[key] = np.linalg.cond(Ad, np.inf)
+        diff = np.max(np.abs(a.X - b.X)) / np.max(np.abs(a.X))
+        assert diff <= 4 * kappas[key] * 1e-12, (diff, kappas[key])
+
+
+def test_serving_admission_budget(torch_dev, lib):
+    """A budget that holds about one factor forces queuing and eviction;
+    nothing above the budget is admitted and results stay correct."""
+    from paper_2202_09288_amd import serving as SV
+    reqs = SV.make_requests(16, 1000.0, 4, max_side={"2d": 40, "3d": 10})
+    srv = SV.Server(slots=3)
+    one = max(srv.footprint(srv.symbolic(r.system), r.nrhs) for r in reqs if r.kind == "factor")
+    srv.budget = int(one * 1.5)
+    peak = []
+    orig = srv._reserve
+
+    def spy(nbytes):
+        ok = orig(nbytes)
+        peak.append(srv.used)
+        return ok
+    srv._reserve = spy
+    out = srv.run(reqs)
+    bad = [(r.rid, r.kind, r.status) for r in out if r.status != "ok"]
+    assert not bad, bad
+    assert max(peak) <= srv.budget
+    assert all(r.berr <= 1e-12 for r in out)
