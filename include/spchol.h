@@ -223,7 +223,8 @@ enum spc_kernel_class {
     SPC_K_PANEL = 1,          /* POTRF of a diagonal block + TRSM of the rows below */
     SPC_K_TRAILING = 2,       /* SYRK/GEMM update inside a wide supernode */
     SPC_K_SCATTER = 3,        /* SYRK/GEMM update scatter-added into ancestors */
-    SPC_K_COUNT = 4
+    SPC_K_SMALL = 4,          /* whole small supernodes: POTRF, TRSM, inverse, scatter */
+    SPC_K_COUNT = 5
 };
 
 typedef struct spc_kernel_stats {

@@ -172,6 +172,8 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.sblock_order.data(), bytes_of(S.sblock_order), (const void **)&P.sblock_order},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
+        {S.small_snodes.data(), bytes_of(S.small_snodes), (const void **)&P.small_snodes},
+        {S.first_blk.data(), bytes_of(S.first_blk), (const void **)&P.first_blk},
     };
     size_t total = 0;
     for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
@@ -200,7 +202,7 @@ size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.super_ptr) + bytes_of(S.rptr) + bytes_of(S.lptr) + bytes_of(S.rows) +
            bytes_of(S.colpair) + bytes_of(S.pairs) + bytes_of(S.rel) + bytes_of(S.amap) +
            bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.trsm_tiles) + bytes_of(S.int_tiles) +
-           bytes_of(S.ext_tiles) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) + bytes_of(S.sblocks) + bytes_of(S.inv_off) + bytes_of(S.sblock_order) +
+           bytes_of(S.ext_tiles) + bytes_of(S.small_snodes) + bytes_of(S.first_blk) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) + bytes_of(S.sblocks) + bytes_of(S.inv_off) + bytes_of(S.sblock_order) +
            bytes_of(S.stasks);
 }
 
@@ -244,6 +246,10 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
     });
     for (int32_t l = 0; l < S.nlevels; ++l) {
+        if (S.small_ptr[l + 1] > S.small_ptr[l])
+            prof.run(SPC_K_SMALL, S.small_flops[l], [&] {
+                spc::launch_small<T>(P, S.small_ptr[l], S.small_ptr[l + 1], Lx, Linv, status, st);
+            });
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
             prof.run(SPC_K_PANEL, stp.panel_flops, [&] {

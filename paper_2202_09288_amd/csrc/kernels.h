@@ -29,6 +29,8 @@ struct DevPlan {
     const int32_t *sblock_order;
     const SolveTask *stasks;
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
+    const int32_t *small_snodes; // supernodes of the single-workgroup path, by level
+    const int32_t *first_blk;    // first column block of each supernode
 };
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
@@ -41,6 +43,9 @@ template <typename T>
 void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx, hipStream_t st);
 template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                  hipStream_t st);
+template <typename T>
+void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st);

@@ -264,6 +264,88 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
 }
 
 // ---------------------------------------------------------------------------
+// k_small: one workgroup per small supernode (w <= kSmallW, m <= kSmallM),
+// the whole m x w panel in LDS:
+//   1. column Cholesky of the panel, right-looking: l_jj = sqrt(d_j),
+//      l_ij = a_ij / l_jj, then a_ik -= l_ij l_kj for the columns right of j
+//      (POTRF of the diagonal block and TRSM of the rows below at once);
+//   2. the inverse of the diagonal triangle, one column per thread by
+//      forward substitution (kept for the solves);
+//   3. the Schur update C = P P^T of the rows below the block, scatter-added
+//      into the ancestors through the relative indices, as in k_tiles.
+// Pivots that are not positive and finite lower the status word.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_small(const int32_t *snodes, const int32_t *super_ptr,
+                                               const int64_t *rptr, const int64_t *lptr, const int32_t *rows,
+                                               const int32_t *colpair, const UpdatePair *pairs,
+                                               const int32_t *rel, const int32_t *first_blk,
+                                               const int64_t *inv_off, T *Lx, T *Linv,
+                                               unsigned long long *status, const int32_t *status_slot) {
+    constexpr int MS = kSmallM, WS = kSmallW;
+    __shared__ T A[WS][MS + 1];   // A[c][i] = panel entry (row i, column c)
+    __shared__ T Vt[WS][WS + 1];  // inverse, Vt[c][a] = (L^{-1})_ac
+    const int s = snodes[blockIdx.x];
+    const int64_t m = rptr[s + 1] - rptr[s];
+    const int w = super_ptr[s + 1] - super_ptr[s];
+    T *P = Lx + lptr[s];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < w * MS; e += 256) {
+        const int i = e % MS, c = e / MS;
+        A[c][i] = (i < m) ? P[(int64_t)c * m + i] : T(0);
+    }
+    __syncthreads();
+    int bad = -1;
+    for (int j = 0; j < w; ++j) {
+        const T d = A[j][j];
+        if (bad < 0 && !finite_pos(d)) bad = j;
+        const T ljj = sqrt(d);
+        __syncthreads();  // every thread has read d
+        for (int i = j + tid; i < m; i += 256) A[j][i] = (i == j) ? ljj : A[j][i] / ljj;
+        __syncthreads();
+        const int rem = w - j - 1;
+        for (int e = tid; e < rem * m; e += 256) {
+            const int k = j + 1 + e / m, i = e % m;
+            if (i >= k) A[k][i] -= A[j][i] * A[j][k];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && bad >= 0)
+        atomicMin(status + (status_slot ? status_slot[s] : 0), (unsigned long long)(super_ptr[s] + bad));
+    // write the panel back (lower part of the diagonal block, all rows below)
+    for (int e = tid; e < w * MS; e += 256) {
+        const int i = e % MS, c = e / MS;
+        if (i < m && i >= c) P[(int64_t)c * m + i] = A[c][i];
+    }
+    // inverse of the diagonal triangle: thread c owns column c
+    if (tid < w) {
+        const int c = tid;
+        for (int a = 0; a < w; ++a) {
+            T v = (a == c) ? T(1) : T(0);
+            for (int k = c; k < a; ++k) v -= A[k][a] * Vt[c][k];
+            Vt[c][a] = (a < c) ? T(0) : v / A[a][a];
+        }
+    }
+    __syncthreads();
+    T *Vi = Linv + inv_off[first_blk[s]];
+    for (int e = tid; e < w * w; e += 256) Vi[e] = Vt[e / w][e % w];
+    // Schur update of the rows below, scatter-added into the ancestors
+    const int mb = (int)m - w;
+    for (int e = tid; e < mb * mb; e += 256) {
+        const int r = w + e % mb, cc = w + e / mb;  // row r, column cc (positions in R_s)
+        if (cc > r) continue;
+        T acc = T(0);
+        for (int k = 0; k < w; ++k) acc += A[k][r] * A[k][cc];
+        const UpdatePair pr = pairs[colpair[rptr[s] + cc]];
+        const int t = pr.target;
+        const int64_t mt = rptr[t + 1] - rptr[t];
+        const int64_t colt = rows[rptr[s] + cc] - super_ptr[t];
+        const int64_t rowt = rel[pr.rel_off + (r - pr.i0)];
+        atomicAdd(&Lx[lptr[t] + colt * mt + rowt], -acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // MFMA tiles.  Task (s, i0, j0, k0, k1, jmax, blk):
 //   C[r][c] = sum_{k0 <= k < k1} P[i0 + r][k] * Q[c][k]
 // over a 64x64 tile, 256 threads = 4 waves in a 2x2 grid of 32x32, each a
@@ -772,6 +854,15 @@ void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 }
 
 template <typename T>
+void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                  hipStream_t st) {
+    if (t1 <= t0) return;
+    hipLaunchKernelGGL(k_small<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.small_snodes + t0, P.super_ptr,
+                       P.rptr, P.lptr, P.rows, P.colpair, P.pairs, P.rel, P.first_blk, P.inv_off, Lx, Linv, status,
+                       P.status_slot);
+}
+
+template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
@@ -877,6 +968,8 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, const T *, hipStream_t);     \
+    template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
+                                  hipStream_t);                                                             \
     template void launch_tiles128<T>(const DevPlan &, int, int64_t, int64_t, T *, hipStream_t);             \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \
                                     hipStream_t);                                                           \

@@ -14,6 +14,10 @@ constexpr int kTile = 64;
 constexpr int kTileBig = 128;
 constexpr int kBigMin = 256;
 constexpr int kBigMinK = 128;
+// Supernodes with w <= kSmallW and m <= kSmallM are factored, inverted and
+// scatter-added by one workgroup each (k_small).
+constexpr int kSmallW = 32;
+constexpr int kSmallM = 128;
 // Width of the column blocks a supernode is cut into, for the panel
 // factorization and for the triangular solves alike; each block's diagonal
 // triangle gets an explicit inverse in the inverse store.
@@ -109,6 +113,10 @@ struct Symbolic {
     std::vector<Step> steps;
     std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles (64)
     std::vector<int64_t> ext_big_ptr;      // [nlevels+1] external tiles (128)
+    std::vector<int64_t> small_ptr;        // [nlevels+1] into small_snodes
+    std::vector<int32_t> small_snodes;     // supernodes of the single-workgroup path
+    std::vector<int32_t> first_blk;        // [nsuper+1] first column block
+    std::vector<double> small_flops;       // [nlevels] flops of the small path
     std::vector<double> ext_flops;         // [nlevels] algorithmic flops per launch
     std::vector<PanelTask> potrf_tasks;
     std::vector<TileTask> trsm_tiles;

@@ -320,6 +320,7 @@ int build_schedule(Symbolic &S) {
     S.ext_flops.clear();
     S.sblocks.clear();
     S.sblock_order.clear();
+    S.first_blk.clear();
     S.stasks.clear();
     (void)n;
     // ---- scatter pairs and relative indices -------------------------------
@@ -362,6 +363,7 @@ int build_schedule(Symbolic &S) {
             S.sblocks.push_back(SolveBlock{s, (int32_t)c0, (int32_t)std::min<int64_t>(c0 + kNB, w), 0});
     }
     first_blk[ns] = (int32_t)S.sblocks.size();
+    S.first_blk = first_blk;
     const int64_t nb = (int64_t)S.sblocks.size();
     S.inv_off.assign(nb + 1, 0);
     for (int64_t q = 0; q < nb; ++q) {
@@ -378,6 +380,28 @@ int build_schedule(Symbolic &S) {
     S.level_step_ptr.assign(S.nlevels + 1, 0);
     S.ext_tile_ptr.assign(S.nlevels + 1, 0);
     S.ext_big_ptr.assign(S.nlevels + 1, 0);
+    S.small_ptr.assign(S.nlevels + 1, 0);
+    S.small_snodes.clear();
+    S.small_flops.assign(S.nlevels, 0.0);
+    auto is_small = [&](int32_t s) {
+        return S.super_ptr[s + 1] - S.super_ptr[s] <= kSmallW && S.rptr[s + 1] - S.rptr[s] <= kSmallM;
+    };
+    for (int32_t l = 0; l < S.nlevels; ++l) {
+        std::vector<int32_t> big;
+        for (int32_t s : bylevel[l]) {
+            if (is_small(s)) {
+                S.small_snodes.push_back(s);
+                // POTRF + TRSM + SYRK of the rows below (LAPACK counts)
+                const double w = S.super_ptr[s + 1] - S.super_ptr[s], m = (double)(S.rptr[s + 1] - S.rptr[s]);
+                S.small_flops[l] += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 + (m - w) * w * w +
+                                    (m - w) * (m - w + 1) * w;
+            } else {
+                big.push_back(s);
+            }
+        }
+        S.small_ptr[l + 1] = (int64_t)S.small_snodes.size();
+        bylevel[l].swap(big);
+    }
     for (int32_t l = 0; l < S.nlevels; ++l) {
         int64_t maxb = 0;
         for (int32_t s : bylevel[l]) {

@@ -39,7 +39,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats")
-KERNEL_CLASSES = {"assemble": 0, "panel": 1, "trailing": 2, "scatter": 3}
+KERNEL_CLASSES = {"assemble": 0, "panel": 1, "trailing": 2, "scatter": 3, "small": 4}
 
 
 class _Options(ctypes.Structure):
