@@ -152,28 +152,21 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
     };
     spc::DevPlan &P = sym->dev.plan;
     std::vector<Piece> pieces = {
-        {S.super_ptr.data(), bytes_of(S.super_ptr), (const void **)&P.super_ptr},
-        {S.rptr.data(), bytes_of(S.rptr), (const void **)&P.rptr},
-        {S.lptr.data(), bytes_of(S.lptr), (const void **)&P.lptr},
         {S.rows.data(), bytes_of(S.rows), (const void **)&P.rows},
-        {S.colpair.data(), bytes_of(S.colpair), (const void **)&P.colpair},
-        {S.pairs.data(), bytes_of(S.pairs), (const void **)&P.pairs},
         {S.rel.data(), bytes_of(S.rel), (const void **)&P.rel},
+        {S.cbase.data(), bytes_of(S.cbase), (const void **)&P.cbase},
+        {S.crel.data(), bytes_of(S.crel), (const void **)&P.crel},
         {S.amap.data(), bytes_of(S.amap), (const void **)&P.amap},
         {S.perm.data(), bytes_of(S.perm), (const void **)&P.perm},
         {S.potrf_tasks.data(), bytes_of(S.potrf_tasks), (const void **)&P.potrf_tasks},
+        {S.small_tasks.data(), bytes_of(S.small_tasks), (const void **)&P.small_tasks},
         {S.trsm_tiles.data(), bytes_of(S.trsm_tiles), (const void **)&P.trsm_tiles},
         {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
         {S.int_tiles_big.data(), bytes_of(S.int_tiles_big), (const void **)&P.int_tiles_big},
         {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
-        {S.sblocks.data(), bytes_of(S.sblocks), (const void **)&P.sblocks},
-        {S.inv_off.data(), bytes_of(S.inv_off), (const void **)&P.inv_off},
-        {S.sblock_order.data(), bytes_of(S.sblock_order), (const void **)&P.sblock_order},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
-        {S.small_snodes.data(), bytes_of(S.small_snodes), (const void **)&P.small_snodes},
-        {S.first_blk.data(), bytes_of(S.first_blk), (const void **)&P.first_blk},
     };
     size_t total = 0;
     for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
@@ -199,11 +192,10 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 }
 
 size_t plan_bytes(const spc::Symbolic &S) {
-    return bytes_of(S.super_ptr) + bytes_of(S.rptr) + bytes_of(S.lptr) + bytes_of(S.rows) +
-           bytes_of(S.colpair) + bytes_of(S.pairs) + bytes_of(S.rel) + bytes_of(S.amap) +
-           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.trsm_tiles) + bytes_of(S.int_tiles) +
-           bytes_of(S.ext_tiles) + bytes_of(S.small_snodes) + bytes_of(S.first_blk) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) + bytes_of(S.sblocks) + bytes_of(S.inv_off) + bytes_of(S.sblock_order) +
-           bytes_of(S.stasks);
+    return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
+           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.trsm_tiles) +
+           bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) +
+           bytes_of(S.stasks) + bytes_of(S.status_slot);
 }
 
 // Brackets one launch with a pair of events when profiling is on.

@@ -7,30 +7,23 @@
 
 namespace spc {
 
-// Device copy of the symbolic arrays the kernels read.
+// Device copy of the symbolic arrays and task lists the kernels read.
 struct DevPlan {
-    const int32_t *super_ptr;
-    const int64_t *rptr;
-    const int64_t *lptr;
-    const int32_t *rows;
-    const int32_t *colpair;
-    const UpdatePair *pairs;
-    const int32_t *rel;
-    const int64_t *amap;
+    const int32_t *rows;        // row lists R_s (solves)
+    const int32_t *rel;         // relative indices of the scatter pairs
+    const int64_t *cbase;       // per row position: target column base
+    const int64_t *crel;        // per row position: offset into rel
+    const int64_t *amap;        // caller entry -> panel entry
     const int32_t *perm;
     const PanelTask *potrf_tasks;
+    const SmallTask *small_tasks;
     const TileTask *trsm_tiles;
     const TileTask *int_tiles;
     const TileTask *ext_tiles;
     const TileTask *int_tiles_big;
     const TileTask *ext_tiles_big;
-    const SolveBlock *sblocks;
-    const int64_t *inv_off;
-    const int32_t *sblock_order;
     const SolveTask *stasks;
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
-    const int32_t *small_snodes; // supernodes of the single-workgroup path, by level
-    const int32_t *first_blk;    // first column block of each supernode
 };
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };

@@ -72,21 +72,31 @@ __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *value
 }
 
 // ---------------------------------------------------------------------------
+// Global loads in the kernels below are issued unconditionally from clamped,
+// always valid indices and masked afterwards, in groups, so that a wave has
+// many loads in flight: a load under a branch makes the compiler wait for
+// memory at the join, which serializes a loop of them.
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
 // k_potrf: one workgroup (4 waves) per diagonal block (nb <= kNB = 64), held
-// in LDS.  Blocked column Cholesky with 16-column panels:
-//   - wave 0 factors the panel (rows >= its first column) with lane = row and
-//     the panel's 16 columns in registers, wave-synchronously: for column j,
-//     d = a_jj (read from lane j), l_jj = sqrt(d), l_ij = a_ij / l_jj, and the
-//     panel columns right of j lose l_ij l_kj (l_kj read from lane k);
-//   - all waves subtract the panel's product from the trailing lower part.
-// Then the inverse, blockwise: each wave inverts one 16x16 diagonal block by
-// forward substitution (lane = column), and for block rows I = 1..3
-//   Linv[I][J] = -inv(L_II) sum_{J <= K < I} L[I][K] Linv[K][J].
-// L stays in the lower triangle of A; the strict lower part of L^{-1} is
-// kept transposed in the strict upper triangle (A[c][a] = Linv[a][c]) and
-// its diagonal in rdg.  A pivot that is not positive and finite lowers the
-// status word to its column.  L^{-1} is stored column-major:
-// Linv[blk][k * nb + i] = (L^{-1})_ik.
+// in LDS.  Blocked right-looking Cholesky with 16-column panels:
+//   - wave 0 factors the panel with lane = row and the panel's 16 columns in
+//     registers: for column j, d = a_jj (read from lane j), 1/l_jj from a
+//     reciprocal square root, l_ij = a_ij / l_jj, and the later panel
+//     columns k lose l_ij l_kj (l_kj read from lane k);
+//   - the four waves subtract the panel's product from the trailing lower
+//     part in 16x16 MFMA tiles.
+// Inverse: each wave inverts one 16x16 diagonal triangle by forward
+// substitution (lane = column; the diagonal of L^{-1} is the 1/l_jj of the
+// factorization), then the 2x2 block formula for a lower triangle,
+//   inv [L11 0; L21 L22] = [X11 0; -X22 L21 X11  X22],
+// on the 16-blocks inside each 32-block and then on the two 32-blocks, the
+// products on MFMA tiles.  L stays in the lower triangle of A; the strict
+// lower part of L^{-1} is kept transposed in the strict upper triangle
+// (A[c][a] = Linv[a][c]) and its diagonal in rdg.  A pivot that is not
+// positive and finite lowers the status word to its global column.
+// L^{-1} is stored column-major: Linv[ioff + k * nb + i] = (L^{-1})_ik.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T lane_read(T v, int src);
@@ -115,39 +125,37 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int32_t *super_ptr,
-                                               const int64_t *rptr, const int64_t *lptr,
-                                               const int64_t *inv_off, T *Lx, T *Linv,
+__global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T *Linv,
                                                unsigned long long *status, const int32_t *status_slot) {
     constexpr int NB = kNB, PW = 16;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
     __shared__ T A[NB][NB + 1];
     __shared__ T rdg[NB];
-    __shared__ T Tb[PW][NB + 1];
-    __shared__ int badcol;
+    __shared__ T Tf[32][33];
     const PanelTask tk = tasks[blockIdx.x];
-    const int s = tk.s;
-    const int64_t m = rptr[s + 1] - rptr[s];
+    const int64_t m = tk.m;
     const int c0 = tk.c0, nb = tk.c1 - tk.c0;
-    T *P = Lx + lptr[s];
+    T *P = Lx + tk.loff;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int npan = (nb + PW - 1) / PW, nbr = PW * npan;
     {
-        // issue every load before the first use (HBM latency is ~1-2 us)
         T ld[NB * NB / 256];
 #pragma unroll
         for (int q = 0; q < NB * NB / 256; ++q) {
             const int e = t + 256 * q, i = e % NB, k = e / NB;
-            ld[q] = (i < nb && k <= i) ? P[(int64_t)(c0 + k) * m + c0 + i] : (i == k ? T(1) : T(0));
+            const int ic = min(i, nb - 1), kc = min(k, ic);
+            ld[q] = P[(int64_t)(c0 + kc) * m + c0 + ic];
         }
 #pragma unroll
         for (int q = 0; q < NB * NB / 256; ++q) {
-            const int e = t + 256 * q;
-            A[e % NB][e / NB] = ld[q];
+            const int e = t + 256 * q, i = e % NB, k = e / NB;
+            A[i][k] = (i < nb && k <= i) ? ld[q] : (i == k ? T(1) : T(0));
         }
     }
-    if (t == 0) badcol = -1;
     __syncthreads();
-    const int npan = (nb + PW - 1) / PW;
+    int bad = -1;  // wave 0: first pivot (block column) that failed
     for (int pb = 0; pb < npan; ++pb) {
         const int p0 = PW * pb;
         if (wv == 0) {
@@ -159,8 +167,9 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
             for (int c = 0; c < PW; ++c) {
                 const int j = p0 + c;
                 const T d = lane_read(r[c], j);
-                if (i == 0 && j < nb && !finite_pos(d) && badcol < 0) badcol = j;
-                const T rs = rsqrt_nr(d);  // 1/sqrt(d)
+                if (bad < 0 && j < nb && !finite_pos(d)) bad = j;
+                const T rs = rsqrt_nr(d);
+                if (i == j) rdg[j] = rs;
                 const T lij = (i == j) ? d * rs : r[c] * rs;
                 r[c] = lij;
 #pragma unroll
@@ -172,21 +181,29 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
                     if (c <= i - p0) A[i][p0 + c] = r[c];
         }
         __syncthreads();
-        // trailing lower part: rows and columns >= p0 + PW
-        const int q0 = p0 + PW, rem = NB - q0;
-        for (int e = t; e < rem * rem; e += 256) {
-            const int i = q0 + e % rem, k = q0 + e / rem;
-            if (k > i) continue;
-            T acc = T(0);
+        // trailing lower part, rows and columns in [q0, nbr): 16x16 MFMA tiles
+        const int q0 = p0 + PW, nt = (nbr - q0) / 16, ntile = nt * (nt + 1) / 2;
+        for (int x = wv; x < ntile; x += 4) {
+            int ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+            const int tj = x - ti * (ti + 1) / 2;
+            const int i0 = q0 + 16 * ti, j0 = q0 + 16 * tj;
+            acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int c = 0; c < PW; ++c) acc += A[i][p0 + c] * A[k][p0 + c];
-            A[i][k] -= acc;
+            for (int kk = 0; kk < PW; kk += 4)
+                acc = M::run(A[i0 + (lane & 15)][p0 + kk + (lane >> 4)], A[j0 + (lane & 15)][p0 + kk + (lane >> 4)],
+                             acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = i0 + M::row(lane, v), c = j0 + (lane & 15);
+                if (r >= c) A[r][c] -= acc[v];
+            }
         }
         __syncthreads();
     }
-    if (t == 0 && badcol >= 0)
-        atomicMin(status + (status_slot ? status_slot[s] : 0), (unsigned long long)(super_ptr[s] + c0 + badcol));
-    // inverses of the 16x16 diagonal blocks: wave w, lane c -> column c
+    if (wv == 0 && lane == 0 && bad >= 0)
+        atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
+    // inverses of the 16x16 diagonal triangles: wave w, lane c -> column c
     {
         const int b0 = PW * wv;
         const int c = lane;
@@ -197,70 +214,69 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
                 T v = (a == c) ? T(1) : T(0);
 #pragma unroll
                 for (int k = 0; k < a; ++k) v -= A[b0 + a][b0 + k] * y[k];
-                y[a] = v / A[b0 + a][b0 + a];
+                y[a] = v * rdg[b0 + a];
             }
 #pragma unroll
-            for (int a = 0; a < PW; ++a) {
+            for (int a = 0; a < PW; ++a)
                 if (a > c) A[b0 + c][b0 + a] = y[a];
-                else if (a == c) rdg[b0 + a] = y[a];
-            }
         }
     }
     __syncthreads();
-    // off-diagonal blocks by the 2x2 block formula for a lower triangle,
-    // inv [L11 0; L21 L22] = [X11 0; -X22 L21 X11  X22]: first inside each
-    // 32-block (16-blocks), then for the 64-block (32-blocks).  INV(a, c)
-    // reads the inverse built so far from its transposed storage.
 #define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
-    T *Tf = &Tb[0][0];  // flat scratch, >= 1024 entries
+    if (nb > 16) {
+        // 16-blocks inside the 32-blocks: wave 0 the one at 0, wave 1 at 32
+        const int o = 32 * wv;
+        if (wv < 2) {
+            acc_t acc = {0, 0, 0, 0};  // L21 X11
 #pragma unroll
-    for (int lvl = 0; lvl < 2; ++lvl) {
-        const int h = lvl == 0 ? 16 : 32;
-        constexpr int NOUT = 4;                       // outputs per thread, at most
-        const int nout = lvl == 0 ? 2 : 4;            // 2 blocks x 16^2 or 1 x 32^2, over 256 threads
-        // Tf = L21 X11, h x h per block (row a, column b)
+            for (int kk = 0; kk < 16; kk += 4)
+                acc = M::run(A[o + 16 + (lane & 15)][o + kk + (lane >> 4)],
+                             SPC_INV(o + kk + (lane >> 4), o + (lane & 15)), acc);
 #pragma unroll
-        for (int q = 0; q < NOUT; ++q) {
-            if (q >= nout) break;
-            const int e = t + 256 * q;
-            const int o = (e / (h * h)) * 2 * h, rem = e % (h * h), a = rem % h, b = rem / h;
-            T acc = T(0);
-            for (int c = b; c < h; ++c) acc += A[o + h + a][o + c] * SPC_INV(o + c, o + b);
-            Tf[e] = acc;
+            for (int v = 0; v < 4; ++v) Tf[16 * wv + M::row(lane, v)][lane & 15] = acc[v];
         }
         __syncthreads();
-        // X21 = -X22 Tf, written transposed into the upper triangle
-        T out[NOUT];
+        if (wv < 2) {
+            acc_t acc = {0, 0, 0, 0};  // X22 (L21 X11)
 #pragma unroll
-        for (int q = 0; q < NOUT; ++q) {
-            out[q] = T(0);
-            if (q >= nout) break;
-            const int e = t + 256 * q;
-            const int base = (e / (h * h)) * h * h;
-            const int o = (e / (h * h)) * 2 * h, rem = e % (h * h), a = rem % h, b = rem / h;
-            T acc = T(0);
-            for (int c = 0; c <= a; ++c) acc += SPC_INV(o + h + a, o + h + c) * Tf[base + b * h + c];
-            out[q] = -acc;
-        }
+            for (int kk = 0; kk < 16; kk += 4)
+                acc = M::run(SPC_INV(o + 16 + (lane & 15), o + 16 + kk + (lane >> 4)),
+                             Tf[16 * wv + kk + (lane >> 4)][lane & 15], acc);
 #pragma unroll
-        for (int q = 0; q < NOUT; ++q) {
-            if (q >= nout) break;
-            const int e = t + 256 * q;
-            const int o = (e / (h * h)) * 2 * h, rem = e % (h * h), a = rem % h, b = rem / h;
-            A[o + b][o + h + a] = out[q];
+            for (int v = 0; v < 4; ++v) A[o + (lane & 15)][o + 16 + M::row(lane, v)] = -acc[v];
         }
         __syncthreads();
     }
-#undef SPC_INV
-    T *Vi = Linv + inv_off[tk.blk];
+    if (nb > 32) {
+        // the two 32-blocks; wave w computes 16x16 tile (w / 2, w % 2)
+        const int ti = wv >> 1, tj = wv & 1;
+        acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4)
+            acc = M::run(A[32 + 16 * ti + (lane & 15)][kk + (lane >> 4)],
+                         SPC_INV(kk + (lane >> 4), 16 * tj + (lane & 15)), acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tf[16 * ti + M::row(lane, v)][16 * tj + (lane & 15)] = acc[v];
+        __syncthreads();
+        acc = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4)
+            acc = M::run(SPC_INV(32 + 16 * ti + (lane & 15), 32 + kk + (lane >> 4)),
+                         Tf[kk + (lane >> 4)][16 * tj + (lane & 15)], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[16 * tj + (lane & 15)][32 + 16 * ti + M::row(lane, v)] = -acc[v];
+        __syncthreads();
+    }
+    T *Vi = Linv + tk.ioff;
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
         const int e = t + 256 * q, i = e % NB, k = e / NB;
         if (i < nb && k < nb) {
             if (k <= i) P[(int64_t)(c0 + k) * m + c0 + i] = A[i][k];
-            Vi[k * nb + i] = (k < i) ? A[k][i] : (k == i ? rdg[i] : T(0));
+            Vi[k * nb + i] = SPC_INV(i, k);
         }
     }
+#undef SPC_INV
 }
 
 // ---------------------------------------------------------------------------
@@ -271,28 +287,39 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, const int
 //      (POTRF of the diagonal block and TRSM of the rows below at once);
 //   2. the inverse of the diagonal triangle, one column per thread by
 //      forward substitution (kept for the solves);
-//   3. the Schur update C = P P^T of the rows below the block, scatter-added
-//      into the ancestors through the relative indices, as in k_tiles.
+//   3. the update C = P P^T of the rows below the block, scatter-added into
+//      the ancestors: C[i][k] goes to cbase[k] + rel[crel[k] + i].
 // Pivots that are not positive and finite lower the status word.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_small(const int32_t *snodes, const int32_t *super_ptr,
-                                               const int64_t *rptr, const int64_t *lptr, const int32_t *rows,
-                                               const int32_t *colpair, const UpdatePair *pairs,
-                                               const int32_t *rel, const int32_t *first_blk,
-                                               const int64_t *inv_off, T *Lx, T *Linv,
-                                               unsigned long long *status, const int32_t *status_slot) {
-    constexpr int MS = kSmallM, WS = kSmallW;
+__global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int64_t *cbase, const int64_t *crel,
+                                               const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
+                                               const int32_t *status_slot) {
+    constexpr int MS = kSmallM, WS = kSmallW, LPT = WS * MS / 256, SB = 8;
     __shared__ T A[WS][MS + 1];   // A[c][i] = panel entry (row i, column c)
     __shared__ T Vt[WS][WS + 1];  // inverse, Vt[c][a] = (L^{-1})_ac
-    const int s = snodes[blockIdx.x];
-    const int64_t m = rptr[s + 1] - rptr[s];
-    const int w = super_ptr[s + 1] - super_ptr[s];
-    T *P = Lx + lptr[s];
+    __shared__ int64_t cb[MS], cr[MS];
+    const SmallTask tk = tasks[blockIdx.x];
+    const int m = tk.m, w = tk.w;
+    T *P = Lx + tk.loff;
     const int tid = threadIdx.x;
-    for (int e = tid; e < w * MS; e += 256) {
-        const int i = e % MS, c = e / MS;
-        A[c][i] = (i < m) ? P[(int64_t)c * m + i] : T(0);
+    {
+        T ld[LPT];
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int e = tid + 256 * q, i = e % MS, c = e / MS;
+            ld[q] = P[(int64_t)min(c, w - 1) * m + min(i, m - 1)];
+        }
+        if (tid < MS) {
+            const int64_t k = tk.roff + min(max(tid, w), m - 1);
+            cb[tid] = cbase[k];
+            cr[tid] = crel[k];
+        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int e = tid + 256 * q, i = e % MS, c = e / MS;
+            A[c][i] = (i < m && c < w) ? ld[q] : T(0);
+        }
     }
     __syncthreads();
     int bad = -1;
@@ -311,8 +338,7 @@ __global__ __launch_bounds__(256) void k_small(const int32_t *snodes, const int3
         __syncthreads();
     }
     if (tid == 0 && bad >= 0)
-        atomicMin(status + (status_slot ? status_slot[s] : 0), (unsigned long long)(super_ptr[s] + bad));
-    // write the panel back (lower part of the diagonal block, all rows below)
+        atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
     for (int e = tid; e < w * MS; e += 256) {
         const int i = e % MS, c = e / MS;
         if (i < m && i >= c) P[(int64_t)c * m + i] = A[c][i];
@@ -327,54 +353,60 @@ __global__ __launch_bounds__(256) void k_small(const int32_t *snodes, const int3
         }
     }
     __syncthreads();
-    T *Vi = Linv + inv_off[first_blk[s]];
+    T *Vi = Linv + tk.ioff;
     for (int e = tid; e < w * w; e += 256) Vi[e] = Vt[e / w][e % w];
-    // Schur update of the rows below, scatter-added into the ancestors
-    const int mb = (int)m - w;
-    for (int e = tid; e < mb * mb; e += 256) {
-        const int r = w + e % mb, cc = w + e / mb;  // row r, column cc (positions in R_s)
-        if (cc > r) continue;
-        T acc = T(0);
-        for (int k = 0; k < w; ++k) acc += A[k][r] * A[k][cc];
-        const UpdatePair pr = pairs[colpair[rptr[s] + cc]];
-        const int t = pr.target;
-        const int64_t mt = rptr[t + 1] - rptr[t];
-        const int64_t colt = rows[rptr[s] + cc] - super_ptr[t];
-        const int64_t rowt = rel[pr.rel_off + (r - pr.i0)];
-        atomicAdd(&Lx[lptr[t] + colt * mt + rowt], -acc);
+    // update of the rows below, scatter-added into the ancestors
+    const int mb = m - w, ne = mb * mb;
+    for (int e0 = 0; e0 < ne; e0 += 256 * SB) {
+        int32_t rr[SB];
+        int cc_[SB];
+        T vv[SB];
+        bool ok[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int e = e0 + tid + 256 * u;
+            const int r = w + e % mb, cc = w + e / mb;  // row, column (positions in R_s)
+            ok[u] = e < ne && cc <= r;
+            const int rc = ok[u] ? r : w, ccc = ok[u] ? cc : w;
+            cc_[u] = ccc;
+            rr[u] = rel[cr[ccc] + rc];
+            T acc = T(0);
+            for (int k = 0; k < w; ++k) acc += A[k][rc] * A[k][ccc];
+            vv[u] = acc;
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u)
+            if (ok[u]) atomicAdd(&Lx[cb[cc_[u]] + rr[u]], -vv[u]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// MFMA tiles.  Task (s, i0, j0, k0, k1, jmax, blk):
-//   C[r][c] = sum_{k0 <= k < k1} P[i0 + r][k] * Q[c][k]
-// over a 64x64 tile, 256 threads = 4 waves in a 2x2 grid of 32x32, each a
-// 2x2 set of 16x16x4 MFMA blocks; K staged through LDS 16 at a time.
-//   MODE_TRAILING: Q = P rows j0.. ; P[i][j] -= C for i >= j, j < jmax.
-//   MODE_SCATTER:  Q = P rows j0.. ; C (i >= j) scatter-added atomically into
-//                  the ancestors: column rows[j] of target t (pair of j), row
-//                  position rel[...] of R_t.
-//   MODE_TRSM:     Q = inverse of block blk, Q[c][k'] stored at k' * nb + c;
-//                  P[i][k0 + c] = C
+// MFMA tiles.  One workgroup (4 waves) computes a 64x64 tile C = A B^T,
+// each wave a 2x2 set of 16x16x4 MFMA blocks; K staged through LDS 16 at a
+// time, the next chunk loaded into registers while the current one is used.
+//   MODE_TRAILING: A, B = panel rows i0.., j0..; P[i][j] -= C for i >= j,
+//                  j < jmax.
+//   MODE_SCATTER:  A, B = panel rows i0.., j0..; C (i >= j) scatter-added
+//                  atomically into the ancestors: C[i][j] goes to
+//                  cbase[j] + rel[crel[j] + i].
+//   MODE_TRSM:     B = inverse of block blk (at aux), stored as
+//                  Q[k' * nb + c] = (L^{-1})_{c k'}; P[i][k0 + c] = C
 //                  (rows times the transposed inverse: X = B L^{-T}).
 // ---------------------------------------------------------------------------
 enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int32_t *super_ptr,
-                                               const int64_t *rptr, const int64_t *lptr,
-                                               const int32_t *rows, const int32_t *colpair,
-                                               const UpdatePair *pairs, const int32_t *rel,
-                                               const T *Linv, const int64_t *inv_off, T *Lx) {
-    constexpr int TM = kTile, KB = 16;
+__global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
+                                               const int32_t *rel, const T *Linv, T *Lx) {
+    constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T As[KB][TM + 4];
     __shared__ T Bs[KB][TM + 4];
     __shared__ T Cs[TM][TM + 1];
+    __shared__ int64_t cb[TM], cr[TM];
     const TileTask tk = tasks[blockIdx.x];
-    const int s = tk.s;
-    const int64_t m = rptr[s + 1] - rptr[s];
-    T *P = Lx + lptr[s];
+    const int64_t m = tk.m;
+    T *P = Lx + tk.loff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     acc_t acc[2][2];
@@ -384,23 +416,38 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int3
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     const int lr = tid & 63, lk = tid >> 6;
-    const bool row_ok = tk.i0 + lr < m;
-    const bool col_ok = tk.j0 + lr < tk.jmax;
     const int kw = tk.k1 - tk.k0;
-    const T *Q = (MODE == MODE_TRSM) ? Linv + inv_off[tk.blk] : nullptr;
+    const bool row_ok = tk.i0 + lr < m;
+    const bool col_ok = (MODE == MODE_TRSM) ? lr < kw : tk.j0 + lr < tk.jmax;
+    const T *pa = P + min<int64_t>(tk.i0 + lr, m - 1);
+    const T *pb = (MODE == MODE_TRSM) ? Linv + tk.aux + min(lr, kw - 1) : P + min(tk.j0 + lr, tk.jmax - 1);
+    const int64_t ldb = (MODE == MODE_TRSM) ? kw : m;
+    const int kofs = (MODE == MODE_TRSM) ? tk.k0 : 0;
+    if (MODE == MODE_SCATTER && tid < TM) {
+        const int64_t k = tk.aux + min(tk.j0 + tid, tk.jmax - 1);
+        cb[tid] = cbase[k];
+        cr[tid] = crel[k];
+    }
+    T ra[KB / 4], rb[KB / 4];
+    auto load = [&](int kb) {
+#pragma unroll
+        for (int e = 0; e < KB / 4; ++e) {
+            const int k = min(kb + lk + 4 * e, tk.k1 - 1);
+            ra[e] = pa[(int64_t)k * m];
+            rb[e] = pb[(int64_t)(k - kofs) * ldb];
+        }
+    };
+    load(tk.k0);
     for (int kb = tk.k0; kb < tk.k1; kb += KB) {
 #pragma unroll
         for (int e = 0; e < KB / 4; ++e) {
             const int kk = lk + 4 * e;
-            const int k = kb + kk;
-            const bool kin = k < tk.k1;
-            As[kk][lr] = (kin && row_ok) ? P[(int64_t)k * m + tk.i0 + lr] : T(0);
-            if (MODE == MODE_TRSM)
-                Bs[kk][lr] = (kin && col_ok) ? Q[(k - tk.k0) * kw + lr] : T(0);
-            else
-                Bs[kk][lr] = (kin && col_ok) ? P[(int64_t)k * m + tk.j0 + lr] : T(0);
+            const bool kin = kb + kk < tk.k1;
+            As[kk][lr] = (kin && row_ok) ? ra[e] : T(0);
+            Bs[kk][lr] = (kin && col_ok) ? rb[e] : T(0);
         }
         __syncthreads();
+        if (kb + KB < tk.k1) load(kb + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
             T af[2], bf[2];
@@ -415,37 +462,50 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int3
         }
         __syncthreads();
     }
+    // epilogue: thread = row r, columns cg*16 .. cg*16+15
+    const int r = tid & 63, cg = tid >> 6;
+    const int64_t gi = tk.i0 + r;
+    T old[CPT];
+    int32_t rv[CPT];
+    if (MODE == MODE_TRAILING) {
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
+            old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+        }
+    }
+    if (MODE == MODE_SCATTER) {
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int c = cg * CPT + cc;
+            const int64_t gj = min(tk.j0 + c, tk.jmax - 1);
+            rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = wr + a * 16 + Mfma<T>::row(lane, v);
+                const int rr = wr + a * 16 + Mfma<T>::row(lane, v);
                 const int c = wc + b * 16 + (lane & 15);
-                Cs[c][r] = acc[a][b][v];
+                Cs[c][rr] = acc[a][b][v];
             }
     __syncthreads();
-    const int r = tid & 63, cg = tid >> 6;
-    const int gi = tk.i0 + r;
     if (gi >= m) return;
-    for (int cc = 0; cc < 16; ++cc) {
-        const int c = cg * 16 + cc;
-        const int gj = tk.j0 + c;
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+        const int c = cg * CPT + cc;
+        const int64_t gj = tk.j0 + c;
         if (gj >= tk.jmax) continue;
         const T v = Cs[c][r];
         if (MODE == MODE_TRSM) {
-            P[(int64_t)gj * m + gi] = v;
+            P[gj * m + gi] = v;
         } else if (MODE == MODE_TRAILING) {
-            if (gj <= gi) P[(int64_t)gj * m + gi] -= v;
+            if (gj <= gi) P[gj * m + gi] = old[cc] - v;
         } else {
-            if (gj > gi) continue;
-            const UpdatePair pr = pairs[colpair[rptr[s] + gj]];
-            const int t = pr.target;
-            const int64_t mt = rptr[t + 1] - rptr[t];
-            const int64_t colt = rows[rptr[s] + gj] - super_ptr[t];
-            const int64_t rowt = rel[pr.rel_off + (gi - pr.i0)];
-            atomicAdd(&Lx[lptr[t] + colt * mt + rowt], -v);
+            if (gj <= gi) atomicAdd(&Lx[cb[c] + rv[cc]], -v);
         }
     }
 }
@@ -454,23 +514,21 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int3
 // k_tiles128: the trailing and scatter updates on 128x128 tiles for the
 // large supernodes.  4 waves in a 2x2 grid of 64x64 quadrants, each a 4x4
 // set of 16x16x4 MFMA blocks; K staged through LDS 16 at a time with the
-// next chunk prefetched into registers while the current one is consumed.
-// The epilogue goes through LDS in four passes of 32 columns.
+// next chunk in registers while the current one is consumed.  The epilogue
+// goes through LDS in four passes of 32 columns.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const int32_t *super_ptr,
-                                                  const int64_t *rptr, const int64_t *lptr,
-                                                  const int32_t *rows, const int32_t *colpair,
-                                                  const UpdatePair *pairs, const int32_t *rel, T *Lx) {
-    constexpr int TM = 128, KB = 16, PADA = 4;
+__global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
+                                                  const int32_t *rel, T *Lx) {
+    constexpr int TM = 128, KB = 16, PADA = 4, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T smem[2 * KB * (TM + PADA)];
+    __shared__ int64_t cb[TM], cr[TM];
     T(*As)[TM + PADA] = reinterpret_cast<T(*)[TM + PADA]>(smem);
     T(*Bs)[TM + PADA] = reinterpret_cast<T(*)[TM + PADA]>(smem + KB * (TM + PADA));
     const TileTask tk = tasks[blockIdx.x];
-    const int s = tk.s;
-    const int64_t m = rptr[s + 1] - rptr[s];
-    T *P = Lx + lptr[s];
+    const int64_t m = tk.m;
+    T *P = Lx + tk.loff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     acc_t acc[4][4];
@@ -482,24 +540,29 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     const int lr = tid & 127, lk = tid >> 7;
     const bool row_ok = tk.i0 + lr < m;
     const bool col_ok = tk.j0 + lr < tk.jmax;
-    const T *pa = P + tk.i0 + lr;
-    const T *pb = P + tk.j0 + lr;
+    const T *pa = P + min<int64_t>(tk.i0 + lr, m - 1);
+    const T *pb = P + min(tk.j0 + lr, tk.jmax - 1);
+    if (MODE == MODE_SCATTER && tid < TM) {
+        const int64_t k = tk.aux + min(tk.j0 + tid, tk.jmax - 1);
+        cb[tid] = cbase[k];
+        cr[tid] = crel[k];
+    }
     T ra[KB / 2], rb[KB / 2];
     auto load = [&](int kb) {
 #pragma unroll
         for (int e = 0; e < KB / 2; ++e) {
-            const int k = kb + lk + 2 * e;
-            const bool kin = k < tk.k1;
-            ra[e] = (kin && row_ok) ? pa[(int64_t)k * m] : T(0);
-            rb[e] = (kin && col_ok) ? pb[(int64_t)k * m] : T(0);
+            const int64_t k = min(kb + lk + 2 * e, tk.k1 - 1);
+            ra[e] = pa[k * m];
+            rb[e] = pb[k * m];
         }
     };
     load(tk.k0);
     for (int kb = tk.k0; kb < tk.k1; kb += KB) {
 #pragma unroll
         for (int e = 0; e < KB / 2; ++e) {
-            As[lk + 2 * e][lr] = ra[e];
-            Bs[lk + 2 * e][lr] = rb[e];
+            const bool kin = kb + lk + 2 * e < tk.k1;
+            As[lk + 2 * e][lr] = (kin && row_ok) ? ra[e] : T(0);
+            Bs[lk + 2 * e][lr] = (kin && col_ok) ? rb[e] : T(0);
         }
         __syncthreads();
         if (kb + KB < tk.k1) load(kb + KB);
@@ -520,9 +583,18 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     // epilogue: 4 passes of 32 columns staged as Cs[32][128 + 1]
     T(*Cs)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
     const int r = tid & 127, ch = tid >> 7;  // row, column half of the pass
-    const int gi = tk.i0 + r;
+    const int64_t gi = tk.i0 + r;
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
+        T old[CPT];
+        int32_t rv[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int c = 32 * pass + ch * CPT + cc;
+            const int64_t gj = min(tk.j0 + c, tk.jmax - 1);
+            if (MODE == MODE_TRAILING) old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+            else rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
+        }
         // the waves holding columns [32 pass, 32 pass + 32) stage them
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -535,21 +607,14 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
             }
         __syncthreads();
         if (gi < m) {
-            for (int cc = 0; cc < 16; ++cc) {
-                const int c = 32 * pass + ch * 16 + cc;
-                const int gj = tk.j0 + c;
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) {
+                const int c = 32 * pass + ch * CPT + cc;
+                const int64_t gj = tk.j0 + c;
                 if (gj >= tk.jmax || gj > gi) continue;
                 const T v = Cs[c & 31][r];
-                if (MODE == MODE_TRAILING) {
-                    P[(int64_t)gj * m + gi] -= v;
-                } else {
-                    const UpdatePair pr = pairs[colpair[rptr[s] + gj]];
-                    const int t = pr.target;
-                    const int64_t mt = rptr[t + 1] - rptr[t];
-                    const int64_t colt = rows[rptr[s] + gj] - super_ptr[t];
-                    const int64_t rowt = rel[pr.rel_off + (gi - pr.i0)];
-                    atomicAdd(&Lx[lptr[t] + colt * mt + rowt], -v);
-                }
+                if (MODE == MODE_TRAILING) P[gj * m + gi] = old[cc] - v;
+                else atomicAdd(&Lx[cb[c] + rv[cc]], -v);
             }
         }
         __syncthreads();
@@ -585,36 +650,102 @@ __global__ void k_perm_out(const int32_t *perm, int64_t n, int nrhs, const T *W,
 
 constexpr int kMaxRhs = 16;
 
+// Forward, one task = rows r0..r1-1 below block q:
+//   x_q = Linv_q y_q (every task; the first task stores it in X), then
+//   Y[rows[r]] -= sum_k L[r][c0+k] x_q[k] (atomic).
+// One right-hand side: thread = row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, const SolveBlock *blocks,
-                                                   const int32_t *super_ptr, const int64_t *rptr,
-                                                   const int64_t *lptr, const int32_t *rows, const T *Lx,
-                                                   const T *Linv, const int64_t *inv_off, T *Y, T *X,
-                                                   int64_t n, int nrhs) {
-    constexpr int NB = kNB;
+__global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, const int32_t *rows, const T *Lx,
+                                                   const T *Linv, T *Y, T *X, int64_t n) {
+    constexpr int NB = kNB, QPT = NB * NB / 256;
     __shared__ T Vi[NB][NB + 1];
-    __shared__ T yq[NB][kMaxRhs];
-    __shared__ T xq[NB][kMaxRhs];
+    __shared__ T yq[NB];
+    __shared__ T xq[NB];
     const SolveTask tk = tasks[blockIdx.x];
-    const SolveBlock B = blocks[tk.blk];
-    const int64_t m = rptr[B.s + 1] - rptr[B.s];
-    const int nb = B.c1 - B.c0;
-    const T *P = Lx + lptr[B.s];
-    const int32_t *R = rows + rptr[B.s];
-    const int64_t g0 = super_ptr[B.s] + B.c0;
-    const T *Q = Linv + inv_off[tk.blk];
+    const int nb = tk.nb;
+    const int64_t m = tk.m;
+    const T *P = Lx + tk.loff;
+    const T *Q = Linv + tk.ioff;
     const int tid = threadIdx.x;
-    // inverse (column-major nb x nb) and the block's right-hand sides
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e % nb, c = e / nb;
-        Vi[i][c] = Q[e];
+    const int64_t r = tk.r0 + tid;
+    const int64_t rc = min(r, m - 1);
+    T qv[QPT], pv[NB];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+    const T yv = Y[tk.g0 + min(tid, nb - 1)];
+    const int64_t gr = rows[tk.roff + rc];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pv[k] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + rc];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
     }
-    for (int e = tid; e < NB * kMaxRhs; e += 256) {
-        const int i = e % NB, q = e / NB;
-        yq[i][q] = (i < nb && q < nrhs) ? Y[g0 + i + (int64_t)q * n] : T(0);
+    if (tid < NB) yq[tid] = tid < nb ? yv : T(0);
+    __syncthreads();
+    if (tid < NB) {
+        T a = T(0);
+        if (tid < nb)
+            for (int c = 0; c <= tid; ++c) a += Vi[tid][c] * yq[c];
+        xq[tid] = a;
+        if (tk.first && tid < nb) X[tk.g0 + tid] = a;
     }
     __syncthreads();
-    for (int e = tid; e < NB * kMaxRhs; e += 256) {
+    if (r >= tk.r1) return;
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc += (k < nb ? pv[k] : T(0)) * xq[k];
+    atomicAdd(&Y[gr], -acc);
+}
+
+// Several right-hand sides (up to kMaxRhs): the update of the task's rows
+// is the product (rows x 64) (64 x 16) on 16x16x4 MFMA blocks, wave w
+// taking rows 64 w .. 64 w + 63; the A operand comes straight from the
+// panel, the B operand (x_q) from LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, const int32_t *rows,
+                                                         const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
+                                                         int nrhs) {
+    constexpr int NB = kNB, NR = kMaxRhs, QPT = NB * NB / 256, YPT = NB * NR / 256, KS = NB / 4;
+    using acc_t = typename Mfma<T>::acc;
+    __shared__ T Vi[NB][NB + 1];
+    __shared__ T yq[NB][NR + 1];
+    __shared__ T xq[NB][NR + 1];
+    __shared__ int64_t grs[256];
+    const SolveTask tk = tasks[blockIdx.x];
+    const int nb = tk.nb;
+    const int64_t m = tk.m;
+    const T *P = Lx + tk.loff;
+    const T *Q = Linv + tk.ioff;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T qv[QPT], yv[YPT], av[4][KS];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) {
+        const int e = tid + 256 * u, i = e % NB, q = e / NB;
+        yv[u] = Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
+    }
+    grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t row = min<int64_t>(tk.r0 + 64 * wave + 16 * t + (lane & 15), m - 1);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            av[t][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
+    }
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) {
+        const int e = tid + 256 * u, i = e % NB, q = e / NB;
+        yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NR; e += 256) {
         const int i = e % NB, q = e / NB;
         T a = T(0);
         if (i < nb)
@@ -622,113 +753,121 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, const
         xq[i][q] = a;
     }
     __syncthreads();
-    if (tk.r0 == B.c1)
+    if (tk.first)
         for (int e = tid; e < nb * nrhs; e += 256) {
             const int i = e % nb, q = e / nb;
-            X[g0 + i + (int64_t)q * n] = xq[i][q];
+            X[tk.g0 + i + (int64_t)q * n] = xq[i][q];
         }
-    for (int r = tk.r0 + tid; r < tk.r1; r += 256) {
-        T acc[kMaxRhs];
+    // rows of x_q beyond nb are zero, so the clamped columns contribute nothing
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q) acc[q] = T(0);
-        for (int k = 0; k < nb; ++k) {
-            const T l = P[(int64_t)(B.c0 + k) * m + r];
+    for (int t = 0; t < 4; ++t) {
+        acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < kMaxRhs; ++q) acc[q] += l * xq[k][q];
+        for (int ks = 0; ks < KS; ++ks)
+            acc = Mfma<T>::run(av[t][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 64 * wave + 16 * t + Mfma<T>::row(lane, v), q = lane & 15;
+            if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] + (int64_t)q * n], -acc[v]);
         }
-        const int64_t gr = R[r];
-        for (int q = 0; q < nrhs; ++q) atomicAdd(&Y[gr + (int64_t)q * n], -acc[q]);
     }
 }
 
-// Backward.  A block with one task sums its rows locally and finishes the
-// block itself; a block split over several tasks adds the partial sums into
-// Acc, and the last task to arrive (block counter) finishes it.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, const SolveBlock *blocks,
-                                                   const int32_t *super_ptr, const int64_t *rptr,
-                                                   const int64_t *lptr, const int32_t *rows, const T *Lx,
-                                                   const T *Linv, const int64_t *inv_off, T *X, T *Acc,
-                                                   int32_t *counters, int64_t n, int nrhs) {
-    constexpr int NB = kNB;
-    __shared__ T Pt[64][NB + 1];  // row tile of P, later the block inverse
-    __shared__ T Yr[64][kMaxRhs + 1];
-    __shared__ T Sm[4][NB][kMaxRhs / 4 + 1];  // partial sums of the 4 row groups
+// Backward, one task = rows r0..r1-1 below block q: thread (k, g) sums
+// L[r][c0+k] X[rows[r]] over the rows r of group g (64 rows each); the four
+// groups are added through LDS.  A block with one task finishes itself:
+//   t = X_q - sum,  x_q = Linv_q^T t.
+// A block split over several tasks adds its sums into Acc, and the last
+// task to arrive (block counter) finishes it.  Rows below the block belong
+// to ancestors, whose x is final when the block's level runs.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, const int32_t *rows, const T *Lx,
+                                                   const T *Linv, T *X, T *Acc, int32_t *counters, int64_t n,
+                                                   int nrhs) {
+    constexpr int NB = kNB, QPT = NB * NB / 256, RG = 64;
+    constexpr int XR = 256 * (NR + 1), SM = 4 * NB * NR, VT = NB * (NB + 1);
+    constexpr int SH = XR > SM ? (XR > VT ? XR : VT) : (SM > VT ? SM : VT);
+    __shared__ T sh[SH];
+    __shared__ T tq[NB][NR];
     __shared__ int last;
+    T(*xr)[NR + 1] = reinterpret_cast<T(*)[NR + 1]>(sh);   // x of the task's rows
+    T(*Sm)[NB][NR] = reinterpret_cast<T(*)[NB][NR]>(sh);    // sums of the 4 groups
+    T(*Vt)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(sh);    // block inverse
     const SolveTask tk = tasks[blockIdx.x];
-    const SolveBlock B = blocks[tk.blk];
-    const int64_t m = rptr[B.s + 1] - rptr[B.s];
-    const int nb = B.c1 - B.c0;
-    const T *P = Lx + lptr[B.s];
-    const int32_t *R = rows + rptr[B.s];
-    const int64_t g0 = super_ptr[B.s] + B.c0;
-    const int tid = threadIdx.x;
-    const int k = tid & 63, qg = tid >> 6;
-    T acc[kMaxRhs / 4];
+    const int nb = tk.nb;
+    const int64_t m = tk.m;
+    const T *P = Lx + tk.loff;
+    const T *Q = Linv + tk.ioff;
+    const int tid = threadIdx.x, k = tid & 63, g = tid >> 6;
+    const int64_t rown = tk.r0 + tid;
+    const int64_t gr = rows[tk.roff + min(rown, m - 1)];
+    T qv[QPT], pv[RG];
 #pragma unroll
-    for (int q = 0; q < kMaxRhs / 4; ++q) acc[q] = T(0);
-    for (int rb = tk.r0; rb < tk.r1; rb += 64) {
-        const int nr = min(64, tk.r1 - rb);
-        for (int e = tid; e < nr * nb; e += 256) {
-            const int r = e % nr, c = e / nr;
-            Pt[r][c] = P[(int64_t)(B.c0 + c) * m + rb + r];
-        }
-        for (int e = tid; e < nr * nrhs; e += 256) {
-            const int r = e % nr, q = e / nr;
-            Yr[r][q] = X[(int64_t)R[rb + r] + (int64_t)q * n];
-        }
-        __syncthreads();
-        if (k < nb)
-            for (int r = 0; r < nr; ++r) {
-                const T l = Pt[r][k];
+    for (int u = 0; u < RG; ++u)
+        pv[u] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + min<int64_t>(tk.r0 + g * RG + u, m - 1)];
 #pragma unroll
-                for (int q = 0; q < kMaxRhs / 4; ++q)
-                    if (qg + 4 * q < nrhs) acc[q] += l * Yr[r][qg + 4 * q];
-            }
-        __syncthreads();
+    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+    T xv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) xv[q] = X[gr + (int64_t)min(q, nrhs - 1) * n];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
+    __syncthreads();
+    T acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        const T l = pv[u];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] += l * xr[g * RG + u][q];
     }
-    // Yr[i][q] <- t = X_q - (sum over rows below), for the block's columns
-    if (B.ntasks == 1) {
+    __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kMaxRhs / 4; ++q) Sm[qg][k][q] = acc[q];
-        __syncthreads();
+    for (int q = 0; q < NR; ++q) Sm[g][k][q] = acc[q];
+    __syncthreads();
+    for (int e = tid; e < NB * NR; e += 256) {
+        const int i = e % NB, q = e / NB;
+        tq[i][q] = Sm[0][i][q] + Sm[1][i][q] + Sm[2][i][q] + Sm[3][i][q];
+    }
+    __syncthreads();
+    if (tk.ntasks == 1) {
         for (int e = tid; e < nb * nrhs; e += 256) {
             const int i = e % nb, q = e / nb;
-            Yr[i][q] = X[g0 + i + (int64_t)q * n] - Sm[q % 4][i][q / 4];
+            tq[i][q] = X[tk.g0 + i + (int64_t)q * n] - tq[i][q];
         }
     } else {
-        if (tk.r1 > tk.r0 && k < nb)
-#pragma unroll
-            for (int q = 0; q < kMaxRhs / 4; ++q) {
-                const int qq = qg + 4 * q;
-                if (qq < nrhs) atomicAdd(&Acc[g0 + k + (int64_t)qq * n], acc[q]);
+        if (tk.r1 > tk.r0)
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int i = e % nb, q = e / nb;
+                atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
             }
         __threadfence();
         __syncthreads();
-        if (tid == 0) last = (atomicAdd(&counters[tk.blk], 1) == B.ntasks - 1);
+        if (tid == 0) last = (atomicAdd(&counters[tk.blk], 1) == tk.ntasks - 1);
         __syncthreads();
         if (!last) return;
         __threadfence();
         for (int e = tid; e < nb * nrhs; e += 256) {
             const int i = e % nb, q = e / nb;
-            const int64_t idx = g0 + i + (int64_t)q * n;
+            const int64_t idx = tk.g0 + i + (int64_t)q * n;
             const T a = __hip_atomic_exchange(&Acc[idx], T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            Yr[i][q] = X[idx] - a;
+            tq[i][q] = X[idx] - a;
         }
         if (tid == 0) counters[tk.blk] = 0;
     }
     // x_q = Linv^T t
-    const T *Q = Linv + inv_off[tk.blk];
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e % nb, c = e / nb;
-        Pt[i][c] = Q[e];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
     }
     __syncthreads();
     for (int e = tid; e < nb * nrhs; e += 256) {
         const int c = e % nb, q = e / nb;
         T a = T(0);
-        for (int i = c; i < nb; ++i) a += Pt[i][c] * Yr[i][q];
-        X[g0 + c + (int64_t)q * n] = a;
+        for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
+        X[tk.g0 + c + (int64_t)q * n] = a;
     }
 }
 
@@ -849,17 +988,16 @@ template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0,
-                       P.super_ptr, P.rptr, P.lptr, P.inv_off, Lx, Linv, status, P.status_slot);
+    hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0, Lx, Linv,
+                       status, P.status_slot);
 }
 
 template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_small<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.small_snodes + t0, P.super_ptr,
-                       P.rptr, P.lptr, P.rows, P.colpair, P.pairs, P.rel, P.first_blk, P.inv_off, Lx, Linv, status,
-                       P.status_slot);
+    hipLaunchKernelGGL(k_small<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.small_tasks + t0, P.cbase,
+                       P.crel, P.rel, Lx, Linv, status, P.status_slot);
 }
 
 template <typename T>
@@ -867,14 +1005,14 @@ void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, con
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
-        hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.super_ptr, P.rptr,
-                           P.lptr, P.rows, P.colpair, P.pairs, P.rel, Linv, P.inv_off, Lx);
+        hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
+                           Linv, Lx);
     else if (mode == kTilesScatter)
-        hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.super_ptr, P.rptr,
-                           P.lptr, P.rows, P.colpair, P.pairs, P.rel, Linv, P.inv_off, Lx);
+        hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
+                           Linv, Lx);
     else
-        hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.super_ptr, P.rptr,
-                           P.lptr, P.rows, P.colpair, P.pairs, P.rel, Linv, P.inv_off, Lx);
+        hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
+                           Linv, Lx);
 }
 
 template <typename T>
@@ -882,11 +1020,11 @@ void launch_tiles128(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, 
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
-        hipLaunchKernelGGL((k_tiles128<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles_big + t0, P.super_ptr,
-                           P.rptr, P.lptr, P.rows, P.colpair, P.pairs, P.rel, Lx);
+        hipLaunchKernelGGL((k_tiles128<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles_big + t0, P.cbase, P.crel,
+                           P.rel, Lx);
     else
-        hipLaunchKernelGGL((k_tiles128<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles_big + t0, P.super_ptr,
-                           P.rptr, P.lptr, P.rows, P.colpair, P.pairs, P.rel, Lx);
+        hipLaunchKernelGGL((k_tiles128<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles_big + t0, P.cbase, P.crel,
+                           P.rel, Lx);
 }
 
 template <typename T>
@@ -909,18 +1047,25 @@ template <typename T>
 void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
                       int64_t n, int nrhs, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_solve_fwd<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.stasks + t0, P.sblocks,
-                       P.super_ptr, P.rptr, P.lptr, P.rows, Lx, Linv, P.inv_off, Y, X, n, nrhs);
+    const dim3 g((unsigned)(t1 - t0)), b(256);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(k_solve_fwd<T>, g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, Y, X, n);
+    else
+        hipLaunchKernelGGL(k_solve_fwd_multi<T>, g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, Y, X, n, nrhs);
 }
 
 template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
                       int32_t *counters, int64_t n, int nrhs, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_solve_bwd<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.stasks + t0, P.sblocks,
-                       P.super_ptr, P.rptr, P.lptr, P.rows, Lx, Linv, P.inv_off, X, Acc, counters, n, nrhs);
+    const dim3 g((unsigned)(t1 - t0)), b(256);
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_solve_bwd<T, 1>), g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, X, Acc, counters,
+                           n, nrhs);
+    else
+        hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs>), g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, X, Acc,
+                           counters, n, nrhs);
 }
-
 
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
                  const double *X, const double *B, double *Y, int64_t n, int nrhs, int64_t ld, hipStream_t st) {

@@ -41,27 +41,44 @@ struct UpdatePair {
 // One output tile of a SYRK/GEMM update of supernode s: rows i0..i0+63 and
 // columns j0..j0+63 (positions in R_s) of P P^T with P the columns
 // k0..k1-1 of the panel.  A TRSM tile is rows i0..i0+63 of block `blk`
-// (columns k0..k1-1) multiplied by the transposed block inverse.
+// (columns k0..k1-1) multiplied by the transposed block inverse.  Every
+// task carries the offsets its kernel needs, so a launch reads its task
+// and then the data, with no further dependent lookups.
 struct TileTask {
+    int64_t loff;   // lptr[s]: the m x w panel
+    int64_t aux;    // update tiles: rptr[s] (row list); TRSM: inv_off[blk]
     int32_t s;
+    int32_t m;      // rows of the panel (leading dimension)
     int32_t i0;
     int32_t j0;
     int32_t k0;
     int32_t k1;
     int32_t jmax;   // columns j >= jmax are outside the update
     int32_t blk;    // TRSM tiles: block id
+};
+
+// POTRF of the block of columns c0..c1-1 (c0 a multiple of kNB) of
+// supernode s: factor the diagonal triangle and write its inverse at ioff.
+struct PanelTask {
+    int64_t loff;  // lptr[s]
+    int64_t ioff;  // inv_off[blk]
+    int32_t s;
+    int32_t m;
+    int32_t c0;
+    int32_t c1;
+    int32_t g0;    // global column of c0 (pivot reports)
     int32_t pad;
 };
 
-// POTRF of block b (columns c0..c1-1, c0 = b*kNB) of supernode s: factor
-// the diagonal triangle and write its inverse at inv_off[blk].
-struct PanelTask {
+// A whole small supernode (k_small): factor, invert, scatter its update.
+struct SmallTask {
+    int64_t loff;  // lptr[s]
+    int64_t roff;  // rptr[s]
+    int64_t ioff;  // inv_off of its single block
     int32_t s;
-    int32_t b;
-    int32_t c0;
-    int32_t c1;
-    int32_t blk;  // global block id (index into the block list)
-    int32_t pad;
+    int32_t m;
+    int32_t w;
+    int32_t g0;    // global column of its first column
 };
 
 // One column block of a supernode (solves and inverse store).
@@ -72,11 +89,20 @@ struct SolveBlock {
     int32_t ntasks;  // solve-update tasks of this block (>= 1)
 };
 
+// Rows r0..r1-1 (positions in R_s, r0 >= c1) below one column block.
 struct SolveTask {
-    int32_t blk;
+    int64_t loff;    // lptr[s]
+    int64_t roff;    // rptr[s]
+    int64_t ioff;    // inv_off[blk]
+    int64_t g0;      // global (permuted) index of the block's first column
+    int32_t m;
+    int32_t c0;
+    int32_t nb;      // block width
     int32_t r0;
     int32_t r1;
-    int32_t pad;
+    int32_t ntasks;  // tasks of the block
+    int32_t blk;
+    int32_t first;   // 1 for the block's first task
 };
 
 struct Symbolic {
@@ -113,8 +139,13 @@ struct Symbolic {
     std::vector<Step> steps;
     std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles (64)
     std::vector<int64_t> ext_big_ptr;      // [nlevels+1] external tiles (128)
-    std::vector<int64_t> small_ptr;        // [nlevels+1] into small_snodes
-    std::vector<int32_t> small_snodes;     // supernodes of the single-workgroup path
+    std::vector<int64_t> small_ptr;        // [nlevels+1] into small_tasks
+    std::vector<SmallTask> small_tasks;    // supernodes of the single-workgroup path
+    // Scatter addressing per row position k >= w_s of R_s (pair p of k,
+    // target t): cbase = lptr[t] + (rows[k] - first column of t) * m_t is
+    // column rows[k] of t's panel; crel = rel_off(p) - i0(p), so row
+    // position i >= k of R_s lands at cbase + rel[crel + i].
+    std::vector<int64_t> cbase, crel;
     std::vector<int32_t> first_blk;        // [nsuper+1] first column block
     std::vector<double> small_flops;       // [nlevels] flops of the small path
     std::vector<double> ext_flops;         // [nlevels] algorithmic flops per launch

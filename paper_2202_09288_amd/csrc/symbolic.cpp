@@ -353,6 +353,18 @@ int build_schedule(Symbolic &S) {
         }
         S.pair_ptr[s + 1] = (int64_t)S.pairs.size();
     }
+    S.cbase.assign(S.rptr[ns], 0);
+    S.crel.assign(S.rptr[ns], 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+        for (int64_t k = w; k < m; ++k) {
+            const UpdatePair &pr = S.pairs[S.colpair[S.rptr[s] + k]];
+            const int32_t t = pr.target;
+            S.cbase[S.rptr[s] + k] =
+                S.lptr[t] + (int64_t)(S.rows[S.rptr[s] + k] - S.super_ptr[t]) * (S.rptr[t + 1] - S.rptr[t]);
+            S.crel[S.rptr[s] + k] = pr.rel_off - pr.i0;
+        }
+    }
 
     // ---- column blocks and the inverse store ------------------------------
     std::vector<int32_t> first_blk(ns + 1, 0);
@@ -381,7 +393,7 @@ int build_schedule(Symbolic &S) {
     S.ext_tile_ptr.assign(S.nlevels + 1, 0);
     S.ext_big_ptr.assign(S.nlevels + 1, 0);
     S.small_ptr.assign(S.nlevels + 1, 0);
-    S.small_snodes.clear();
+    S.small_tasks.clear();
     S.small_flops.assign(S.nlevels, 0.0);
     auto is_small = [&](int32_t s) {
         return S.super_ptr[s + 1] - S.super_ptr[s] <= kSmallW && S.rptr[s + 1] - S.rptr[s] <= kSmallM;
@@ -390,7 +402,9 @@ int build_schedule(Symbolic &S) {
         std::vector<int32_t> big;
         for (int32_t s : bylevel[l]) {
             if (is_small(s)) {
-                S.small_snodes.push_back(s);
+                S.small_tasks.push_back(SmallTask{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s,
+                                                  (int32_t)(S.rptr[s + 1] - S.rptr[s]),
+                                                  S.super_ptr[s + 1] - S.super_ptr[s], S.super_ptr[s]});
                 // POTRF + TRSM + SYRK of the rows below (LAPACK counts)
                 const double w = S.super_ptr[s + 1] - S.super_ptr[s], m = (double)(S.rptr[s + 1] - S.rptr[s]);
                 S.small_flops[l] += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 + (m - w) * w * w +
@@ -399,7 +413,7 @@ int build_schedule(Symbolic &S) {
                 big.push_back(s);
             }
         }
-        S.small_ptr[l + 1] = (int64_t)S.small_snodes.size();
+        S.small_ptr[l + 1] = (int64_t)S.small_tasks.size();
         bylevel[l].swap(big);
     }
     for (int32_t l = 0; l < S.nlevels; ++l) {
@@ -429,10 +443,11 @@ int build_schedule(Symbolic &S) {
                                   (double)(m - c1) * nbd * nbd;
                 st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
                                      2.0 * (double)(m - w) * (double)(w - c1) * nbd;
-                S.potrf_tasks.push_back(PanelTask{s, (int32_t)b, (int32_t)c0, (int32_t)c1, blk, 0});
+                S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
+                                                  (int32_t)c1, (int32_t)(S.super_ptr[s] + c0), 0});
                 for (int64_t r = c1; r < m; r += kTile)
-                    S.trsm_tiles.push_back(TileTask{s, (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
-                                                    (int32_t)c1, blk, 0});
+                    S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r, (int32_t)c0,
+                                                    (int32_t)c0, (int32_t)c1, (int32_t)c1, blk});
                 // trailing update inside the panel: rows [c1, m), cols [c1, w)
                 // K is one block (<= 64) here: the small tiles do better
                 const bool big = false;
@@ -440,8 +455,8 @@ int build_schedule(Symbolic &S) {
                 for (int64_t j0 = c1; j0 < w; j0 += tsz)
                     for (int64_t i0 = j0; i0 < m; i0 += tsz)
                         (big ? S.int_tiles_big : S.int_tiles)
-                            .push_back(TileTask{s, (int32_t)i0, (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w,
-                                                -1, 0});
+                            .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0,
+                                                (int32_t)c0, (int32_t)c1, (int32_t)w, -1});
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
@@ -459,7 +474,8 @@ int build_schedule(Symbolic &S) {
             for (int64_t j0 = w; j0 < m; j0 += tsz)
                 for (int64_t i0 = j0; i0 < m; i0 += tsz)
                     (big ? S.ext_tiles_big : S.ext_tiles)
-                        .push_back(TileTask{s, (int32_t)i0, (int32_t)j0, 0, (int32_t)w, (int32_t)m, -1, 0});
+                        .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0, 0,
+                                            (int32_t)w, (int32_t)m, -1});
         }
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
         S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();
@@ -503,15 +519,29 @@ int build_schedule(Symbolic &S) {
             int32_t q = S.sblock_order[e];
             SolveBlock &B = S.sblocks[q];
             int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
+            const size_t first = S.stasks.size();
             int32_t cnt = 0;
             int64_t r = B.c1;
             do {
                 int64_t r1 = std::min<int64_t>(r + kSolveRows, m);
-                S.stasks.push_back(SolveTask{q, (int32_t)r, (int32_t)r1, 0});
+                SolveTask tk;
+                tk.loff = S.lptr[B.s];
+                tk.roff = S.rptr[B.s];
+                tk.ioff = S.inv_off[q];
+                tk.g0 = S.super_ptr[B.s] + B.c0;
+                tk.m = (int32_t)m;
+                tk.c0 = B.c0;
+                tk.nb = B.c1 - B.c0;
+                tk.r0 = (int32_t)r;
+                tk.r1 = (int32_t)r1;
+                tk.blk = q;
+                tk.first = cnt == 0;
+                S.stasks.push_back(tk);
                 ++cnt;
                 r = r1;
             } while (r < m);
             B.ntasks = cnt;
+            for (size_t e = first; e < S.stasks.size(); ++e) S.stasks[e].ntasks = cnt;
         }
         S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
     }
