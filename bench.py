@@ -56,8 +56,8 @@ def cpu_baseline(s, target_s):
     cc = S.colcount.astype(np.float64)
     sp = S.super_ptr
     lev = S.level
-    # estimate of the oracle's rate to size the sample (~2.5 GFLOP/s)
-    budget = target_s * 2.5e9
+    # estimate of the oracle's rate to size the sample (~10 GFLOP/s on one core)
+    budget = target_s * 1.0e10
     best = None
     for L in range(S.sizes["nlevels"] - 1, -1, -1):
         roots = np.nonzero(lev == L)[0]
@@ -155,16 +155,19 @@ def main():
             for key in p:
                 p[key] += v[key]
     F.set_profiling(False)
-    dom = max(prof, key=lambda n: prof[n]["ms"])
+    nprof = max(1, min(args.steps, 3))
+    dom = max((n for n in prof if n != "assemble"), key=lambda n: prof[n]["ms"])
     peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
     d = prof[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel_class": dom, "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None, "launches_per_step": d["launches"] // max(1, min(args.steps, 3)),
+    tname = "double" if args.precision == "fp64" else "float"
+    roofline = {"bound": "mfma", "kernel": spchol.KERNEL_NAMES[dom].format(t=tname),
+                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "launches_per_step": d["launches"] // nprof,
                 "avg_launch_ms": round(d["ms"] / max(1, d["launches"]), 4),
-                "classes_ms_per_step": {n: round(v["ms"] / max(1, min(args.steps, 3)), 3)
-                                        for n, v in prof.items()}}
+                "flops_per_launch": round(d["flops"] / max(1, d["launches"])),
+                "classes_ms_per_step": {n: round(v["ms"] / nprof, 3) for n, v in prof.items()}}
 
     fac_mean = float(fac_ms.mean())
     value = flops / (fac_mean * 1e-3) / 1e9

@@ -217,14 +217,18 @@ int spc_factor_export(spc_factor f, double *h_dst);
  * measured with events around its launches on its stream. */
 int spc_factor_last_ms(spc_factor f, float *ms);
 
-/* Kernel classes of the numeric phase, for spc_factor_kernel_stats. */
+/* Kernel classes of the numeric phase, for spc_factor_kernel_stats; each
+ * class is one kernel (the assemble class: the zero fill and the scatter
+ * of A), so per-launch figures of a class are those of its kernel. */
 enum spc_kernel_class {
     SPC_K_ASSEMBLE = 0,       /* zero the panels, scatter A into them */
-    SPC_K_PANEL = 1,          /* POTRF of a diagonal block + TRSM of the rows below */
-    SPC_K_TRAILING = 2,       /* SYRK/GEMM update inside a wide supernode */
-    SPC_K_SCATTER = 3,        /* SYRK/GEMM update scatter-added into ancestors */
-    SPC_K_SMALL = 4,          /* whole small supernodes: POTRF, TRSM, inverse, scatter */
-    SPC_K_COUNT = 5
+    SPC_K_POTRF = 1,          /* POTRF of 64-column diagonal blocks, with their inverses */
+    SPC_K_TRSM = 2,           /* rows below a block times its transposed inverse */
+    SPC_K_TRAILING = 3,       /* SYRK/GEMM update inside a wide supernode (64x64 tiles) */
+    SPC_K_SCATTER = 4,        /* SYRK/GEMM update scatter-added into ancestors, 64x64 tiles */
+    SPC_K_SCATTER_BIG = 5,    /* the same on 128x128 tiles (large supernodes) */
+    SPC_K_SMALL = 6,          /* whole small supernodes: POTRF, TRSM, inverse, scatter */
+    SPC_K_COUNT = 7
 };
 
 typedef struct spc_kernel_stats {

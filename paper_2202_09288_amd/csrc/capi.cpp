@@ -163,7 +163,6 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.trsm_tiles.data(), bytes_of(S.trsm_tiles), (const void **)&P.trsm_tiles},
         {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
-        {S.int_tiles_big.data(), bytes_of(S.int_tiles_big), (const void **)&P.int_tiles_big},
         {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
@@ -194,7 +193,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
            bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.trsm_tiles) +
-           bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.int_tiles_big) + bytes_of(S.ext_tiles_big) +
+           bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
            bytes_of(S.stasks) + bytes_of(S.status_slot);
 }
 
@@ -244,19 +243,21 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
             });
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
-            prof.run(SPC_K_PANEL, stp.panel_flops, [&] {
-                spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st);
-                spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, st);
-            });
-            if (stp.t1 > stp.t0 || stp.u1 > stp.u0)
-                prof.run(SPC_K_TRAILING, stp.trailing_flops, [&] {
-                    spc::launch_tiles128<T>(P, spc::kTilesTrailing, stp.u0, stp.u1, Lx, st);
-                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, st);
-                });
+            prof.run(SPC_K_POTRF, stp.potrf_flops,
+                     [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
+            if (stp.p1 > stp.p0)
+                prof.run(SPC_K_TRSM, stp.trsm_flops,
+                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, st); });
+            if (stp.t1 > stp.t0)
+                prof.run(SPC_K_TRAILING, stp.trailing_flops,
+                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, st); });
         }
-        if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l] || S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
+        if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
+            prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], [&] {
+                spc::launch_tiles128<T>(P, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, st);
+            });
+        if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], [&] {
-                spc::launch_tiles128<T>(P, spc::kTilesScatter, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, st);
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
                                      st);
             });

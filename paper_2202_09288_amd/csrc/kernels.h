@@ -20,7 +20,6 @@ struct DevPlan {
     const TileTask *trsm_tiles;
     const TileTask *int_tiles;
     const TileTask *ext_tiles;
-    const TileTask *int_tiles_big;
     const TileTask *ext_tiles_big;
     const SolveTask *stasks;
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
@@ -44,7 +43,7 @@ template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st);
 
 template <typename T>
-void launch_tiles128(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
 
 template <typename T>
 void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,

@@ -511,13 +511,13 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
 }
 
 // ---------------------------------------------------------------------------
-// k_tiles128: the trailing and scatter updates on 128x128 tiles for the
-// large supernodes.  4 waves in a 2x2 grid of 64x64 quadrants, each a 4x4
+// k_tiles128: the scatter update on 128x128 tiles for the large supernodes
+// (same operation as k_tiles in MODE_SCATTER).  4 waves in a 2x2 grid of 64x64 quadrants, each a 4x4
 // set of 16x16x4 MFMA blocks; K staged through LDS 16 at a time with the
 // next chunk in registers while the current one is consumed.  The epilogue
 // goes through LDS in four passes of 32 columns.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T>
 __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                   const int32_t *rel, T *Lx) {
     constexpr int TM = 128, KB = 16, PADA = 4, CPT = 16;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     const bool col_ok = tk.j0 + lr < tk.jmax;
     const T *pa = P + min<int64_t>(tk.i0 + lr, m - 1);
     const T *pb = P + min(tk.j0 + lr, tk.jmax - 1);
-    if (MODE == MODE_SCATTER && tid < TM) {
+    if (tid < TM) {
         const int64_t k = tk.aux + min(tk.j0 + tid, tk.jmax - 1);
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
@@ -586,14 +586,12 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     const int64_t gi = tk.i0 + r;
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
-        T old[CPT];
         int32_t rv[CPT];
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             const int c = 32 * pass + ch * CPT + cc;
             const int64_t gj = min(tk.j0 + c, tk.jmax - 1);
-            if (MODE == MODE_TRAILING) old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
-            else rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
+            rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
         }
         // the waves holding columns [32 pass, 32 pass + 32) stage them
 #pragma unroll
@@ -612,9 +610,7 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
                 const int c = 32 * pass + ch * CPT + cc;
                 const int64_t gj = tk.j0 + c;
                 if (gj >= tk.jmax || gj > gi) continue;
-                const T v = Cs[c & 31][r];
-                if (MODE == MODE_TRAILING) P[gj * m + gi] = old[cc] - v;
-                else atomicAdd(&Lx[cb[c] + rv[cc]], -v);
+                atomicAdd(&Lx[cb[c] + rv[cc]], -Cs[c & 31][r]);
             }
         }
         __syncthreads();
@@ -1016,15 +1012,10 @@ void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, con
 }
 
 template <typename T>
-void launch_tiles128(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, hipStream_t st) {
+void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st) {
     if (t1 <= t0) return;
-    const dim3 g((unsigned)(t1 - t0)), b(256);
-    if (mode == kTilesTrailing)
-        hipLaunchKernelGGL((k_tiles128<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles_big + t0, P.cbase, P.crel,
-                           P.rel, Lx);
-    else
-        hipLaunchKernelGGL((k_tiles128<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles_big + t0, P.cbase, P.crel,
-                           P.rel, Lx);
+    hipLaunchKernelGGL(k_tiles128<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st,
+                       P.ext_tiles_big + t0, P.cbase, P.crel, P.rel, Lx);
 }
 
 template <typename T>
@@ -1115,7 +1106,7 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, const T *, hipStream_t);     \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
-    template void launch_tiles128<T>(const DevPlan &, int, int64_t, int64_t, T *, hipStream_t);             \
+    template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \
                                     hipStream_t);                                                           \
     template void launch_perm_out<T>(const DevPlan &, int64_t, int, const T *, double *, int64_t,           \

@@ -132,8 +132,7 @@ struct Symbolic {
         int64_t f0, f1;   // POTRF tasks
         int64_t p0, p1;   // TRSM tiles
         int64_t t0, t1;   // internal trailing-update tiles (64)
-        int64_t u0, u1;   // internal trailing-update tiles (128)
-        double panel_flops, trailing_flops;  // algorithmic flops of the two launches
+        double potrf_flops, trsm_flops, trailing_flops;  // algorithmic flops of its launches
     };
     std::vector<int64_t> level_step_ptr;   // [nlevels+1]
     std::vector<Step> steps;
@@ -148,12 +147,12 @@ struct Symbolic {
     std::vector<int64_t> cbase, crel;
     std::vector<int32_t> first_blk;        // [nsuper+1] first column block
     std::vector<double> small_flops;       // [nlevels] flops of the small path
-    std::vector<double> ext_flops;         // [nlevels] algorithmic flops per launch
+    std::vector<double> ext_flops;         // [nlevels] flops of the 64-tile scatter launch
+    std::vector<double> ext_big_flops;     // [nlevels] flops of the 128-tile scatter launch
     std::vector<PanelTask> potrf_tasks;
     std::vector<TileTask> trsm_tiles;
     std::vector<TileTask> int_tiles;
     std::vector<TileTask> ext_tiles;
-    std::vector<TileTask> int_tiles_big;
     std::vector<TileTask> ext_tiles_big;
 
     // column blocks, their inverse-store offsets, and the solve schedule

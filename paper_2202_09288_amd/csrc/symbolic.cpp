@@ -315,9 +315,9 @@ int build_schedule(Symbolic &S) {
     S.trsm_tiles.clear();
     S.int_tiles.clear();
     S.ext_tiles.clear();
-    S.int_tiles_big.clear();
     S.ext_tiles_big.clear();
     S.ext_flops.clear();
+    S.ext_big_flops.clear();
     S.sblocks.clear();
     S.sblock_order.clear();
     S.first_blk.clear();
@@ -424,12 +424,12 @@ int build_schedule(Symbolic &S) {
         }
         for (int64_t b = 0; b < maxb; ++b) {
             Symbolic::Step st;
-            st.panel_flops = 0.0;
+            st.potrf_flops = 0.0;
+            st.trsm_flops = 0.0;
             st.trailing_flops = 0.0;
             st.f0 = (int64_t)S.potrf_tasks.size();
             st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
-            st.u0 = (int64_t)S.int_tiles_big.size();
             for (int32_t s : bylevel[l]) {
                 int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
                 int64_t c0 = b * kNB;
@@ -439,8 +439,8 @@ int build_schedule(Symbolic &S) {
                 // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                 // SYRK k n(n+1), GEMM 2 m n k
                 double nbd = (double)(c1 - c0);
-                st.panel_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0 +
-                                  (double)(m - c1) * nbd * nbd;
+                st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
+                st.trsm_flops += (double)(m - c1) * nbd * nbd;
                 st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
                                      2.0 * (double)(m - w) * (double)(w - c1) * nbd;
                 S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
@@ -448,28 +448,24 @@ int build_schedule(Symbolic &S) {
                 for (int64_t r = c1; r < m; r += kTile)
                     S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r, (int32_t)c0,
                                                     (int32_t)c0, (int32_t)c1, (int32_t)c1, blk});
-                // trailing update inside the panel: rows [c1, m), cols [c1, w)
-                // K is one block (<= 64) here: the small tiles do better
-                const bool big = false;
-                const int64_t tsz = kTile;
-                for (int64_t j0 = c1; j0 < w; j0 += tsz)
-                    for (int64_t i0 = j0; i0 < m; i0 += tsz)
-                        (big ? S.int_tiles_big : S.int_tiles)
-                            .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0,
-                                                (int32_t)c0, (int32_t)c1, (int32_t)w, -1});
+                // trailing update inside the panel: rows [c1, m), cols [c1, w);
+                // K is one block (<= 64), where 64x64 tiles do better than 128
+                for (int64_t j0 = c1; j0 < w; j0 += kTile)
+                    for (int64_t i0 = j0; i0 < m; i0 += kTile)
+                        S.int_tiles.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
+                                                       (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w, -1});
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
             st.t1 = (int64_t)S.int_tiles.size();
-            st.u1 = (int64_t)S.int_tiles_big.size();
             S.steps.push_back(st);
         }
         S.level_step_ptr[l + 1] = (int64_t)S.steps.size();
-        double ef = 0.0;
+        double ef = 0.0, efb = 0.0;
         for (int32_t s : bylevel[l]) {
             int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
-            ef += (double)(m - w) * (double)(m - w + 1) * (double)w;
             const bool big = m - w >= kBigMin && w >= kBigMinK;
+            (big ? efb : ef) += (double)(m - w) * (double)(m - w + 1) * (double)w;
             const int64_t tsz = big ? kTileBig : kTile;
             for (int64_t j0 = w; j0 < m; j0 += tsz)
                 for (int64_t i0 = j0; i0 < m; i0 += tsz)
@@ -480,6 +476,7 @@ int build_schedule(Symbolic &S) {
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
         S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();
         S.ext_flops.push_back(ef);
+        S.ext_big_flops.push_back(efb);
     }
 
     // ---- solve schedule: block-tree levels ---------------------------------
