@@ -8,6 +8,7 @@
 #include <atomic>
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -166,6 +167,10 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
+        {S.stgt_ptr.data(), bytes_of(S.stgt_ptr), (const void **)&P.stgt_ptr},
+        {S.stgt.data(), bytes_of(S.stgt), (const void **)&P.stgt},
+        {S.fdep.data(), bytes_of(S.fdep), (const void **)&P.fdep},
+        {S.bwd_order.data(), bytes_of(S.bwd_order), (const void **)&P.bwd_order},
     };
     size_t total = 0;
     for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
@@ -194,7 +199,8 @@ size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
            bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.trsm_tiles) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
-           bytes_of(S.stasks) + bytes_of(S.status_slot);
+           bytes_of(S.stasks) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
+           bytes_of(S.fdep) + bytes_of(S.bwd_order);
 }
 
 // Brackets one launch with a pair of events when profiling is on.
@@ -243,14 +249,15 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
             });
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
-            prof.run(SPC_K_POTRF, stp.potrf_flops,
-                     [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
+            if (stp.f1 > stp.f0)
+                prof.run(SPC_K_POTRF, stp.potrf_flops,
+                         [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
             if (stp.p1 > stp.p0)
                 prof.run(SPC_K_TRSM, stp.trsm_flops,
-                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, st); });
+                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, st); });
             if (stp.t1 > stp.t0)
                 prof.run(SPC_K_TRAILING, stp.trailing_flops,
-                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, st); });
+                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, st); });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
             prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], [&] {
@@ -259,23 +266,41 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     st);
+                                     status, st);
             });
     }
 }
 
 // Y holds the permuted right-hand sides on entry; X receives the solution.
+// sync points to kSolveSyncInts(blocks) words of workspace.  Each sweep runs
+// one launch per block-tree level.  SPC_SOLVE_PERSIST=1 in the environment
+// runs the narrow levels at the top (levels solve_split..) as one persistent
+// launch per sweep instead; on MI355X that measured slower (device-scope
+// fences cost more per hop than a launch), so it is off by default.
+bool solve_persistent() {
+    static const bool v = [] {
+        const char *e = std::getenv("SPC_SOLVE_PERSIST");
+        return e && e[0] == '1';
+    }();
+    return v;
+}
+
 template <typename T>
 void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, const T *Linv, T *Y, T *X,
-                   T *Acc, int32_t *counters, int nrhs, hipStream_t st) {
-    const int64_t n = S.n;
+                   T *Acc, int32_t *sync, int nrhs, hipStream_t st) {
+    const int64_t n = S.n, nb = (int64_t)S.sblocks.size(), nt = (int64_t)S.stasks.size();
+    const spc::SolveSync sy = spc::make_solve_sync(sync, nb);
     spc::launch_zero<T>(Acc, n * nrhs, st);
-    spc::launch_zero<int32_t>(counters, (int64_t)S.sblocks.size(), st);
-    for (int32_t l = 0; l < S.nslevels; ++l)
-        spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, st);
-    for (int32_t l = S.nslevels - 1; l >= 0; --l)
-        spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, counters, n, nrhs,
-                                 st);
+    spc::launch_solve_reset(P, nb, sy, st);
+    const int32_t split = solve_persistent() ? S.solve_split : S.nslevels;
+    for (int32_t l = 0; l < split; ++l)
+        spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, sy, false, st);
+    if (split < S.nslevels) {
+        spc::launch_solve_fwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, Y, X, n, nrhs, sy, true, st);
+        spc::launch_solve_bwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, X, Acc, n, nrhs, sy, true, st);
+    }
+    for (int32_t l = split - 1; l >= 0; --l)
+        spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, n, nrhs, sy, false, st);
 }
 
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
@@ -641,7 +666,8 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
     constexpr int kChunk = 16;
     const size_t vec = (size_t)S.n * kChunk * esz;
     const size_t cnt_off = (3 * vec + 255) & ~size_t(255);
-    int rc = ensure_bytes(&f->work, &f->work_bytes, cnt_off + sizeof(int32_t) * (S.sblocks.size() + 1));
+    int rc = ensure_bytes(&f->work, &f->work_bytes,
+                          cnt_off + sizeof(int32_t) * spc::kSolveSyncInts((int64_t)S.sblocks.size()));
     if (rc) return rc;
     char *base = (char *)f->work;
     int32_t *counters = (int32_t *)(base + cnt_off);

@@ -23,7 +23,25 @@ struct DevPlan {
     const TileTask *ext_tiles_big;
     const SolveTask *stasks;
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
+    const int64_t *stgt_ptr;     // persistent solves: target blocks per task
+    const int32_t *stgt;
+    const int32_t *fdep;         // forward contributions per block
+    const int32_t *bwd_order;    // task order of the backward sweep
 };
+
+// Device state of one persistent solve (in the caller's workspace):
+// kSolveSyncInts(nblocks) int32 words.
+struct SolveSync {
+    int32_t *dep;    // [nblocks] forward contributions still due
+    int32_t *done;   // [nblocks] 1 once x of the block is final (backward)
+    int32_t *cnt;    // [nblocks] backward tasks of the block that arrived
+    int32_t *queue;  // [2] work counters of the two sweeps
+    int32_t *err;    // [1] nonzero when a wait gave up
+};
+inline int64_t kSolveSyncInts(int64_t nblocks) { return 3 * nblocks + 4; }
+inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks) {
+    return SolveSync{base, base + nblocks, base + 2 * nblocks, base + 3 * nblocks, base + 3 * nblocks + 2};
+}
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
@@ -40,7 +58,8 @@ template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);
 template <typename T>
-void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st);
+void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                  hipStream_t st);
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
@@ -51,12 +70,17 @@ void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int6
 template <typename T>
 void launch_perm_out(const DevPlan &P, int64_t n, int nrhs, const T *W, double *B, int64_t ldb,
                      hipStream_t st);
+void launch_solve_reset(const DevPlan &P, int64_t nblocks, SolveSync sy, hipStream_t st);
+// Solve sweeps over tasks t0..t1-1 (one block-tree level), or, with
+// persist, over the tasks of levels solve_split.. in one persistent launch
+// (t0 = first task of that range, t1 = all tasks; needs launch_solve_reset
+// first).
 template <typename T>
 void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
-                      int64_t n, int nrhs, hipStream_t st);
+                      int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);
 template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
-                      int32_t *counters, int64_t n, int nrhs, hipStream_t st);
+                      int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);
 
 // refinement (FP64)
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,

@@ -17,6 +17,7 @@
 //   k_solve_fwd / k_solve_bwd   block-level forward / backward substitution
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "kernels.h"
@@ -124,37 +125,20 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
     return y * (1.5f - 0.5f * d * y * y);
 }
 
+// Factor the block in A (nb <= 64; rows and columns >= nb hold the identity,
+// the upper triangle is zero), write L into P (columns c0.., leading
+// dimension m, lower triangle only) and the inverse into Vi; a failed pivot
+// lowers *status to g0 + its column.  rdg: 64 entries, Tf: 32 x 33, both
+// LDS.  Called by all 256 threads of the workgroup.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T *Linv,
-                                               unsigned long long *status, const int32_t *status_slot) {
+__device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], int nb, T *P, int64_t m, int c0,
+                                          T *Vi, unsigned long long *status, int64_t g0) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
-    __shared__ T A[NB][NB + 1];
-    __shared__ T rdg[NB];
-    __shared__ T Tf[32][33];
-    const PanelTask tk = tasks[blockIdx.x];
-    const int64_t m = tk.m;
-    const int c0 = tk.c0, nb = tk.c1 - tk.c0;
-    T *P = Lx + tk.loff;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int npan = (nb + PW - 1) / PW, nbr = PW * npan;
-    {
-        T ld[NB * NB / 256];
-#pragma unroll
-        for (int q = 0; q < NB * NB / 256; ++q) {
-            const int e = t + 256 * q, i = e % NB, k = e / NB;
-            const int ic = min(i, nb - 1), kc = min(k, ic);
-            ld[q] = P[(int64_t)(c0 + kc) * m + c0 + ic];
-        }
-#pragma unroll
-        for (int q = 0; q < NB * NB / 256; ++q) {
-            const int e = t + 256 * q, i = e % NB, k = e / NB;
-            A[i][k] = (i < nb && k <= i) ? ld[q] : (i == k ? T(1) : T(0));
-        }
-    }
-    __syncthreads();
     int bad = -1;  // wave 0: first pivot (block column) that failed
     for (int pb = 0; pb < npan; ++pb) {
         const int p0 = PW * pb;
@@ -201,28 +185,32 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
         }
         __syncthreads();
     }
-    if (wv == 0 && lane == 0 && bad >= 0)
-        atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
-    // inverses of the 16x16 diagonal triangles: wave w, lane c -> column c
+    if (wv == 0 && lane == 0 && bad >= 0) atomicMin(status, (unsigned long long)(g0 + bad));
+#define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
+    // L^{-1} by the 2x2 block formula for a lower triangle,
+    //   inv [L11 0; L21 L22] = [X11 0; -X22 L21 X11  X22],
+    // from the diagonal (rdg = 1/l_jj) up: blocks of h = 1, 2, 4, 8 here, one
+    // element of X21 per thread; h = 16, 32 below on MFMA tiles.  X21 is kept
+    // transposed in the upper triangle, so every level reads finished data.
     {
-        const int b0 = PW * wv;
-        const int c = lane;
-        if (c < PW) {
-            T y[PW];
-#pragma unroll
-            for (int a = 0; a < PW; ++a) {
-                T v = (a == c) ? T(1) : T(0);
-#pragma unroll
-                for (int k = 0; k < a; ++k) v -= A[b0 + a][b0 + k] * y[k];
-                y[a] = v * rdg[b0 + a];
+        T *tf = &Tf[0][0];
+        for (int h = 1; h < 16; h <<= 1) {
+            const int nel = 32 * h;  // 64 / (2h) blocks of h x h
+            const int blk = t / (h * h), rem = t % (h * h), a = rem % h, b = rem / h, o = 2 * h * blk;
+            if (t < nel) {
+                T acc = T(0);  // (L21 X11)[a][b]
+                for (int c = b; c < h; ++c) acc += A[o + h + a][o + c] * SPC_INV(o + c, o + b);
+                tf[t] = acc;
             }
-#pragma unroll
-            for (int a = 0; a < PW; ++a)
-                if (a > c) A[b0 + c][b0 + a] = y[a];
+            __syncthreads();
+            T out = T(0);
+            if (t < nel)  // -(X22 (L21 X11))[a][b]
+                for (int c = 0; c <= a; ++c) out -= SPC_INV(o + h + a, o + h + c) * tf[blk * h * h + b * h + c];
+            __syncthreads();
+            if (t < nel) A[o + b][o + h + a] = out;
+            __syncthreads();
         }
     }
-    __syncthreads();
-#define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
     if (nb > 16) {
         // 16-blocks inside the 32-blocks: wave 0 the one at 0, wave 1 at 32
         const int o = 32 * wv;
@@ -267,7 +255,6 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
         for (int v = 0; v < 4; ++v) A[16 * tj + (lane & 15)][32 + 16 * ti + M::row(lane, v)] = -acc[v];
         __syncthreads();
     }
-    T *Vi = Linv + tk.ioff;
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
         const int e = t + 256 * q, i = e % NB, k = e / NB;
@@ -277,6 +264,36 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
         }
     }
 #undef SPC_INV
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T *Linv,
+                                               unsigned long long *status, const int32_t *status_slot) {
+    constexpr int NB = kNB;
+    __shared__ T A[NB][NB + 1];
+    __shared__ T rdg[NB];
+    __shared__ T Tf[32][33];
+    const PanelTask tk = tasks[blockIdx.x];
+    const int64_t m = tk.m;
+    const int c0 = tk.c0, nb = tk.c1 - tk.c0;
+    T *P = Lx + tk.loff;
+    const int t = threadIdx.x;
+    {
+        T ld[NB * NB / 256];
+#pragma unroll
+        for (int q = 0; q < NB * NB / 256; ++q) {
+            const int e = t + 256 * q, i = e % NB, k = e / NB;
+            const int ic = min(i, nb - 1), kc = min(k, ic);
+            ld[q] = P[(int64_t)(c0 + kc) * m + c0 + ic];
+        }
+#pragma unroll
+        for (int q = 0; q < NB * NB / 256; ++q) {
+            const int e = t + 256 * q, i = e % NB, k = e / NB;
+            A[i][k] = (i < nb && k <= i) ? ld[q] : (i == k ? T(1) : T(0));
+        }
+    }
+    __syncthreads();
+    potrf_lds<T>(A, rdg, Tf, nb, P, m, c0, Linv + tk.ioff, status + (status_slot ? status_slot[tk.s] : 0), tk.g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +414,8 @@ enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
-                                               const int32_t *rel, const T *Linv, T *Lx) {
+                                               const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
+                                               const int32_t *status_slot) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T As[KB][TM + 4];
@@ -428,26 +446,51 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
     }
-    T ra[KB / 4], rb[KB / 4];
+    // K chunks held in registers: all of K (<= 64) for TRSM and trailing
+    // tiles, so one round trip to memory covers the tile; one chunk ahead
+    // for the scatter tiles (K = w, unbounded)
+#ifndef SPC_TILE_PREFETCH_ALL
+#define SPC_TILE_PREFETCH_ALL 0
+#endif
+    constexpr int NCH = (MODE == MODE_SCATTER || !SPC_TILE_PREFETCH_ALL) ? 1 : kNB / KB;
+    T ra[NCH][KB / 4], rb[NCH][KB / 4];
     auto load = [&](int kb) {
 #pragma unroll
-        for (int e = 0; e < KB / 4; ++e) {
-            const int k = min(kb + lk + 4 * e, tk.k1 - 1);
-            ra[e] = pa[(int64_t)k * m];
-            rb[e] = pb[(int64_t)(k - kofs) * ldb];
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int e = 0; e < KB / 4; ++e) {
+                const int k = min(kb + KB * ch + lk + 4 * e, tk.k1 - 1);
+                ra[ch][e] = pa[(int64_t)k * m];
+                rb[ch][e] = pb[(int64_t)(k - kofs) * ldb];
+            }
+    };
+    const int r = tid & 63, cg = tid >> 6;
+    const int64_t gi = tk.i0 + r;
+    T old[CPT];
+#ifndef SPC_TILE_OLD_EARLY
+#define SPC_TILE_OLD_EARLY 0
+#endif
+    auto load_old = [&]() {
+        if (MODE == MODE_TRAILING) {
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) {
+                const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
+                old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+            }
         }
     };
-    load(tk.k0);
-    for (int kb = tk.k0; kb < tk.k1; kb += KB) {
+    if (SPC_TILE_OLD_EARLY) load_old();
+    // one K chunk: registers -> LDS, then the 2x2 MFMA blocks of each wave
+    auto chunk = [&](int kb, const T *va, const T *vb) {
 #pragma unroll
         for (int e = 0; e < KB / 4; ++e) {
             const int kk = lk + 4 * e;
             const bool kin = kb + kk < tk.k1;
-            As[kk][lr] = (kin && row_ok) ? ra[e] : T(0);
-            Bs[kk][lr] = (kin && col_ok) ? rb[e] : T(0);
+            As[kk][lr] = (kin && row_ok) ? va[e] : T(0);
+            Bs[kk][lr] = (kin && col_ok) ? vb[e] : T(0);
         }
         __syncthreads();
-        if (kb + KB < tk.k1) load(kb + KB);
+        if (NCH == 1 && kb + KB < tk.k1) load(kb + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
             T af[2], bf[2];
@@ -461,19 +504,23 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
                 for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
         }
         __syncthreads();
-    }
-    // epilogue: thread = row r, columns cg*16 .. cg*16+15
-    const int r = tid & 63, cg = tid >> 6;
-    const int64_t gi = tk.i0 + r;
-    T old[CPT];
-    int32_t rv[CPT];
-    if (MODE == MODE_TRAILING) {
+    };
+    load(tk.k0);
+    if constexpr (NCH > 1) {
 #pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
-            const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
-            old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+        for (int ch = 0; ch < NCH; ++ch)
+            if (tk.k0 + KB * ch < tk.k1) chunk(tk.k0 + KB * ch, ra[ch], rb[ch]);
+    } else {
+        for (int kb = tk.k0; kb < tk.k1; kb += KB) {
+            T va[KB / 4], vb[KB / 4];
+#pragma unroll
+            for (int e = 0; e < KB / 4; ++e) va[e] = ra[0][e], vb[e] = rb[0][e];
+            chunk(kb, va, vb);
         }
     }
+    // epilogue: thread = row r, columns cg*16 .. cg*16+15
+    if (!SPC_TILE_OLD_EARLY) load_old();
+    int32_t rv[CPT];
     if (MODE == MODE_SCATTER) {
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
@@ -493,6 +540,34 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
                 Cs[c][rr] = acc[a][b][v];
             }
     __syncthreads();
+    if (MODE == MODE_TRAILING && tk.blk >= 0) {
+        // diagonal tile of the next column block: its rows r < nb2 form the
+        // block, final after this update; factor it here (rows below it are
+        // stored as in any other tile)
+        const int nb2 = min(TM, tk.jmax - tk.j0);
+        T nv[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) nv[cc] = old[cc] - Cs[cg * CPT + cc][r];
+        if (r >= nb2 && gi < m)
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) {
+                const int64_t gj = tk.j0 + cg * CPT + cc;
+                if (gj < tk.jmax) P[gj * m + gi] = nv[cc];
+            }
+        __syncthreads();
+        T(*A)[TM + 1] = Cs;
+        T *rdg = &As[0][0];
+        T(*Tf)[33] = reinterpret_cast<T(*)[33]>(&Bs[0][0]);
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int c = cg * CPT + cc;
+            A[r][c] = (r < nb2 && c <= r) ? nv[cc] : (r == c ? T(1) : T(0));
+        }
+        __syncthreads();
+        potrf_lds<T>(A, rdg, Tf, nb2, P, m, tk.j0, Linv + tk.aux,
+                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk);
+        return;
+    }
     if (gi >= m) return;
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
@@ -646,126 +721,194 @@ __global__ void k_perm_out(const int32_t *perm, int64_t n, int nrhs, const T *W,
 
 constexpr int kMaxRhs = 16;
 
+// Persistent sweeps: instead of one launch per block-tree level, a grid of
+// resident workgroups takes tasks from an atomic counter in an order where
+// every task's dependencies come first, so a task waits only on tasks that
+// running workgroups already hold and the sweep cannot deadlock.  Forward:
+// a block's tasks wait until every task updating its rows has counted down
+// dep[block]; backward: a task waits until the blocks owning its rows are
+// done.  A wait gives up after kSpinLimit polls (about a second), flags err
+// and goes on, so every wave always exits.
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
+        // once any wait has given up, the others stop waiting too
+        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicExch(err, 1);
+}
+
+// Next task of a workgroup: the persistent grid takes it from the work
+// counter (through `order` when given), the level-launch grid takes its
+// own index once.  Returns -1 when there is none.
+template <bool PERSIST>
+__device__ __forceinline__ int64_t next_task(int pass, const int32_t *order, int32_t *queue, int64_t ntasks,
+                                             int32_t *slot) {
+    if (!PERSIST) return pass == 0 ? (int64_t)blockIdx.x : -1;
+    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int64_t i = *slot;
+    if (i >= ntasks) return -1;
+    return order ? order[i] : i;
+}
+
 // Forward, one task = rows r0..r1-1 below block q:
 //   x_q = Linv_q y_q (every task; the first task stores it in X), then
 //   Y[rows[r]] -= sum_k L[r][c0+k] x_q[k] (atomic).
 // One right-hand side: thread = row.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, const int32_t *rows, const T *Lx,
-                                                   const T *Linv, T *Y, T *X, int64_t n) {
+template <typename T, bool PERSIST>
+__global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64_t ntasks, const int32_t *rows,
+                                                   const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
+                                                   const int64_t *tgt_ptr, const int32_t *tgt, SolveSync sy) {
     constexpr int NB = kNB, QPT = NB * NB / 256;
     __shared__ T Vi[NB][NB + 1];
     __shared__ T yq[NB];
     __shared__ T xq[NB];
-    const SolveTask tk = tasks[blockIdx.x];
-    const int nb = tk.nb;
-    const int64_t m = tk.m;
-    const T *P = Lx + tk.loff;
-    const T *Q = Linv + tk.ioff;
+    __shared__ int32_t slot;
     const int tid = threadIdx.x;
-    const int64_t r = tk.r0 + tid;
-    const int64_t rc = min(r, m - 1);
-    T qv[QPT], pv[NB];
+    for (int pass = 0;; ++pass) {
+        const int64_t t = next_task<PERSIST>(pass, nullptr, sy.queue, ntasks, &slot);
+        if (t < 0) return;
+        const SolveTask tk = tasks[t];
+        const int nb = tk.nb;
+        const int64_t m = tk.m;
+        const T *P = Lx + tk.loff;
+        const T *Q = Linv + tk.ioff;
+        const int64_t r = tk.r0 + tid;
+        const int64_t rc = min(r, m - 1);
+        T qv[QPT], pv[NB];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
-    const T yv = Y[tk.g0 + min(tid, nb - 1)];
-    const int64_t gr = rows[tk.roff + rc];
+        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        const int64_t gr = rows[tk.roff + rc];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) pv[k] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + rc];
+        for (int k = 0; k < NB; ++k) pv[k] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + rc];
+        if (PERSIST) {
+            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
+            __syncthreads();
+            __threadfence();
+        }
+        const T yv = Y[tk.g0 + min(tid, nb - 1)];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) {
-        const int e = tid + 256 * u;
-        if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
+        for (int u = 0; u < QPT; ++u) {
+            const int e = tid + 256 * u;
+            if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
+        }
+        if (tid < NB) yq[tid] = tid < nb ? yv : T(0);
+        __syncthreads();
+        if (tid < NB) {
+            T a = T(0);
+            if (tid < nb)
+                for (int c = 0; c <= tid; ++c) a += Vi[tid][c] * yq[c];
+            xq[tid] = a;
+            if (tk.first && tid < nb) X[tk.g0 + tid] = a;
+        }
+        __syncthreads();
+        if (r < tk.r1) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc += (k < nb ? pv[k] : T(0)) * xq[k];
+            atomicAdd(&Y[gr], -acc);
+        }
+        if (PERSIST) {
+            __threadfence();
+            __syncthreads();
+            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
+        }
     }
-    if (tid < NB) yq[tid] = tid < nb ? yv : T(0);
-    __syncthreads();
-    if (tid < NB) {
-        T a = T(0);
-        if (tid < nb)
-            for (int c = 0; c <= tid; ++c) a += Vi[tid][c] * yq[c];
-        xq[tid] = a;
-        if (tk.first && tid < nb) X[tk.g0 + tid] = a;
-    }
-    __syncthreads();
-    if (r >= tk.r1) return;
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) acc += (k < nb ? pv[k] : T(0)) * xq[k];
-    atomicAdd(&Y[gr], -acc);
 }
 
 // Several right-hand sides (up to kMaxRhs): the update of the task's rows
 // is the product (rows x 64) (64 x 16) on 16x16x4 MFMA blocks, wave w
 // taking rows 64 w .. 64 w + 63; the A operand comes straight from the
 // panel, the B operand (x_q) from LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, const int32_t *rows,
-                                                         const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
-                                                         int nrhs) {
+template <typename T, bool PERSIST>
+__global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, int64_t ntasks,
+                                                         const int32_t *rows, const T *Lx, const T *Linv, T *Y,
+                                                         T *X, int64_t n, int nrhs, const int64_t *tgt_ptr,
+                                                         const int32_t *tgt, SolveSync sy) {
     constexpr int NB = kNB, NR = kMaxRhs, QPT = NB * NB / 256, YPT = NB * NR / 256, KS = NB / 4;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T Vi[NB][NB + 1];
     __shared__ T yq[NB][NR + 1];
     __shared__ T xq[NB][NR + 1];
     __shared__ int64_t grs[256];
-    const SolveTask tk = tasks[blockIdx.x];
-    const int nb = tk.nb;
-    const int64_t m = tk.m;
-    const T *P = Lx + tk.loff;
-    const T *Q = Linv + tk.ioff;
+    __shared__ int32_t slot;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    T qv[QPT], yv[YPT], av[4][KS];
+    for (int pass = 0;; ++pass) {
+        const int64_t t = next_task<PERSIST>(pass, nullptr, sy.queue, ntasks, &slot);
+        if (t < 0) return;
+        const SolveTask tk = tasks[t];
+        const int nb = tk.nb;
+        const int64_t m = tk.m;
+        const T *P = Lx + tk.loff;
+        const T *Q = Linv + tk.ioff;
+        T qv[QPT], yv[YPT], av[4][KS];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
 #pragma unroll
-    for (int u = 0; u < YPT; ++u) {
-        const int e = tid + 256 * u, i = e % NB, q = e / NB;
-        yv[u] = Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
-    }
-    grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
+        for (int tt = 0; tt < 4; ++tt) {
+            const int64_t row = min<int64_t>(tk.r0 + 64 * wave + 16 * tt + (lane & 15), m - 1);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int64_t row = min<int64_t>(tk.r0 + 64 * wave + 16 * t + (lane & 15), m - 1);
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            av[t][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
-    }
-#pragma unroll
-    for (int u = 0; u < QPT; ++u) {
-        const int e = tid + 256 * u;
-        if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
-    }
-#pragma unroll
-    for (int u = 0; u < YPT; ++u) {
-        const int e = tid + 256 * u, i = e % NB, q = e / NB;
-        yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * NR; e += 256) {
-        const int i = e % NB, q = e / NB;
-        T a = T(0);
-        if (i < nb)
-            for (int c = 0; c <= i; ++c) a += Vi[i][c] * yq[c][q];
-        xq[i][q] = a;
-    }
-    __syncthreads();
-    if (tk.first)
-        for (int e = tid; e < nb * nrhs; e += 256) {
-            const int i = e % nb, q = e / nb;
-            X[tk.g0 + i + (int64_t)q * n] = xq[i][q];
+            for (int ks = 0; ks < KS; ++ks)
+                av[tt][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
         }
-    // rows of x_q beyond nb are zero, so the clamped columns contribute nothing
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = Mfma<T>::run(av[t][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rr = 64 * wave + 16 * t + Mfma<T>::row(lane, v), q = lane & 15;
-            if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] + (int64_t)q * n], -acc[v]);
+        if (PERSIST) {
+            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
+            __syncthreads();
+            __threadfence();
         }
+#pragma unroll
+        for (int u = 0; u < YPT; ++u) {
+            const int e = tid + 256 * u, i = e % NB, q = e / NB;
+            yv[u] = Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
+        }
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int e = tid + 256 * u;
+            if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < YPT; ++u) {
+            const int e = tid + 256 * u, i = e % NB, q = e / NB;
+            yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NR; e += 256) {
+            const int i = e % NB, q = e / NB;
+            T a = T(0);
+            if (i < nb)
+                for (int c = 0; c <= i; ++c) a += Vi[i][c] * yq[c][q];
+            xq[i][q] = a;
+        }
+        __syncthreads();
+        if (tk.first)
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int i = e % nb, q = e / nb;
+                X[tk.g0 + i + (int64_t)q * n] = xq[i][q];
+            }
+        // rows of x_q beyond nb are zero, so the clamped columns contribute nothing
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc = Mfma<T>::run(av[tt][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = 64 * wave + 16 * tt + Mfma<T>::row(lane, v), q = lane & 15;
+                if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] + (int64_t)q * n], -acc[v]);
+            }
+        }
+        if (PERSIST) {
+            __threadfence();
+            __syncthreads();
+            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
+        }
+        __syncthreads();
     }
 }
 
@@ -774,97 +917,133 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 // groups are added through LDS.  A block with one task finishes itself:
 //   t = X_q - sum,  x_q = Linv_q^T t.
 // A block split over several tasks adds its sums into Acc, and the last
-// task to arrive (block counter) finishes it.  Rows below the block belong
-// to ancestors, whose x is final when the block's level runs.
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, const int32_t *rows, const T *Lx,
-                                                   const T *Linv, T *X, T *Acc, int32_t *counters, int64_t n,
-                                                   int nrhs) {
+// task to arrive (sy.cnt) finishes it.  Rows below the block belong to
+// ancestors, whose x is final before the block's tasks read it (level order,
+// or the done flags of the persistent sweep).
+template <typename T, int NR, bool PERSIST>
+__global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64_t ntasks, const int32_t *order,
+                                                   const int32_t *rows, const T *Lx, const T *Linv, T *X, T *Acc,
+                                                   int64_t n, int nrhs, const int64_t *tgt_ptr, const int32_t *tgt,
+                                                   SolveSync sy) {
     constexpr int NB = kNB, QPT = NB * NB / 256, RG = 64;
     constexpr int XR = 256 * (NR + 1), SM = 4 * NB * NR, VT = NB * (NB + 1);
     constexpr int SH = XR > SM ? (XR > VT ? XR : VT) : (SM > VT ? SM : VT);
     __shared__ T sh[SH];
     __shared__ T tq[NB][NR];
     __shared__ int last;
+    __shared__ int32_t slot;
     T(*xr)[NR + 1] = reinterpret_cast<T(*)[NR + 1]>(sh);   // x of the task's rows
     T(*Sm)[NB][NR] = reinterpret_cast<T(*)[NB][NR]>(sh);    // sums of the 4 groups
     T(*Vt)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(sh);    // block inverse
-    const SolveTask tk = tasks[blockIdx.x];
-    const int nb = tk.nb;
-    const int64_t m = tk.m;
-    const T *P = Lx + tk.loff;
-    const T *Q = Linv + tk.ioff;
     const int tid = threadIdx.x, k = tid & 63, g = tid >> 6;
-    const int64_t rown = tk.r0 + tid;
-    const int64_t gr = rows[tk.roff + min(rown, m - 1)];
-    T qv[QPT], pv[RG];
+    for (int pass = 0;; ++pass) {
+        const int64_t t = next_task<PERSIST>(pass, order, sy.queue + 1, ntasks, &slot);
+        if (t < 0) return;
+        const SolveTask tk = tasks[t];
+        const int nb = tk.nb;
+        const int64_t m = tk.m;
+        const T *P = Lx + tk.loff;
+        const T *Q = Linv + tk.ioff;
+        const int64_t rown = tk.r0 + tid;
+        const int64_t gr = rows[tk.roff + min(rown, m - 1)];
+        T qv[QPT], pv[RG];
 #pragma unroll
-    for (int u = 0; u < RG; ++u)
-        pv[u] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + min<int64_t>(tk.r0 + g * RG + u, m - 1)];
+        for (int u = 0; u < RG; ++u)
+            pv[u] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + min<int64_t>(tk.r0 + g * RG + u, m - 1)];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
-    T xv[NR];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) xv[q] = X[gr + (int64_t)min(q, nrhs - 1) * n];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
-    __syncthreads();
-    T acc[NR];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = T(0);
-#pragma unroll
-    for (int u = 0; u < RG; ++u) {
-        const T l = pv[u];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += l * xr[g * RG + u][q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NR; ++q) Sm[g][k][q] = acc[q];
-    __syncthreads();
-    for (int e = tid; e < NB * NR; e += 256) {
-        const int i = e % NB, q = e / NB;
-        tq[i][q] = Sm[0][i][q] + Sm[1][i][q] + Sm[2][i][q] + Sm[3][i][q];
-    }
-    __syncthreads();
-    if (tk.ntasks == 1) {
-        for (int e = tid; e < nb * nrhs; e += 256) {
-            const int i = e % nb, q = e / nb;
-            tq[i][q] = X[tk.g0 + i + (int64_t)q * n] - tq[i][q];
+        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        if (PERSIST) {
+            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) wait_value(&sy.done[tgt[e]], 1, sy.err);
+            __syncthreads();
+            __threadfence();
         }
-    } else {
-        if (tk.r1 > tk.r0)
+        T xv[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) xv[q] = X[gr + (int64_t)min(q, nrhs - 1) * n];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
+        __syncthreads();
+        T acc[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] = T(0);
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+            const T l = pv[u];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q] += l * xr[g * RG + u][q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NR; ++q) Sm[g][k][q] = acc[q];
+        __syncthreads();
+        for (int e = tid; e < NB * NR; e += 256) {
+            const int i = e % NB, q = e / NB;
+            tq[i][q] = Sm[0][i][q] + Sm[1][i][q] + Sm[2][i][q] + Sm[3][i][q];
+        }
+        __syncthreads();
+        bool fin = true;
+        if (tk.ntasks == 1) {
             for (int e = tid; e < nb * nrhs; e += 256) {
                 const int i = e % nb, q = e / nb;
-                atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
+                tq[i][q] = X[tk.g0 + i + (int64_t)q * n] - tq[i][q];
             }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) last = (atomicAdd(&counters[tk.blk], 1) == tk.ntasks - 1);
-        __syncthreads();
-        if (!last) return;
-        __threadfence();
-        for (int e = tid; e < nb * nrhs; e += 256) {
-            const int i = e % nb, q = e / nb;
-            const int64_t idx = tk.g0 + i + (int64_t)q * n;
-            const T a = __hip_atomic_exchange(&Acc[idx], T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tq[i][q] = X[idx] - a;
+        } else {
+            if (tk.r1 > tk.r0)
+                for (int e = tid; e < nb * nrhs; e += 256) {
+                    const int i = e % nb, q = e / nb;
+                    atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
+                }
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) last = (atomicAdd(&sy.cnt[tk.blk], 1) == tk.ntasks - 1);
+            __syncthreads();
+            fin = last;
+            if (fin) {
+                __threadfence();
+                for (int e = tid; e < nb * nrhs; e += 256) {
+                    const int i = e % nb, q = e / nb;
+                    const int64_t idx = tk.g0 + i + (int64_t)q * n;
+                    const T a = __hip_atomic_exchange(&Acc[idx], T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    tq[i][q] = X[idx] - a;
+                }
+                if (tid == 0) sy.cnt[tk.blk] = 0;
+            }
         }
-        if (tid == 0) counters[tk.blk] = 0;
-    }
-    // x_q = Linv^T t
+        if (fin) {
+            // x_q = Linv^T t
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) {
-        const int e = tid + 256 * u;
-        if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
+            for (int u = 0; u < QPT; ++u) {
+                const int e = tid + 256 * u;
+                if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
+            }
+            __syncthreads();
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int c = e % nb, q = e / nb;
+                T a = T(0);
+                for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
+                X[tk.g0 + c + (int64_t)q * n] = a;
+            }
+            if (PERSIST) {
+                __threadfence();
+                __syncthreads();
+                if (tid == 0) atomicExch(&sy.done[tk.blk], 1);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < nb * nrhs; e += 256) {
-        const int c = e % nb, q = e / nb;
-        T a = T(0);
-        for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
-        X[tk.g0 + c + (int64_t)q * n] = a;
+}
+
+// Per solve: dep <- the forward counts, done and cnt <- 0, queues and the
+// error word <- 0.
+__global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nblocks) {
+        sy.dep[i] = fdep[i];
+        sy.done[i] = 0;
+        sy.cnt[i] = 0;
     }
+    if (i < 2) sy.queue[i] = 0;
+    if (i == 0) sy.err[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -997,18 +1176,19 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 }
 
 template <typename T>
-void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, const T *Linv, hipStream_t st) {
+void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                  hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx);
+                           Linv, Lx, status, P.status_slot);
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx);
+                           Linv, Lx, status, P.status_slot);
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx);
+                           Linv, Lx, status, P.status_slot);
 }
 
 template <typename T>
@@ -1034,28 +1214,65 @@ void launch_perm_out(const DevPlan &P, int64_t n, int nrhs, const T *W, double *
                        B, ldb);
 }
 
+inline unsigned persist_grid(int64_t ntasks) {
+    // two resident workgroups per CU on 256 CUs; more only queue behind them
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntasks, 512));
+}
+
+void launch_solve_reset(const DevPlan &P, int64_t nblocks, SolveSync sy, hipStream_t st) {
+    hipLaunchKernelGGL(k_solve_reset, dim3(grid1(std::max<int64_t>(nblocks, 2), 256)), dim3(256), 0, st, P.fdep,
+                       nblocks, sy);
+}
+
 template <typename T>
 void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
-                      int64_t n, int nrhs, hipStream_t st) {
+                      int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st) {
     if (t1 <= t0) return;
-    const dim3 g((unsigned)(t1 - t0)), b(256);
-    if (nrhs == 1)
-        hipLaunchKernelGGL(k_solve_fwd<T>, g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, Y, X, n);
-    else
-        hipLaunchKernelGGL(k_solve_fwd_multi<T>, g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, Y, X, n, nrhs);
+    const int64_t nt = t1 - t0;
+    const dim3 g(persist ? persist_grid(nt) : (unsigned)nt), b(256);
+    const SolveTask *tk = P.stasks + t0;
+    const int64_t *tp = P.stgt_ptr + t0;
+    if (nrhs == 1) {
+        if (persist)
+            hipLaunchKernelGGL((k_solve_fwd<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, tp, P.stgt, sy);
+        else
+            hipLaunchKernelGGL((k_solve_fwd<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, tp, P.stgt,
+                               sy);
+    } else {
+        if (persist)
+            hipLaunchKernelGGL((k_solve_fwd_multi<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, nrhs,
+                               tp, P.stgt, sy);
+        else
+            hipLaunchKernelGGL((k_solve_fwd_multi<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, nrhs,
+                               tp, P.stgt, sy);
+    }
 }
 
 template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
-                      int32_t *counters, int64_t n, int nrhs, hipStream_t st) {
+                      int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st) {
     if (t1 <= t0) return;
-    const dim3 g((unsigned)(t1 - t0)), b(256);
-    if (nrhs == 1)
-        hipLaunchKernelGGL((k_solve_bwd<T, 1>), g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, X, Acc, counters,
-                           n, nrhs);
-    else
-        hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs>), g, b, 0, st, P.stasks + t0, P.rows, Lx, Linv, X, Acc,
-                           counters, n, nrhs);
+    const int64_t nt = t1 - t0;
+    const dim3 g(persist ? persist_grid(nt) : (unsigned)nt), b(256);
+    // the persistent sweep takes its tasks (global indices) from bwd_order
+    const SolveTask *tk = persist ? P.stasks : P.stasks + t0;
+    const int64_t *tp = persist ? P.stgt_ptr : P.stgt_ptr + t0;
+    const int32_t *ord = persist ? P.bwd_order : nullptr;
+    if (nrhs == 1) {
+        if (persist)
+            hipLaunchKernelGGL((k_solve_bwd<T, 1, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, n,
+                               nrhs, tp, P.stgt, sy);
+        else
+            hipLaunchKernelGGL((k_solve_bwd<T, 1, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, n,
+                               nrhs, tp, P.stgt, sy);
+    } else {
+        if (persist)
+            hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc,
+                               n, nrhs, tp, P.stgt, sy);
+        else
+            hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc,
+                               n, nrhs, tp, P.stgt, sy);
+    }
 }
 
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
@@ -1103,7 +1320,8 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_assemble<T>(const DevPlan &, int64_t, const double *, T *, hipStream_t);           \
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
-    template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, const T *, hipStream_t);     \
+    template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
+                                  hipStream_t);                                                             \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \
@@ -1112,9 +1330,9 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_perm_out<T>(const DevPlan &, int64_t, int, const T *, double *, int64_t,           \
                                      hipStream_t);                                                          \
     template void launch_solve_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
-                                      int64_t, int, hipStream_t);                                           \
+                                      int64_t, int, SolveSync, bool, hipStream_t);                          \
     template void launch_solve_bwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
-                                      int32_t *, int64_t, int, hipStream_t);
+                                      int64_t, int, SolveSync, bool, hipStream_t);
 SPC_INSTANTIATE(double)
 SPC_INSTANTIATE(float)
 

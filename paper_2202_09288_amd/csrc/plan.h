@@ -26,6 +26,9 @@ constexpr int kPanelNB = kNB;
 constexpr int kSolveNB = kNB;
 // Rows of one solve-update task.
 constexpr int kSolveRows = 256;
+// Solve levels from the top with fewer tasks than this run as one
+// persistent launch per sweep; the wide levels below keep one launch each.
+constexpr int kSolvePersistMax = 256;
 
 // One pair (source supernode s, ancestor t) of the scatter: rows
 // i0..i1-1 of R_s (positions, i0 >= w_s) are columns of t, and rows
@@ -46,7 +49,8 @@ struct UpdatePair {
 // and then the data, with no further dependent lookups.
 struct TileTask {
     int64_t loff;   // lptr[s]: the m x w panel
-    int64_t aux;    // update tiles: rptr[s] (row list); TRSM: inv_off[blk]
+    int64_t aux;    // scatter tiles: rptr[s] (row list); TRSM tiles and
+                    // fused trailing tiles: inv_off of the block factored
     int32_t s;
     int32_t m;      // rows of the panel (leading dimension)
     int32_t i0;
@@ -54,7 +58,10 @@ struct TileTask {
     int32_t k0;
     int32_t k1;
     int32_t jmax;   // columns j >= jmax are outside the update
-    int32_t blk;    // TRSM tiles: block id
+    int32_t blk;    // TRSM tiles: block id.  Trailing tiles: -1, or, for the
+                    // diagonal tile of the next column block (i0 = j0 = k1),
+                    // that block's global first column: the tile's
+                    // workgroup factors the block after updating it
 };
 
 // POTRF of the block of columns c0..c1-1 (c0 a multiple of kNB) of
@@ -164,6 +171,17 @@ struct Symbolic {
     std::vector<int64_t> stask_ptr;        // [nslevels+1] into stasks
     std::vector<SolveTask> stasks;
     int32_t nslevels = 0;
+    // Persistent solves: for each task the column blocks its rows fall in
+    // (ascending, distinct), for each block the number of (task, block)
+    // contributions its forward step waits for, and the task order of the
+    // backward sweep (block-tree levels from the top).
+    // Levels solve_split.. run persistently; fdep counts only their tasks,
+    // and bwd_order lists only their tasks.
+    int32_t solve_split = 0;
+    std::vector<int64_t> stgt_ptr;
+    std::vector<int32_t> stgt;
+    std::vector<int32_t> fdep;
+    std::vector<int32_t> bwd_order;
 
     // batches: status word of each supernode (empty: one word)
     std::vector<int32_t> status_slot;

@@ -439,21 +439,33 @@ int build_schedule(Symbolic &S) {
                 // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                 // SYRK k n(n+1), GEMM 2 m n k
                 double nbd = (double)(c1 - c0);
-                st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
                 st.trsm_flops += (double)(m - c1) * nbd * nbd;
+                if (c1 < w) {  // the next block's POTRF runs in this step's trailing launch
+                    const double nx = (double)(std::min<int64_t>(c1 + kNB, w) - c1);
+                    st.trailing_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
+                }
                 st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
                                      2.0 * (double)(m - w) * (double)(w - c1) * nbd;
-                S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
-                                                  (int32_t)c1, (int32_t)(S.super_ptr[s] + c0), 0});
+                // block 0 gets a POTRF task; block b+1 is factored by the
+                // workgroup of its diagonal tile in step b's trailing update
+                if (b == 0) {
+                    st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
+                    S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
+                                                      (int32_t)c1, (int32_t)(S.super_ptr[s] + c0), 0});
+                }
                 for (int64_t r = c1; r < m; r += kTile)
                     S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r, (int32_t)c0,
                                                     (int32_t)c0, (int32_t)c1, (int32_t)c1, blk});
                 // trailing update inside the panel: rows [c1, m), cols [c1, w);
                 // K is one block (<= 64), where 64x64 tiles do better than 128
                 for (int64_t j0 = c1; j0 < w; j0 += kTile)
-                    for (int64_t i0 = j0; i0 < m; i0 += kTile)
-                        S.int_tiles.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
-                                                       (int32_t)j0, (int32_t)c0, (int32_t)c1, (int32_t)w, -1});
+                    for (int64_t i0 = j0; i0 < m; i0 += kTile) {
+                        const bool fuse = i0 == c1 && j0 == c1;
+                        S.int_tiles.push_back(TileTask{S.lptr[s], fuse ? S.inv_off[blk + 1] : S.rptr[s], s,
+                                                       (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
+                                                       (int32_t)c1, (int32_t)w,
+                                                       fuse ? (int32_t)(S.super_ptr[s] + c1) : -1});
+                    }
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
@@ -541,6 +553,37 @@ int build_schedule(Symbolic &S) {
             for (size_t e = first; e < S.stasks.size(); ++e) S.stasks[e].ntasks = cnt;
         }
         S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
+    }
+    // dependencies of the persistent solves
+    {
+        std::vector<int32_t> col_blk(S.n);
+        for (int32_t s = 0; s < ns; ++s)
+            for (int32_t c = S.super_ptr[s]; c < S.super_ptr[s + 1]; ++c)
+                col_blk[c] = first_blk[s] + (c - S.super_ptr[s]) / kNB;
+        const int64_t nt = (int64_t)S.stasks.size();
+        int32_t split = nsl;
+        while (split > 0 && S.stask_ptr[split] - S.stask_ptr[split - 1] < kSolvePersistMax) --split;
+        S.solve_split = split;
+        const int64_t tp0 = S.stask_ptr[split];
+        S.stgt_ptr.assign(nt + 1, 0);
+        S.stgt.clear();
+        S.fdep.assign(nb, 0);
+        for (int64_t t = 0; t < nt; ++t) {
+            const SolveTask &tk = S.stasks[t];
+            int32_t last = -1;
+            for (int64_t r = tk.r0; r < tk.r1; ++r) {
+                const int32_t b = col_blk[S.rows[tk.roff + r]];
+                if (b != last) {
+                    S.stgt.push_back(b);
+                    if (t >= tp0) S.fdep[b]++;
+                    last = b;
+                }
+            }
+            S.stgt_ptr[t + 1] = (int64_t)S.stgt.size();
+        }
+        S.bwd_order.clear();
+        for (int32_t l = nsl - 1; l >= split; --l)
+            for (int64_t e = S.stask_ptr[l]; e < S.stask_ptr[l + 1]; ++e) S.bwd_order.push_back((int32_t)e);
     }
     return SPC_OK;
 }

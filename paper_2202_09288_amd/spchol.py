@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspchol.so")
+# SPCHOL_LIBRARY names another build of the same library (A/B timing)
+LIB_PATH = os.environ.get("SPCHOL_LIBRARY") or os.path.join(_HERE, "libspchol.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_09288_amd/build.py "
