@@ -52,6 +52,8 @@ struct spc_factor_s {
     void *Lx = nullptr;
     void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
+    int32_t *flags = nullptr;   // per block: epoch whose inverse is stored; then one error word
+    int32_t epoch = 0;          // factorizations run so far
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
@@ -203,12 +205,12 @@ size_t plan_bytes(const spc::Symbolic &S) {
            bytes_of(S.fdep) + bytes_of(S.bwd_order);
 }
 
-// Brackets one launch with a pair of events when profiling is on.
+// Brackets one launch with a pair of events (on the launch's stream) when
+// profiling is on.
 struct Prof {
     spc_factor_s *f;
-    hipStream_t st;
     template <typename Fn>
-    void run(int cls, double flops, Fn &&fn) {
+    void run(int cls, double flops, hipStream_t st, Fn &&fn) {
         if (!f || !f->profiling) {
             fn();
             return;
@@ -235,38 +237,45 @@ struct Prof {
     }
 };
 
+// The numeric factorization, level by level (Sec. 3, Fig. 1).  Inside a
+// level, step b runs TRSM of block b, then one launch of the trailing update
+// by panel b: the tiles of block b+1's columns first (the diagonal-tile
+// workgroup also factors block b+1), then the columns beyond, so that
+// factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, hipStream_t st, Prof &prof) {
-    prof.run(SPC_K_ASSEMBLE, 0.0, [&] {
+                    unsigned long long *status, const spc::BlockFlags &fl, hipStream_t st, Prof &prof) {
+    prof.run(SPC_K_ASSEMBLE, 0.0, st, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
     });
     for (int32_t l = 0; l < S.nlevels; ++l) {
         if (S.small_ptr[l + 1] > S.small_ptr[l])
-            prof.run(SPC_K_SMALL, S.small_flops[l], [&] {
+            prof.run(SPC_K_SMALL, S.small_flops[l], st, [&] {
                 spc::launch_small<T>(P, S.small_ptr[l], S.small_ptr[l + 1], Lx, Linv, status, st);
             });
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
             if (stp.f1 > stp.f0)
-                prof.run(SPC_K_POTRF, stp.potrf_flops,
+                prof.run(SPC_K_POTRF, stp.potrf_flops, st,
                          [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
             if (stp.p1 > stp.p0)
-                prof.run(SPC_K_TRSM, stp.trsm_flops,
-                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, st); });
+                prof.run(SPC_K_TRSM, stp.trsm_flops, st, [&] {
+                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, fl, st);
+                });
             if (stp.t1 > stp.t0)
-                prof.run(SPC_K_TRAILING, stp.trailing_flops,
-                         [&] { spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, st); });
+                prof.run(SPC_K_TRAILING, stp.look_flops + stp.rest_flops, st, [&] {
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, fl, st);
+                });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
-            prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], [&] {
+            prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], st, [&] {
                 spc::launch_tiles128<T>(P, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, st);
             });
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
-            prof.run(SPC_K_SCATTER, S.ext_flops[l], [&] {
+            prof.run(SPC_K_SCATTER, S.ext_flops[l], st, [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     status, st);
+                                     status, fl, st);
             });
     }
 }
@@ -307,14 +316,18 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
     (void)hipGetLastError();  // judge only the launches below
-    spc::launch_status_reset(f->status, f->nstatus, st);
+    const int64_t nblk = (int64_t)S.sblocks.size();
+    spc::launch_status_reset(f->status, f->nstatus, f->flags + nblk, st);
+    // epochs run 1, 2, ...; the flags start at 0 (wraps after 2^31 factorizations)
+    f->epoch = f->epoch == INT32_MAX ? 1 : f->epoch + 1;
+    const spc::BlockFlags fl{f->flags, f->flags + nblk, f->epoch};
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
-    Prof prof{f, st};
+    Prof prof{f};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, fl, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, fl, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -341,8 +354,12 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus);
+    const size_t flag_bytes = sizeof(int32_t) * (sym->S.sblocks.size() + 1);
+    if (e == hipSuccess) e = hipMalloc((void **)&f->flags, flag_bytes);
+    if (e == hipSuccess) e = hipMemset(f->flags, 0, flag_bytes);
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
+
     if (e != hipSuccess) {
         spc_free_factor(f);
         return record_error(e, "factor allocation", __LINE__);
@@ -726,10 +743,24 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
     return all_conv ? SPC_OK : SPC_NO_CONVERGENCE;
 }
 
+// A wait between workgroups of the factorization that gave up (never
+// expected: it needs a workgroup that was dispatched not to progress).
+int check_wait_error(spc_factor f) {
+    if (!f->flags) return SPC_OK;
+    int32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, f->flags + f->sym->S.sblocks.size(), sizeof(err), hipMemcpyDeviceToHost));
+    if (err) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%s", "factorization: a wait for a diagonal block timed out");
+        return SPC_DEVICE_ERROR;
+    }
+    return SPC_OK;
+}
+
 int spc_sync(spc_factor f, int64_t *bad_pivot) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
+    if (int rc = check_wait_error(f->batch ? f->batch->F : f)) return rc;
     unsigned long long v = 0;
     HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
     if (v != ~0ull) {
@@ -815,6 +846,7 @@ void spc_free_factor(spc_factor f) {
     if (f->Lx) (void)hipFree(f->Lx);
     if (f->Linv) (void)hipFree(f->Linv);
     if (f->status) (void)hipFree(f->status);
+    if (f->flags) (void)hipFree(f->flags);
     if (f->work) (void)hipFree(f->work);
     if (f->refine) (void)hipFree(f->refine);
     if (f->ev0) (void)hipEventDestroy(f->ev0);
@@ -950,6 +982,7 @@ int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {
     if (bad_system) *bad_system = -1;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(b->F->stream));
+    if (int rc = check_wait_error(b->F)) return rc;
     std::vector<unsigned long long> v(b->count);
     HIP_TRY(hipMemcpy(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
     for (int i = 0; i < b->count; ++i)

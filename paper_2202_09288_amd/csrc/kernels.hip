@@ -61,15 +61,32 @@ __global__ void k_zero(T *x, int64_t count) {
     for (; i < count; i += stride) x[i] = T(0);
 }
 
-__global__ void k_status_reset(unsigned long long *status, int count) {
+__global__ void k_status_reset(unsigned long long *status, int count, int32_t *err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) status[i] = ~0ull;
+    if (i == 0 && err) *err = 0;
 }
 
 template <typename T>
 __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *values, T *Lx) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nnz) Lx[amap[k]] = (T)values[k];
+}
+
+// Bounded waits between workgroups of one launch: poll an int until it holds
+// `want`; after kSpinLimit polls (about a second) give up, flag err and go on,
+// so every wave always exits.  Once any wait has given up, the others stop
+// waiting too.
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
+        // once any wait has given up, the others stop waiting too
+        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicExch(err, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +432,8 @@ enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
-                                               const int32_t *status_slot) {
+                                               const int32_t *status_slot, int32_t *flags, int32_t *err,
+                                               int32_t epoch) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T As[KB][TM + 4];
@@ -446,51 +464,29 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
     }
-    // K chunks held in registers: all of K (<= 64) for TRSM and trailing
-    // tiles, so one round trip to memory covers the tile; one chunk ahead
-    // for the scatter tiles (K = w, unbounded)
-#ifndef SPC_TILE_PREFETCH_ALL
-#define SPC_TILE_PREFETCH_ALL 0
-#endif
-    constexpr int NCH = (MODE == MODE_SCATTER || !SPC_TILE_PREFETCH_ALL) ? 1 : kNB / KB;
-    T ra[NCH][KB / 4], rb[NCH][KB / 4];
+    // the next K chunk is loaded into registers while the current one is used
+    T ra[KB / 4], rb[KB / 4];
     auto load = [&](int kb) {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-            for (int e = 0; e < KB / 4; ++e) {
-                const int k = min(kb + KB * ch + lk + 4 * e, tk.k1 - 1);
-                ra[ch][e] = pa[(int64_t)k * m];
-                rb[ch][e] = pb[(int64_t)(k - kofs) * ldb];
-            }
+        for (int e = 0; e < KB / 4; ++e) {
+            const int k = min(kb + lk + 4 * e, tk.k1 - 1);
+            ra[e] = pa[(int64_t)k * m];
+            rb[e] = pb[(int64_t)(k - kofs) * ldb];
+        }
     };
     const int r = tid & 63, cg = tid >> 6;
     const int64_t gi = tk.i0 + r;
-    T old[CPT];
-#ifndef SPC_TILE_OLD_EARLY
-#define SPC_TILE_OLD_EARLY 0
-#endif
-    auto load_old = [&]() {
-        if (MODE == MODE_TRAILING) {
-#pragma unroll
-            for (int cc = 0; cc < CPT; ++cc) {
-                const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
-                old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
-            }
-        }
-    };
-    if (SPC_TILE_OLD_EARLY) load_old();
-    // one K chunk: registers -> LDS, then the 2x2 MFMA blocks of each wave
-    auto chunk = [&](int kb, const T *va, const T *vb) {
+    load(tk.k0);
+    for (int kb = tk.k0; kb < tk.k1; kb += KB) {
 #pragma unroll
         for (int e = 0; e < KB / 4; ++e) {
             const int kk = lk + 4 * e;
             const bool kin = kb + kk < tk.k1;
-            As[kk][lr] = (kin && row_ok) ? va[e] : T(0);
-            Bs[kk][lr] = (kin && col_ok) ? vb[e] : T(0);
+            As[kk][lr] = (kin && row_ok) ? ra[e] : T(0);
+            Bs[kk][lr] = (kin && col_ok) ? rb[e] : T(0);
         }
         __syncthreads();
-        if (NCH == 1 && kb + KB < tk.k1) load(kb + KB);
+        if (kb + KB < tk.k1) load(kb + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
             T af[2], bf[2];
@@ -504,22 +500,16 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
                 for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
         }
         __syncthreads();
-    };
-    load(tk.k0);
-    if constexpr (NCH > 1) {
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            if (tk.k0 + KB * ch < tk.k1) chunk(tk.k0 + KB * ch, ra[ch], rb[ch]);
-    } else {
-        for (int kb = tk.k0; kb < tk.k1; kb += KB) {
-            T va[KB / 4], vb[KB / 4];
-#pragma unroll
-            for (int e = 0; e < KB / 4; ++e) va[e] = ra[0][e], vb[e] = rb[0][e];
-            chunk(kb, va, vb);
-        }
     }
     // epilogue: thread = row r, columns cg*16 .. cg*16+15
-    if (!SPC_TILE_OLD_EARLY) load_old();
+    T old[CPT];
+    if (MODE == MODE_TRAILING) {
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
+            old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+        }
+    }
     int32_t rv[CPT];
     if (MODE == MODE_SCATTER) {
 #pragma unroll
@@ -566,6 +556,74 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
         __syncthreads();
         potrf_lds<T>(A, rdg, Tf, nb2, P, m, tk.j0, Linv + tk.aux,
                      status + (status_slot ? status_slot[tk.s] : 0), tk.blk);
+        if (tk.flag >= 0) {
+            // the block's L and inverse are stored: release the tiles below
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) atomicExch(&flags[tk.flag], epoch);
+        }
+        return;
+    }
+    if (MODE == MODE_TRAILING && tk.flag >= 0) {
+        // a tile below the diagonal of a full next block: after its update
+        // it is solved against that block, X = B L^{-T} as B times the
+        // transposed inverse, once the diagonal tile's workgroup has raised
+        // the block's flag (it was dispatched before this one)
+        T nv[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) nv[cc] = old[cc] - Cs[cg * CPT + cc][r];
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) Cs[cg * CPT + cc][r] = gi < m ? nv[cc] : T(0);  // B, column-major
+        if (tid == 0) wait_value(&flags[tk.flag], epoch, err);
+        __syncthreads();
+        // the inverse is read with device-scope atomic loads, which see what
+        // the diagonal workgroup wrote back before raising the flag; an
+        // acquire fence here would invalidate this XCD's L2 under the other
+        // tiles of the launch (measured: 1.8 ms more on the 60^3 factor)
+        const T *Q = Linv + tk.aux;  // Q[k * kNB + c] = (L^{-1})_{ck}
+        T qv[TM / KB][KB / 4];
+#pragma unroll
+        for (int ch = 0; ch < TM / KB; ++ch)
+#pragma unroll
+            for (int e = 0; e < KB / 4; ++e)
+                qv[ch][e] = __hip_atomic_load(Q + (KB * ch + lk + 4 * e) * TM + lr, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        acc_t x[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) x[a][b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ch = 0; ch < TM / KB; ++ch) {
+#pragma unroll
+            for (int e = 0; e < KB / 4; ++e) Bs[lk + 4 * e][lr] = qv[ch][e];
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < KB; kk += 4) {
+                T af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = Cs[KB * ch + kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) x[a][b] = Mfma<T>::run(af[a], bf[b], x[a][b]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Cs[wc + b * 16 + (lane & 15)][wr + a * 16 + Mfma<T>::row(lane, v)] = x[a][b][v];
+        __syncthreads();
+        if (gi < m)
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) P[(tk.j0 + cg * CPT + cc) * m + gi] = Cs[cg * CPT + cc][r];
         return;
     }
     if (gi >= m) return;
@@ -727,20 +785,7 @@ constexpr int kMaxRhs = 16;
 // running workgroups already hold and the sweep cannot deadlock.  Forward:
 // a block's tasks wait until every task updating its rows has counted down
 // dep[block]; backward: a task waits until the blocks owning its rows are
-// done.  A wait gives up after kSpinLimit polls (about a second), flags err
-// and goes on, so every wave always exits.
-constexpr int kSpinLimit = 1 << 20;
-
-__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
-    for (int it = 0; it < kSpinLimit; ++it) {
-        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
-        // once any wait has given up, the others stop waiting too
-        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    atomicExch(err, 1);
-}
-
+// done (bounded waits, wait_value).
 // Next task of a workgroup: the persistent grid takes it from the work
 // counter (through `order` when given), the level-launch grid takes its
 // own index once.  Returns -1 when there is none.
@@ -1140,9 +1185,9 @@ inline unsigned grid1(int64_t count, int block) {
 
 }  // namespace
 
-void launch_status_reset(unsigned long long *status, int count, hipStream_t st) {
+void launch_status_reset(unsigned long long *status, int count, int32_t *err, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
+    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count, err);
 }
 
 template <typename T>
@@ -1177,18 +1222,18 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st) {
+                  const BlockFlags &fl, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
 }
 
 template <typename T>
@@ -1321,7 +1366,7 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
-                                  hipStream_t);                                                             \
+                                  const BlockFlags &, hipStream_t);                                         \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \

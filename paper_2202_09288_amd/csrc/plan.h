@@ -62,6 +62,12 @@ struct TileTask {
                     // diagonal tile of the next column block (i0 = j0 = k1),
                     // that block's global first column: the tile's
                     // workgroup factors the block after updating it
+    int32_t flag;   // trailing tiles in the next block's columns, when that
+                    // block is a full kNB wide: its block id.  The diagonal
+                    // tile raises the block's flag once the inverse is
+                    // stored; the tiles below wait for it and then apply
+                    // the TRSM themselves (aux = inverse offset).  Else -1.
+    int32_t pad;
 };
 
 // POTRF of the block of columns c0..c1-1 (c0 a multiple of kNB) of
@@ -135,11 +141,16 @@ struct Symbolic {
 
     // factor schedule: for each level, a list of steps; each step is a
     // panel-task range followed by a tile-task range
+    // Step b of a level: POTRF of block 0 (b = 0 only), TRSM of block b,
+    // then the trailing update by panel b, split in two: the tiles of block
+    // b+1's own columns (t0..tm, which also factor block b+1) and the tiles
+    // of the columns beyond (tm..t1), which can run beside the next step's
+    // TRSM and column update (lookahead).
     struct Step {
         int64_t f0, f1;   // POTRF tasks
         int64_t p0, p1;   // TRSM tiles
-        int64_t t0, t1;   // internal trailing-update tiles (64)
-        double potrf_flops, trsm_flops, trailing_flops;  // algorithmic flops of its launches
+        int64_t t0, tm, t1;  // trailing tiles: next block's columns, then the rest
+        double potrf_flops, trsm_flops, look_flops, rest_flops;  // algorithmic flops of its launches
     };
     std::vector<int64_t> level_step_ptr;   // [nlevels+1]
     std::vector<Step> steps;

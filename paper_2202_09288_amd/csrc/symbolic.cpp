@@ -426,46 +426,68 @@ int build_schedule(Symbolic &S) {
             Symbolic::Step st;
             st.potrf_flops = 0.0;
             st.trsm_flops = 0.0;
-            st.trailing_flops = 0.0;
+            st.look_flops = 0.0;
+            st.rest_flops = 0.0;
             st.f0 = (int64_t)S.potrf_tasks.size();
             st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
-            for (int32_t s : bylevel[l]) {
-                int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
-                int64_t c0 = b * kNB;
-                if (c0 >= w) continue;
-                int64_t c1 = std::min<int64_t>(c0 + kNB, w);
-                int32_t blk = first_blk[s] + (int32_t)b;
-                // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
-                // SYRK k n(n+1), GEMM 2 m n k
-                double nbd = (double)(c1 - c0);
-                st.trsm_flops += (double)(m - c1) * nbd * nbd;
-                if (c1 < w) {  // the next block's POTRF runs in this step's trailing launch
-                    const double nx = (double)(std::min<int64_t>(c1 + kNB, w) - c1);
-                    st.trailing_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
-                }
-                st.trailing_flops += (double)(w - c1) * (double)(w - c1 + 1) * nbd +
-                                     2.0 * (double)(m - w) * (double)(w - c1) * nbd;
-                // block 0 gets a POTRF task; block b+1 is factored by the
-                // workgroup of its diagonal tile in step b's trailing update
-                if (b == 0) {
-                    st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
-                    S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
-                                                      (int32_t)c1, (int32_t)(S.super_ptr[s] + c0), 0});
-                }
-                for (int64_t r = c1; r < m; r += kTile)
-                    S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r, (int32_t)c0,
-                                                    (int32_t)c0, (int32_t)c1, (int32_t)c1, blk});
-                // trailing update inside the panel: rows [c1, m), cols [c1, w);
-                // K is one block (<= 64), where 64x64 tiles do better than 128
-                for (int64_t j0 = c1; j0 < w; j0 += kTile)
-                    for (int64_t i0 = j0; i0 < m; i0 += kTile) {
-                        const bool fuse = i0 == c1 && j0 == c1;
-                        S.int_tiles.push_back(TileTask{S.lptr[s], fuse ? S.inv_off[blk + 1] : S.rptr[s], s,
-                                                       (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
-                                                       (int32_t)c1, (int32_t)w,
-                                                       fuse ? (int32_t)(S.super_ptr[s] + c1) : -1});
+            // trailing tiles: pass 0 the columns of block b+1 (its diagonal
+            // tile first: that workgroup also factors block b+1), pass 1 the rest
+            for (int pass = 0; pass < 2; ++pass) {
+                if (pass == 1) st.tm = (int64_t)S.int_tiles.size();
+                for (int32_t s : bylevel[l]) {
+                    int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+                    int64_t c0 = b * kNB;
+                    if (c0 >= w) continue;
+                    int64_t c1 = std::min<int64_t>(c0 + kNB, w);
+                    int32_t blk = first_blk[s] + (int32_t)b;
+                    const double nbd = (double)(c1 - c0);
+                    const int64_t cx = std::min<int64_t>(c1 + kNB, w);  // end of block b+1
+                    if (pass == 0) {
+                        // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
+                        // SYRK k n(n+1), GEMM 2 m n k
+                        const double nx = (double)(cx - c1), tot = (double)(w - c1);
+                        if (c1 < w)  // block b+1's POTRF runs in this step's column update
+                            st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
+                        st.look_flops += nx * (nx + 1) * nbd + 2.0 * ((double)(m - c1) - nx) * nx * nbd;
+                        st.rest_flops += tot * (tot + 1) * nbd + 2.0 * (double)(m - w) * tot * nbd -
+                                         (nx * (nx + 1) * nbd + 2.0 * ((double)(m - c1) - nx) * nx * nbd);
+                        // block 0 gets a POTRF task; block b+1 is factored by the
+                        // workgroup of its diagonal tile in step b's column update
+                        if (b == 0) {
+                            st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
+                            S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
+                                                              (int32_t)c0, (int32_t)c1,
+                                                              (int32_t)(S.super_ptr[s] + c0), 0});
+                        }
+                        // TRSM of block b: its own launch for block 0 and for a
+                        // last block narrower than kNB; a full block b >= 1 was
+                        // solved by the tiles of step b-1's column update
+                        if (b == 0 || c1 - c0 < kNB) {
+                            st.trsm_flops += (double)(m - c1) * nbd * nbd;
+                            for (int64_t r = c1; r < m; r += kTile)
+                                S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
+                                                                (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
+                                                                (int32_t)c1, blk, -1, 0});
+                        }
+                        if (cx - c1 == kNB)  // block b+1's TRSM runs in this step's column update
+                            st.look_flops += (double)(m - cx) * (double)kNB * (double)kNB;
                     }
+                    // trailing update inside the panel: rows [c1, m), cols [c1, w);
+                    // K is one block (<= 64), where 64x64 tiles do better than 128
+                    const int64_t j0a = pass == 0 ? c1 : c1 + kTile, j0b = pass == 0 ? cx : w;
+                    for (int64_t j0 = j0a; j0 < j0b; j0 += kTile)
+                        for (int64_t i0 = j0; i0 < m; i0 += kTile) {
+                            const bool fuse = i0 == c1 && j0 == c1;
+                            // tiles of a full next block hand over through its flag
+                            const bool full = pass == 0 && cx - c1 == kNB;
+                            S.int_tiles.push_back(TileTask{S.lptr[s], (fuse || full) ? S.inv_off[blk + 1] : S.rptr[s],
+                                                           s, (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
+                                                           (int32_t)c1, (int32_t)w,
+                                                           fuse ? (int32_t)(S.super_ptr[s] + c1) : -1,
+                                                           full ? blk + 1 : -1, 0});
+                        }
+                }
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
@@ -483,7 +505,7 @@ int build_schedule(Symbolic &S) {
                 for (int64_t i0 = j0; i0 < m; i0 += tsz)
                     (big ? S.ext_tiles_big : S.ext_tiles)
                         .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0, 0,
-                                            (int32_t)w, (int32_t)m, -1});
+                                            (int32_t)w, (int32_t)m, -1, -1, 0});
         }
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
         S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();

@@ -156,6 +156,31 @@ def test_refactorize_and_repeat(torch_dev, lib):
     assert oracle.rel_frobenius(L3, L1, S.lower_mask()) <= 1e-14
 
 
+def test_refactorize_new_values_wide(torch_dev, lib):
+    """One pattern refactorized with unrelated values, alternately.  The
+    blocks of a wide supernode hand their inverses to the tiles below inside
+    one launch, so nothing may survive from the previous factorization."""
+    n = 300
+    rng = np.random.default_rng(11)
+    r, c = np.tril_indices(n)
+    vals = []
+    for _ in range(2):
+        X = rng.standard_normal((n, n))
+        A = X @ X.T + n * np.eye(n)
+        colptr, rowidx, v = W.lower_csc(n, r, c, A[r, c])
+        vals.append(v)
+    perm = np.arange(n, dtype=np.int32)
+    sym = lib.Symbolic(colptr, rowidx, perm, 0.05)
+    S = oracle.Symbolic(colptr, rowidx, perm, 0.05)
+    refs = [S.factor(v) for v in vals]
+    dvs = [torch_dev.from_numpy(v).cuda() for v in vals]
+    F = lib.factorize(sym, dvs[0])
+    for k in (1, 0, 1, 1, 0):
+        F.refactorize(dvs[k])
+        F.sync()
+        assert oracle.rel_frobenius(F.export(), refs[k], S.lower_mask()) <= REL_F_FP64
+
+
 def test_zero_rhs_and_empty(torch_dev, lib):
     s = grid((6, 6))
     sym = lib.Symbolic(s.colptr, s.rowidx, s.perm)
