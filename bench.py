@@ -40,6 +40,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--workload", default="grid3d60",
+                    choices=["grid3d60", "grid2d64", "elast48", "batch512", "serving"],
+                    help="grid3d60: the headline FP64 factor + solve (default); grid2d64: small-system "
+                         "latency; elast48: FP32 factor + FP64 refinement on the 48^3 elasticity "
+                         "operator; batch512: 512 systems in one schedule; serving: request loop")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second (0: sweep)")
+    ap.add_argument("--requests", type=int, default=300, help="serving: requests per rate")
     return ap.parse_args()
 
 
@@ -99,6 +106,196 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
+    modes = {"grid3d60": bench_grid3d, "grid2d64": bench_grid2d, "elast48": bench_elast,
+             "batch512": bench_batch, "serving": bench_serving}
+    modes[args.workload](args)
+
+
+def head(args, value, unit, dtype, config, ms_per_step, higher=True):
+    return {"metric": "factor GFLOP/s + solve p50/p99 ms at 1e-12 backward error vs plain FP64",
+            "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def timed(fn, steps, warmup, torch):
+    """Device time per call of fn() (events on the current stream), ms."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        out.append((e0, e1))
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in out])
+
+
+def bench_grid2d(args):
+    """64x64 5-point Laplacian (n = 4,096), FP64: a latency-bound system."""
+    import torch
+    from paper_2202_09288_amd import spchol
+    from paper_2202_09288_amd import workloads as W
+    import oracle
+    torch.cuda.set_device(0)
+    s = W.grid2d_unit()
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    Bw = torch.empty_like(B0)
+    F = spchol.factorize(sym, dv)
+    F.sync()
+    steps, warm = max(args.steps, 50), max(args.warmup, 5)
+    fac = timed(lambda: F.refactorize(dv), steps, warm, torch)
+    sol = timed(lambda: (Bw.copy_(B0), F.solve(Bw)), steps, warm, torch)
+    F.sync()
+    berr = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Bw.cpu().numpy().T, s.B)
+    flops = float(sym.info["flops"])
+    out = head(args, round(flops / (fac.mean() * 1e-3) / 1e9, 3), "GFLOP/s", "f64",
+               {"workload": "2D 5-point, 64x64 grid, diagonal = degree + 1e-2, geometric nested dissection, "
+                            "1 RHS, plain FP64 factor + solve", "n": s.n, "flops": int(flops),
+                "levels": sym.info["levels"], "nsuper": sym.info["nsuper"]},
+               round(float(fac.mean() + sol.mean()), 4))
+    out.update({"factor_us_p50": round(float(np.median(fac)) * 1e3, 1),
+                "solve_us_p50": round(float(np.median(sol)) * 1e3, 1),
+                "solve_us_p99": round(float(np.percentile(sol, 99)) * 1e3, 1),
+                "berr": berr, "berr_ok": bool(berr <= 1e-12)})
+    print(json.dumps(out), flush=True)
+
+
+def bench_elast(args):
+    """48^3 27-point 3-dof elasticity operator (kappa ~ 1e8), 4 RHS: FP32
+    factorization + FP64 refinement to eta <= 1e-12, next to plain FP64."""
+    import torch
+    from paper_2202_09288_amd import spchol
+    from paper_2202_09288_amd import workloads as W
+    import oracle
+    torch.cuda.set_device(0)
+    s = W.elast48()
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    flops = float(sym.info["flops"])
+    dv = torch.from_numpy(s.values).cuda()
+    B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    res = {}
+    for prec in ("fp32", "fp64"):
+        F = spchol.factorize(sym, dv, prec)
+        F.sync()
+        fac = timed(lambda: F.refactorize(dv), args.steps, args.warmup, torch)
+        X = torch.zeros_like(B0)
+        info = {}
+
+        def solve():
+            info.update(F.solve_refined(dv, B0, X, tol=1e-12, maxit=200))
+        sol = timed(solve, max(3, args.steps // 2), 1, torch)
+        F.sync()
+        berr = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+        res[prec] = {"factor_ms": round(float(fac.mean()), 3),
+                     "factor_gflops": round(flops / (fac.mean() * 1e-3) / 1e9, 1),
+                     "refined_solve_ms_p50": round(float(np.median(sol)), 3),
+                     "iterations": info.get("iterations"), "converged": info.get("converged"),
+                     "berr": berr, "berr_ok": bool(berr <= 1e-12)}
+        F.close()
+    r32 = res["fp32"]
+    out = head(args, r32["factor_gflops"], "GFLOP/s", "f32",
+               {"workload": "3D 27-point 3-dof elasticity-like operator, 48^3 grid, kappa ~1e8, 4 RHS, "
+                            "FP32 factor + FP64 refinement to 1e-12", "n": s.n, "nnz_lower": s.nnz,
+                "flops": int(flops), "nnz_L": sym.info["nnz_l"]},
+               round(r32["factor_ms"] + r32["refined_solve_ms_p50"], 3))
+    out.update({"fp32": res["fp32"], "fp64": res["fp64"],
+                "fp32_factor_frac_of_peak": round(r32["factor_gflops"] / (FP32_PEAK_TFLOPS * 1e3), 4),
+                "fp64_factor_frac_of_peak": round(res["fp64"]["factor_gflops"] / (FP64_PEAK_TFLOPS * 1e3), 4)})
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """512 independent systems (2D/3D grids, n from ~1k to ~40k), 16 RHS each,
+    merged into one forest: one schedule factors them all (FP32), one batched
+    solve; FP64 refinement per system through its view of the batch."""
+    import torch
+    from paper_2202_09288_amd import spchol
+    from paper_2202_09288_amd import workloads as W
+    import oracle
+    torch.cuda.set_device(0)
+    systems = W.batch512()
+    syms = [spchol.Symbolic(x.colptr, x.rowidx, x.perm, 0.05) for x in systems]
+    flops = float(sum(x.info["flops"] for x in syms))
+    dvs = [torch.from_numpy(x.values).cuda() for x in systems]
+    Bs0 = [torch.from_numpy(np.ascontiguousarray(x.B.T)).cuda() for x in systems]
+    res = {}
+    for prec in ("fp32", "fp64"):
+        batch = spchol.Batch(syms, prec)
+        batch.factorize(dvs)
+        batch.sync()
+        fac = timed(lambda: batch.factorize(dvs), args.steps, args.warmup, torch)
+        Bw = [torch.empty_like(b) for b in Bs0]
+
+        def solve():
+            for b, b0 in zip(Bw, Bs0):
+                b.copy_(b0)
+            batch.solve(Bw)
+        sol = timed(solve, max(3, args.steps // 2), 1, torch)
+        batch.sync()
+        res[prec] = {"factor_ms": round(float(fac.mean()), 3),
+                     "factor_gflops": round(flops / (fac.mean() * 1e-3) / 1e9, 1),
+                     "batched_solve_ms_p50": round(float(np.median(sol)), 3)}
+        if prec == "fp32":
+            # FP64 refinement of every system through its view of the batch
+            t0 = time.perf_counter()
+            worst, iters = 0.0, []
+            Xs = [torch.zeros_like(b) for b in Bs0]
+            for i, x in enumerate(systems):
+                info = batch.factor(i).solve_refined(dvs[i], Bs0[i], Xs[i], tol=1e-12, maxit=100)
+                iters.append(info["iterations"])
+            torch.cuda.synchronize()
+            res[prec]["refine_all_s"] = round(time.perf_counter() - t0, 3)
+            for i, x in enumerate(systems[:64]):
+                worst = max(worst, oracle.backward_error(x.n, x.colptr, x.rowidx, x.values,
+                                                         Xs[i].cpu().numpy().T, x.B))
+            res[prec].update({"refine_iterations_max": int(max(iters)), "berr_max_first64": worst,
+                              "berr_ok": bool(worst <= 1e-12)})
+        batch.close()
+    r32 = res["fp32"]
+    out = head(args, r32["factor_gflops"], "GFLOP/s", "f32",
+               {"workload": "batch of 512 SPD systems: 2D 5-point / 3D 7-point grids, sides U[32,200] / "
+                            "U[10,34], conductances 10^U[-2,2), shift 1e-2, 16 RHS each; one merged schedule",
+                "systems": len(systems), "n_total": int(sum(x.n for x in systems)), "flops": int(flops)},
+               round(r32["factor_ms"] + r32["batched_solve_ms_p50"], 3))
+    out.update({"fp32": res["fp32"], "fp64": res["fp64"]})
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Request loop: Poisson arrivals of factor-then-solve requests from the
+    batch size mix (plus 5% 3D 50^3), 30% re-solves with 8 RHS on resident
+    factors; p50/p99 latency and solves/s per arrival rate."""
+    import torch
+    from paper_2202_09288_amd import serving
+    torch.cuda.set_device(0)
+    rates = [args.rate] if args.rate > 0 else [20.0, 50.0, 100.0]
+    runs = []
+    for rate in rates:
+        reqs = serving.make_requests(args.requests, rate, seed=0)
+        srv = serving.Server(slots=4, hbm_budget=64 << 30, precision="fp32", tol=1e-12, maxit=100)
+        t0 = time.perf_counter()
+        srv.run(reqs)
+        wall = time.perf_counter() - t0
+        summ = serving.summarize(reqs, wall)
+        summ["rate_hz"] = rate
+        runs.append(summ)
+        print(f"serving rate {rate}: {summ}", file=sys.stderr, flush=True)
+    best = min(runs, key=lambda r: r["p99_ms"] or 1e30)
+    out = head(args, round(best["solves_per_s"], 2), "solves/s", "f32",
+               {"workload": "serving: Poisson arrivals, batch size mix + 5% 3D 50^3, 30% re-solves (8 RHS) "
+                            "on resident factors, FP32 + FP64 refinement to 1e-12, 4 slots",
+                "requests_per_rate": args.requests}, None)
+    out.update({"runs": runs})
+    print(json.dumps(out), flush=True)
+
+
+def bench_grid3d(args):
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W

@@ -786,6 +786,31 @@ constexpr int kMaxRhs = 16;
 // a block's tasks wait until every task updating its rows has counted down
 // dep[block]; backward: a task waits until the blocks owning its rows are
 // done (bounded waits, wait_value).
+// Data handed between workgroups of one persistent sweep moves through
+// device-scope atomics (loads after a wait, stores before a flag is raised),
+// and a workgroup raises a flag after waiting for its own memory operations;
+// no cache-wide fences, whose writeback and invalidation cost more than the
+// data.  SPC_SOLVE_FENCES=1 restores the fences.
+#ifndef SPC_SOLVE_FENCES
+#define SPC_SOLVE_FENCES 0
+#endif
+template <typename T>
+__device__ __forceinline__ T shared_load(const T *p) {
+    return SPC_SOLVE_FENCES ? *p : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void shared_store(T *p, T v) {
+    if (SPC_SOLVE_FENCES) *p = v;
+    else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void release_own() {
+    if (SPC_SOLVE_FENCES) __threadfence();
+    else __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void acquire_after_wait() {
+    if (SPC_SOLVE_FENCES) __threadfence();
+}
+
 // Next task of a workgroup: the persistent grid takes it from the work
 // counter (through `order` when given), the level-launch grid takes its
 // own index once.  Returns -1 when there is none.
@@ -833,9 +858,9 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
         if (PERSIST) {
             if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
             __syncthreads();
-            __threadfence();
+            acquire_after_wait();
         }
-        const T yv = Y[tk.g0 + min(tid, nb - 1)];
+        const T yv = PERSIST ? shared_load(&Y[tk.g0 + min(tid, nb - 1)]) : Y[tk.g0 + min(tid, nb - 1)];
 #pragma unroll
         for (int u = 0; u < QPT; ++u) {
             const int e = tid + 256 * u;
@@ -858,7 +883,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
             atomicAdd(&Y[gr], -acc);
         }
         if (PERSIST) {
-            __threadfence();
+            release_own();
             __syncthreads();
             for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
         }
@@ -904,12 +929,13 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         if (PERSIST) {
             if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
             __syncthreads();
-            __threadfence();
+            acquire_after_wait();
         }
 #pragma unroll
         for (int u = 0; u < YPT; ++u) {
             const int e = tid + 256 * u, i = e % NB, q = e / NB;
-            yv[u] = Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
+            const T *py = &Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
+            yv[u] = PERSIST ? shared_load(py) : *py;
         }
 #pragma unroll
         for (int u = 0; u < QPT; ++u) {
@@ -949,7 +975,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
             }
         }
         if (PERSIST) {
-            __threadfence();
+            release_own();
             __syncthreads();
             for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
         }
@@ -1000,11 +1026,14 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         if (PERSIST) {
             for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) wait_value(&sy.done[tgt[e]], 1, sy.err);
             __syncthreads();
-            __threadfence();
+            acquire_after_wait();
         }
         T xv[NR];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) xv[q] = X[gr + (int64_t)min(q, nrhs - 1) * n];
+        for (int q = 0; q < NR; ++q) {
+            const T *px = &X[gr + (int64_t)min(q, nrhs - 1) * n];
+            xv[q] = PERSIST ? shared_load(px) : *px;
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
         __syncthreads();
@@ -1038,13 +1067,20 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                     const int i = e % nb, q = e / nb;
                     atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
                 }
-            __threadfence();
+#ifndef SPC_BWD_FENCE
+#define SPC_BWD_FENCE 1
+#endif
+            // the partial sums are device-scope atomics and the last task
+            // reads them back with atomic exchanges: each thread only waits
+            // for its own atomics to be performed before the count goes up
+            if (SPC_BWD_FENCE) __threadfence();
+            else __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) last = (atomicAdd(&sy.cnt[tk.blk], 1) == tk.ntasks - 1);
             __syncthreads();
             fin = last;
             if (fin) {
-                __threadfence();
+                if (SPC_BWD_FENCE) __threadfence();
                 for (int e = tid; e < nb * nrhs; e += 256) {
                     const int i = e % nb, q = e / nb;
                     const int64_t idx = tk.g0 + i + (int64_t)q * n;
@@ -1066,10 +1102,11 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                 const int c = e % nb, q = e / nb;
                 T a = T(0);
                 for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
-                X[tk.g0 + c + (int64_t)q * n] = a;
+                if (PERSIST) shared_store(&X[tk.g0 + c + (int64_t)q * n], a);
+                else X[tk.g0 + c + (int64_t)q * n] = a;
             }
             if (PERSIST) {
-                __threadfence();
+                release_own();
                 __syncthreads();
                 if (tid == 0) atomicExch(&sy.done[tk.blk], 1);
             }
