@@ -52,8 +52,6 @@ struct spc_factor_s {
     void *Lx = nullptr;
     void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
-    int32_t *flags = nullptr;   // per block: epoch whose inverse is stored; then one error word
-    int32_t epoch = 0;          // factorizations run so far
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
@@ -244,7 +242,7 @@ struct Prof {
 // factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, const spc::BlockFlags &fl, hipStream_t st, Prof &prof) {
+                    unsigned long long *status, hipStream_t st, Prof &prof) {
     prof.run(SPC_K_ASSEMBLE, 0.0, st, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
@@ -261,11 +259,11 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
                          [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
             if (stp.p1 > stp.p0)
                 prof.run(SPC_K_TRSM, stp.trsm_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, fl, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, st);
                 });
             if (stp.t1 > stp.t0)
                 prof.run(SPC_K_TRAILING, stp.look_flops + stp.rest_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, fl, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, st);
                 });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
@@ -275,21 +273,21 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], st, [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     status, fl, st);
+                                     status, st);
             });
     }
 }
 
 // Y holds the permuted right-hand sides on entry; X receives the solution.
 // sync points to kSolveSyncInts(blocks) words of workspace.  Each sweep runs
-// one launch per block-tree level.  SPC_SOLVE_PERSIST=1 in the environment
-// runs the narrow levels at the top (levels solve_split..) as one persistent
-// launch per sweep instead; on MI355X that measured slower (device-scope
-// fences cost more per hop than a launch), so it is off by default.
+// one launch per wide block-tree level, and the narrow levels at the top
+// (levels solve_split..) as one persistent launch per sweep, which removes
+// a launch per level from the long chains of the top supernodes.
+// SPC_SOLVE_LEVELS=1 in the environment runs every level as its own launch.
 bool solve_persistent() {
     static const bool v = [] {
-        const char *e = std::getenv("SPC_SOLVE_PERSIST");
-        return e && e[0] == '1';
+        const char *e = std::getenv("SPC_SOLVE_LEVELS");
+        return !(e && e[0] == '1');
     }();
     return v;
 }
@@ -316,18 +314,14 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
     (void)hipGetLastError();  // judge only the launches below
-    const int64_t nblk = (int64_t)S.sblocks.size();
-    spc::launch_status_reset(f->status, f->nstatus, f->flags + nblk, st);
-    // epochs run 1, 2, ...; the flags start at 0 (wraps after 2^31 factorizations)
-    f->epoch = f->epoch == INT32_MAX ? 1 : f->epoch + 1;
-    const spc::BlockFlags fl{f->flags, f->flags + nblk, f->epoch};
+    spc::launch_status_reset(f->status, f->nstatus, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
     Prof prof{f};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, fl, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, fl, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -354,9 +348,6 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus);
-    const size_t flag_bytes = sizeof(int32_t) * (sym->S.sblocks.size() + 1);
-    if (e == hipSuccess) e = hipMalloc((void **)&f->flags, flag_bytes);
-    if (e == hipSuccess) e = hipMemset(f->flags, 0, flag_bytes);
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
 
@@ -743,24 +734,10 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
     return all_conv ? SPC_OK : SPC_NO_CONVERGENCE;
 }
 
-// A wait between workgroups of the factorization that gave up (never
-// expected: it needs a workgroup that was dispatched not to progress).
-int check_wait_error(spc_factor f) {
-    if (!f->flags) return SPC_OK;
-    int32_t err = 0;
-    HIP_TRY(hipMemcpy(&err, f->flags + f->sym->S.sblocks.size(), sizeof(err), hipMemcpyDeviceToHost));
-    if (err) {
-        std::snprintf(g_last_error, sizeof(g_last_error), "%s", "factorization: a wait for a diagonal block timed out");
-        return SPC_DEVICE_ERROR;
-    }
-    return SPC_OK;
-}
-
 int spc_sync(spc_factor f, int64_t *bad_pivot) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
-    if (int rc = check_wait_error(f->batch ? f->batch->F : f)) return rc;
     unsigned long long v = 0;
     HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
     if (v != ~0ull) {
@@ -846,7 +823,6 @@ void spc_free_factor(spc_factor f) {
     if (f->Lx) (void)hipFree(f->Lx);
     if (f->Linv) (void)hipFree(f->Linv);
     if (f->status) (void)hipFree(f->status);
-    if (f->flags) (void)hipFree(f->flags);
     if (f->work) (void)hipFree(f->work);
     if (f->refine) (void)hipFree(f->refine);
     if (f->ev0) (void)hipEventDestroy(f->ev0);
@@ -982,7 +958,6 @@ int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {
     if (bad_system) *bad_system = -1;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(b->F->stream));
-    if (int rc = check_wait_error(b->F)) return rc;
     std::vector<unsigned long long> v(b->count);
     HIP_TRY(hipMemcpy(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
     for (int i = 0; i < b->count; ++i)

@@ -45,18 +45,8 @@ inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks) {
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
-// Per-block flags of one factorization: a block's flag holds the epoch of
-// the factorization that last stored its inverse (so nothing is cleared
-// between factorizations); err is nonzero when a wait gave up.
-struct BlockFlags {
-    int32_t *flags;
-    int32_t *err;
-    int32_t epoch;
-};
-
-// status word: lowest permuted column whose pivot failed, or ~0ull; also
-// clears *err when given
-void launch_status_reset(unsigned long long *status, int count, int32_t *err, hipStream_t st);
+// status word: lowest permuted column whose pivot failed, or ~0ull
+void launch_status_reset(unsigned long long *status, int count, hipStream_t st);
 template <typename T>
 void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
@@ -69,7 +59,7 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
                   hipStream_t st);
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  const BlockFlags &fl, hipStream_t st);
+                  hipStream_t st);
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);

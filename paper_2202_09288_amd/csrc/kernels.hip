@@ -61,32 +61,15 @@ __global__ void k_zero(T *x, int64_t count) {
     for (; i < count; i += stride) x[i] = T(0);
 }
 
-__global__ void k_status_reset(unsigned long long *status, int count, int32_t *err) {
+__global__ void k_status_reset(unsigned long long *status, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) status[i] = ~0ull;
-    if (i == 0 && err) *err = 0;
 }
 
 template <typename T>
 __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *values, T *Lx) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nnz) Lx[amap[k]] = (T)values[k];
-}
-
-// Bounded waits between workgroups of one launch: poll an int until it holds
-// `want`; after kSpinLimit polls (about a second) give up, flag err and go on,
-// so every wave always exits.  Once any wait has given up, the others stop
-// waiting too.
-constexpr int kSpinLimit = 1 << 20;
-
-__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
-    for (int it = 0; it < kSpinLimit; ++it) {
-        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
-        // once any wait has given up, the others stop waiting too
-        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    atomicExch(err, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,8 +415,7 @@ enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
-                                               const int32_t *status_slot, int32_t *flags, int32_t *err,
-                                               int32_t epoch) {
+                                               const int32_t *status_slot) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T As[KB][TM + 4];
@@ -556,74 +538,6 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
         __syncthreads();
         potrf_lds<T>(A, rdg, Tf, nb2, P, m, tk.j0, Linv + tk.aux,
                      status + (status_slot ? status_slot[tk.s] : 0), tk.blk);
-        if (tk.flag >= 0) {
-            // the block's L and inverse are stored: release the tiles below
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) atomicExch(&flags[tk.flag], epoch);
-        }
-        return;
-    }
-    if (MODE == MODE_TRAILING && tk.flag >= 0) {
-        // a tile below the diagonal of a full next block: after its update
-        // it is solved against that block, X = B L^{-T} as B times the
-        // transposed inverse, once the diagonal tile's workgroup has raised
-        // the block's flag (it was dispatched before this one)
-        T nv[CPT];
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) nv[cc] = old[cc] - Cs[cg * CPT + cc][r];
-        __syncthreads();
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) Cs[cg * CPT + cc][r] = gi < m ? nv[cc] : T(0);  // B, column-major
-        if (tid == 0) wait_value(&flags[tk.flag], epoch, err);
-        __syncthreads();
-        // the inverse is read with device-scope atomic loads, which see what
-        // the diagonal workgroup wrote back before raising the flag; an
-        // acquire fence here would invalidate this XCD's L2 under the other
-        // tiles of the launch (measured: 1.8 ms more on the 60^3 factor)
-        const T *Q = Linv + tk.aux;  // Q[k * kNB + c] = (L^{-1})_{ck}
-        T qv[TM / KB][KB / 4];
-#pragma unroll
-        for (int ch = 0; ch < TM / KB; ++ch)
-#pragma unroll
-            for (int e = 0; e < KB / 4; ++e)
-                qv[ch][e] = __hip_atomic_load(Q + (KB * ch + lk + 4 * e) * TM + lr, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-        acc_t x[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) x[a][b] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int ch = 0; ch < TM / KB; ++ch) {
-#pragma unroll
-            for (int e = 0; e < KB / 4; ++e) Bs[lk + 4 * e][lr] = qv[ch][e];
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < KB; kk += 4) {
-                T af[2], bf[2];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) af[a] = Cs[KB * ch + kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) x[a][b] = Mfma<T>::run(af[a], bf[b], x[a][b]);
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Cs[wc + b * 16 + (lane & 15)][wr + a * 16 + Mfma<T>::row(lane, v)] = x[a][b][v];
-        __syncthreads();
-        if (gi < m)
-#pragma unroll
-            for (int cc = 0; cc < CPT; ++cc) P[(tk.j0 + cg * CPT + cc) * m + gi] = Cs[cg * CPT + cc][r];
         return;
     }
     if (gi >= m) return;
@@ -786,6 +700,21 @@ constexpr int kMaxRhs = 16;
 // a block's tasks wait until every task updating its rows has counted down
 // dep[block]; backward: a task waits until the blocks owning its rows are
 // done (bounded waits, wait_value).
+// Bounded waits: poll an int until it holds `want`; after kSpinLimit polls
+// (about a second) give up, flag err and go on, so every wave always exits.
+// Once any wait has given up, the others stop waiting too.
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
+        // once any wait has given up, the others stop waiting too
+        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicExch(err, 1);
+}
+
 // Data handed between workgroups of one persistent sweep moves through
 // device-scope atomics (loads after a wait, stores before a flag is raised),
 // and a workgroup raises a flag after waiting for its own memory operations;
@@ -1067,20 +996,15 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                     const int i = e % nb, q = e / nb;
                     atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
                 }
-#ifndef SPC_BWD_FENCE
-#define SPC_BWD_FENCE 1
-#endif
             // the partial sums are device-scope atomics and the last task
             // reads them back with atomic exchanges: each thread only waits
             // for its own atomics to be performed before the count goes up
-            if (SPC_BWD_FENCE) __threadfence();
-            else __builtin_amdgcn_s_waitcnt(0);
+            release_own();
             __syncthreads();
             if (tid == 0) last = (atomicAdd(&sy.cnt[tk.blk], 1) == tk.ntasks - 1);
             __syncthreads();
             fin = last;
             if (fin) {
-                if (SPC_BWD_FENCE) __threadfence();
                 for (int e = tid; e < nb * nrhs; e += 256) {
                     const int i = e % nb, q = e / nb;
                     const int64_t idx = tk.g0 + i + (int64_t)q * n;
@@ -1222,9 +1146,9 @@ inline unsigned grid1(int64_t count, int block) {
 
 }  // namespace
 
-void launch_status_reset(unsigned long long *status, int count, int32_t *err, hipStream_t st) {
+void launch_status_reset(unsigned long long *status, int count, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count, err);
+    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
 }
 
 template <typename T>
@@ -1259,18 +1183,18 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  const BlockFlags &fl, hipStream_t st) {
+                  hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
+                           Linv, Lx, status, P.status_slot);
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
+                           Linv, Lx, status, P.status_slot);
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, fl.flags, fl.err, fl.epoch);
+                           Linv, Lx, status, P.status_slot);
 }
 
 template <typename T>
@@ -1403,7 +1327,7 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
-                                  const BlockFlags &, hipStream_t);                                         \
+                                  hipStream_t);                                                             \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \

@@ -460,18 +460,11 @@ int build_schedule(Symbolic &S) {
                                                               (int32_t)c0, (int32_t)c1,
                                                               (int32_t)(S.super_ptr[s] + c0), 0});
                         }
-                        // TRSM of block b: its own launch for block 0 and for a
-                        // last block narrower than kNB; a full block b >= 1 was
-                        // solved by the tiles of step b-1's column update
-                        if (b == 0 || c1 - c0 < kNB) {
-                            st.trsm_flops += (double)(m - c1) * nbd * nbd;
-                            for (int64_t r = c1; r < m; r += kTile)
-                                S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
-                                                                (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
-                                                                (int32_t)c1, blk, -1, 0});
-                        }
-                        if (cx - c1 == kNB)  // block b+1's TRSM runs in this step's column update
-                            st.look_flops += (double)(m - cx) * (double)kNB * (double)kNB;
+                        st.trsm_flops += (double)(m - c1) * nbd * nbd;
+                        for (int64_t r = c1; r < m; r += kTile)
+                            S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r,
+                                                            (int32_t)c0, (int32_t)c0, (int32_t)c1, (int32_t)c1,
+                                                            blk});
                     }
                     // trailing update inside the panel: rows [c1, m), cols [c1, w);
                     // K is one block (<= 64), where 64x64 tiles do better than 128
@@ -479,13 +472,10 @@ int build_schedule(Symbolic &S) {
                     for (int64_t j0 = j0a; j0 < j0b; j0 += kTile)
                         for (int64_t i0 = j0; i0 < m; i0 += kTile) {
                             const bool fuse = i0 == c1 && j0 == c1;
-                            // tiles of a full next block hand over through its flag
-                            const bool full = pass == 0 && cx - c1 == kNB;
-                            S.int_tiles.push_back(TileTask{S.lptr[s], (fuse || full) ? S.inv_off[blk + 1] : S.rptr[s],
-                                                           s, (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
+                            S.int_tiles.push_back(TileTask{S.lptr[s], fuse ? S.inv_off[blk + 1] : S.rptr[s], s,
+                                                           (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
                                                            (int32_t)c1, (int32_t)w,
-                                                           fuse ? (int32_t)(S.super_ptr[s] + c1) : -1,
-                                                           full ? blk + 1 : -1, 0});
+                                                           fuse ? (int32_t)(S.super_ptr[s] + c1) : -1});
                         }
                 }
             }
@@ -505,7 +495,7 @@ int build_schedule(Symbolic &S) {
                 for (int64_t i0 = j0; i0 < m; i0 += tsz)
                     (big ? S.ext_tiles_big : S.ext_tiles)
                         .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0, 0,
-                                            (int32_t)w, (int32_t)m, -1, -1, 0});
+                                            (int32_t)w, (int32_t)m, -1});
         }
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
         S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();
