@@ -20,8 +20,11 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Numeric calls are asynchronous on it; numeric failure (a non-positive
  *     pivot) is reported by spc_sync.
- *   - One handle must not be used from two host threads at once.  Distinct
- *     handles may be used concurrently on distinct streams.
+ *   - One handle must not be used from two host threads at once, and the
+ *     work of two calls on one factor must not overlap on the device (a
+ *     factor owns one solve workspace): queue them on one stream, or wait
+ *     for one before issuing the other on another stream.  Distinct handles
+ *     may be used concurrently on distinct streams.
  */
 #ifndef SPCHOL_H
 #define SPCHOL_H
