@@ -231,7 +231,8 @@ enum spc_kernel_class {
     SPC_K_SCATTER = 4,        /* SYRK/GEMM update scatter-added into ancestors, 64x64 tiles */
     SPC_K_SCATTER_BIG = 5,    /* the same on 128x128 tiles (large supernodes) */
     SPC_K_SMALL = 6,          /* whole small supernodes: POTRF, TRSM, inverse, scatter */
-    SPC_K_COUNT = 7
+    SPC_K_TINY = 7,           /* the same for tiny supernodes, one wave each */
+    SPC_K_COUNT = 8
 };
 
 typedef struct spc_kernel_stats {

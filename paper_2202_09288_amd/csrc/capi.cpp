@@ -161,6 +161,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.perm.data(), bytes_of(S.perm), (const void **)&P.perm},
         {S.potrf_tasks.data(), bytes_of(S.potrf_tasks), (const void **)&P.potrf_tasks},
         {S.small_tasks.data(), bytes_of(S.small_tasks), (const void **)&P.small_tasks},
+        {S.tiny_tasks.data(), bytes_of(S.tiny_tasks), (const void **)&P.tiny_tasks},
         {S.trsm_tiles.data(), bytes_of(S.trsm_tiles), (const void **)&P.trsm_tiles},
         {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
@@ -197,7 +198,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 
 size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
-           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.trsm_tiles) +
+           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
            bytes_of(S.stasks) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
            bytes_of(S.fdep) + bytes_of(S.bwd_order);
@@ -248,6 +249,10 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
     });
     for (int32_t l = 0; l < S.nlevels; ++l) {
+        if (S.tiny_ptr[l + 1] > S.tiny_ptr[l])
+            prof.run(SPC_K_TINY, S.tiny_flops[l], st, [&] {
+                spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_ptr[l + 1], Lx, Linv, status, st);
+            });
         if (S.small_ptr[l + 1] > S.small_ptr[l])
             prof.run(SPC_K_SMALL, S.small_flops[l], st, [&] {
                 spc::launch_small<T>(P, S.small_ptr[l], S.small_ptr[l + 1], Lx, Linv, status, st);

@@ -17,6 +17,7 @@ struct DevPlan {
     const int32_t *perm;
     const PanelTask *potrf_tasks;
     const SmallTask *small_tasks;
+    const SmallTask *tiny_tasks;
     const TileTask *trsm_tiles;
     const TileTask *int_tiles;
     const TileTask *ext_tiles;
@@ -57,6 +58,9 @@ void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);
+template <typename T>
+void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                 hipStream_t st);
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);

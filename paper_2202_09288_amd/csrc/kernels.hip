@@ -297,6 +297,107 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
 }
 
 // ---------------------------------------------------------------------------
+// k_tiny: one wave per supernode with w <= kTinyW and m <= kTinyM (four per
+// workgroup, no LDS, no barriers): lane = row of the panel, the row's w
+// entries in registers, values of other rows read from their lanes.
+//   1. column Cholesky: l_jj = sqrt(d_j), l_ij = a_ij / l_jj, then
+//      a_ik -= l_ij l_kj for the later columns;
+//   2. inverse of the diagonal triangle: lane c < w forms column c by
+//      forward substitution;
+//   3. the update C[i][k] = sum_j l_ij l_kj of the rows below (w <= k <= i),
+//      scatter-added into the ancestors: C[i][k] goes to cbase[k] +
+//      rel[crel[k] + i].
+// Pivots that are not positive and finite lower the status word.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lane_read_i64(int64_t v, int src) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t ntasks, const int64_t *cbase,
+                                              const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
+                                              unsigned long long *status, const int32_t *status_slot) {
+    constexpr int WT = kTinyW, CB = 8;  // CB: update columns per batch of loads
+    const int lane = threadIdx.x & 63;
+    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ti >= ntasks) return;  // the whole wave
+    const SmallTask tk = tasks[ti];
+    const int m = tk.m, w = tk.w;
+    T *P = Lx + tk.loff;
+    const int rc = min(lane, m - 1);
+    T r[WT];
+#pragma unroll
+    for (int c = 0; c < WT; ++c) r[c] = P[(int64_t)min(c, w - 1) * m + rc];
+    // scatter addressing of this lane's row position taken as a column
+    const int64_t kpos = tk.roff + min(max(lane, w), m - 1);
+    const int64_t my_cb = cbase[kpos], my_cr = crel[kpos];
+    // 1. column Cholesky
+    int bad = -1;
+    T rdg[WT];
+#pragma unroll
+    for (int c = 0; c < WT; ++c) {
+        if (c < w) {
+            const T d = lane_read(r[c], c);
+            if (bad < 0 && !finite_pos(d)) bad = c;
+            const T rs = rsqrt_nr(d);
+            rdg[c] = rs;
+            const T lic = (lane == c) ? d * rs : r[c] * rs;
+            r[c] = lic;
+#pragma unroll
+            for (int c2 = c + 1; c2 < WT; ++c2)
+                if (c2 < w) r[c2] -= lic * lane_read(lic, c2);
+        }
+    }
+    if (lane == 0 && bad >= 0)
+        atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
+    if (lane < m)
+#pragma unroll
+        for (int c = 0; c < WT; ++c)
+            if (c < w && c <= lane) P[(int64_t)c * m + lane] = r[c];
+    // 2. inverse of the diagonal triangle, column `lane`
+    {
+        T y[WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a) {
+            T v = (a == lane) ? T(1) : T(0);
+#pragma unroll
+            for (int k = 0; k < a; ++k) v -= lane_read(r[k], a) * y[k];
+            y[a] = a < w ? v * rdg[a] : T(0);
+        }
+        T *Vi = Linv + tk.ioff;
+        if (lane < w)
+#pragma unroll
+            for (int a = 0; a < WT; ++a)
+                if (a < w) Vi[lane * w + a] = y[a];
+    }
+    // 3. update of the rows below, scatter-added into the ancestors
+    for (int k0 = w; k0 < m; k0 += CB) {
+        int32_t rv[CB];
+        int64_t cbk[CB];
+        T acc[CB];
+        bool ok[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int k = k0 + u, kc = min(k, m - 1);
+            cbk[u] = lane_read_i64(my_cb, kc);
+            const int64_t crk = lane_read_i64(my_cr, kc);
+            ok[u] = k < m && lane >= k && lane < m;
+            rv[u] = rel[crk + (ok[u] ? lane : kc)];
+            T a = T(0);
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+                if (j < w) a += r[j] * lane_read(r[j], kc);
+            acc[u] = a;
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+            if (ok[u]) atomicAdd(&Lx[cbk[u] + rv[u]], -acc[u]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_small: one workgroup per small supernode (w <= kSmallW, m <= kSmallM),
 // the whole m x w panel in LDS:
 //   1. column Cholesky of the panel, right-looking: l_jj = sqrt(d_j),
@@ -1174,6 +1275,14 @@ void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 }
 
 template <typename T>
+void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
+                 hipStream_t st) {
+    if (t1 <= t0) return;
+    hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(256), 0, st, P.tiny_tasks + t0, t1 - t0,
+                       P.cbase, P.crel, P.rel, Lx, Linv, status, P.status_slot);
+}
+
+template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st) {
     if (t1 <= t0) return;
@@ -1330,6 +1439,8 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
                                   hipStream_t);                                                             \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
+    template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \
+                                 hipStream_t);                                                              \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \
                                     hipStream_t);                                                           \

@@ -15,9 +15,12 @@ constexpr int kTileBig = 128;
 constexpr int kBigMin = 256;
 constexpr int kBigMinK = 128;
 // Supernodes with w <= kSmallW and m <= kSmallM are factored, inverted and
-// scatter-added by one workgroup each (k_small).
+// scatter-added by one workgroup each (k_small); those with w <= kTinyW and
+// m <= kTinyM by one wave each (k_tiny, four per workgroup).
 constexpr int kSmallW = 32;
 constexpr int kSmallM = 128;
+constexpr int kTinyW = 8;
+constexpr int kTinyM = 64;
 // Width of the column blocks a supernode is cut into, for the panel
 // factorization and for the triangular solves alike; each block's diagonal
 // triangle gets an explicit inverse in the inverse store.
@@ -155,6 +158,8 @@ struct Symbolic {
     std::vector<int64_t> ext_big_ptr;      // [nlevels+1] external tiles (128)
     std::vector<int64_t> small_ptr;        // [nlevels+1] into small_tasks
     std::vector<SmallTask> small_tasks;    // supernodes of the single-workgroup path
+    std::vector<int64_t> tiny_ptr;         // [nlevels+1] into tiny_tasks
+    std::vector<SmallTask> tiny_tasks;     // supernodes of the single-wave path
     // Scatter addressing per row position k >= w_s of R_s (pair p of k,
     // target t): cbase = lptr[t] + (rows[k] - first column of t) * m_t is
     // column rows[k] of t's panel; crel = rel_off(p) - i0(p), so row
@@ -162,6 +167,7 @@ struct Symbolic {
     std::vector<int64_t> cbase, crel;
     std::vector<int32_t> first_blk;        // [nsuper+1] first column block
     std::vector<double> small_flops;       // [nlevels] flops of the small path
+    std::vector<double> tiny_flops;        // [nlevels] flops of the single-wave path
     std::vector<double> ext_flops;         // [nlevels] flops of the 64-tile scatter launch
     std::vector<double> ext_big_flops;     // [nlevels] flops of the 128-tile scatter launch
     std::vector<PanelTask> potrf_tasks;

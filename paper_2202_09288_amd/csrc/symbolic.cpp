@@ -395,6 +395,9 @@ int build_schedule(Symbolic &S) {
     S.small_ptr.assign(S.nlevels + 1, 0);
     S.small_tasks.clear();
     S.small_flops.assign(S.nlevels, 0.0);
+    S.tiny_ptr.assign(S.nlevels + 1, 0);
+    S.tiny_tasks.clear();
+    S.tiny_flops.assign(S.nlevels, 0.0);
     auto is_small = [&](int32_t s) {
         return S.super_ptr[s + 1] - S.super_ptr[s] <= kSmallW && S.rptr[s + 1] - S.rptr[s] <= kSmallM;
     };
@@ -402,18 +405,22 @@ int build_schedule(Symbolic &S) {
         std::vector<int32_t> big;
         for (int32_t s : bylevel[l]) {
             if (is_small(s)) {
-                S.small_tasks.push_back(SmallTask{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s,
-                                                  (int32_t)(S.rptr[s + 1] - S.rptr[s]),
-                                                  S.super_ptr[s + 1] - S.super_ptr[s], S.super_ptr[s]});
+                const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
+                const int64_t mi = S.rptr[s + 1] - S.rptr[s];
+                const bool tiny = wi <= kTinyW && mi <= kTinyM;
+                (tiny ? S.tiny_tasks : S.small_tasks)
+                    .push_back(SmallTask{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s, (int32_t)mi, wi,
+                                         S.super_ptr[s]});
                 // POTRF + TRSM + SYRK of the rows below (LAPACK counts)
-                const double w = S.super_ptr[s + 1] - S.super_ptr[s], m = (double)(S.rptr[s + 1] - S.rptr[s]);
-                S.small_flops[l] += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 + (m - w) * w * w +
-                                    (m - w) * (m - w + 1) * w;
+                const double w = wi, m = (double)mi;
+                (tiny ? S.tiny_flops : S.small_flops)[l] += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 +
+                                                            (m - w) * w * w + (m - w) * (m - w + 1) * w;
             } else {
                 big.push_back(s);
             }
         }
         S.small_ptr[l + 1] = (int64_t)S.small_tasks.size();
+        S.tiny_ptr[l + 1] = (int64_t)S.tiny_tasks.size();
         bylevel[l].swap(big);
     }
     for (int32_t l = 0; l < S.nlevels; ++l) {

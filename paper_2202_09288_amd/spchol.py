@@ -41,10 +41,11 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
-                  "small": 6}
+                  "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
 KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": "k_tiles<{t}, 0>",
                 "scatter": "k_tiles<{t}, 1>", "scatter_big": "k_tiles128<{t}>", "small": "k_small<{t}>",
+                "tiny": "k_tiny<{t}>",
                 "assemble": "k_zero<{t}> + k_assemble<{t}>"}
 
 
