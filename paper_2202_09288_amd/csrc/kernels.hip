@@ -660,15 +660,16 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
 
 // ---------------------------------------------------------------------------
 // k_tiles128: the scatter update on 128x128 tiles for the large supernodes
-// (same operation as k_tiles in MODE_SCATTER).  4 waves in a 2x2 grid of 64x64 quadrants, each a 4x4
-// set of 16x16x4 MFMA blocks; K staged through LDS 16 at a time with the
-// next chunk in registers while the current one is consumed.  The epilogue
-// goes through LDS in four passes of 32 columns.
+// (same operation as k_tiles in MODE_SCATTER).  8 waves in a 2x4 grid of
+// 64x32 sub-tiles, each a 4x2 set of 16x16x4 MFMA blocks, so two waves share
+// each SIMD and hide each other's MFMA latency; K staged through LDS 16 at a
+// time with the next chunk in registers while the current one is consumed.
+// The epilogue goes through LDS in four passes of 32 columns.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
+__global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                   const int32_t *rel, T *Lx) {
-    constexpr int TM = 128, KB = 16, PADA = 4, CPT = 16;
+    constexpr int TM = 128, KB = 16, PADA = 4, CPT = 8, NT = 512;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T smem[2 * KB * (TM + PADA)];
     __shared__ int64_t cb[TM], cr[TM];
@@ -678,13 +679,13 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     const int64_t m = tk.m;
     T *P = Lx + tk.loff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    acc_t acc[4][4];
+    const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
+    acc_t acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    // loader: thread covers row lr (0..127) and k-rows lk, lk+2, ..., lk+14
+        for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    // loader: thread covers row lr (0..127) and k-rows lk, lk+4, lk+8, lk+12
     const int lr = tid & 127, lk = tid >> 7;
     const bool row_ok = tk.i0 + lr < m;
     const bool col_ok = tk.j0 + lr < tk.jmax;
@@ -695,11 +696,11 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
     }
-    T ra[KB / 2], rb[KB / 2];
+    T ra[KB / 4], rb[KB / 4];
     auto load = [&](int kb) {
 #pragma unroll
-        for (int e = 0; e < KB / 2; ++e) {
-            const int64_t k = min(kb + lk + 2 * e, tk.k1 - 1);
+        for (int e = 0; e < KB / 4; ++e) {
+            const int64_t k = min(kb + lk + 4 * e, tk.k1 - 1);
             ra[e] = pa[k * m];
             rb[e] = pb[k * m];
         }
@@ -707,55 +708,55 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
     load(tk.k0);
     for (int kb = tk.k0; kb < tk.k1; kb += KB) {
 #pragma unroll
-        for (int e = 0; e < KB / 2; ++e) {
-            const bool kin = kb + lk + 2 * e < tk.k1;
-            As[lk + 2 * e][lr] = (kin && row_ok) ? ra[e] : T(0);
-            Bs[lk + 2 * e][lr] = (kin && col_ok) ? rb[e] : T(0);
+        for (int e = 0; e < KB / 4; ++e) {
+            const bool kin = kb + lk + 4 * e < tk.k1;
+            As[lk + 4 * e][lr] = (kin && row_ok) ? ra[e] : T(0);
+            Bs[lk + 4 * e][lr] = (kin && col_ok) ? rb[e] : T(0);
         }
         __syncthreads();
         if (kb + KB < tk.k1) load(kb + KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
-            T af[4], bf[4];
+            T af[4], bf[2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) af[a] = As[kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
+                for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
         }
         __syncthreads();
     }
-    // epilogue: 4 passes of 32 columns staged as Cs[32][128 + 1]
+    // epilogue: 4 passes of 32 columns staged as Cs[32][128 + 1]; in pass p
+    // the two waves with wc = 32 p stage their columns, then thread (row r,
+    // quarter cq) adds 8 of them
     T(*Cs)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
-    const int r = tid & 127, ch = tid >> 7;  // row, column half of the pass
+    const int r = tid & 127, cq = tid >> 7;
     const int64_t gi = tk.i0 + r;
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         int32_t rv[CPT];
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
-            const int c = 32 * pass + ch * CPT + cc;
+            const int c = 32 * pass + cq * CPT + cc;
             const int64_t gj = min(tk.j0 + c, tk.jmax - 1);
             rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
         }
-        // the waves holding columns [32 pass, 32 pass + 32) stage them
+        if (wc == 32 * pass)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = wc + b * 16 + (lane & 15);
-                if ((c >> 5) != pass) continue;
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Cs[c & 31][wr + a * 16 + Mfma<T>::row(lane, v)] = acc[a][b][v];
-            }
+                    for (int v = 0; v < 4; ++v)
+                        Cs[b * 16 + (lane & 15)][wr + a * 16 + Mfma<T>::row(lane, v)] = acc[a][b][v];
         __syncthreads();
         if (gi < m) {
 #pragma unroll
             for (int cc = 0; cc < CPT; ++cc) {
-                const int c = 32 * pass + ch * CPT + cc;
+                const int c = 32 * pass + cq * CPT + cc;
                 const int64_t gj = tk.j0 + c;
                 if (gj >= tk.jmax || gj > gi) continue;
                 atomicAdd(&Lx[cb[c] + rv[cc]], -Cs[c & 31][r]);
@@ -763,6 +764,7 @@ __global__ __launch_bounds__(256) void k_tiles128(const TileTask *tasks, const i
         }
         __syncthreads();
     }
+    (void)NT;
 }
 
 // ---------------------------------------------------------------------------
@@ -1309,7 +1311,7 @@ void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_tiles128<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_tiles128<T>, dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
                        P.ext_tiles_big + t0, P.cbase, P.crel, P.rel, Lx);
 }
 

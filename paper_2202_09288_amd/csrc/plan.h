@@ -26,6 +26,13 @@ constexpr int kTinyM = 64;
 // triangle gets an explicit inverse in the inverse store.
 constexpr int kNB = 64;
 constexpr int kPanelNB = kNB;
+// Column blocks per bulk trailing update: the columns beyond a group of
+// kDelay blocks are updated once, with all of the group's panels (K =
+// kDelay * kNB), while each next block inside the group is brought up to
+// date on its own just before it is factored.  Measured on the 60^3 grid:
+// 1 -> 16.3 ms, 2 -> 16.6, 3 -> 17.0, 4 -> 17.3 (the column-only launches
+// lengthen the chain of dependent steps more than the deeper updates save).
+constexpr int kDelay = 1;
 constexpr int kSolveNB = kNB;
 // Rows of one solve-update task.
 constexpr int kSolveRows = 256;

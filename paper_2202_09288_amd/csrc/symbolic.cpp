@@ -438,8 +438,15 @@ int build_schedule(Symbolic &S) {
             st.f0 = (int64_t)S.potrf_tasks.size();
             st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
-            // trailing tiles: pass 0 the columns of block b+1 (its diagonal
-            // tile first: that workgroup also factors block b+1), pass 1 the rest
+            // Blocks go in groups of kDelay.  Inside a group, step b brings
+            // block b+1's columns up to date with the group's panels so far
+            // (one column of tiles, K = the group's columns up to b) and
+            // factors block b+1 in that column's diagonal tile; the last step
+            // of a group updates every column beyond with all of the group's
+            // panels at once (K = kDelay blocks).  Pass 0 emits the columns of
+            // block b+1 (diagonal tile first), pass 1 the columns beyond.
+            const int64_t gb = b - b % kDelay;  // first block of b's group
+            const bool bulk = b % kDelay == kDelay - 1;
             for (int pass = 0; pass < 2; ++pass) {
                 if (pass == 1) st.tm = (int64_t)S.int_tiles.size();
                 for (int32_t s : bylevel[l]) {
@@ -450,15 +457,20 @@ int build_schedule(Symbolic &S) {
                     int32_t blk = first_blk[s] + (int32_t)b;
                     const double nbd = (double)(c1 - c0);
                     const int64_t cx = std::min<int64_t>(c1 + kNB, w);  // end of block b+1
+                    const int64_t k0 = gb * kNB;                         // the group's first column
+                    const double kd = (double)(c1 - k0);
+                    // the last block of a supernode closes its group too
+                    const bool close = bulk || cx >= w;
                     if (pass == 0) {
                         // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                         // SYRK k n(n+1), GEMM 2 m n k
                         const double nx = (double)(cx - c1), tot = (double)(w - c1);
                         if (c1 < w)  // block b+1's POTRF runs in this step's column update
                             st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
-                        st.look_flops += nx * (nx + 1) * nbd + 2.0 * ((double)(m - c1) - nx) * nx * nbd;
-                        st.rest_flops += tot * (tot + 1) * nbd + 2.0 * (double)(m - w) * tot * nbd -
-                                         (nx * (nx + 1) * nbd + 2.0 * ((double)(m - c1) - nx) * nx * nbd);
+                        st.look_flops += nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd;
+                        if (close)
+                            st.rest_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
+                                             (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
                         // block 0 gets a POTRF task; block b+1 is factored by the
                         // workgroup of its diagonal tile in step b's column update
                         if (b == 0) {
@@ -473,14 +485,15 @@ int build_schedule(Symbolic &S) {
                                                             (int32_t)c0, (int32_t)c0, (int32_t)c1, (int32_t)c1,
                                                             blk});
                     }
-                    // trailing update inside the panel: rows [c1, m), cols [c1, w);
-                    // K is one block (<= 64), where 64x64 tiles do better than 128
+                    if (pass == 1 && !close) continue;
+                    // trailing update inside the panel by the group's panels:
+                    // rows [j0, m), columns [j0, ...) with j0 >= c1, K = [k0, c1)
                     const int64_t j0a = pass == 0 ? c1 : c1 + kTile, j0b = pass == 0 ? cx : w;
                     for (int64_t j0 = j0a; j0 < j0b; j0 += kTile)
                         for (int64_t i0 = j0; i0 < m; i0 += kTile) {
                             const bool fuse = i0 == c1 && j0 == c1;
                             S.int_tiles.push_back(TileTask{S.lptr[s], fuse ? S.inv_off[blk + 1] : S.rptr[s], s,
-                                                           (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)c0,
+                                                           (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)k0,
                                                            (int32_t)c1, (int32_t)w,
                                                            fuse ? (int32_t)(S.super_ptr[s] + c1) : -1});
                         }
