@@ -207,6 +207,23 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
                       int nrhs, int64_t ld, double tol, int maxit, void *stream,
                       spc_refine_info *info);
 
+/*
+ * spc_batch_solve_refined -- spc_solve_refined for every system of a batch
+ * at once: one merged solve per step serves all systems, while the norms,
+ * the backward error and the conjugate-gradient coefficients are kept per
+ * system and right-hand side, so each system converges (and is judged)
+ * on its own.  A is the matrix of the last spc_batch_factorize.
+ *   d_B[i]  system i's right-hand sides (device, n_i x nrhs column-major,
+ *           leading dimension ld[i] >= n_i), not modified
+ *   d_X[i]  receives system i's solution (same layout)
+ *   infos   nullable host array [count]: per-system result
+ * d_B, d_X and ld are host arrays.  Returns SPC_NO_CONVERGENCE if any
+ * system missed tol; returns after the stream has drained.
+ */
+int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const *d_X, int nrhs,
+                            const int64_t *ld, double tol, int maxit, void *stream,
+                            spc_refine_info *infos);
+
 /* Wait for the factor's work on its stream; SPC_NOT_SPD if a pivot failed,
  * with *bad_pivot (nullable) set to the permuted column of the first
  * failing pivot found, else -1. */

@@ -89,8 +89,9 @@ struct spc_batch_s {
     double *vbuf = nullptr;      // concatenated values
     double *bbuf = nullptr;      // merged right-hand sides
     size_t bbuf_bytes = 0;
-    void *meta = nullptr;        // device: pointer table, leading dims, row offsets
+    void *meta = nullptr;        // device: pointer table, leading dims, row offsets, second pointer table
     size_t meta_bytes = 0;
+    int32_t *rowseg = nullptr;   // device: system of each merged row (refinement)
 };
 
 namespace {
@@ -418,121 +419,155 @@ double bits_to_double(unsigned long long b) {
     return d;
 }
 
+// What one refinement runs on: the factor whose solve is the
+// preconditioner, the full-A CSR with the caller values it points into,
+// and, for a batch, the system of every row (the rows of a system are
+// contiguous); every norm, dot product and coefficient is then kept per
+// system and column, so each system refines as if it were alone.
+struct RefineTarget {
+    spc_factor f = nullptr;
+    const int64_t *rp = nullptr, *vm = nullptr;
+    const int32_t *ci = nullptr;
+    const double *values = nullptr;
+    int64_t n = 0;
+    const int32_t *seg = nullptr;  // row -> system, or null (one system)
+    int nseg = 1;
+};
+
 // One chunk of q <= kRefineChunk right-hand sides.  x0 = low-precision
 // solve; then each step computes r = b - A x in FP64 and the backward error
-//   eta_k = ||r_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf).
-// Classical refinement (x += solve(r)) runs while eta at least halves every
-// two steps; after that, conjugate gradients in FP64 preconditioned by the
-// factor (M^{-1} = solve) continue from the current x.  Stops at
-// max_k eta_k <= tol or after maxit steps of either kind.
-int refine_chunk(spc_factor f, const double *d_values, const double *B, double *X, int q, int64_t ld, double tol,
-                 int maxit, hipStream_t st, RefineResult *res) {
-    const spc::Symbolic &S = f->sym->S;
-    const int64_t n = S.n;
+//   eta_k = ||r_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf)
+// per system and column.  Classical refinement (x += solve(r)) runs while
+// the largest eta at least halves every two steps; after that, conjugate
+// gradients in FP64 preconditioned by the factor (M^{-1} = solve) continue
+// from the current x, with alpha and beta per system and column (the
+// preconditioner is block diagonal over the systems, so the iterations of
+// different systems do not mix).  Stops when every eta <= tol or after
+// maxit steps of either kind.  res[s] receives system s's result; its
+// iteration count is the step at which all its columns first met tol.
+int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64_t ld, double tol, int maxit,
+                 hipStream_t st, RefineResult *res) {
+    const int64_t n = T.n;
+    const int ns = T.nseg;
     constexpr int C = kRefineChunk;
+    const int64_t K = (int64_t)C * ns;  // (column, system) slots
     // workspace: 7 vectors of n x C (leading dimension n), then scalars
     const size_t vec = ((size_t)n * C * sizeof(double) + 255) & ~size_t(255);
-    const size_t scal = 16 * C * sizeof(double);
-    int rc = ensure_bytes((void **)&f->refine, &f->refine_bytes, 7 * vec + scal);
+    const size_t scal = (size_t)(7 * K + ns) * sizeof(double);
+    int rc = ensure_bytes((void **)&T.f->refine, &T.f->refine_bytes, 7 * vec + scal);
     if (rc) return rc;
-    char *base = (char *)f->refine;
+    char *base = (char *)T.f->refine;
     double *Bw = (double *)base, *Xw = (double *)(base + vec), *Tv = (double *)(base + 2 * vec),
            *Rv = (double *)(base + 3 * vec), *Zv = (double *)(base + 4 * vec), *Pv = (double *)(base + 5 * vec),
            *Qv = (double *)(base + 6 * vec);
-    unsigned long long *umax = (unsigned long long *)(base + 7 * vec);  // r[C], x[C], b[C], |A|
-    double *dots = (double *)(umax + 4 * C);                               // [C]
-    double *coef = dots + C;                                               // alpha[C], -alpha[C], beta[C]
-    const int64_t *rp = f->sym->d_csr_ptr, *vm = f->sym->d_csr_val;
-    const int32_t *ci = f->sym->d_csr_col;
+    unsigned long long *umax = (unsigned long long *)(base + 7 * vec);  // r[K], x[K], b[K], |A|[ns]
+    double *dots = (double *)(umax + 3 * K + ns);                          // [K]
+    double *coef = dots + K;                                               // alpha[K], -alpha[K], beta[K]
+    auto colmax = [&](const double *V, unsigned long long *out) {
+        if (T.seg) spc::launch_seg_colmax(V, T.seg, n, q, n, ns, out, st);
+        else spc::launch_colmax(V, n, q, n, out, st);
+    };
+    auto axpby = [&](const double *a, double a0, const double *Xv, const double *bb, double b0, double *Y) {
+        if (T.seg) spc::launch_seg_axpby(a, a0, Xv, bb, b0, Y, T.seg, n, q, n, ns, st);
+        else spc::launch_axpby(a, a0, Xv, bb, b0, Y, n, q, n, st);
+    };
 
     spc::launch_copy_cols(B, ld, Bw, n, n, q, st);
     spc::launch_copy_cols(Bw, n, Xw, n, n, q, st);
-    rc = spc_solve(f, Xw, q, n, st);
+    rc = spc_solve(T.f, Xw, q, n, st);
     if (rc) return rc;
-    spc::launch_zero<unsigned long long>(umax, 4 * C, st);
-    spc::launch_norm_inf_A(rp, vm, d_values, n, umax + 3 * C, st);
-    spc::launch_colmax(Bw, n, q, n, umax + 2 * C, st);
+    spc::launch_zero<unsigned long long>(umax, 3 * K + ns, st);
+    if (T.seg) spc::launch_seg_norm_inf_A(T.rp, T.vm, T.values, T.seg, n, umax + 3 * K, st);
+    else spc::launch_norm_inf_A(T.rp, T.vm, T.values, n, umax + 3 * K, st);
+    colmax(Bw, umax + 2 * K);
 
-    std::vector<unsigned long long> hb(4 * C);
-    std::vector<double> hdot(C), hcoef(3 * C);
-    std::vector<double> eta_hist, rho(C, 0.0);
-    std::vector<char> frozen(C, 0);
+    std::vector<unsigned long long> hb(3 * K + ns);
+    std::vector<double> hdot(K), hcoef(3 * K);
+    std::vector<double> eta_hist, rho(K, 0.0), eta_s(ns);
+    std::vector<char> frozen(K, 0), done(ns, 0);
     bool cg = false, cg_started = false;
     int it = 0;
     auto dot = [&](const double *U, const double *V) -> int {
-        HIP_TRY(hipMemsetAsync(dots, 0, C * sizeof(double), st));
-        spc::launch_coldot(U, V, n, q, n, dots, st);
-        HIP_TRY(hipMemcpyAsync(hdot.data(), dots, C * sizeof(double), hipMemcpyDeviceToHost, st));
+        spc::launch_zero<double>(dots, K, st);
+        if (T.seg) spc::launch_seg_coldot(U, V, T.seg, n, q, n, ns, dots, st);
+        else spc::launch_coldot(U, V, n, q, n, dots, st);
+        HIP_TRY(hipMemcpyAsync(hdot.data(), dots, K * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         return SPC_OK;
     };
     for (;;) {
-        spc::launch_spmv(rp, ci, vm, d_values, Xw, Bw, Tv, n, q, n, st);  // T = b - A x
-        spc::launch_zero<unsigned long long>(umax, 2 * C, st);
-        spc::launch_colmax(Tv, n, q, n, umax, st);
-        spc::launch_colmax(Xw, n, q, n, umax + C, st);
-        HIP_TRY(hipMemcpyAsync(hb.data(), umax, 4 * C * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, q, n, st);  // T = b - A x
+        spc::launch_zero<unsigned long long>(umax, 2 * K, st);
+        colmax(Tv, umax);
+        colmax(Xw, umax + K);
+        HIP_TRY(hipMemcpyAsync(hb.data(), umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               st));
         HIP_TRY(hipStreamSynchronize(st));
-        const double normA = bits_to_double(hb[3 * C]);
         double eta = 0.0;
-        for (int k = 0; k < q; ++k) {
-            const double rn = bits_to_double(hb[k]), xn = bits_to_double(hb[C + k]), bn = bits_to_double(hb[2 * C + k]);
-            const double den = normA * xn + bn;
-            double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
-            if (std::isnan(e)) e = INFINITY;
-            frozen[k] = e <= tol;
-            eta = std::max(eta, e);
+        std::fill(eta_s.begin(), eta_s.end(), 0.0);
+        for (int k = 0; k < q; ++k)
+            for (int sg = 0; sg < ns; ++sg) {
+                const int64_t j = (int64_t)k * ns + sg;
+                const double normA = bits_to_double(hb[3 * K + sg]);
+                const double rn = bits_to_double(hb[j]), xn = bits_to_double(hb[K + j]),
+                             bn = bits_to_double(hb[2 * K + j]);
+                const double den = normA * xn + bn;
+                double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+                if (std::isnan(e)) e = INFINITY;
+                frozen[j] = e <= tol;
+                eta_s[sg] = std::max(eta_s[sg], e);
+                eta = std::max(eta, e);
+            }
+        for (int sg = 0; sg < ns; ++sg) {
+            res[sg].berr = eta_s[sg];
+            res[sg].converged = eta_s[sg] <= tol;
+            if (!done[sg]) res[sg].iterations = it;
+            if (res[sg].converged) done[sg] = 1;
         }
         eta_hist.push_back(eta);
-        res->berr = eta;
-        res->iterations = it;
-        if (eta <= tol) {
-            res->converged = true;
-            break;
-        }
-        if (it >= maxit) break;
+        if (eta <= tol || it >= maxit) break;
         const size_t h = eta_hist.size();
         if (!cg && h >= 3 && !(eta_hist[h - 1] <= 0.5 * eta_hist[h - 3])) cg = true;
         ++it;
         if (!cg) {
             spc::launch_copy_cols(Tv, n, Zv, n, n, q, st);
-            rc = spc_solve(f, Zv, q, n, st);  // d = M^{-1} r
+            rc = spc_solve(T.f, Zv, q, n, st);  // d = M^{-1} r
             if (rc) return rc;
-            spc::launch_axpby(nullptr, 1.0, Zv, nullptr, 1.0, Xw, n, q, n, st);  // x += d
+            axpby(nullptr, 1.0, Zv, nullptr, 1.0, Xw);  // x += d
             continue;
         }
         if (!cg_started) {
             // r = b - A x, z = M^{-1} r, p = z, rho = r.z
             spc::launch_copy_cols(Tv, n, Rv, n, n, q, st);
             spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
-            rc = spc_solve(f, Zv, q, n, st);
+            rc = spc_solve(T.f, Zv, q, n, st);
             if (rc) return rc;
             spc::launch_copy_cols(Zv, n, Pv, n, n, q, st);
             if ((rc = dot(Rv, Zv))) return rc;
-            for (int k = 0; k < q; ++k) rho[k] = hdot[k];
+            for (int64_t j = 0; j < K; ++j) rho[j] = hdot[j];
             cg_started = true;
         }
-        spc::launch_spmv(rp, ci, vm, d_values, Pv, nullptr, Qv, n, q, n, st);  // q = A p
+        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Pv, nullptr, Qv, n, q, n, st);  // q = A p
         if ((rc = dot(Pv, Qv))) return rc;
-        for (int k = 0; k < q; ++k) {
-            const double a = (!frozen[k] && hdot[k] > 0.0 && std::isfinite(rho[k] / hdot[k])) ? rho[k] / hdot[k] : 0.0;
-            hcoef[k] = a;
-            hcoef[C + k] = -a;
+        for (int64_t j = 0; j < K; ++j) {
+            const double a = (!frozen[j] && hdot[j] > 0.0 && std::isfinite(rho[j] / hdot[j])) ? rho[j] / hdot[j] : 0.0;
+            hcoef[j] = a;
+            hcoef[K + j] = -a;
         }
-        HIP_TRY(hipMemcpyAsync(coef, hcoef.data(), 2 * C * sizeof(double), hipMemcpyHostToDevice, st));
-        spc::launch_axpby(coef, 0.0, Pv, nullptr, 1.0, Xw, n, q, n, st);      // x += alpha p
-        spc::launch_axpby(coef + C, 0.0, Qv, nullptr, 1.0, Rv, n, q, n, st);  // r -= alpha q
+        HIP_TRY(hipMemcpyAsync(coef, hcoef.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
+        axpby(coef, 0.0, Pv, nullptr, 1.0, Xw);      // x += alpha p
+        axpby(coef + K, 0.0, Qv, nullptr, 1.0, Rv);  // r -= alpha q
         spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
-        rc = spc_solve(f, Zv, q, n, st);  // z = M^{-1} r
+        rc = spc_solve(T.f, Zv, q, n, st);  // z = M^{-1} r
         if (rc) return rc;
         if ((rc = dot(Rv, Zv))) return rc;
-        for (int k = 0; k < q; ++k) {
-            const double b = (rho[k] != 0.0 && std::isfinite(hdot[k] / rho[k])) ? hdot[k] / rho[k] : 0.0;
-            hcoef[2 * C + k] = frozen[k] ? 0.0 : b;
-            if (!frozen[k]) rho[k] = hdot[k];
+        for (int64_t j = 0; j < K; ++j) {
+            const double bt = (rho[j] != 0.0 && std::isfinite(hdot[j] / rho[j])) ? hdot[j] / rho[j] : 0.0;
+            hcoef[2 * K + j] = frozen[j] ? 0.0 : bt;
+            if (!frozen[j]) rho[j] = hdot[j];
         }
-        HIP_TRY(hipMemcpyAsync(coef + 2 * C, hcoef.data() + 2 * C, C * sizeof(double), hipMemcpyHostToDevice, st));
-        spc::launch_axpby(nullptr, 1.0, Zv, coef + 2 * C, 0.0, Pv, n, q, n, st);  // p = z + beta p
+        HIP_TRY(hipMemcpyAsync(coef + 2 * K, hcoef.data() + 2 * K, K * sizeof(double), hipMemcpyHostToDevice, st));
+        axpby(nullptr, 1.0, Zv, coef + 2 * K, 0.0, Pv);  // p = z + beta p
     }
     spc::launch_copy_cols(Xw, n, X, ld, n, q, st);
     HIP_TRY(hipGetLastError());
@@ -546,6 +581,7 @@ void batch_release(spc_batch_s *b) {
     if (b->vbuf) (void)hipFree(b->vbuf);
     if (b->bbuf) (void)hipFree(b->bbuf);
     if (b->meta) (void)hipFree(b->meta);
+    if (b->rowseg) (void)hipFree(b->rowseg);
     if (b->merged) sym_release(b->merged);
     for (spc_symbolic_s *m : b->members) sym_release(m);
     b->magic = kDead;
@@ -725,7 +761,14 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
     for (int q0 = 0; q0 < nrhs; q0 += kRefineChunk) {
         const int q = std::min(kRefineChunk, nrhs - q0);
         RefineResult res;
-        rc = refine_chunk(f, d_values, d_B + (int64_t)q0 * ld, d_X + (int64_t)q0 * ld, q, ld, tol, maxit, st, &res);
+        RefineTarget T;
+        T.f = f;
+        T.rp = f->sym->d_csr_ptr;
+        T.vm = f->sym->d_csr_val;
+        T.ci = f->sym->d_csr_col;
+        T.values = d_values;
+        T.n = n;
+        rc = refine_chunk(T, d_B + (int64_t)q0 * ld, d_X + (int64_t)q0 * ld, q, ld, tol, maxit, st, &res);
         if (rc) return rc;
         worst = std::max(worst, res.iterations);
         worst_berr = std::max(worst_berr, res.berr);
@@ -873,8 +916,9 @@ int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_bat
     if (rc == SPC_OK && hipMalloc((void **)&b->vbuf, std::max<int64_t>(1, b->val_off[count]) * sizeof(double)) !=
                             hipSuccess)
         rc = SPC_OUT_OF_MEMORY;
-    // meta: pointer table [count], leading dims [count], row offsets [count + 1]
-    b->meta_bytes = sizeof(double *) * count + sizeof(int64_t) * (2 * count + 1);
+    // meta: pointer table [count], leading dims [count], row offsets
+    // [count + 1], second pointer table [count]
+    b->meta_bytes = 2 * sizeof(double *) * count + sizeof(int64_t) * (2 * count + 1);
     if (rc == SPC_OK && hipMalloc(&b->meta, b->meta_bytes) != hipSuccess) rc = SPC_OUT_OF_MEMORY;
     if (rc == SPC_OK &&
         hipMemcpy((char *)b->meta + sizeof(double *) * count + sizeof(int64_t) * count, b->col_off.data(),
@@ -956,6 +1000,81 @@ int spc_batch_solve(spc_batch b, double *const *d_B, int nrhs, const int64_t *ld
     // so the caller may reuse its host arrays
     HIP_TRY(hipStreamSynchronize(st));
     return SPC_OK;
+}
+
+int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const *d_X, int nrhs, const int64_t *ld,
+                            double tol, int maxit, void *stream, spc_refine_info *infos) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    if (nrhs < 0 || maxit < 0 || !(tol >= 0.0) || (nrhs > 0 && (!d_B || !d_X || !ld))) return SPC_INVALID_INPUT;
+    const int cnt = b->count;
+    if (nrhs > 0)
+        for (int i = 0; i < cnt; ++i) {
+            const int64_t ni = b->col_off[i + 1] - b->col_off[i];
+            if (ld[i] < ni || (ni > 0 && (!d_B[i] || !d_X[i]))) return SPC_INVALID_INPUT;
+        }
+    if (infos)
+        for (int i = 0; i < cnt; ++i) infos[i] = spc_refine_info{0, 1, 0.0};
+    const int64_t n = b->col_off[cnt];
+    if (nrhs == 0 || n == 0) return SPC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_csr(b->merged);
+    if (rc) return rc;
+    if (!b->rowseg) {
+        std::vector<int32_t> seg(n);
+        for (int i = 0; i < cnt; ++i)
+            std::fill(seg.begin() + b->col_off[i], seg.begin() + b->col_off[i + 1], (int32_t)i);
+        int32_t *d = nullptr;
+        HIP_TRY(hipMalloc((void **)&d, n * sizeof(int32_t)));
+        hipError_t e = hipMemcpy(d, seg.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return record_error(e, "row systems upload", __LINE__);
+        }
+        b->rowseg = d;
+    }
+    rc = ensure_bytes((void **)&b->bbuf, &b->bbuf_bytes, (size_t)n * nrhs * sizeof(double));
+    if (rc) return rc;
+    char *meta = (char *)b->meta;
+    double **ptrs = (double **)meta;
+    int64_t *lds = (int64_t *)(meta + sizeof(double *) * cnt);
+    int64_t *offs = lds + cnt;
+    double **xptrs = (double **)(offs + cnt + 1);
+    HIP_TRY(hipMemcpyAsync(ptrs, d_B, sizeof(double *) * cnt, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(xptrs, d_X, sizeof(double *) * cnt, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(lds, ld, sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st));
+    spc::launch_batch_move(ptrs, lds, offs, b->bbuf, n, cnt, nrhs, true, st);
+    RefineTarget T;
+    T.f = b->F;
+    T.rp = b->merged->d_csr_ptr;
+    T.vm = b->merged->d_csr_val;
+    T.ci = b->merged->d_csr_col;
+    T.values = b->vbuf;
+    T.n = n;
+    T.seg = b->rowseg;
+    T.nseg = cnt;
+    std::vector<RefineResult> res(cnt);
+    bool all_conv = true;
+    for (int q0 = 0; q0 < nrhs; q0 += kRefineChunk) {
+        const int q = std::min(kRefineChunk, nrhs - q0);
+        std::vector<RefineResult> part(cnt);
+        double *Bq = b->bbuf + (int64_t)q0 * n;
+        rc = refine_chunk(T, Bq, Bq, q, n, tol, maxit, st, part.data());
+        if (rc) return rc;
+        for (int i = 0; i < cnt; ++i) {
+            res[i].iterations = std::max(res[i].iterations, part[i].iterations);
+            res[i].berr = std::max(res[i].berr, part[i].berr);
+            res[i].converged = (q0 == 0 || res[i].converged) && part[i].converged;
+            all_conv = all_conv && part[i].converged;
+        }
+    }
+    spc::launch_batch_move(xptrs, lds, offs, b->bbuf, n, cnt, nrhs, false, st);
+    HIP_TRY(hipGetLastError());
+    // the pointer tables are read by the kernels above
+    HIP_TRY(hipStreamSynchronize(st));
+    if (infos)
+        for (int i = 0; i < cnt; ++i)
+            infos[i] = spc_refine_info{res[i].iterations, res[i].converged ? 1 : 0, res[i].berr};
+    return all_conv ? SPC_OK : SPC_NO_CONVERGENCE;
 }
 
 int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {

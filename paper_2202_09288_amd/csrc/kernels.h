@@ -96,6 +96,17 @@ void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_
 void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
                   int nrhs, int64_t ld, hipStream_t st);
 void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st);
+// segmented forms (batches): row i belongs to system seg[i]; results and
+// coefficients per (column q, system) at q * nseg + seg[i]; norm_inf_A per
+// system
+void launch_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, const int32_t *seg,
+                           int64_t n, unsigned long long *out, hipStream_t st);
+void launch_seg_colmax(const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg,
+                       unsigned long long *out, hipStream_t st);
+void launch_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld,
+                       int nseg, double *out, hipStream_t st);
+void launch_seg_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y,
+                      const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg, hipStream_t st);
 void launch_batch_move(double *const *ptrs, const int64_t *lds, const int64_t *offs, double *M, int64_t n,
                        int count, int nrhs, bool to_merged, hipStream_t st);
 

@@ -1242,6 +1242,74 @@ __global__ void k_batch_move(double *const *ptrs, const int64_t *lds, const int6
     }
 }
 
+// Segmented forms for batches: row i belongs to system seg[i] (the rows of
+// a system are contiguous and the ids ascend), and every reduction or
+// coefficient is kept per (column q, system) at index q * nseg + seg[i].
+// One row per thread: a wave whose rows all lie in one system reduces in
+// registers and makes one atomic; a wave across a boundary makes one per
+// row.  Lanes past n contribute the identity (0 for max of magnitudes and
+// for sums).
+__device__ inline bool wave_in_one_segment(int s) { return __shfl(s, 0) == __shfl(s, 63); }
+
+__global__ void k_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values,
+                                 const int32_t *seg, int64_t n, unsigned long long *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = seg[i < n ? i : n - 1];
+    double sum = 0.0;
+    if (i < n)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) sum += fabs(values[valmap[e]]);
+    if (wave_in_one_segment(s)) {
+        for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(&out[s], (unsigned long long)__double_as_longlong(sum));
+    } else if (i < n) {
+        atomicMax(&out[s], (unsigned long long)__double_as_longlong(sum));
+    }
+}
+
+__global__ void k_seg_colmax(const double *V, const int32_t *seg, int64_t n, int64_t ld, int nseg,
+                             unsigned long long *out) {
+    const int q = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ic = i < n ? i : n - 1;
+    const int s = seg[ic];
+    double mx = i < n ? fabs(V[ic + q * ld]) : 0.0;
+    unsigned long long *o = out + (int64_t)q * nseg + s;
+    if (wave_in_one_segment(s)) {
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(o, (unsigned long long)__double_as_longlong(mx));
+    } else if (i < n) {
+        atomicMax(o, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+__global__ void k_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n, int64_t ld, int nseg,
+                             double *out) {
+    const int q = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ic = i < n ? i : n - 1;
+    const int s = seg[ic];
+    double acc = i < n ? U[ic + q * ld] * V[ic + q * ld] : 0.0;
+    double *o = out + (int64_t)q * nseg + s;
+    if (wave_in_one_segment(s)) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0) atomicAdd(o, acc);
+    } else if (i < n) {
+        atomicAdd(o, acc);
+    }
+}
+
+// Y[:, q] = a X[:, q] + b Y[:, q] with a = a[q * nseg + seg[i]] (or a0 when
+// a is null), likewise b; b = 0 does not read Y.
+__global__ void k_seg_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y,
+                            const int32_t *seg, int64_t n, int64_t ld, int nseg) {
+    const int q = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = (int64_t)q * nseg + seg[i];
+    const double aq = a ? a[k] : a0, bq = b ? b[k] : b0;
+    Y[i + q * ld] = (bq == 0.0) ? aq * X[i + q * ld] : aq * X[i + q * ld] + bq * Y[i + q * ld];
+}
+
 inline unsigned grid1(int64_t count, int block) {
     int64_t g = (count + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
@@ -1419,6 +1487,28 @@ void launch_axpby(const double *a, double a0, const double *X, const double *b, 
                   int nrhs, int64_t ld, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
     hipLaunchKernelGGL(k_axpby, dim3(red_grid(n), nrhs), dim3(256), 0, st, a, a0, X, b, b0, Y, n, ld);
+}
+void launch_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, const int32_t *seg,
+                           int64_t n, unsigned long long *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_seg_norm_inf_A, dim3(grid1(n, 256)), dim3(256), 0, st, rowptr, valmap, values, seg, n,
+                       out);
+}
+void launch_seg_colmax(const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg,
+                       unsigned long long *out, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_seg_colmax, dim3(grid1(n, 256), nrhs), dim3(256), 0, st, V, seg, n, ld, nseg, out);
+}
+void launch_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld,
+                       int nseg, double *out, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_seg_coldot, dim3(grid1(n, 256), nrhs), dim3(256), 0, st, U, V, seg, n, ld, nseg, out);
+}
+void launch_seg_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y,
+                      const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_seg_axpby, dim3(grid1(n, 256), nrhs), dim3(256), 0, st, a, a0, X, b, b0, Y, seg, n, ld,
+                       nseg);
 }
 void launch_batch_move(double *const *ptrs, const int64_t *lds, const int64_t *offs, double *M, int64_t n,
                        int count, int nrhs, bool to_merged, hipStream_t st) {

@@ -636,6 +636,7 @@ int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<i
     M.super_ptr.push_back(0);
     M.rptr.push_back(0);
     M.lptr.push_back(0);
+    M.csr_ptr.push_back(0);
     for (size_t i = 0; i < k; ++i) {
         const Symbolic &S = *parts[i];
         const int64_t c0 = col_off[i], p0 = panel_off[i];
@@ -656,6 +657,12 @@ int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<i
         for (int32_t r : S.rows) M.rows.push_back((int32_t)(c0 + r));
         for (int32_t s = 0; s < S.nsuper; ++s) M.status_slot.push_back((int32_t)i);
         for (int64_t a : S.amap) M.amap.push_back(p0 + a);
+        // the full-A CSR of the union: rows and columns shifted by the
+        // part's first column, entries by its first caller value
+        const int64_t e0 = M.csr_ptr.back();
+        for (int64_t r = 0; r < S.n; ++r) M.csr_ptr.push_back(e0 + S.csr_ptr[r + 1]);
+        for (int32_t c : S.csr_col) M.csr_col.push_back((int32_t)(c0 + c));
+        for (int64_t v : S.csr_val) M.csr_val.push_back(val_off[i] + v);
         M.nnzA += S.nnzA;
         M.flops += S.flops;
         M.nnzL += S.nnzL;

@@ -39,7 +39,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string",
            "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
-           "spc_batch_set_profiling", "spc_batch_kernel_stats")
+           "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -89,6 +89,9 @@ _lib.spc_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int
 _lib.spc_batch_factorize.argtypes = [_P, ctypes.POINTER(_P), _P]
 _lib.spc_batch_factor.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_P)]
 _lib.spc_batch_solve.argtypes = [_P, ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_i64), _P]
+_lib.spc_batch_solve_refined.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int,
+                                         ctypes.POINTER(_i64), ctypes.c_double, ctypes.c_int, _P,
+                                         ctypes.POINTER(_RefineInfo)]
 _lib.spc_batch_sync.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.spc_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.spc_batch_info.argtypes = [_P, ctypes.POINTER(_Info)]
@@ -323,6 +326,24 @@ class Batch:
         lds = (_i64 * len(Bs))(*[x.n for x in self.syms])
         _check(_lib.spc_batch_solve(self._h, ptrs, nrhs, lds, _stream_ptr(stream)), "spc_batch_solve")
         return Bs
+
+    def solve_refined(self, Bs, Xs, tol: float = 1e-12, maxit: int = 10, stream=None):
+        """Refined solve of every system (against the values of the last
+        factorize): Bs[i], Xs[i] float64 device tensors (nrhs, n_i); returns
+        the status and one {iterations, converged, berr} per system."""
+        count = len(self.syms)
+        nrhs = 1 if Bs[0].dim() == 1 else Bs[0].shape[0]
+        bp = (_P * count)(*[_dev_ptr(b, "torch.float64") for b in Bs])
+        xp = (_P * count)(*[_dev_ptr(x, "torch.float64") for x in Xs])
+        lds = (_i64 * count)(*[x.n for x in self.syms])
+        infos = (_RefineInfo * count)()
+        rc = _lib.spc_batch_solve_refined(self._h, bp, xp, nrhs, lds, float(tol), int(maxit),
+                                          _stream_ptr(stream), infos)
+        if rc not in (OK, NO_CONVERGENCE):
+            _check(rc, "spc_batch_solve_refined")
+        per = [{"iterations": int(r.iterations), "converged": bool(r.converged), "berr": float(r.berr)}
+               for r in infos]
+        return {"status": rc, "systems": per}
 
     def sync(self):
         sy, col = _i64(-1), _i64(-1)

@@ -364,6 +364,39 @@ def test_batch_alone_equals_in_mix(torch_dev, lib):
         assert oracle.rel_frobenius(b, a, S.lower_mask()) <= 1e-13
 
 
+@pytest.mark.parametrize("nrhs", [3, 17])
+def test_batch_solve_refined_per_system(torch_dev, lib, nrhs):
+    """Merged refinement of an FP32 batch: a system that needs the CG phase
+    (3-dof operator, kappa = 1e8) sits among grids that converge in a few
+    classical steps; each must reach tol on its own, with its own reported
+    error and step count, and 17 right-hand sides span two chunks."""
+    torch = torch_dev
+    systems = small_batch(5, seed=3, nrhs=nrhs)
+    systems.insert(2, W.elasticity27((6, 5, 5), 88, 4, kappa=1e8, nrhs=nrhs, power_iters=50))
+    syms = [lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05) for s in systems]
+    batch = lib.Batch(syms, "fp32")
+    batch.factorize([torch.from_numpy(s.values).cuda() for s in systems])
+    batch.sync()
+    Bs = [torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda() for s in systems]
+    Xs = [torch.zeros_like(b) for b in Bs]
+    out = batch.solve_refined(Bs, Xs, tol=1e-12, maxit=200)
+    assert out["status"] == lib.OK, out
+    for i, s in enumerate(systems):
+        r = out["systems"][i]
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Xs[i].cpu().numpy().T, s.B)
+        print(f"batch refine {s.name}: {r} host eta={eta:.2e}", flush=True)
+        assert r["converged"] and r["berr"] <= 1e-12
+        assert eta <= 1e-12
+        # B is left as given
+        assert np.array_equal(Bs[i].cpu().numpy().T, s.B)
+    hard = out["systems"][2]["iterations"]
+    easy = max(out["systems"][i]["iterations"] for i in range(len(systems)) if i != 2)
+    assert easy < hard
+    out0 = batch.solve_refined(Bs, Xs, tol=1e-15, maxit=0)
+    assert out0["status"] == lib.NO_CONVERGENCE
+    assert all(r["iterations"] == 0 for r in out0["systems"])
+
+
 def test_batch_not_spd_names_system(torch_dev, lib):
     torch = torch_dev
     systems = small_batch(5, seed=2, nrhs=1)
