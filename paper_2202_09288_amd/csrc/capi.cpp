@@ -168,6 +168,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
         {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
+        {S.stiny.data(), bytes_of(S.stiny), (const void **)&P.stiny},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
         {S.stgt_ptr.data(), bytes_of(S.stgt_ptr), (const void **)&P.stgt_ptr},
         {S.stgt.data(), bytes_of(S.stgt), (const void **)&P.stgt},
@@ -201,7 +202,7 @@ size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
            bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
-           bytes_of(S.stasks) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
+           bytes_of(S.stasks) + bytes_of(S.stiny) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
            bytes_of(S.fdep) + bytes_of(S.bwd_order);
 }
 
@@ -306,14 +307,23 @@ void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, c
     spc::launch_zero<T>(Acc, n * nrhs, st);
     spc::launch_solve_reset(P, nb, sy, st);
     const int32_t split = solve_persistent() ? S.solve_split : S.nslevels;
-    for (int32_t l = 0; l < split; ++l)
+    // below solve_split the tiny supernodes of a level have their own
+    // (one-wave) launch beside the level's task launch
+    const int32_t tsplit = S.solve_split;
+    for (int32_t l = 0; l < split; ++l) {
+        if (l < tsplit)
+            spc::launch_solve_tiny_fwd<T>(P, S.stiny_ptr[l], S.stiny_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, st);
         spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, sy, false, st);
+    }
     if (split < S.nslevels) {
         spc::launch_solve_fwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, Y, X, n, nrhs, sy, true, st);
         spc::launch_solve_bwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, X, Acc, n, nrhs, sy, true, st);
     }
-    for (int32_t l = split - 1; l >= 0; --l)
+    for (int32_t l = split - 1; l >= 0; --l) {
+        if (l < tsplit)
+            spc::launch_solve_tiny_bwd<T>(P, S.stiny_ptr[l], S.stiny_ptr[l + 1], Lx, Linv, X, n, nrhs, st);
         spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, n, nrhs, sy, false, st);
+    }
 }
 
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {

@@ -23,6 +23,7 @@ struct DevPlan {
     const TileTask *ext_tiles;
     const TileTask *ext_tiles_big;
     const SolveTask *stasks;
+    const SmallTask *stiny;      // one-wave solve tasks (tiny supernodes)
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
     const int64_t *stgt_ptr;     // persistent solves: target blocks per task
     const int32_t *stgt;
@@ -82,6 +83,13 @@ void launch_solve_reset(const DevPlan &P, int64_t nblocks, SolveSync sy, hipStre
 template <typename T>
 void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);
+// One-wave solve sweeps over the tiny supernodes t0..t1-1 of one level.
+template <typename T>
+void launch_solve_tiny_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
+                           int64_t n, int nrhs, hipStream_t st);
+template <typename T>
+void launch_solve_tiny_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, int64_t n,
+                           int nrhs, hipStream_t st);
 template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);

@@ -1142,6 +1142,148 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// One-wave solves of tiny supernodes (w <= kTinyW, m <= kTinyM), four per
+// workgroup, for the wide bottom levels where nearly every supernode is
+// tiny: lane i holds row position i of R_s, so a supernode costs one wave
+// instead of a workgroup sized for a 64-column block.
+// Forward: x = Linv y on the w diagonal lanes (y_c broadcast from lane c),
+// stored in X; then each row i >= w below takes
+//   Y[rows[i]] -= sum_c L[i][c] x_c      (atomic, as in the block sweep).
+// ---------------------------------------------------------------------------
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_solve_tiny_fwd(const SmallTask *tasks, int64_t ntasks, const int32_t *rows,
+                                                        const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
+                                                        int nrhs) {
+    constexpr int WT = kTinyW;
+    const int lane = threadIdx.x & 63;
+    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ti >= ntasks) return;  // the whole wave
+    const SmallTask tk = tasks[ti];
+    const int m = tk.m, w = tk.w;
+    const T *P = Lx + tk.loff;
+    const T *Q = Linv + tk.ioff;
+    const int rc = min(lane, m - 1), dc = min(lane, w - 1);
+    T l[WT], vi[WT], y[NR];
+#pragma unroll
+    for (int c = 0; c < WT; ++c) l[c] = P[(int64_t)min(c, w - 1) * m + rc];
+#pragma unroll
+    for (int c = 0; c < WT; ++c) vi[c] = Q[dc + min(c, w - 1) * w];  // (L^{-1})[dc][c]
+    const int64_t g = rows[tk.roff + rc];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) y[q] = Y[tk.g0 + dc + (int64_t)min(q, nrhs - 1) * n];
+    T x[NR], acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) x[q] = acc[q] = T(0);
+#pragma unroll
+    for (int c = 0; c < WT; ++c)
+        if (c < w) {
+            const T v = c <= lane ? vi[c] : T(0);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) x[q] += v * lane_read(y[q], c);
+        }
+#pragma unroll
+    for (int c = 0; c < WT; ++c)
+        if (c < w)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q] += l[c] * lane_read(x[q], c);
+    if (lane < w) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (q < nrhs) X[tk.g0 + lane + (int64_t)q * n] = x[q];
+    } else if (lane < m) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (q < nrhs) atomicAdd(&Y[g + (int64_t)q * n], -acc[q]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Backward: t_c = X[g0 + c] - sum_{i >= w} L[i][c] X[rows[i]] for the w
+// columns c (the rows below are ancestors, final already), then
+// x = Linv^T t.  One right-hand side: the sums are wave reductions.
+// Several: the sums form the product (L_below^T)(X_rows), w x 16 with up to
+// 64 rows of contraction, on 16x16x4 MFMA (A: lane l brings L[k][l%16],
+// B: X[rows[k]][l%16], k = 4 s + l/16); t goes through LDS for the final
+// small product with the inverse.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_solve_tiny_bwd(const SmallTask *tasks, int64_t ntasks, const int32_t *rows,
+                                                        const T *Lx, const T *Linv, T *X, int64_t n, int nrhs) {
+    constexpr int WT = kTinyW;
+    __shared__ T ts[4][WT][kMaxRhs + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t tr = (int64_t)blockIdx.x * 4 + wv;
+    const bool active = tr < ntasks;
+    const SmallTask tk = tasks[active ? tr : ntasks - 1];  // idle waves mirror a task, store nothing
+    const int m = tk.m, w = tk.w;
+    const T *P = Lx + tk.loff;
+    const T *Q = Linv + tk.ioff;
+    const int rc = min(lane, m - 1), dc = min(lane, w - 1);
+    const int64_t g = rows[tk.roff + rc];
+    if constexpr (NR == 1) {
+        T l[WT], vt[WT];
+#pragma unroll
+        for (int c = 0; c < WT; ++c) l[c] = P[(int64_t)min(c, w - 1) * m + rc];
+#pragma unroll
+        for (int i = 0; i < WT; ++i) vt[i] = Q[min(i, w - 1) + dc * w];  // (L^{-1})[i][dc]
+        const T xr = (lane >= w && lane < m) ? X[g] : T(0);
+        T t = X[tk.g0 + dc];
+#pragma unroll
+        for (int c = 0; c < WT; ++c)
+            if (c < w) {
+                const T sc = wave_sum(l[c] * xr);
+                if (lane == c) t -= sc;
+            }
+        T xv = T(0);
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+            if (i < w) xv += (i >= lane ? vt[i] : T(0)) * lane_read(t, i);
+        if (active && lane < w) X[tk.g0 + lane] = xv;
+    } else {
+        using acc_t = typename Mfma<T>::acc;
+        const int kq = lane & 15, kr = lane >> 4;
+        T a[16], b[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int k = 4 * s + kr, kc = min(k, m - 1);
+            const int64_t gk = __shfl(g, kc);
+            const bool row_ok = k >= w && k < m;
+            const T av = P[(int64_t)min(kq, w - 1) * m + kc];
+            const T bv = X[gk + (int64_t)min(kq, nrhs - 1) * n];
+            a[s] = (row_ok && kq < w) ? av : T(0);
+            b[s] = (row_ok && kq < nrhs) ? bv : T(0);
+        }
+        acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = Mfma<T>::run(a[s], b[s], acc);
+        // element v of this lane: row c of (L_below^T X_rows), column kq
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = Mfma<T>::row(lane, v);
+            const T xo = X[tk.g0 + min(c, w - 1) + (int64_t)min(kq, nrhs - 1) * n];
+            if (c < WT) ts[wv][c][kq] = (c < w && kq < nrhs) ? xo - acc[v] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = kr + 4 * h;
+            T xv = T(0);
+#pragma unroll
+            for (int i = 0; i < WT; ++i) {
+                const T vq = Q[min(i, w - 1) + (int64_t)min(c, w - 1) * w];  // (L^{-1})[i][c]
+                xv += (i >= c && i < w) ? vq * ts[wv][i][kq] : T(0);
+            }
+            if (active && c < w && kq < nrhs) X[tk.g0 + c + (int64_t)kq * n] = xv;
+        }
+    }
+}
+
 // Per solve: dep <- the forward counts, done and cnt <- 0, queues and the
 // error word <- 0.
 __global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy) {
@@ -1434,6 +1576,32 @@ void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
 }
 
 template <typename T>
+void launch_solve_tiny_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
+                           int64_t n, int nrhs, hipStream_t st) {
+    if (t1 <= t0) return;
+    const dim3 g((unsigned)((t1 - t0 + 3) / 4)), b(256);
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_solve_tiny_fwd<T, 1>), g, b, 0, st, P.stiny + t0, t1 - t0, P.rows, Lx, Linv, Y, X, n,
+                           nrhs);
+    else
+        hipLaunchKernelGGL((k_solve_tiny_fwd<T, kMaxRhs>), g, b, 0, st, P.stiny + t0, t1 - t0, P.rows, Lx, Linv, Y,
+                           X, n, nrhs);
+}
+
+template <typename T>
+void launch_solve_tiny_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, int64_t n,
+                           int nrhs, hipStream_t st) {
+    if (t1 <= t0) return;
+    const dim3 g((unsigned)((t1 - t0 + 3) / 4)), b(256);
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_solve_tiny_bwd<T, 1>), g, b, 0, st, P.stiny + t0, t1 - t0, P.rows, Lx, Linv, X, n,
+                           nrhs);
+    else
+        hipLaunchKernelGGL((k_solve_tiny_bwd<T, kMaxRhs>), g, b, 0, st, P.stiny + t0, t1 - t0, P.rows, Lx, Linv, X,
+                           n, nrhs);
+}
+
+template <typename T>
 void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st) {
     if (t1 <= t0) return;
@@ -1541,7 +1709,11 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_solve_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
                                       int64_t, int, SolveSync, bool, hipStream_t);                          \
     template void launch_solve_bwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
-                                      int64_t, int, SolveSync, bool, hipStream_t);
+                                      int64_t, int, SolveSync, bool, hipStream_t);                          \
+    template void launch_solve_tiny_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *, \
+                                           int64_t, int, hipStream_t);                                      \
+    template void launch_solve_tiny_bwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *,     \
+                                           int64_t, int, hipStream_t);
 SPC_INSTANTIATE(double)
 SPC_INSTANTIATE(float)
 

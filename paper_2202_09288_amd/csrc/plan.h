@@ -191,6 +191,8 @@ struct Symbolic {
     std::vector<int32_t> sblock_order;
     std::vector<int64_t> stask_ptr;        // [nslevels+1] into stasks
     std::vector<SolveTask> stasks;
+    std::vector<int64_t> stiny_ptr;        // [nslevels+1] into stiny
+    std::vector<SmallTask> stiny;          // tiny supernodes of levels < solve_split (one wave each)
     int32_t nslevels = 0;
     // Persistent solves: for each task the column blocks its rows fall in
     // (ascending, distinct), for each block the number of (task, block)

@@ -553,13 +553,38 @@ int build_schedule(Symbolic &S) {
         for (int64_t q = 0; q < nb; ++q) S.sblock_order[f[blev[q]]++] = (int32_t)q;
     }
     // one task per chunk of rows below the block; a block with no rows
-    // below still gets one (empty) task, which does its diagonal part
+    // below still gets one (empty) task, which does its diagonal part.
+    // Levels from the top with fewer than kSolvePersistMax tasks run
+    // persistently (solve_split..); below them, the blocks of tiny
+    // supernodes (w <= kTinyW, m <= kTinyM: a single block and a single
+    // task) go to the one-wave solve kernels instead.
+    auto block_tasks = [&](const SolveBlock &B) {
+        const int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
+        return std::max<int64_t>(1, (m - B.c1 + kSolveRows - 1) / kSolveRows);
+    };
+    int32_t split = nsl;
+    for (; split > 0; --split) {
+        int64_t cnt = 0;
+        for (int64_t e = S.slevel_ptr[split - 1]; e < S.slevel_ptr[split]; ++e)
+            cnt += block_tasks(S.sblocks[S.sblock_order[e]]);
+        if (cnt >= kSolvePersistMax) break;
+    }
+    S.solve_split = split;
     S.stask_ptr.assign(nsl + 1, 0);
+    S.stiny_ptr.assign(nsl + 1, 0);
+    S.stiny.clear();
     for (int32_t l = 0; l < nsl; ++l) {
         for (int64_t e = S.slevel_ptr[l]; e < S.slevel_ptr[l + 1]; ++e) {
             int32_t q = S.sblock_order[e];
             SolveBlock &B = S.sblocks[q];
             int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
+            const int64_t w = S.super_ptr[B.s + 1] - S.super_ptr[B.s];
+            if (l < split && w <= kTinyW && m <= kTinyM) {
+                S.stiny.push_back(SmallTask{S.lptr[B.s], S.rptr[B.s], S.inv_off[q], B.s, (int32_t)m, (int32_t)w,
+                                            S.super_ptr[B.s]});
+                B.ntasks = 1;
+                continue;
+            }
             const size_t first = S.stasks.size();
             int32_t cnt = 0;
             int64_t r = B.c1;
@@ -585,6 +610,7 @@ int build_schedule(Symbolic &S) {
             for (size_t e = first; e < S.stasks.size(); ++e) S.stasks[e].ntasks = cnt;
         }
         S.stask_ptr[l + 1] = (int64_t)S.stasks.size();
+        S.stiny_ptr[l + 1] = (int64_t)S.stiny.size();
     }
     // dependencies of the persistent solves
     {
@@ -593,9 +619,6 @@ int build_schedule(Symbolic &S) {
             for (int32_t c = S.super_ptr[s]; c < S.super_ptr[s + 1]; ++c)
                 col_blk[c] = first_blk[s] + (c - S.super_ptr[s]) / kNB;
         const int64_t nt = (int64_t)S.stasks.size();
-        int32_t split = nsl;
-        while (split > 0 && S.stask_ptr[split] - S.stask_ptr[split - 1] < kSolvePersistMax) --split;
-        S.solve_split = split;
         const int64_t tp0 = S.stask_ptr[split];
         S.stgt_ptr.assign(nt + 1, 0);
         S.stgt.clear();
