@@ -80,6 +80,10 @@ typedef struct spc_info {
     int64_t max_rows;         /* longest row list */
     int64_t factor_bytes_fp64;/* device bytes of an FP64 factor + plan */
     int64_t factor_bytes_fp32;/* device bytes of an FP32 factor + plan */
+    int64_t solve_levels;     /* levels of the column-block tree the solves sweep */
+    int64_t solve_persistent_levels; /* top levels run as one persistent launch per sweep */
+    int64_t solve_block_tasks;/* row tasks of the block solve kernels */
+    int64_t solve_tiny_tasks; /* tiny supernodes solved one wave each */
 } spc_info;
 
 /*

@@ -644,6 +644,10 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     const int64_t entries = S.panel_entries() + (S.inv_off.empty() ? 0 : S.inv_off.back());
     out->factor_bytes_fp64 = (int64_t)(entries * 8 + plan_bytes(S));
     out->factor_bytes_fp32 = (int64_t)(entries * 4 + plan_bytes(S));
+    out->solve_levels = S.nslevels;
+    out->solve_persistent_levels = S.nslevels - S.solve_split;
+    out->solve_block_tasks = (int64_t)S.stasks.size();
+    out->solve_tiny_tasks = (int64_t)S.stiny.size();
     return SPC_OK;
 }
 

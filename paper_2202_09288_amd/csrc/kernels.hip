@@ -782,7 +782,7 @@ template <typename T>
 __global__ void k_perm_in(const int32_t *perm, int64_t n, int nrhs, const double *B, int64_t ldb, T *W) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
-    int64_t k = i % n, r = i / n;
+    int64_t k = i / nrhs, r = i % nrhs;
     W[i] = (T)B[perm[k] + r * ldb];
 }
 
@@ -790,7 +790,7 @@ template <typename T>
 __global__ void k_perm_out(const int32_t *perm, int64_t n, int nrhs, const T *W, double *B, int64_t ldb) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
-    int64_t k = i % n, r = i / n;
+    int64_t k = i / nrhs, r = i % nrhs;
     B[perm[k] + r * ldb] = (double)W[i];
 }
 
@@ -965,8 +965,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         }
 #pragma unroll
         for (int u = 0; u < YPT; ++u) {
-            const int e = tid + 256 * u, i = e % NB, q = e / NB;
-            const T *py = &Y[tk.g0 + min(i, nb - 1) + (int64_t)min(q, nrhs - 1) * n];
+            const int e = tid + 256 * u, i = e / NR, q = e % NR;
+            const T *py = &Y[(tk.g0 + min(i, nb - 1)) * nrhs + min(q, nrhs - 1)];
             yv[u] = PERSIST ? shared_load(py) : *py;
         }
 #pragma unroll
@@ -976,7 +976,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         }
 #pragma unroll
         for (int u = 0; u < YPT; ++u) {
-            const int e = tid + 256 * u, i = e % NB, q = e / NB;
+            const int e = tid + 256 * u, i = e / NR, q = e % NR;
             yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
         }
         __syncthreads();
@@ -990,8 +990,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         __syncthreads();
         if (tk.first)
             for (int e = tid; e < nb * nrhs; e += 256) {
-                const int i = e % nb, q = e / nb;
-                X[tk.g0 + i + (int64_t)q * n] = xq[i][q];
+                const int i = e / nrhs, q = e % nrhs;
+                X[(tk.g0 + i) * nrhs + q] = xq[i][q];
             }
         // rows of x_q beyond nb are zero, so the clamped columns contribute nothing
 #pragma unroll
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = 64 * wave + 16 * tt + Mfma<T>::row(lane, v), q = lane & 15;
-                if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] + (int64_t)q * n], -acc[v]);
+                if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] * nrhs + q], -acc[v]);
             }
         }
         if (PERSIST) {
@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         T xv[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-            const T *px = &X[gr + (int64_t)min(q, nrhs - 1) * n];
+            const T *px = &X[gr * nrhs + min(q, nrhs - 1)];
             xv[q] = PERSIST ? shared_load(px) : *px;
         }
 #pragma unroll
@@ -1090,14 +1090,14 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         bool fin = true;
         if (tk.ntasks == 1) {
             for (int e = tid; e < nb * nrhs; e += 256) {
-                const int i = e % nb, q = e / nb;
-                tq[i][q] = X[tk.g0 + i + (int64_t)q * n] - tq[i][q];
+                const int i = e / nrhs, q = e % nrhs;
+                tq[i][q] = X[(tk.g0 + i) * nrhs + q] - tq[i][q];
             }
         } else {
             if (tk.r1 > tk.r0)
                 for (int e = tid; e < nb * nrhs; e += 256) {
-                    const int i = e % nb, q = e / nb;
-                    atomicAdd(&Acc[tk.g0 + i + (int64_t)q * n], tq[i][q]);
+                    const int i = e / nrhs, q = e % nrhs;
+                    atomicAdd(&Acc[(tk.g0 + i) * nrhs + q], tq[i][q]);
                 }
             // the partial sums are device-scope atomics and the last task
             // reads them back with atomic exchanges: each thread only waits
@@ -1109,8 +1109,8 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             fin = last;
             if (fin) {
                 for (int e = tid; e < nb * nrhs; e += 256) {
-                    const int i = e % nb, q = e / nb;
-                    const int64_t idx = tk.g0 + i + (int64_t)q * n;
+                    const int i = e / nrhs, q = e % nrhs;
+                    const int64_t idx = (tk.g0 + i) * nrhs + q;
                     const T a = __hip_atomic_exchange(&Acc[idx], T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     tq[i][q] = X[idx] - a;
                 }
@@ -1126,11 +1126,11 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             }
             __syncthreads();
             for (int e = tid; e < nb * nrhs; e += 256) {
-                const int c = e % nb, q = e / nb;
+                const int c = e / nrhs, q = e % nrhs;
                 T a = T(0);
                 for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
-                if (PERSIST) shared_store(&X[tk.g0 + c + (int64_t)q * n], a);
-                else X[tk.g0 + c + (int64_t)q * n] = a;
+                if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], a);
+                else X[(tk.g0 + c) * nrhs + q] = a;
             }
             if (PERSIST) {
                 release_own();
@@ -1145,56 +1145,102 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
 // ---------------------------------------------------------------------------
 // One-wave solves of tiny supernodes (w <= kTinyW, m <= kTinyM), four per
 // workgroup, for the wide bottom levels where nearly every supernode is
-// tiny: lane i holds row position i of R_s, so a supernode costs one wave
-// instead of a workgroup sized for a 64-column block.
-// Forward: x = Linv y on the w diagonal lanes (y_c broadcast from lane c),
-// stored in X; then each row i >= w below takes
+// tiny: a supernode costs one wave instead of a workgroup sized for a
+// 64-column block.  Right-hand sides are interleaved by row (entry (k, q) at
+// k * nrhs + q), so the values of one row sit together.
+// Forward: x = Linv y for the w diagonal rows, stored in X; then each row
+// i >= w below takes
 //   Y[rows[i]] -= sum_c L[i][c] x_c      (atomic, as in the block sweep).
+// One right-hand side: lane i holds row position i, y_c and x_c are
+// broadcast from lane c.  Several: x goes through LDS and the update is the
+// product (rows x w)(w x 16) on 16x16x4 MFMA (four row tiles, two steps of
+// the contraction), so the 16 lanes of one output row write its 16
+// consecutive values.
 // ---------------------------------------------------------------------------
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_solve_tiny_fwd(const SmallTask *tasks, int64_t ntasks, const int32_t *rows,
                                                         const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
                                                         int nrhs) {
     constexpr int WT = kTinyW;
-    const int lane = threadIdx.x & 63;
-    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (ti >= ntasks) return;  // the whole wave
-    const SmallTask tk = tasks[ti];
-    const int m = tk.m, w = tk.w;
-    const T *P = Lx + tk.loff;
-    const T *Q = Linv + tk.ioff;
-    const int rc = min(lane, m - 1), dc = min(lane, w - 1);
-    T l[WT], vi[WT], y[NR];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ti = (int64_t)blockIdx.x * 4 + wv;
+    if constexpr (NR == 1) {
+        if (ti >= ntasks) return;  // the whole wave
+        const SmallTask tk = tasks[ti];
+        const int m = tk.m, w = tk.w;
+        const T *P = Lx + tk.loff;
+        const T *Q = Linv + tk.ioff;
+        const int rc = min(lane, m - 1), dc = min(lane, w - 1);
+        T l[WT], vi[WT];
 #pragma unroll
-    for (int c = 0; c < WT; ++c) l[c] = P[(int64_t)min(c, w - 1) * m + rc];
+        for (int c = 0; c < WT; ++c) l[c] = P[(int64_t)min(c, w - 1) * m + rc];
 #pragma unroll
-    for (int c = 0; c < WT; ++c) vi[c] = Q[dc + min(c, w - 1) * w];  // (L^{-1})[dc][c]
-    const int64_t g = rows[tk.roff + rc];
+        for (int c = 0; c < WT; ++c) vi[c] = Q[dc + min(c, w - 1) * w];  // (L^{-1})[dc][c]
+        const int64_t g = rows[tk.roff + rc];
+        const T y = Y[tk.g0 + dc];
+        T x = T(0), acc = T(0);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) y[q] = Y[tk.g0 + dc + (int64_t)min(q, nrhs - 1) * n];
-    T x[NR], acc[NR];
+        for (int c = 0; c < WT; ++c)
+            if (c < w) x += (c <= lane ? vi[c] : T(0)) * lane_read(y, c);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) x[q] = acc[q] = T(0);
+        for (int c = 0; c < WT; ++c)
+            if (c < w) acc += l[c] * lane_read(x, c);
+        if (lane < w) X[tk.g0 + lane] = x;
+        else if (lane < m) atomicAdd(&Y[g], -acc);
+    } else {
+        using acc_t = typename Mfma<T>::acc;
+        __shared__ T ys[4][WT][kMaxRhs + 1];
+        __shared__ T xs[4][WT][kMaxRhs + 1];
+        const bool active = ti < ntasks;
+        const SmallTask tk = tasks[active ? ti : ntasks - 1];  // idle waves mirror a task, store nothing
+        const int m = tk.m, w = tk.w;
+        const T *P = Lx + tk.loff;
+        const T *Q = Linv + tk.ioff;
+        const int kq = lane & 15, kr = lane >> 4;
+        const int64_t g = rows[tk.roff + min(lane, m - 1)];  // lane = row position
+        // A operands: row 16 tt + kq of the panel, columns 4 s + kr
+        T a[4][2];
 #pragma unroll
-    for (int c = 0; c < WT; ++c)
-        if (c < w) {
-            const T v = c <= lane ? vi[c] : T(0);
+        for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-            for (int q = 0; q < NR; ++q) x[q] += v * lane_read(y[q], c);
+            for (int s2 = 0; s2 < 2; ++s2)
+                a[tt][s2] = P[(int64_t)min(4 * s2 + kr, w - 1) * m + min(16 * tt + kq, m - 1)];
+        // y of the diagonal rows, two (c, q) slots per lane: c = kr + 4 h
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = kr + 4 * h;
+            const T yv = Y[(tk.g0 + min(c, w - 1)) * nrhs + min(kq, nrhs - 1)];
+            ys[wv][c][kq] = (c < w && kq < nrhs) ? yv : T(0);
         }
+        __syncthreads();
 #pragma unroll
-    for (int c = 0; c < WT; ++c)
-        if (c < w)
+        for (int h = 0; h < 2; ++h) {
+            const int c = kr + 4 * h;
+            T xv = T(0);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) acc[q] += l[c] * lane_read(x[q], c);
-    if (lane < w) {
+            for (int j = 0; j < WT; ++j) {
+                const T vq = Q[min(c, w - 1) + (int64_t)min(j, w - 1) * w];  // (L^{-1})[c][j]
+                xv += (j <= c && c < w) ? vq * ys[wv][j][kq] : T(0);
+            }
+            xs[wv][c][kq] = xv;
+            if (active && c < w && kq < nrhs) X[(tk.g0 + c) * nrhs + kq] = xv;
+        }
+        __syncthreads();
+        // B operands: x[4 s + kr][kq] (zero beyond w)
+        const T b0 = xs[wv][kr][kq], b1 = xs[wv][4 + kr][kq];
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-            if (q < nrhs) X[tk.g0 + lane + (int64_t)q * n] = x[q];
-    } else if (lane < m) {
+        for (int tt = 0; tt < 4; ++tt) {
+            if (16 * tt >= m) break;  // uniform
+            acc_t acc = {0, 0, 0, 0};
+            acc = Mfma<T>::run(4 * 0 + kr < w ? a[tt][0] : T(0), b0, acc);
+            acc = Mfma<T>::run(4 + kr < w ? a[tt][1] : T(0), b1, acc);
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-            if (q < nrhs) atomicAdd(&Y[g + (int64_t)q * n], -acc[q]);
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * tt + Mfma<T>::row(lane, v);
+                const int64_t gr = __shfl(g, min(r, 63));
+                if (active && r >= w && r < m && kq < nrhs) atomicAdd(&Y[gr * nrhs + kq], -acc[v]);
+            }
+        }
     }
 }
 
@@ -1255,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_solve_tiny_bwd(const SmallTask *tasks, 
             const int64_t gk = __shfl(g, kc);
             const bool row_ok = k >= w && k < m;
             const T av = P[(int64_t)min(kq, w - 1) * m + kc];
-            const T bv = X[gk + (int64_t)min(kq, nrhs - 1) * n];
+            const T bv = X[gk * nrhs + min(kq, nrhs - 1)];
             a[s] = (row_ok && kq < w) ? av : T(0);
             b[s] = (row_ok && kq < nrhs) ? bv : T(0);
         }
@@ -1266,7 +1312,7 @@ __global__ __launch_bounds__(256) void k_solve_tiny_bwd(const SmallTask *tasks, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int c = Mfma<T>::row(lane, v);
-            const T xo = X[tk.g0 + min(c, w - 1) + (int64_t)min(kq, nrhs - 1) * n];
+            const T xo = X[(tk.g0 + min(c, w - 1)) * nrhs + min(kq, nrhs - 1)];
             if (c < WT) ts[wv][c][kq] = (c < w && kq < nrhs) ? xo - acc[v] : T(0);
         }
         __syncthreads();
@@ -1279,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_solve_tiny_bwd(const SmallTask *tasks, 
                 const T vq = Q[min(i, w - 1) + (int64_t)min(c, w - 1) * w];  // (L^{-1})[i][c]
                 xv += (i >= c && i < w) ? vq * ts[wv][i][kq] : T(0);
             }
-            if (active && c < w && kq < nrhs) X[tk.g0 + c + (int64_t)kq * n] = xv;
+            if (active && c < w && kq < nrhs) X[(tk.g0 + c) * nrhs + kq] = xv;
         }
     }
 }

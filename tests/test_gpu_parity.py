@@ -73,6 +73,24 @@ def test_fp64_parity(torch_dev, lib, name, make):
     assert eta <= BERR_FP64
 
 
+@pytest.mark.parametrize("dims,nrhs,precision", [((30, 30, 30), 1, "fp64"), ((30, 30, 30), 16, "fp64"),
+                                                 ((150, 150), 5, "fp64"), ((30, 30, 30), 16, "fp32"),
+                                                 ((150, 150), 1, "fp32")])
+def test_solve_wide_levels_one_wave_path(torch_dev, lib, dims, nrhs, precision):
+    """Grids whose bottom solve levels hold thousands of tiny supernodes, so
+    the one-wave forward/backward kernels carry most of the solve; 16 and 5
+    right-hand sides take the MFMA form and its clamped columns."""
+    s = grid(dims, seed=9, nrhs=nrhs)
+    sym_info = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05).info
+    assert sym_info["solve_tiny_tasks"] > 1000
+    relF, eta, _, _ = run_case(torch_dev, lib, s.colptr, s.rowidx, s.values, s.perm, s.B, precision=precision)
+    print(f"one-wave path {dims} nrhs={nrhs} {precision}: relF={relF:.2e} eta={eta:.2e}")
+    if precision == "fp64":
+        assert relF <= REL_F_FP64 and eta <= BERR_FP64
+    else:
+        assert relF <= 1e-4 and eta <= 1e-5
+
+
 @pytest.mark.parametrize("z", [-1.0, 0.0, 0.5])
 def test_fp64_amalgamation_settings(torch_dev, lib, z):
     s = grid((14, 13, 12), seed=3, nrhs=2)

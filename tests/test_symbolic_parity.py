@@ -80,3 +80,28 @@ def test_grid3d_60():
     s = W.grid3d_cond()
     S, L = compare(s.colptr, s.rowidx, s.perm, 0.05)
     assert S.sizes["flops"] == 279230799993
+
+
+@pytest.mark.parametrize("dims,expect_tiny", [((8, 8), False), ((30, 30, 30), True), ((150, 150), True)])
+def test_solve_schedule_split(dims, expect_tiny):
+    """The solve schedule: levels with few tasks at the top run persistently;
+    below them, tiny supernodes (w <= 8, m <= 64) leave the block-task list
+    for the one-wave kernels.  A small grid is persistent throughout; the
+    30^3 and 150^2 grids have wide bottom levels full of tiny supernodes."""
+    s = W.laplacian(dims, "5pt" if len(dims) == 2 else "7pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
+    L = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    info = L.info
+    w = np.diff(L.export("super_ptr"))
+    m = np.diff(L.export("rptr"))
+    tiny = int(((w <= 8) & (m <= 64)).sum())
+    assert 1 <= info["solve_persistent_levels"] <= info["solve_levels"]
+    assert info["solve_tiny_tasks"] <= tiny
+    # every column block keeps at least one block task unless it went to the
+    # one-wave list: blocks = sum over supernodes of ceil(w / 64)
+    blocks = int(((w + 63) // 64).sum())
+    assert info["solve_block_tasks"] + info["solve_tiny_tasks"] >= blocks
+    if expect_tiny:
+        assert info["solve_persistent_levels"] < info["solve_levels"]
+        assert info["solve_tiny_tasks"] > tiny // 2
+    else:
+        assert info["solve_persistent_levels"] == info["solve_levels"] and info["solve_tiny_tasks"] == 0
