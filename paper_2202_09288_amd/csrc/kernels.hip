@@ -1019,10 +1019,15 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 // L[r][c0+k] X[rows[r]] over the rows r of group g (64 rows each); the four
 // groups are added through LDS.  A block with one task finishes itself:
 //   t = X_q - sum,  x_q = Linv_q^T t.
-// A block split over several tasks adds its sums into Acc, and the last
-// task to arrive (sy.cnt) finishes it.  Rows below the block belong to
-// ancestors, whose x is final before the block's tasks read it (level order,
-// or the done flags of the persistent sweep).
+// A block split over several tasks adds its sums into Acc.  In a level
+// launch the last task to arrive (sy.cnt) finishes the block.  In the
+// persistent sweep the block's first task does: it holds the rows nearest
+// the block, whose x are final last, and it is queued after the block's
+// other tasks, so it collects their sums (waiting on sy.cnt) before its own
+// rows are ready, which keeps that exchange off the chain of blocks.
+// Rows below the block belong to ancestors, whose x is final before the
+// block's tasks read it (level order, or the done flags of the persistent
+// sweep).
 template <typename T, int NR, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64_t ntasks, const int32_t *order,
                                                    const int32_t *rows, const T *Lx, const T *Linv, T *X, T *Acc,
@@ -1033,6 +1038,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
     constexpr int SH = XR > SM ? (XR > VT ? XR : VT) : (SM > VT ? SM : VT);
     __shared__ T sh[SH];
     __shared__ T tq[NB][NR];
+    __shared__ T ao[NB][NR];  // persistent finisher: the other tasks' sums
     __shared__ int last;
     __shared__ int32_t slot;
     T(*xr)[NR + 1] = reinterpret_cast<T(*)[NR + 1]>(sh);   // x of the task's rows
@@ -1055,6 +1061,18 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             pv[u] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + min<int64_t>(tk.r0 + g * RG + u, m - 1)];
 #pragma unroll
         for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        const bool finisher = PERSIST && tk.first && tk.ntasks > 1;
+        if (finisher) {
+            // every other task of the block was dequeued before this one
+            if (tid == 0) wait_value(&sy.cnt[tk.blk], tk.ntasks - 1, sy.err);
+            __syncthreads();
+            acquire_after_wait();
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int i = e / nrhs, q = e % nrhs;
+                ao[i][q] = __hip_atomic_exchange(&Acc[(tk.g0 + i) * nrhs + q], T(0), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (PERSIST) {
             for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) wait_value(&sy.done[tgt[e]], 1, sy.err);
             __syncthreads();
@@ -1093,6 +1111,21 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                 const int i = e / nrhs, q = e % nrhs;
                 tq[i][q] = X[(tk.g0 + i) * nrhs + q] - tq[i][q];
             }
+        } else if (finisher) {
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int i = e / nrhs, q = e % nrhs;
+                tq[i][q] = X[(tk.g0 + i) * nrhs + q] - (tq[i][q] + ao[i][q]);
+            }
+            if (tid == 0) sy.cnt[tk.blk] = 0;
+        } else if (PERSIST) {
+            for (int e = tid; e < nb * nrhs; e += 256) {
+                const int i = e / nrhs, q = e % nrhs;
+                atomicAdd(&Acc[(tk.g0 + i) * nrhs + q], tq[i][q]);
+            }
+            release_own();
+            __syncthreads();
+            if (tid == 0) atomicAdd(&sy.cnt[tk.blk], 1);
+            fin = false;
         } else {
             if (tk.r1 > tk.r0)
                 for (int e = tid; e < nb * nrhs; e += 256) {

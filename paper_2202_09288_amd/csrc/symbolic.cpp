@@ -636,9 +636,15 @@ int build_schedule(Symbolic &S) {
             }
             S.stgt_ptr[t + 1] = (int64_t)S.stgt.size();
         }
+        // backward order: levels from the top; inside a level, each block's
+        // other tasks and then its first task, which finishes the block (it
+        // holds the rows nearest the block, whose x come last)
         S.bwd_order.clear();
         for (int32_t l = nsl - 1; l >= split; --l)
-            for (int64_t e = S.stask_ptr[l]; e < S.stask_ptr[l + 1]; ++e) S.bwd_order.push_back((int32_t)e);
+            for (int64_t e = S.stask_ptr[l]; e < S.stask_ptr[l + 1]; e += S.stasks[e].ntasks) {
+                for (int32_t k = 1; k < S.stasks[e].ntasks; ++k) S.bwd_order.push_back((int32_t)(e + k));
+                S.bwd_order.push_back((int32_t)e);
+            }
     }
     return SPC_OK;
 }
