@@ -860,17 +860,22 @@ __device__ __forceinline__ int64_t next_task(int pass, const int32_t *order, int
 // Forward, one task = rows r0..r1-1 below block q:
 //   x_q = Linv_q y_q (every task; the first task stores it in X), then
 //   Y[rows[r]] -= sum_k L[r][c0+k] x_q[k] (atomic).
-// One right-hand side: thread = row.
+// One right-hand side: thread = row for the update; for x_q four threads
+// share a row of Linv (16 columns each, held in registers) and add up by
+// lane shuffles.  Everything a task reads besides y (its panel rows, its
+// part of Linv, its target blocks) is loaded before it waits.
+// A persistent task's rows fall in at most 256 blocks (one per row), so
+// each thread holds at most one target block to count down.
 template <typename T, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64_t ntasks, const int32_t *rows,
                                                    const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
                                                    const int64_t *tgt_ptr, const int32_t *tgt, SolveSync sy) {
-    constexpr int NB = kNB, QPT = NB * NB / 256;
-    __shared__ T Vi[NB][NB + 1];
+    constexpr int NB = kNB, QW = NB / 4;
     __shared__ T yq[NB];
     __shared__ T xq[NB];
     __shared__ int32_t slot;
     const int tid = threadIdx.x;
+    const int vi = tid >> 2, vp = tid & 3;  // x: row vi of Linv, columns QW vp .. QW vp + QW - 1
     for (int pass = 0;; ++pass) {
         const int64_t t = next_task<PERSIST>(pass, nullptr, sy.queue, ntasks, &slot);
         if (t < 0) return;
@@ -881,43 +886,60 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
         const T *Q = Linv + tk.ioff;
         const int64_t r = tk.r0 + tid;
         const int64_t rc = min(r, m - 1);
-        T qv[QPT], pv[NB];
+        T qv[QW], pv[NB];
+        const int qi = min(vi, nb - 1);
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        for (int k = 0; k < QW; ++k) qv[k] = Q[qi + (int64_t)min(QW * vp + k, nb - 1) * nb];
         const int64_t gr = rows[tk.roff + rc];
 #pragma unroll
         for (int k = 0; k < NB; ++k) pv[k] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + rc];
+        int32_t my_tgt = -1;
         if (PERSIST) {
+            const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
+            if (tid < te - tb) my_tgt = tgt[tb + tid];
             if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
             __syncthreads();
             acquire_after_wait();
         }
-        const T yv = PERSIST ? shared_load(&Y[tk.g0 + min(tid, nb - 1)]) : Y[tk.g0 + min(tid, nb - 1)];
-#pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-            const int e = tid + 256 * u;
-            if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
-        }
-        if (tid < NB) yq[tid] = tid < nb ? yv : T(0);
-        __syncthreads();
         if (tid < NB) {
-            T a = T(0);
-            if (tid < nb)
-                for (int c = 0; c <= tid; ++c) a += Vi[tid][c] * yq[c];
-            xq[tid] = a;
-            if (tk.first && tid < nb) X[tk.g0 + tid] = a;
+            const T *py = &Y[tk.g0 + min(tid, nb - 1)];
+            const T yv = PERSIST ? shared_load(py) : *py;
+            yq[tid] = tid < nb ? yv : T(0);
+        }
+        __syncthreads();
+        {
+            T a0 = T(0), a1 = T(0);
+#pragma unroll
+            for (int k = 0; k < QW; k += 2) {
+                const int c = QW * vp + k;
+                a0 += (c <= vi ? qv[k] : T(0)) * yq[c];
+                a1 += (c + 1 <= vi ? qv[k + 1] : T(0)) * yq[c + 1];
+            }
+            T a = a0 + a1;
+            a += __shfl_xor(a, 1);
+            a += __shfl_xor(a, 2);
+            if (vp == 0) {
+                xq[vi] = vi < nb ? a : T(0);
+                if (tk.first && vi < nb) X[tk.g0 + vi] = a;
+            }
         }
         __syncthreads();
         if (r < tk.r1) {
-            T acc = T(0);
+            // entries of x_q beyond nb are zero, so clamped columns add nothing
+            T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-            for (int k = 0; k < NB; ++k) acc += (k < nb ? pv[k] : T(0)) * xq[k];
-            atomicAdd(&Y[gr], -acc);
+            for (int k = 0; k < NB; k += 4) {
+                a0 += pv[k] * xq[k];
+                a1 += pv[k + 1] * xq[k + 1];
+                a2 += pv[k + 2] * xq[k + 2];
+                a3 += pv[k + 3] * xq[k + 3];
+            }
+            atomicAdd(&Y[gr], -((a0 + a1) + (a2 + a3)));
         }
         if (PERSIST) {
             release_own();
             __syncthreads();
-            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
+            if (my_tgt >= 0) atomicSub(&sy.dep[my_tgt], 1);
         }
     }
 }
@@ -931,9 +953,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
                                                          const int32_t *rows, const T *Lx, const T *Linv, T *Y,
                                                          T *X, int64_t n, int nrhs, const int64_t *tgt_ptr,
                                                          const int32_t *tgt, SolveSync sy) {
-    constexpr int NB = kNB, NR = kMaxRhs, QPT = NB * NB / 256, YPT = NB * NR / 256, KS = NB / 4;
+    constexpr int NB = kNB, NR = kMaxRhs, YPT = NB * NR / 256, KS = NB / 4;
     using acc_t = typename Mfma<T>::acc;
-    __shared__ T Vi[NB][NB + 1];
     __shared__ T yq[NB][NR + 1];
     __shared__ T xq[NB][NR + 1];
     __shared__ int64_t grs[256];
@@ -947,9 +968,15 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         const int64_t m = tk.m;
         const T *P = Lx + tk.loff;
         const T *Q = Linv + tk.ioff;
-        T qv[QPT], yv[YPT], av[4][KS];
+        // x = Linv y on MFMA as well: wave w the rows 16 w .. 16 w + 15 of x,
+        // lane bringing Linv[16 w + lane % 16][4 s + lane / 16]
+        T qv[KS], yv[YPT], av[4][KS];
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        for (int s2 = 0; s2 < KS; ++s2) {
+            const int i = 16 * wave + (lane & 15), c = 4 * s2 + (lane >> 4);
+            const T v = Q[min(i, nb - 1) + (int64_t)min(c, nb - 1) * nb];
+            qv[s2] = (c <= i && i < nb) ? v : T(0);
+        }
         grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
@@ -958,7 +985,11 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
             for (int ks = 0; ks < KS; ++ks)
                 av[tt][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
         }
+        int32_t my_tgt = -1;
         if (PERSIST) {
+            // at most one target block per row of the task
+            const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
+            if (tid < te - tb) my_tgt = tgt[tb + tid];
             if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
             __syncthreads();
             acquire_after_wait();
@@ -970,22 +1001,17 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
             yv[u] = PERSIST ? shared_load(py) : *py;
         }
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-            const int e = tid + 256 * u;
-            if (e < nb * nb) Vi[e % nb][e / nb] = qv[u];
-        }
-#pragma unroll
         for (int u = 0; u < YPT; ++u) {
             const int e = tid + 256 * u, i = e / NR, q = e % NR;
             yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
         }
         __syncthreads();
-        for (int e = tid; e < NB * NR; e += 256) {
-            const int i = e % NB, q = e / NB;
-            T a = T(0);
-            if (i < nb)
-                for (int c = 0; c <= i; ++c) a += Vi[i][c] * yq[c][q];
-            xq[i][q] = a;
+        {
+            acc_t xa = {0, 0, 0, 0};
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) xa = Mfma<T>::run(qv[s2], yq[4 * s2 + (lane >> 4)][lane & 15], xa);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xq[16 * wave + Mfma<T>::row(lane, v)][lane & 15] = xa[v];
         }
         __syncthreads();
         if (tk.first)
@@ -1009,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         if (PERSIST) {
             release_own();
             __syncthreads();
-            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) atomicSub(&sy.dep[tgt[e]], 1);
+            if (my_tgt >= 0) atomicSub(&sy.dep[my_tgt], 1);
         }
         __syncthreads();
     }
@@ -1033,8 +1059,8 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                                                    const int32_t *rows, const T *Lx, const T *Linv, T *X, T *Acc,
                                                    int64_t n, int nrhs, const int64_t *tgt_ptr, const int32_t *tgt,
                                                    SolveSync sy) {
-    constexpr int NB = kNB, QPT = NB * NB / 256, RG = 64;
-    constexpr int XR = 256 * (NR + 1), SM = 4 * NB * NR, VT = NB * (NB + 1);
+    constexpr int NB = kNB, QW = 16, RG = 64;
+    constexpr int XR = 256 * (NR + 1), SM = 4 * NB * NR, VT = NR == 1 ? 0 : NB * (NB + 1);
     constexpr int SH = XR > SM ? (XR > VT ? XR : VT) : (SM > VT ? SM : VT);
     __shared__ T sh[SH];
     __shared__ T tq[NB][NR];
@@ -1043,8 +1069,15 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
     __shared__ int32_t slot;
     T(*xr)[NR + 1] = reinterpret_cast<T(*)[NR + 1]>(sh);   // x of the task's rows
     T(*Sm)[NB][NR] = reinterpret_cast<T(*)[NB][NR]>(sh);    // sums of the 4 groups
-    T(*Vt)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(sh);    // block inverse
+    T(*Vt)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(sh);    // block inverse (several RHS)
     const int tid = threadIdx.x, k = tid & 63, g = tid >> 6;
+    // x_q = Linv^T t, with (Linv^T)[c][i] = Linv[i][c] nonzero for i >= c.
+    // One right-hand side: four threads per output c, 16 rows i each, that
+    // part of Linv held in registers.  Several: Linv is loaded coalesced and
+    // staged in LDS, then 16x16x4 MFMA, wave g the outputs 16 g .. 16 g + 15,
+    // lane bringing A[c][i] for c = 16 g + lane % 16, i = 4 s + lane / 16.
+    const int oc = tid >> 2;
+    auto inv_row = [&](int s2) { return QW * (tid & 3) + s2; };
     for (int pass = 0;; ++pass) {
         const int64_t t = next_task<PERSIST>(pass, order, sy.queue + 1, ntasks, &slot);
         if (t < 0) return;
@@ -1055,12 +1088,27 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         const T *Q = Linv + tk.ioff;
         const int64_t rown = tk.r0 + tid;
         const int64_t gr = rows[tk.roff + min(rown, m - 1)];
-        T qv[QPT], pv[RG];
+        T qv[QW], pv[RG];
 #pragma unroll
         for (int u = 0; u < RG; ++u)
             pv[u] = P[(int64_t)(tk.c0 + min(k, nb - 1)) * m + min<int64_t>(tk.r0 + g * RG + u, m - 1)];
+        if constexpr (NR == 1) {
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+            for (int s2 = 0; s2 < QW; ++s2) {
+                const int i = inv_row(s2);
+                const T v = Q[min(i, nb - 1) + (int64_t)min(oc, nb - 1) * nb];
+                qv[s2] = (i >= oc && i < nb && oc < nb) ? v : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < QW; ++u) qv[u] = Q[min(tid + 256 * u, nb * nb - 1)];
+        }
+        int32_t my_tgt = -1;
+        if (PERSIST) {
+            // at most one target block per row of the task
+            const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
+            if (tid < te - tb) my_tgt = tgt[tb + tid];
+        }
         const bool finisher = PERSIST && tk.first && tk.ntasks > 1;
         if (finisher) {
             // every other task of the block was dequeued before this one
@@ -1074,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             }
         }
         if (PERSIST) {
-            for (int64_t e = tgt_ptr[t] + tid; e < tgt_ptr[t + 1]; e += 256) wait_value(&sy.done[tgt[e]], 1, sy.err);
+            if (my_tgt >= 0) wait_value(&sy.done[my_tgt], 1, sy.err);
             __syncthreads();
             acquire_after_wait();
         }
@@ -1088,13 +1136,25 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
         __syncthreads();
         T acc[NR];
+        if constexpr (NR == 1) {
+            T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] = T(0);
+            for (int u = 0; u < RG; u += 4) {
+                a0 += pv[u] * xr[g * RG + u][0];
+                a1 += pv[u + 1] * xr[g * RG + u + 1][0];
+                a2 += pv[u + 2] * xr[g * RG + u + 2][0];
+                a3 += pv[u + 3] * xr[g * RG + u + 3][0];
+            }
+            acc[0] = (a0 + a1) + (a2 + a3);
+        } else {
 #pragma unroll
-        for (int u = 0; u < RG; ++u) {
-            const T l = pv[u];
+            for (int q = 0; q < NR; ++q) acc[q] = T(0);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) acc[q] += l * xr[g * RG + u][q];
+            for (int u = 0; u < RG; ++u) {
+                const T l = pv[u];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[q] += l * xr[g * RG + u][q];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -1151,19 +1211,46 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             }
         }
         if (fin) {
-            // x_q = Linv^T t
-#pragma unroll
-            for (int u = 0; u < QPT; ++u) {
-                const int e = tid + 256 * u;
-                if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
-            }
+            // x_q = Linv^T t (rows of t beyond nb meet zero entries of qv)
             __syncthreads();
-            for (int e = tid; e < nb * nrhs; e += 256) {
-                const int c = e / nrhs, q = e % nrhs;
-                T a = T(0);
-                for (int i = c; i < nb; ++i) a += Vt[i][c] * tq[i][q];
-                if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], a);
-                else X[(tk.g0 + c) * nrhs + q] = a;
+            if constexpr (NR == 1) {
+                T a0 = T(0), a1 = T(0);
+#pragma unroll
+                for (int s2 = 0; s2 < QW; s2 += 2) {
+                    a0 += qv[s2] * tq[inv_row(s2)][0];
+                    a1 += qv[s2 + 1] * tq[inv_row(s2 + 1)][0];
+                }
+                T a = a0 + a1;
+                a += __shfl_xor(a, 1);
+                a += __shfl_xor(a, 2);
+                if ((tid & 3) == 0 && oc < nb) {
+                    if (PERSIST) shared_store(&X[tk.g0 + oc], a);
+                    else X[tk.g0 + oc] = a;
+                }
+            } else {
+                using acc_t = typename Mfma<T>::acc;
+#pragma unroll
+                for (int u = 0; u < QW; ++u) {
+                    const int e = tid + 256 * u;
+                    if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
+                }
+                __syncthreads();
+                const int c0 = 16 * g + (k & 15);
+                acc_t xa = {0, 0, 0, 0};
+#pragma unroll
+                for (int s2 = 0; s2 < QW; ++s2) {
+                    const int i = 4 * s2 + (k >> 4);
+                    const T a = (i >= c0 && i < nb && c0 < nb) ? Vt[min(i, nb - 1)][min(c0, nb - 1)] : T(0);
+                    xa = Mfma<T>::run(a, tq[i][k & 15], xa);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 16 * g + Mfma<T>::row(k, v), q = k & 15;
+                    if (c < nb && q < nrhs) {
+                        if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], xa[v]);
+                        else X[(tk.g0 + c) * nrhs + q] = xa[v];
+                    }
+                }
             }
             if (PERSIST) {
                 release_own();
