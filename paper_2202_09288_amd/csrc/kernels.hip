@@ -1109,6 +1109,19 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
             if (tid < te - tb) my_tgt = tgt[tb + tid];
         }
+        // the block's own forward values: final since the forward sweep, and
+        // overwritten only by the task that finishes this block, so a task
+        // known to finish it loads them before it waits
+        constexpr int XPT = NB * NR / 256 > 0 ? NB * NR / 256 : 1;
+        T xb[XPT];
+        auto load_xb = [&]() {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, i = min(e / nrhs, nb - 1), q = min(e % nrhs, nrhs - 1);
+                xb[u] = X[(tk.g0 + i) * nrhs + q];
+            }
+        };
+        if (tk.ntasks == 1 || (PERSIST && tk.first)) load_xb();
         const bool finisher = PERSIST && tk.first && tk.ntasks > 1;
         if (finisher) {
             // every other task of the block was dequeued before this one
@@ -1167,14 +1180,16 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         __syncthreads();
         bool fin = true;
         if (tk.ntasks == 1) {
-            for (int e = tid; e < nb * nrhs; e += 256) {
-                const int i = e / nrhs, q = e % nrhs;
-                tq[i][q] = X[(tk.g0 + i) * nrhs + q] - tq[i][q];
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, i = e / nrhs, q = e % nrhs;
+                if (e < nb * nrhs) tq[i][q] = xb[u] - tq[i][q];
             }
         } else if (finisher) {
-            for (int e = tid; e < nb * nrhs; e += 256) {
-                const int i = e / nrhs, q = e % nrhs;
-                tq[i][q] = X[(tk.g0 + i) * nrhs + q] - (tq[i][q] + ao[i][q]);
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, i = e / nrhs, q = e % nrhs;
+                if (e < nb * nrhs) tq[i][q] = xb[u] - (tq[i][q] + ao[i][q]);
             }
             if (tid == 0) sy.cnt[tk.blk] = 0;
         } else if (PERSIST) {
@@ -1201,11 +1216,15 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             __syncthreads();
             fin = last;
             if (fin) {
-                for (int e = tid; e < nb * nrhs; e += 256) {
-                    const int i = e / nrhs, q = e % nrhs;
-                    const int64_t idx = (tk.g0 + i) * nrhs + q;
-                    const T a = __hip_atomic_exchange(&Acc[idx], T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    tq[i][q] = X[idx] - a;
+                load_xb();
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, i = e / nrhs, q = e % nrhs;
+                    if (e < nb * nrhs) {
+                        const T a = __hip_atomic_exchange(&Acc[(tk.g0 + i) * nrhs + q], T(0), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                        tq[i][q] = xb[u] - a;
+                    }
                 }
                 if (tid == 0) sy.cnt[tk.blk] = 0;
             }
