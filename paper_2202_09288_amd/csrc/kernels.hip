@@ -125,25 +125,135 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
     return y * (1.5f - 0.5f * d * y * y);
 }
 
+// Bounded wait on an LDS word written by another wave of the workgroup
+// (all of whose waves are resident, so the wait ends unless the code is
+// wrong; the bound keeps even that from hanging the device).
+__device__ __forceinline__ bool lds_wait_geq(int *f, int v) {
+    for (int it = 0; it < (1 << 22); ++it) {
+        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+// Completes a wave's own LDS operations (and keeps the compiler from moving
+// memory accesses across), so its later LDS reads of other lanes' data, and
+// other waves after a flag, see them.  Global memory operations in flight
+// are not waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __asm__ volatile("" ::: "memory");
+}
+__device__ __forceinline__ void lds_flag_store(int *f, int v) {
+    wave_lds_sync();
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_flag_add(int *f) {
+    wave_lds_sync();
+    __hip_atomic_fetch_add(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Factor the block in A (nb <= 64; rows and columns >= nb hold the identity,
 // the upper triangle is zero), write L into P (columns c0.., leading
 // dimension m, lower triangle only) and the inverse into Vi; a failed pivot
-// lowers *status to g0 + its column.  rdg: 64 entries, Tf: 32 x 33, both
-// LDS.  Called by all 256 threads of the workgroup.
+// lowers *status to g0 + its column.  LDS scratch from the caller: rdg (64
+// entries), Tf and T32 (32 x 33 each), flags (8 ints).  Called by all 256
+// threads of the workgroup.
+//
+// Blocked by 16-column panels with lookahead: wave 0 factors panel p (lane
+// = row, pivots broadcast by readlane) right after bringing its columns up
+// to date with panel p-1 itself (16x16x4 MFMA), while waves 1-3 apply panel
+// p-1 to the columns two panels on and beyond, store its L and invert its
+// 16x16 diagonal triangle, merging a 32-column block's inverse as soon as
+// its two panels are inverted.  The waves hand over through LDS flags, so
+// the panel chain never waits for a whole-workgroup barrier.  Each trailing
+// tile belongs to one wave for all panels, so no tile is updated by two
+// waves at once.
 template <typename T>
-__device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], int nb, T *P, int64_t m, int c0,
-                                          T *Vi, unsigned long long *status, int64_t g0) {
+__device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], T (*T32)[33], int *flags, int nb,
+                                          T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int64_t g0) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
+    int &flag_panel = flags[0];   // panels 0 .. flag_panel - 1 are factored in A
+    int *flag_trail = flags + 1;  // [4] trailing waves done with panel p (0..3)
+    int &flag_err = flags[5];
+    int &flag_x11 = flags[6];     // inverse of the first 32-column block done
+    // T32: L21 X11 of the two 32-column blocks
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int npan = (nb + PW - 1) / PW, nbr = PW * npan;
+    const int npan = (nb + PW - 1) / PW;
+    if (t == 0) {
+        flag_panel = 0;
+        flag_trail[0] = flag_trail[1] = flag_trail[2] = flag_trail[3] = 0;
+        flag_err = 0;
+        flag_x11 = 0;
+    }
+    if (t >= PW * npan && t < NB) rdg[t] = T(1);  // identity rows past the last panel
+    __syncthreads();
+#define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
+    // inverse of the 32-column block at o from its two 16-block inverses
+    // (one wave): X21 = -X22 L21 X11, kept transposed in the upper triangle
+    auto inv16 = [&](int o) {
+        const int tr = o >> 1;  // Tf rows tr .. tr + 15
+        acc_t acc = {0, 0, 0, 0};  // L21 X11
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+            acc = M::run(A[o + 16 + (lane & 15)][o + kk + (lane >> 4)], SPC_INV(o + kk + (lane >> 4), o + (lane & 15)),
+                         acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tf[tr + M::row(lane, v)][lane & 15] = acc[v];
+        wave_lds_sync();
+        acc = acc_t{0, 0, 0, 0};  // X22 (L21 X11)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+            acc = M::run(SPC_INV(o + 16 + (lane & 15), o + 16 + kk + (lane >> 4)), Tf[tr + kk + (lane >> 4)][lane & 15],
+                         acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[o + (lane & 15)][o + 16 + M::row(lane, v)] = -acc[v];
+        wave_lds_sync();
+    };
     int bad = -1;  // wave 0: first pivot (block column) that failed
-    for (int pb = 0; pb < npan; ++pb) {
-        const int p0 = PW * pb;
-        if (wv == 0) {
-            const int i = lane;
+    if (wv == 0) {
+        const int i = lane;
+        for (int pb = 0; pb < npan; ++pb) {
+            const int p0 = PW * pb;
+            if (pb >= 2 && !lds_wait_geq(&flag_trail[pb - 2], 3)) flag_err = 1;
+            if (pb >= 1) {
+                // this panel's columns (rows >= p0) minus panel pb-1's
+                // product: up to three 16-row tiles, their loads, products
+                // and updates each issued together
+                const int q0 = p0 - PW;
+                T bop[4], aop[3][4], cold[3][4];
+                acc_t acc[3];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) bop[kk] = A[p0 + (lane & 15)][q0 + 4 * kk + (lane >> 4)];
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const int tt = min(pb + x, 3);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) aop[x][kk] = A[16 * tt + (lane & 15)][q0 + 4 * kk + (lane >> 4)];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) cold[x][v] = A[16 * tt + M::row(lane, v)][p0 + (lane & 15)];
+                }
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    acc[x] = acc_t{0, 0, 0, 0};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) acc[x] = M::run(aop[x][kk], bop[kk], acc[x]);
+                }
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const int tt = pb + x;
+                    if (tt < npan)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int r = 16 * tt + M::row(lane, v), c = p0 + (lane & 15);
+                            if (r >= c) A[r][c] = cold[x][v] - acc[x][v];
+                        }
+                }
+                wave_lds_sync();
+            }
             T r[PW];
 #pragma unroll
             for (int c = 0; c < PW; ++c) r[c] = A[i][p0 + c];
@@ -159,108 +269,130 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
 #pragma unroll
                 for (int c2 = c + 1; c2 < PW; ++c2) r[c2] -= lij * lane_read(lij, p0 + c2);
             }
+            // rows >= p0 in full: the entries above the diagonal hold
+            // scratch until the inverse levels overwrite every one of them
             if (i >= p0)
 #pragma unroll
-                for (int c = 0; c < PW; ++c)
-                    if (c <= i - p0) A[i][p0 + c] = r[c];
+                for (int c = 0; c < PW; ++c) A[i][p0 + c] = r[c];
+            lds_flag_store(&flag_panel, pb + 1);
         }
-        __syncthreads();
-        // trailing lower part, rows and columns in [q0, nbr): 16x16 MFMA tiles
-        const int q0 = p0 + PW, nt = (nbr - q0) / 16, ntile = nt * (nt + 1) / 2;
-        for (int x = wv; x < ntile; x += 4) {
-            int ti = 0;
-            while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
-            const int tj = x - ti * (ti + 1) / 2;
-            const int i0 = q0 + 16 * ti, j0 = q0 + 16 * tj;
-            acc_t acc = {0, 0, 0, 0};
+    } else {
+        const int tw = wv - 1;  // trailing wave 0..2
+        for (int pb = 0; pb < npan; ++pb) {
+            const int p0 = PW * pb;
+            if (!lds_wait_geq(&flag_panel, pb + 1)) flag_err = 1;
+            // panel pb applied to the tiles (ti, tj), tj >= pb + 2, lower part;
+            // tile x = ti (ti + 1) / 2 + tj belongs to trailing wave x % 3
+            for (int x = tw; x < 10; x += 3) {
+                int ti = 0;
+                while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+                const int tj = x - ti * (ti + 1) / 2;
+                if (tj < pb + 2 || ti >= npan) continue;
+                const int i0 = 16 * ti, j0 = 16 * tj;
+                acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int kk = 0; kk < PW; kk += 4)
-                acc = M::run(A[i0 + (lane & 15)][p0 + kk + (lane >> 4)], A[j0 + (lane & 15)][p0 + kk + (lane >> 4)],
-                             acc);
+                for (int kk = 0; kk < PW; kk += 4)
+                    acc = M::run(A[i0 + (lane & 15)][p0 + kk + (lane >> 4)], A[j0 + (lane & 15)][p0 + kk + (lane >> 4)],
+                                 acc);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = i0 + M::row(lane, v), c = j0 + (lane & 15);
-                if (r >= c) A[r][c] -= acc[v];
+                for (int v = 0; v < 4; ++v) {
+                    const int r = i0 + M::row(lane, v), c = j0 + (lane & 15);
+                    if (r >= c) A[r][c] -= acc[v];
+                }
+            }
+            if (lane == 0) lds_flag_add(&flag_trail[pb]);
+            else wave_lds_sync();
+            if (wv == 1) {
+                // inverse of panel pb's diagonal 16x16 triangle: 2x2 block
+                // formula from the diagonal (rdg = 1/l_jj) up, h = 1, 2, 4, 8;
+                // X21 is kept transposed in the upper triangle
+                T *tf = &Tf[0][0];
+                // fixed trip counts (h unrolled, terms masked) so each
+                // level issues its LDS reads together; lanes >= 8 h compute
+                // a clamped copy and store nothing
+#pragma unroll
+                for (int lv = 0; lv < 4; ++lv) {
+                    const int h = 1 << lv, nel = 8 * h;  // 16 / (2h) blocks of h x h
+                    const int ln = min(lane, nel - 1);
+                    const int blk = ln / (h * h), rem = ln % (h * h), a = rem % h, b = rem / h, o = p0 + 2 * h * blk;
+                    T acc = T(0);  // (L21 X11)[a][b]
+#pragma unroll
+                    for (int c = 0; c < h; ++c) {
+                        const T l = A[o + h + a][o + c], x = SPC_INV(o + c, o + b);
+                        acc += (c >= b) ? l * x : T(0);
+                    }
+                    if (lane < nel) tf[lane] = acc;
+                    wave_lds_sync();
+                    T out = T(0);  // -(X22 (L21 X11))[a][b]
+#pragma unroll
+                    for (int c = 0; c < h; ++c) {
+                        const T x = SPC_INV(o + h + a, o + h + c), u = tf[blk * h * h + b * h + c];
+                        out -= (c <= a) ? x * u : T(0);
+                    }
+                    wave_lds_sync();
+                    if (lane < nel) A[o + b][o + h + a] = out;
+                    wave_lds_sync();
+                }
+                // both 16-blocks of a 32-block inverted (the second may be
+                // identity padding): merge them now, off the panel chain
+                if (nb > PW && ((pb & 1) || pb == npan - 1)) inv16(32 * (pb >> 1));
+                if (pb == 1) lds_flag_store(&flag_x11, 1);
+            }
+            // L of panel pb to the panel store (rows >= p0 of its columns)
+            for (int e = lane + 64 * tw; e < PW * NB; e += 192) {
+                const int k = p0 + e / NB, row = e % NB;
+                if (k < nb && row >= k && row < nb) P[(int64_t)(c0 + k) * m + c0 + row] = A[row][k];
+            }
+            if (pb == 1 && nb > 2 * PW && wv >= 2) {
+                // the first 32-column block's inverse X11 is final: wave 2
+                // forms L21 X11 for the last merge, wave 3 stores the
+                // inverse's first 32 rows (X11, zeros to its right)
+                if (!lds_wait_geq(&flag_x11, 1)) flag_err = 1;
+                if (wv == 2) {
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        const int ti = tt >> 1, tj = tt & 1;
+                        acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+                        for (int kk = 0; kk < 32; kk += 4)
+                            acc = M::run(A[32 + 16 * ti + (lane & 15)][kk + (lane >> 4)],
+                                         SPC_INV(kk + (lane >> 4), 16 * tj + (lane & 15)), acc);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) T32[16 * ti + M::row(lane, v)][16 * tj + (lane & 15)] = acc[v];
+                    }
+                } else {
+                    for (int e = lane; e < 32 * nb; e += 64) {
+                        const int i = e & 31, k = e >> 5;
+                        Vi[k * nb + i] = SPC_INV(i, k);
+                    }
+                }
             }
         }
-        __syncthreads();
     }
-    if (wv == 0 && lane == 0 && bad >= 0) atomicMin(status, (unsigned long long)(g0 + bad));
-#define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
-    // L^{-1} by the 2x2 block formula for a lower triangle,
-    //   inv [L11 0; L21 L22] = [X11 0; -X22 L21 X11  X22],
-    // from the diagonal (rdg = 1/l_jj) up: blocks of h = 1, 2, 4, 8 here, one
-    // element of X21 per thread; h = 16, 32 below on MFMA tiles.  X21 is kept
-    // transposed in the upper triangle, so every level reads finished data.
-    {
-        T *tf = &Tf[0][0];
-        for (int h = 1; h < 16; h <<= 1) {
-            const int nel = 32 * h;  // 64 / (2h) blocks of h x h
-            const int blk = t / (h * h), rem = t % (h * h), a = rem % h, b = rem / h, o = 2 * h * blk;
-            if (t < nel) {
-                T acc = T(0);  // (L21 X11)[a][b]
-                for (int c = b; c < h; ++c) acc += A[o + h + a][o + c] * SPC_INV(o + c, o + b);
-                tf[t] = acc;
-            }
-            __syncthreads();
-            T out = T(0);
-            if (t < nel)  // -(X22 (L21 X11))[a][b]
-                for (int c = 0; c <= a; ++c) out -= SPC_INV(o + h + a, o + h + c) * tf[blk * h * h + b * h + c];
-            __syncthreads();
-            if (t < nel) A[o + b][o + h + a] = out;
-            __syncthreads();
-        }
-    }
-    if (nb > 16) {
-        // 16-blocks inside the 32-blocks: wave 0 the one at 0, wave 1 at 32
-        const int o = 32 * wv;
-        if (wv < 2) {
-            acc_t acc = {0, 0, 0, 0};  // L21 X11
-#pragma unroll
-            for (int kk = 0; kk < 16; kk += 4)
-                acc = M::run(A[o + 16 + (lane & 15)][o + kk + (lane >> 4)],
-                             SPC_INV(o + kk + (lane >> 4), o + (lane & 15)), acc);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Tf[16 * wv + M::row(lane, v)][lane & 15] = acc[v];
-        }
-        __syncthreads();
-        if (wv < 2) {
-            acc_t acc = {0, 0, 0, 0};  // X22 (L21 X11)
-#pragma unroll
-            for (int kk = 0; kk < 16; kk += 4)
-                acc = M::run(SPC_INV(o + 16 + (lane & 15), o + 16 + kk + (lane >> 4)),
-                             Tf[16 * wv + kk + (lane >> 4)][lane & 15], acc);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) A[o + (lane & 15)][o + 16 + M::row(lane, v)] = -acc[v];
-        }
-        __syncthreads();
-    }
+    __syncthreads();
+    if (wv == 0 && lane == 0 && (bad >= 0 || flag_err)) atomicMin(status, (unsigned long long)(g0 + (bad >= 0 ? bad : 0)));
     if (nb > 32) {
-        // the two 32-blocks; wave w computes 16x16 tile (w / 2, w % 2)
+        // the two 32-blocks: X21 = -X22 (L21 X11), wave w the 16x16 tile
+        // (w / 2, w % 2); the first 32 rows of the inverse are stored already
         const int ti = wv >> 1, tj = wv & 1;
         acc_t acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 32; kk += 4)
-            acc = M::run(A[32 + 16 * ti + (lane & 15)][kk + (lane >> 4)],
-                         SPC_INV(kk + (lane >> 4), 16 * tj + (lane & 15)), acc);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Tf[16 * ti + M::row(lane, v)][16 * tj + (lane & 15)] = acc[v];
-        __syncthreads();
-        acc = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < 32; kk += 4)
             acc = M::run(SPC_INV(32 + 16 * ti + (lane & 15), 32 + kk + (lane >> 4)),
-                         Tf[kk + (lane >> 4)][16 * tj + (lane & 15)], acc);
+                         T32[kk + (lane >> 4)][16 * tj + (lane & 15)], acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) A[16 * tj + (lane & 15)][32 + 16 * ti + M::row(lane, v)] = -acc[v];
         __syncthreads();
-    }
 #pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-        const int e = t + 256 * q, i = e % NB, k = e / NB;
-        if (i < nb && k < nb) {
-            if (k <= i) P[(int64_t)(c0 + k) * m + c0 + i] = A[i][k];
-            Vi[k * nb + i] = SPC_INV(i, k);
+        for (int q = 0; q < 32 * NB / 256; ++q) {
+            const int e = t + 256 * q, i = 32 + e % 32, k = e / 32;
+            if (i < nb && k < nb) Vi[k * nb + i] = SPC_INV(i, k);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NB * NB / 256; ++q) {
+            const int e = t + 256 * q, i = e % NB, k = e / NB;
+            if (i < nb && k < nb) Vi[k * nb + i] = SPC_INV(i, k);
         }
     }
 #undef SPC_INV
@@ -273,6 +405,8 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
     __shared__ T A[NB][NB + 1];
     __shared__ T rdg[NB];
     __shared__ T Tf[32][33];
+    __shared__ T T32[32][33];
+    __shared__ int flags[8];
     const PanelTask tk = tasks[blockIdx.x];
     const int64_t m = tk.m;
     const int c0 = tk.c0, nb = tk.c1 - tk.c0;
@@ -293,7 +427,8 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
         }
     }
     __syncthreads();
-    potrf_lds<T>(A, rdg, Tf, nb, P, m, c0, Linv + tk.ioff, status + (status_slot ? status_slot[tk.s] : 0), tk.g0);
+    potrf_lds<T>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
+                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,16 +763,20 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
                 if (gj < tk.jmax) P[gj * m + gi] = nv[cc];
             }
         __syncthreads();
+        // LDS for the factorization: the tile buffers, free now (cb and cr
+        // hold no scatter addresses in this mode)
         T(*A)[TM + 1] = Cs;
-        T *rdg = &As[0][0];
+        T *rdg = reinterpret_cast<T *>(cb);
+        int *flags = reinterpret_cast<int *>(cr);
         T(*Tf)[33] = reinterpret_cast<T(*)[33]>(&Bs[0][0]);
+        T(*T32)[33] = reinterpret_cast<T(*)[33]>(&As[0][0]);
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             const int c = cg * CPT + cc;
             A[r][c] = (r < nb2 && c <= r) ? nv[cc] : (r == c ? T(1) : T(0));
         }
         __syncthreads();
-        potrf_lds<T>(A, rdg, Tf, nb2, P, m, tk.j0, Linv + tk.aux,
+        potrf_lds<T>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
                      status + (status_slot ? status_slot[tk.s] : 0), tk.blk);
         return;
     }
