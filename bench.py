@@ -45,6 +45,8 @@ def parse():
                     help="grid3d60: the headline FP64 factor + solve (default); grid2d64: small-system "
                          "latency; elast48: FP32 factor + FP64 refinement on the 48^3 elasticity "
                          "operator; batch512: 512 systems in one schedule; serving: request loop")
+    ap.add_argument("--tuning", default="auto", choices=["auto", "default"],
+                    help="schedule cut-offs: the autotuner's cache entry for this workload (auto), else defaults")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second (0: sweep)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per rate")
     return ap.parse_args()
@@ -134,6 +136,15 @@ def timed(fn, steps, warmup, torch):
     return np.array([a.elapsed_time(b) for a, b in out])
 
 
+def cutoffs(args, systems, nrhs, precision):
+    """The autotuned schedule cut-offs for this workload and precision (from
+    the tuner's cache), or {} for the library defaults."""
+    if args.tuning != "auto":
+        return {}
+    from paper_2202_09288_amd import tune
+    return tune.load(tune.cache_key(systems, precision, nrhs)) or {}
+
+
 def bench_grid2d(args):
     """64x64 5-point Laplacian (n = 4,096), FP64: a latency-bound system."""
     import torch
@@ -142,7 +153,8 @@ def bench_grid2d(args):
     import oracle
     torch.cuda.set_device(0)
     s = W.grid2d_unit()
-    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    tuning = cutoffs(args, [s], 1, "fp64")
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tuning)
     dv = torch.from_numpy(s.values).cuda()
     B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
     Bw = torch.empty_like(B0)
@@ -157,7 +169,8 @@ def bench_grid2d(args):
     out = head(args, round(flops / (fac.mean() * 1e-3) / 1e9, 3), "GFLOP/s", "f64",
                {"workload": "2D 5-point, 64x64 grid, diagonal = degree + 1e-2, geometric nested dissection, "
                             "1 RHS, plain FP64 factor + solve", "n": s.n, "flops": int(flops),
-                "levels": sym.info["levels"], "nsuper": sym.info["nsuper"]},
+                "levels": sym.info["levels"], "nsuper": sym.info["nsuper"],
+                "schedule_cutoffs": tuning or "library defaults"},
                round(float(fac.mean() + sol.mean()), 4))
     out.update({"factor_us_p50": round(float(np.median(fac)) * 1e3, 1),
                 "solve_us_p50": round(float(np.median(sol)) * 1e3, 1),
@@ -175,7 +188,8 @@ def bench_elast(args):
     import oracle
     torch.cuda.set_device(0)
     s = W.elast48()
-    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    tuning = cutoffs(args, [s], 4, "fp32")
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tuning)
     flops = float(sym.info["flops"])
     dv = torch.from_numpy(s.values).cuda()
     B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
@@ -202,7 +216,8 @@ def bench_elast(args):
     out = head(args, r32["factor_gflops"], "GFLOP/s", "f32",
                {"workload": "3D 27-point 3-dof elasticity-like operator, 48^3 grid, kappa ~1e8, 4 RHS, "
                             "FP32 factor + FP64 refinement to 1e-12", "n": s.n, "nnz_lower": s.nnz,
-                "flops": int(flops), "nnz_L": sym.info["nnz_l"]},
+                "flops": int(flops), "nnz_L": sym.info["nnz_l"],
+                "schedule_cutoffs": tuning or "library defaults"},
                round(r32["factor_ms"] + r32["refined_solve_ms_p50"], 3))
     out.update({"fp32": res["fp32"], "fp64": res["fp64"],
                 "fp32_factor_frac_of_peak": round(r32["factor_gflops"] / (FP32_PEAK_TFLOPS * 1e3), 4),
@@ -220,7 +235,8 @@ def bench_batch(args):
     import oracle
     torch.cuda.set_device(0)
     systems = W.batch512()
-    syms = [spchol.Symbolic(x.colptr, x.rowidx, x.perm, 0.05) for x in systems]
+    tuning = cutoffs(args, systems, 16, "fp32")
+    syms = [spchol.Symbolic(x.colptr, x.rowidx, x.perm, 0.05, tuning) for x in systems]
     flops = float(sum(x.info["flops"] for x in syms))
     dvs = [torch.from_numpy(x.values).cuda() for x in systems]
     Bs0 = [torch.from_numpy(np.ascontiguousarray(x.B.T)).cuda() for x in systems]
@@ -266,7 +282,8 @@ def bench_batch(args):
     out = head(args, r32["factor_gflops"], "GFLOP/s", "f32",
                {"workload": "batch of 512 SPD systems: 2D 5-point / 3D 7-point grids, sides U[32,200] / "
                             "U[10,34], conductances 10^U[-2,2), shift 1e-2, 16 RHS each; one merged schedule",
-                "systems": len(systems), "n_total": int(sum(x.n for x in systems)), "flops": int(flops)},
+                "systems": len(systems), "n_total": int(sum(x.n for x in systems)), "flops": int(flops),
+                "schedule_cutoffs": tuning or "library defaults"},
                round(r32["factor_ms"] + r32["batched_solve_ms_p50"], 3))
     out.update({"fp32": res["fp32"], "fp64": res["fp64"]})
     print(json.dumps(out), flush=True)
@@ -307,8 +324,9 @@ def bench_grid3d(args):
 
     torch.cuda.set_device(0)
     s = W.grid3d_cond(k=args.grid)
+    tuning = cutoffs(args, [s], 1, args.precision)
     t0 = time.perf_counter()
-    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tuning)
     t_analyze = time.perf_counter() - t0
     info = sym.info
     flops = float(info["flops"])
@@ -390,6 +408,7 @@ def bench_grid3d(args):
                                "geometric nested dissection, 1 RHS, plain supernodal factor + solve",
                    "n": s.n, "nnz_lower": s.nnz, "flops": int(flops), "nnz_L": info["nnz_l"],
                    "nsuper": info["nsuper"], "levels": info["levels"], "amalg_z": 0.05,
+                   "schedule_cutoffs": tuning or "library defaults",
                    "precision": args.precision},
         "factor_ms_mean": round(fac_mean, 3),
         "factor_ms_p50": round(float(np.median(fac_ms)), 3),

@@ -63,7 +63,23 @@ typedef struct spc_options {
      * this library's).  z < 0 keeps the fundamental supernodes.
      * Default 0.05. */
     double amalg_z;
-    int32_t reserved[8];
+    /* Schedule cut-offs (the choice between batching small supernodes of a
+     * level into one launch and giving a large one the whole device).
+     * 0 keeps the library default, a negative value turns the path off.
+     *   tiny_w, tiny_m    supernodes with w <= tiny_w and m <= tiny_m are
+     *                     factored (and solved in the wide levels) one wave
+     *                     each; at most 8 and 64 (default 8, 64)
+     *   small_w, small_m  the same limits for one workgroup each; at most 32
+     *                     and 128 (default 32, 128)
+     *   big_min, big_min_k  scatter updates with m - w >= big_min and
+     *                     w >= big_min_k use 128x128 tiles (default 256, 128)
+     *   solve_persist_max  solve levels from the top with fewer tasks than
+     *                     this run as one persistent launch per sweep
+     *                     (default 1024)
+     * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
+    int32_t tiny_w, tiny_m, small_w, small_m;
+    int32_t big_min, big_min_k, solve_persist_max;
+    int32_t reserved;
 } spc_options;
 
 /* Summary numbers of an analysis. */

@@ -611,9 +611,32 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
     spc_symbolic s = new (std::nothrow) spc_symbolic_s;
     if (!s) return SPC_OUT_OF_MEMORY;
     double z = opts ? opts->amalg_z : 0.05;
+    spc::Tuning tu;
+    if (opts) {
+        // 0: default; < 0: off; > limit: invalid
+        auto pick = [](int32_t v, int32_t def, int32_t lim, int32_t off, int32_t *out) {
+            if (v == 0) *out = def;
+            else if (v < 0) *out = off;
+            else if (v > lim) return false;
+            else *out = v;
+            return true;
+        };
+        constexpr int32_t kNone = INT32_MAX;
+        const bool ok = pick(opts->tiny_w, spc::kTinyW, spc::kTinyW, 0, &tu.tiny_w) &&
+                        pick(opts->tiny_m, spc::kTinyM, spc::kTinyM, 0, &tu.tiny_m) &&
+                        pick(opts->small_w, spc::kSmallW, spc::kSmallW, 0, &tu.small_w) &&
+                        pick(opts->small_m, spc::kSmallM, spc::kSmallM, 0, &tu.small_m) &&
+                        pick(opts->big_min, spc::kBigMin, kNone, kNone, &tu.big_min) &&
+                        pick(opts->big_min_k, spc::kBigMinK, kNone, kNone, &tu.big_min_k) &&
+                        pick(opts->solve_persist_max, spc::kSolvePersistMax, kNone, 0, &tu.solve_persist_max);
+        if (!ok) {
+            delete s;
+            return SPC_INVALID_INPUT;
+        }
+    }
     int rc;
     try {
-        rc = spc::analyze(n, h_colptr, h_rowidx, h_perm, z, s->S);
+        rc = spc::analyze(n, h_colptr, h_rowidx, h_perm, z, tu, s->S);
     } catch (const std::bad_alloc &) {
         rc = SPC_OUT_OF_MEMORY;
     } catch (...) {

@@ -42,6 +42,18 @@ constexpr int kSolveRows = 256;
 // levels persistent -> 4.9).
 constexpr int kSolvePersistMax = 1024;
 
+// Schedule cut-offs of one analysis (the defaults above, or chosen per
+// workload through the analysis options, e.g. by the autotuner).  The
+// tiny and small limits are bounded by what their kernels hold (kTinyW x
+// kTinyM in one wave, kSmallW x kSmallM in one workgroup's LDS); 0 turns a
+// path off.
+struct Tuning {
+    int32_t tiny_w = kTinyW, tiny_m = kTinyM;
+    int32_t small_w = kSmallW, small_m = kSmallM;
+    int32_t big_min = kBigMin, big_min_k = kBigMinK;
+    int32_t solve_persist_max = kSolvePersistMax;
+};
+
 // One pair (source supernode s, ancestor t) of the scatter: rows
 // i0..i1-1 of R_s (positions, i0 >= w_s) are columns of t, and rows
 // i0..m_s-1 of R_s sit at positions rel[rel_off + (i - i0)] of R_t.
@@ -126,6 +138,7 @@ struct SolveTask {
 };
 
 struct Symbolic {
+    Tuning tune;
     int64_t n = 0, nnzA = 0;
     std::vector<int32_t> perm, iperm, parent, colcount;
     int32_t nsuper = 0;
@@ -215,7 +228,7 @@ struct Symbolic {
 
 // Returns 0 or a negative spc_status.
 int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm,
-            double z, Symbolic &S);
+            double z, const Tuning &tune, Symbolic &S);
 // Schedule of an analysis whose structural arrays are set.
 int build_schedule(Symbolic &S);
 // Disjoint union of analyses with a schedule over the whole forest; the

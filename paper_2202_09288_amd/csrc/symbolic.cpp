@@ -93,7 +93,7 @@ int64_t find_pos(const int32_t *R, int64_t m, int32_t row) {
 int build_schedule(Symbolic &S);
 
 int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm_in,
-            double z, Symbolic &S) {
+            double z, const Tuning &tune, Symbolic &S) {
     // ---- validation --------------------------------------------------------
     if (n < 0 || n > INT32_MAX - 1 || !colptr) return SPC_INVALID_INPUT;
     if (colptr[0] != 0) return SPC_INVALID_INPUT;
@@ -105,6 +105,7 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
             if (rowidx[k] <= rowidx[k - 1] || rowidx[k] >= n) return SPC_INVALID_INPUT;
     }
     S = Symbolic();
+    S.tune = tune;
     S.n = n;
     S.nnzA = colptr[n];
     std::vector<int32_t> perm0(n), iperm0(n, -1);
@@ -398,8 +399,13 @@ int build_schedule(Symbolic &S) {
     S.tiny_ptr.assign(S.nlevels + 1, 0);
     S.tiny_tasks.clear();
     S.tiny_flops.assign(S.nlevels, 0.0);
+    const Tuning &tu = S.tune;
+    auto is_tiny = [&](int32_t s) {
+        return S.super_ptr[s + 1] - S.super_ptr[s] <= tu.tiny_w && S.rptr[s + 1] - S.rptr[s] <= tu.tiny_m;
+    };
     auto is_small = [&](int32_t s) {
-        return S.super_ptr[s + 1] - S.super_ptr[s] <= kSmallW && S.rptr[s + 1] - S.rptr[s] <= kSmallM;
+        return is_tiny(s) ||
+               (S.super_ptr[s + 1] - S.super_ptr[s] <= tu.small_w && S.rptr[s + 1] - S.rptr[s] <= tu.small_m);
     };
     for (int32_t l = 0; l < S.nlevels; ++l) {
         std::vector<int32_t> big;
@@ -407,7 +413,7 @@ int build_schedule(Symbolic &S) {
             if (is_small(s)) {
                 const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
                 const int64_t mi = S.rptr[s + 1] - S.rptr[s];
-                const bool tiny = wi <= kTinyW && mi <= kTinyM;
+                const bool tiny = is_tiny(s);
                 (tiny ? S.tiny_tasks : S.small_tasks)
                     .push_back(SmallTask{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s, (int32_t)mi, wi,
                                          S.super_ptr[s]});
@@ -508,7 +514,7 @@ int build_schedule(Symbolic &S) {
         double ef = 0.0, efb = 0.0;
         for (int32_t s : bylevel[l]) {
             int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
-            const bool big = m - w >= kBigMin && w >= kBigMinK;
+            const bool big = m - w >= tu.big_min && w >= tu.big_min_k;
             (big ? efb : ef) += (double)(m - w) * (double)(m - w + 1) * (double)w;
             const int64_t tsz = big ? kTileBig : kTile;
             for (int64_t j0 = w; j0 < m; j0 += tsz)
@@ -554,10 +560,10 @@ int build_schedule(Symbolic &S) {
     }
     // one task per chunk of rows below the block; a block with no rows
     // below still gets one (empty) task, which does its diagonal part.
-    // Levels from the top with fewer than kSolvePersistMax tasks run
+    // Levels from the top with fewer than solve_persist_max tasks run
     // persistently (solve_split..); below them, the blocks of tiny
-    // supernodes (w <= kTinyW, m <= kTinyM: a single block and a single
-    // task) go to the one-wave solve kernels instead.
+    // supernodes (a single block and a single task) go to the one-wave
+    // solve kernels instead.
     auto block_tasks = [&](const SolveBlock &B) {
         const int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
         return std::max<int64_t>(1, (m - B.c1 + kSolveRows - 1) / kSolveRows);
@@ -567,7 +573,7 @@ int build_schedule(Symbolic &S) {
         int64_t cnt = 0;
         for (int64_t e = S.slevel_ptr[split - 1]; e < S.slevel_ptr[split]; ++e)
             cnt += block_tasks(S.sblocks[S.sblock_order[e]]);
-        if (cnt >= kSolvePersistMax) break;
+        if (cnt >= tu.solve_persist_max) break;
     }
     S.solve_split = split;
     S.stask_ptr.assign(nsl + 1, 0);
@@ -579,7 +585,7 @@ int build_schedule(Symbolic &S) {
             SolveBlock &B = S.sblocks[q];
             int64_t m = S.rptr[B.s + 1] - S.rptr[B.s];
             const int64_t w = S.super_ptr[B.s + 1] - S.super_ptr[B.s];
-            if (l < split && w <= kTinyW && m <= kTinyM) {
+            if (l < split && w <= tu.tiny_w && m <= tu.tiny_m) {
                 S.stiny.push_back(SmallTask{S.lptr[B.s], S.rptr[B.s], S.inv_off[q], B.s, (int32_t)m, (int32_t)w,
                                             S.super_ptr[B.s]});
                 B.ntasks = 1;
@@ -657,6 +663,7 @@ int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<i
           std::vector<int64_t> &panel_off, std::vector<int64_t> &inv_base, std::vector<int64_t> &val_off) {
     M = Symbolic();
     const size_t k = parts.size();
+    if (k) M.tune = parts[0]->tune;
     col_off.assign(k + 1, 0);
     panel_off.assign(k + 1, 0);
     inv_base.assign(k + 1, 0);

@@ -49,8 +49,13 @@ KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": 
                 "assemble": "k_zero<{t}> + k_assemble<{t}>"}
 
 
+# schedule cut-offs of spc_options (0: library default, < 0: path off)
+TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max")
+
+
 class _Options(ctypes.Structure):
-    _fields_ = [("amalg_z", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+    _fields_ = [("amalg_z", ctypes.c_double)] + [(k, ctypes.c_int32) for k in TUNING_FIELDS] + \
+        [("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -170,12 +175,17 @@ _EXPORT_ARRAYS = {"perm": (0, np.int32, "n"), "parent": (1, np.int32, "n"),
 class Symbolic:
     """spc_analyze: host-only symbolic analysis of a lower-CSC pattern."""
 
-    def __init__(self, colptr, rowidx, perm=None, amalg_z: float = 0.05):
+    def __init__(self, colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None):
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
         n = self._colptr.size - 1
         opts = _Options(amalg_z=float(amalg_z))
+        self.tuning = dict(tuning or {})
+        for k, v in self.tuning.items():
+            if k not in TUNING_FIELDS:
+                raise ValueError(f"unknown schedule cut-off {k!r}")
+            setattr(opts, k, int(v))
         h = _P()
         rc = _lib.spc_analyze(n, _np_ptr(self._colptr), _np_ptr(self._rowidx),
                               _np_ptr(self._perm) if self._perm is not None else None,
@@ -378,8 +388,8 @@ class Batch:
         self.close()
 
 
-def analyze(colptr, rowidx, perm=None, amalg_z: float = 0.05) -> Symbolic:
-    return Symbolic(colptr, rowidx, perm, amalg_z)
+def analyze(colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None) -> Symbolic:
+    return Symbolic(colptr, rowidx, perm, amalg_z, tuning)
 
 
 def factorize(sym: Symbolic, d_values, precision="fp64", stream=None) -> Factor:

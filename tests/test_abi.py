@@ -114,3 +114,31 @@ def test_info_and_export():
     with pytest.raises(KeyError):
         S.export("nope")
     assert spchol._lib.spc_symbolic_export(S.handle, 99, ctypes.c_void_p(1)) == spchol.INVALID_INPUT
+
+
+@pytest.mark.parametrize("field,value", [("tiny_w", 9), ("tiny_m", 65), ("small_w", 33), ("small_m", 129)])
+def test_cutoffs_beyond_kernel_limits_rejected(field, value):
+    s = W.laplacian((6, 5), "5pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {field: value})
+    assert e.value.status == spchol.INVALID_INPUT
+
+
+def test_cutoffs_shape_the_schedule():
+    """Schedule cut-offs from the analysis options: turning the one-wave
+    path off empties the one-wave solve list; no persistent levels when the
+    threshold is off, all of them when it is huge; an unknown name is
+    refused by the binding.  The structure of L does not depend on them."""
+    s = W.laplacian((30, 30, 30), "7pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
+    base = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    no_tiny = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"tiny_w": -1})
+    assert base.info["solve_tiny_tasks"] > 0 and no_tiny.info["solve_tiny_tasks"] == 0
+    none = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"solve_persist_max": -1})
+    assert none.info["solve_persistent_levels"] == 0
+    allp = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"solve_persist_max": 1 << 30})
+    assert allp.info["solve_persistent_levels"] == allp.info["solve_levels"]
+    for other in (no_tiny, none, allp):
+        for name in ("super_ptr", "rows", "lptr"):
+            assert np.array_equal(other.export(name), base.export(name))
+    with pytest.raises(ValueError):
+        spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"tile": 3})

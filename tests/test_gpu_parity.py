@@ -91,6 +91,36 @@ def test_solve_wide_levels_one_wave_path(torch_dev, lib, dims, nrhs, precision):
         assert relF <= 1e-4 and eta <= 1e-5
 
 
+SCHEDULES = {
+    "blocked only": {"tiny_w": -1, "small_w": -1},
+    "tiny 4x32, small 16x64": {"tiny_w": 4, "tiny_m": 32, "small_w": 16, "small_m": 64},
+    "128-tiles everywhere": {"big_min": 1, "big_min_k": 1},
+    "no 128-tiles": {"big_min": -1},
+    "solve levels only": {"solve_persist_max": -1},
+    "solve all persistent": {"solve_persist_max": 1 << 30},
+}
+
+
+@pytest.mark.parametrize("name", list(SCHEDULES))
+def test_schedule_cutoffs_same_factor(torch_dev, lib, name):
+    """Every choice of the schedule cut-offs (what the autotuner varies)
+    gives the oracle's factor and a solve at the FP64 bar, 1 and 16 RHS."""
+    torch = torch_dev
+    s = grid((22, 21, 20), seed=11, nrhs=16)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, SCHEDULES[name])
+    F = lib.factorize(sym, torch.from_numpy(s.values).cuda())
+    F.sync()
+    relF = oracle.rel_frobenius(F.export(), S.factor(s.values), S.lower_mask())
+    for q in (1, 16):
+        Bt = torch.from_numpy(np.ascontiguousarray(s.B[:, :q].T)).cuda()
+        F.solve(Bt)
+        eta = oracle.backward_error(S.n, s.colptr, s.rowidx, s.values, Bt.cpu().numpy().T, s.B[:, :q])
+        print(f"schedule {name}: relF={relF:.2e} eta({q})={eta:.2e}", flush=True)
+        assert eta <= BERR_FP64
+    assert relF <= REL_F_FP64
+
+
 @pytest.mark.parametrize("z", [-1.0, 0.0, 0.5])
 def test_fp64_amalgamation_settings(torch_dev, lib, z):
     s = grid((14, 13, 12), seed=3, nrhs=2)
