@@ -47,6 +47,8 @@ def parse():
                          "operator; batch512: 512 systems in one schedule; serving: request loop")
     ap.add_argument("--tuning", default="auto", choices=["auto", "default"],
                     help="schedule cut-offs: the autotuner's cache entry for this workload (auto), else defaults")
+    ap.add_argument("--graph", default="on", choices=["on", "off"],
+                    help="replay the factorization from a captured HIP graph (on) or launch it eagerly")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second (0: sweep)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per rate")
     return ap.parse_args()
@@ -160,6 +162,7 @@ def bench_grid2d(args):
     Bw = torch.empty_like(B0)
     F = spchol.factorize(sym, dv)
     F.sync()
+    F.set_graph(args.graph == "on")
     steps, warm = max(args.steps, 50), max(args.warmup, 5)
     fac = timed(lambda: F.refactorize(dv), steps, warm, torch)
     sol = timed(lambda: (Bw.copy_(B0), F.solve(Bw)), steps, warm, torch)
@@ -197,6 +200,7 @@ def bench_elast(args):
     for prec in ("fp32", "fp64"):
         F = spchol.factorize(sym, dv, prec)
         F.sync()
+        F.set_graph(args.graph == "on")
         fac = timed(lambda: F.refactorize(dv), args.steps, args.warmup, torch)
         X = torch.zeros_like(B0)
         info = {}
@@ -243,6 +247,7 @@ def bench_batch(args):
     res = {}
     for prec in ("fp32", "fp64"):
         batch = spchol.Batch(syms, prec)
+        batch.set_graph(args.graph == "on")
         batch.factorize(dvs)
         batch.sync()
         fac = timed(lambda: batch.factorize(dvs), args.steps, args.warmup, torch)
@@ -335,6 +340,7 @@ def bench_grid3d(args):
     Bw = torch.empty_like(B0)
     F = spchol.factorize(sym, dv, args.precision)
     F.sync()
+    F.set_graph(args.graph == "on")
     stream = torch.cuda.current_stream()
 
     def step(ev):

@@ -282,6 +282,18 @@ typedef struct spc_kernel_stats {
  * While on, every numeric launch is bracketed by two events on the stream. */
 int spc_factor_set_profiling(spc_factor f, int on);
 
+/* Graph replay (for callers that refactor the same pattern again and
+ * again, e.g. under a launch-bound schedule): on (1), the next factorization
+ * of f captures its whole launch sequence into a HIP graph, and later ones
+ * replay it with one launch on the given stream; the graph is captured
+ * again when the values pointer changes.  Results are those of the eager
+ * path.  Profiling (spc_factor_set_profiling) takes the eager path.  Off
+ * (0) frees the graph.  A batch view refuses it (SPC_INVALID_INPUT); use
+ * spc_batch_set_graph, which covers spc_batch_factorize (the per-system
+ * value copies stay outside the graph). */
+int spc_factor_set_graph(spc_factor f, int on);
+int spc_batch_set_graph(spc_batch b, int on);
+
 /* Per-class totals of the last profiled factorization of f (synchronizes). */
 int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *out);
 int spc_batch_set_profiling(spc_batch b, int on);

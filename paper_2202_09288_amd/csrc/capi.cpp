@@ -65,6 +65,14 @@ struct spc_factor_s {
     struct spc_batch_s *batch = nullptr;
     int batch_index = -1;
     int64_t status_col_off = 0;
+    // graph replay of the factorization: captured once on cap_stream (a
+    // graph cannot be captured on the legacy default stream), then launched
+    // on the caller's stream; recaptured when the values pointer changes
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double *graph_values = nullptr;
     // per-launch profiling
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;     // pairs
@@ -326,10 +334,56 @@ void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, c
     }
 }
 
+void drop_graph(spc_factor_s *f) {
+    if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    f->gexec = nullptr;
+    f->graph = nullptr;
+    f->graph_values = nullptr;
+}
+
+// Capture the status reset and every launch of the factorization (kernels
+// only: the fills are kernels too) into f's graph.
+int capture_factor(spc_factor f, const double *d_values) {
+    const spc::Symbolic &S = f->sym->S;
+    const spc::DevPlan &P = f->sym->dev.plan;
+    drop_graph(f);
+    if (!f->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal));
+    spc::launch_status_reset(f->status, f->nstatus, f->cap_stream);
+    Prof none{nullptr};
+    if (f->precision == SPC_FP64)
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->cap_stream, none);
+    else
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->cap_stream, none);
+    hipGraph_t g = nullptr;
+    const hipError_t e0 = hipGetLastError();
+    const hipError_t e1 = hipStreamEndCapture(f->cap_stream, &g);
+    if (e0 != hipSuccess || e1 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return record_error(e0 != hipSuccess ? e0 : e1, "factor capture", __LINE__);
+    }
+    f->graph = g;
+    HIP_TRY(hipGraphInstantiate(&f->gexec, g, nullptr, nullptr, 0));
+    f->graph_values = d_values;
+    return SPC_OK;
+}
+
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
     (void)hipGetLastError();  // judge only the launches below
+    if (f->use_graph && !f->profiling) {
+        if (!f->gexec || f->graph_values != d_values) {
+            int rc = capture_factor(f, d_values);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipEventRecord(f->ev0, st));
+        HIP_TRY(hipGraphLaunch(f->gexec, st));
+        HIP_TRY(hipEventRecord(f->ev1, st));
+        f->stream = st;
+        return SPC_OK;
+    }
     spc::launch_status_reset(f->status, f->nstatus, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
@@ -913,10 +967,27 @@ void spc_free_factor(spc_factor f) {
     if (f->ev0) (void)hipEventDestroy(f->ev0);
     if (f->ev1) (void)hipEventDestroy(f->ev1);
     for (hipEvent_t e : f->prof_ev) (void)hipEventDestroy(e);
+    drop_graph(f);
+    if (f->cap_stream) (void)hipStreamDestroy(f->cap_stream);
     spc_symbolic_s *s = f->sym;
     f->magic = kDead;
     delete f;
     if (s) sym_release(s);
+}
+
+int spc_factor_set_graph(spc_factor f, int on) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (f->batch) return SPC_INVALID_INPUT;  // a batch view: spc_batch_set_graph
+    f->use_graph = on != 0;
+    if (!f->use_graph) drop_graph(f);
+    return SPC_OK;
+}
+
+int spc_batch_set_graph(spc_batch b, int on) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    b->F->use_graph = on != 0;
+    if (!b->F->use_graph) drop_graph(b->F);
+    return SPC_OK;
 }
 
 

@@ -39,7 +39,8 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string",
            "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
-           "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined")
+           "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
+           "spc_factor_set_graph", "spc_batch_set_graph")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -98,6 +99,8 @@ _lib.spc_batch_solve.argtypes = [_P, ctypes.POINTER(_P), ctypes.c_int, ctypes.PO
 _lib.spc_batch_solve_refined.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int,
                                          ctypes.POINTER(_i64), ctypes.c_double, ctypes.c_int, _P,
                                          ctypes.POINTER(_RefineInfo)]
+_lib.spc_factor_set_graph.argtypes = [_P, ctypes.c_int]
+_lib.spc_batch_set_graph.argtypes = [_P, ctypes.c_int]
 _lib.spc_batch_sync.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.spc_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.spc_batch_info.argtypes = [_P, ctypes.POINTER(_Info)]
@@ -261,6 +264,10 @@ class Factor:
     def set_profiling(self, on: bool = True):
         _check(_lib.spc_factor_set_profiling(self._h, 1 if on else 0), "spc_factor_set_profiling")
 
+    def set_graph(self, on: bool = True):
+        """Capture the factorization into a HIP graph and replay it."""
+        _check(_lib.spc_factor_set_graph(self._h, 1 if on else 0), "spc_factor_set_graph")
+
     def kernel_stats(self) -> dict:
         """Per kernel class: launches, total device ms and algorithmic flops of
         the last profiled factorization."""
@@ -370,6 +377,9 @@ class Batch:
 
     def set_profiling(self, on: bool = True):
         _check(_lib.spc_batch_set_profiling(self._h, 1 if on else 0), "spc_batch_set_profiling")
+
+    def set_graph(self, on: bool = True):
+        _check(_lib.spc_batch_set_graph(self._h, 1 if on else 0), "spc_batch_set_graph")
 
     def kernel_stats(self) -> dict:
         out = {}

@@ -121,6 +121,62 @@ def test_schedule_cutoffs_same_factor(torch_dev, lib, name):
     assert relF <= REL_F_FP64
 
 
+def test_factor_graph_replay_matches_eager(torch_dev, lib):
+    """The captured factorization replays like the eager one: several
+    replays with eager solves and synchronizations between them; values
+    changed in place under the same pointer (the replay reads them); a new
+    values pointer (captured again)."""
+    torch = torch_dev
+    s = grid((20, 19, 18), seed=12, nrhs=2)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    mask = S.lower_mask()
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    Fe = lib.factorize(sym, dv)
+    Fe.sync()
+    Le = Fe.export()
+    Fg = lib.factorize(sym, dv)
+    Fg.sync()
+    Fg.set_graph(True)
+    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    for rep in range(6):
+        if rep == 3:
+            dv.mul_(4.0)  # same pointer, new values: L doubles
+        if rep == 5:
+            dv = dv.clone()  # new pointer
+        Fg.refactorize(dv)
+        Fg.sync()
+        scale = 1.0 if rep < 3 else 2.0
+        relF = oracle.rel_frobenius(Fg.export(), scale * Le, mask)
+        X = B.clone()
+        Fg.solve(X)  # eager work between replays
+        torch.cuda.synchronize()
+        eta = oracle.backward_error(S.n, s.colptr, s.rowidx, (scale * scale) * s.values, X.cpu().numpy().T, s.B)
+        print(f"graph replay {rep}: relF={relF:.2e} eta={eta:.2e}", flush=True)
+        assert relF <= 1e-13 and eta <= BERR_FP64
+
+
+def test_batch_graph_replay_matches_eager(torch_dev, lib):
+    torch = torch_dev
+    systems = small_batch(6, seed=4, nrhs=1)
+    syms = [lib.Symbolic(x.colptr, x.rowidx, x.perm, 0.05) for x in systems]
+    dvs = [torch.from_numpy(x.values).cuda() for x in systems]
+    eager = lib.Batch(syms, "fp64")
+    eager.factorize(dvs)
+    eager.sync()
+    ref = [eager.factor(i).export() for i in range(len(systems))]
+    g = lib.Batch(syms, "fp64")
+    g.set_graph(True)
+    for rep in range(3):
+        g.factorize(dvs)
+        g.sync()
+        for i, x in enumerate(systems):
+            S = oracle.Symbolic(x.colptr, x.rowidx, x.perm, 0.05)
+            assert oracle.rel_frobenius(g.factor(i).export(), ref[i], S.lower_mask()) <= 1e-13
+        Bs = [torch.from_numpy(np.ascontiguousarray(x.B.T)).cuda() for x in systems]
+        g.solve(Bs)  # eager work between replays
+
+
 @pytest.mark.parametrize("z", [-1.0, 0.0, 0.5])
 def test_fp64_amalgamation_settings(torch_dev, lib, z):
     s = grid((14, 13, 12), seed=3, nrhs=2)
