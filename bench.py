@@ -373,6 +373,7 @@ def bench_grid3d(args):
     # profiled pass of the same steps: per-launch events around each kernel class
     F.set_profiling(True)
     prof = {}
+    lv_ms = None
     for k in range(max(1, min(args.steps, 3))):
         step([torch.cuda.Event(enable_timing=True) for _ in range(3)])
         ks = F.kernel_stats()
@@ -380,6 +381,8 @@ def bench_grid3d(args):
             p = prof.setdefault(name, {"launches": 0, "ms": 0.0, "flops": 0.0})
             for key in p:
                 p[key] += v[key]
+        ls = F.level_stats()
+        lv_ms = ls if lv_ms is None else [dict(a, ms=a["ms"] + b["ms"]) for a, b in zip(lv_ms, ls)]
     F.set_profiling(False)
     nprof = max(1, min(args.steps, 3))
     dom = max((n for n in prof if n != "assemble"), key=lambda n: prof[n]["ms"])
@@ -394,6 +397,9 @@ def bench_grid3d(args):
                 "avg_launch_ms": round(d["ms"] / max(1, d["launches"]), 4),
                 "flops_per_launch": round(d["flops"] / max(1, d["launches"])),
                 "classes_ms_per_step": {n: round(v["ms"] / nprof, 3) for n, v in prof.items()}}
+    # per etree level (-1: assembly): launches, device ms and TFLOP/s of one factorization
+    levels = [[v["level"], v["launches"], round(v["ms"] / nprof, 3),
+               round(v["flops"] / (v["ms"] / nprof * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0] for v in lv_ms]
 
     fac_mean = float(fac_ms.mean())
     value = flops / (fac_mean * 1e-3) / 1e9
@@ -425,6 +431,8 @@ def bench_grid3d(args):
         "frac_of_peak": round(value / (peak * 1e3), 4),
         "analyze_s": round(t_analyze, 2),
         "roofline": roofline,
+        "factor_levels": {"columns": ["etree level (-1: assembly)", "launches", "device ms", "TFLOP/s"],
+                          "rows": levels},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)

@@ -299,6 +299,11 @@ int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *ou
 int spc_batch_set_profiling(spc_batch b, int on);
 int spc_batch_kernel_stats(spc_batch b, int kernel_class, spc_kernel_stats *out);
 
+/* The same totals per elimination-tree level of the schedule (0 = leaves,
+ * up to spc_info.levels - 1; -1 = the assembly of A), over all classes. */
+int spc_factor_level_stats(spc_factor f, int level, spc_kernel_stats *out);
+int spc_batch_level_stats(spc_batch b, int level, spc_kernel_stats *out);
+
 void spc_free_symbolic(spc_symbolic sym);
 void spc_free_factor(spc_factor f);
 const char *spc_status_string(int status);

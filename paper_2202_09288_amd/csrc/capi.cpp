@@ -77,6 +77,7 @@ struct spc_factor_s {
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;     // pairs
     std::vector<int> prof_cls;
+    std::vector<int> prof_lvl;   // etree level of each launch (-1: assembly)
     std::vector<double> prof_flops;
     size_t prof_used = 0;
 };
@@ -218,6 +219,7 @@ size_t plan_bytes(const spc::Symbolic &S) {
 // profiling is on.
 struct Prof {
     spc_factor_s *f;
+    int level = -1;  // etree level of the launches that follow
     template <typename Fn>
     void run(int cls, double flops, hipStream_t st, Fn &&fn) {
         if (!f || !f->profiling) {
@@ -236,9 +238,11 @@ struct Prof {
         }
         if (f->prof_cls.size() <= i) {
             f->prof_cls.resize(i + 1);
+            f->prof_lvl.resize(i + 1);
             f->prof_flops.resize(i + 1);
         }
         f->prof_cls[i] = cls;
+        f->prof_lvl[i] = level;
         f->prof_flops[i] = flops;
         (void)hipEventRecord(f->prof_ev[2 * i], st);
         fn();
@@ -259,6 +263,7 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
     });
     for (int32_t l = 0; l < S.nlevels; ++l) {
+        prof.level = l;
         if (S.tiny_ptr[l + 1] > S.tiny_ptr[l])
             prof.run(SPC_K_TINY, S.tiny_flops[l], st, [&] {
                 spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_ptr[l + 1], Lx, Linv, status, st);
@@ -940,6 +945,24 @@ int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *ou
     return SPC_OK;
 }
 
+int spc_factor_level_stats(spc_factor f, int level, spc_kernel_stats *out) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!out || level < -1 || level >= f->sym->S.nlevels) return SPC_INVALID_INPUT;
+    out->launches = 0;
+    out->total_ms = 0.0;
+    out->flops = 0.0;
+    if (f->prof_used) HIP_TRY(hipEventSynchronize(f->prof_ev[2 * f->prof_used - 1]));
+    for (size_t i = 0; i < f->prof_used; ++i) {
+        if (f->prof_lvl[i] != level) continue;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, f->prof_ev[2 * i], f->prof_ev[2 * i + 1]));
+        out->launches++;
+        out->total_ms += ms;
+        out->flops += f->prof_flops[i];
+    }
+    return SPC_OK;
+}
+
 void spc_free_symbolic(spc_symbolic sym) {
     if (!sym_ok(sym)) return;
     sym_release(sym);
@@ -1214,6 +1237,11 @@ int spc_batch_set_profiling(spc_batch b, int on) {
 int spc_batch_kernel_stats(spc_batch b, int kernel_class, spc_kernel_stats *out) {
     if (!batch_ok(b)) return SPC_BAD_HANDLE;
     return spc_factor_kernel_stats(b->F, kernel_class, out);
+}
+
+int spc_batch_level_stats(spc_batch b, int level, spc_kernel_stats *out) {
+    if (!batch_ok(b)) return SPC_BAD_HANDLE;
+    return spc_factor_level_stats(b->F, level, out);
 }
 
 int spc_batch_info(spc_batch b, spc_info *out) {

@@ -40,7 +40,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_facto
            "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
-           "spc_factor_set_graph", "spc_batch_set_graph")
+           "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -100,6 +100,8 @@ _lib.spc_batch_solve_refined.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(
                                          ctypes.POINTER(_i64), ctypes.c_double, ctypes.c_int, _P,
                                          ctypes.POINTER(_RefineInfo)]
 _lib.spc_factor_set_graph.argtypes = [_P, ctypes.c_int]
+_lib.spc_factor_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
+_lib.spc_batch_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
 _lib.spc_batch_set_graph.argtypes = [_P, ctypes.c_int]
 _lib.spc_batch_sync.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.spc_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
@@ -263,6 +265,17 @@ class Factor:
 
     def set_profiling(self, on: bool = True):
         _check(_lib.spc_factor_set_profiling(self._h, 1 if on else 0), "spc_factor_set_profiling")
+
+    def level_stats(self) -> list:
+        """Per elimination-tree level (index 0 = the assembly, then levels
+        0..): launches, device ms and flops of the last profiled factorization."""
+        out = []
+        for lv in range(-1, self.sym.info["levels"]):
+            st = _KernelStats()
+            _check(_lib.spc_factor_level_stats(self._h, lv, ctypes.byref(st)), "spc_factor_level_stats")
+            out.append({"level": lv, "launches": int(st.launches), "ms": float(st.total_ms),
+                        "flops": float(st.flops)})
+        return out
 
     def set_graph(self, on: bool = True):
         """Capture the factorization into a HIP graph and replay it."""
