@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--workload", default="grid3d60",
-                    choices=["grid3d60", "grid2d64", "elast48", "batch512", "serving"],
+                    choices=["grid3d60", "grid2d64", "elast48", "batch512", "serving", "copy"],
                     help="grid3d60: the headline FP64 factor + solve (default); grid2d64: small-system "
                          "latency; elast48: FP32 factor + FP64 refinement on the 48^3 elasticity "
                          "operator; batch512: 512 systems in one schedule; serving: request loop")
@@ -111,8 +111,40 @@ def main():
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     modes = {"grid3d60": bench_grid3d, "grid2d64": bench_grid2d, "elast48": bench_elast,
-             "batch512": bench_batch, "serving": bench_serving}
+             "batch512": bench_batch, "serving": bench_serving, "copy": bench_copy}
     modes[args.workload](args)
+
+
+def bench_copy(args):
+    """Calibration for the HBM byte counters: a plain device-to-device copy
+    of a known size (1 GiB read, 1 GiB written per launch), three launches."""
+    import torch
+    torch.cuda.set_device(0)
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src), 3, 1, torch)
+    gbs = 2 * (1 << 30) / (float(np.median(t)) * 1e-3) / 1e9
+    print(json.dumps({"workload": "copy", "bytes_read_per_launch": 1 << 30, "bytes_written_per_launch": 1 << 30,
+                      "ms_per_launch": round(float(np.median(t)), 4), "GB/s": round(gbs, 1)}), flush=True)
+
+
+def counted_traffic(kernel: str, precision: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    there is none for it or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"counters_grid3d60_{precision}.md")
+    try:
+        txt = open(path).read()
+        src = open(os.path.join(ROOT, "paper_2202_09288_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and line[:1].islower())
+    if fields.get("traffic_kernel") != kernel or fields.get("kernels_source_sha1") != hashlib.sha1(src).hexdigest():
+        return None
+    return {"bytes": int(fields["traffic_bytes_per_launch"]), "read": int(fields["traffic_read_bytes_per_launch"]),
+            "written": int(fields["traffic_written_bytes_per_launch"])}
 
 
 def head(args, value, unit, dtype, config, ms_per_step, higher=True):
@@ -390,9 +422,13 @@ def bench_grid3d(args):
     d = prof[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
     tname = "double" if args.precision == "fp64" else "float"
-    roofline = {"bound": "mfma", "kernel": spchol.KERNEL_NAMES[dom].format(t=tname),
+    kname = spchol.KERNEL_NAMES[dom].format(t=tname)
+    tr = counted_traffic(kname, args.precision) if args.grid == 60 else None
+    roofline = {"bound": "mfma", "kernel": kname,
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_read_written": [tr["read"], tr["written"]] if tr else None,
                 "launches_per_step": d["launches"] // nprof,
                 "avg_launch_ms": round(d["ms"] / max(1, d["launches"]), 4),
                 "flops_per_launch": round(d["flops"] / max(1, d["launches"])),
