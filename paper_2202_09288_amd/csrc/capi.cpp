@@ -52,6 +52,10 @@ struct spc_factor_s {
     void *Lx = nullptr;
     void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
+    // hand-over flags of the trailing launches, one per column block (in
+    // the status allocation, after the status words)
+    int32_t *hflags = nullptr;
+    int nflags = 0;
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
@@ -257,7 +261,7 @@ struct Prof {
 // factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, hipStream_t st, Prof &prof) {
+                    unsigned long long *status, int32_t *hflags, hipStream_t st, Prof &prof) {
     prof.run(SPC_K_ASSEMBLE, 0.0, st, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
@@ -279,11 +283,11 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
                          [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
             if (stp.p1 > stp.p0)
                 prof.run(SPC_K_TRSM, stp.trsm_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, nullptr, st);
                 });
             if (stp.t1 > stp.t0)
                 prof.run(SPC_K_TRAILING, stp.look_flops + stp.rest_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, st);
                 });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
@@ -293,7 +297,7 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], st, [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     status, st);
+                                     status, nullptr, st);
             });
     }
 }
@@ -355,12 +359,14 @@ int capture_factor(spc_factor f, const double *d_values) {
     drop_graph(f);
     if (!f->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal));
-    spc::launch_status_reset(f->status, f->nstatus, f->cap_stream);
+    spc::launch_status_reset(f->status, f->nstatus, f->hflags, f->nflags, f->cap_stream);
     Prof none{nullptr};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->cap_stream, none);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags,
+                               f->cap_stream, none);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->cap_stream, none);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags,
+                              f->cap_stream, none);
     hipGraph_t g = nullptr;
     const hipError_t e0 = hipGetLastError();
     const hipError_t e1 = hipStreamEndCapture(f->cap_stream, &g);
@@ -389,14 +395,14 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
         f->stream = st;
         return SPC_OK;
     }
-    spc::launch_status_reset(f->status, f->nstatus, st);
+    spc::launch_status_reset(f->status, f->nstatus, f->hflags, f->nflags, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
     Prof prof{f};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -422,7 +428,10 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     hipError_t e = hipMalloc(&f->Lx, bytes);
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus);
+    f->nflags = (int)sym->S.sblocks.size();
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus + sizeof(int32_t) * f->nflags);
+    if (e == hipSuccess) f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus);
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
 

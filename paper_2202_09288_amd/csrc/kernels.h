@@ -47,8 +47,9 @@ inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks) {
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
-// status word: lowest permuted column whose pivot failed, or ~0ull
-void launch_status_reset(unsigned long long *status, int count, hipStream_t st);
+// status word: lowest permuted column whose pivot failed, or ~0ull; the
+// hand-over flags of the trailing launches (one per column block) to 0
+void launch_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags, hipStream_t st);
 template <typename T>
 void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
@@ -64,7 +65,7 @@ void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsig
                  hipStream_t st);
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st);
+                  int32_t *hflags, hipStream_t st);
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);

@@ -61,9 +61,32 @@ __global__ void k_zero(T *x, int64_t count) {
     for (; i < count; i += stride) x[i] = T(0);
 }
 
-__global__ void k_status_reset(unsigned long long *status, int count) {
+__global__ void k_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) status[i] = ~0ull;
+    if (i < nflags) flags[i] = 0;
+}
+
+// Data handed from one workgroup to another inside a launch (which may run
+// on another XCD, with its own L2) moves through device-scope atomic loads
+// and stores, and the flag that announces it is raised only after the
+// writer's own stores have completed; no cache-wide fences.
+template <typename T>
+__device__ __forceinline__ T dev_load(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void dev_store(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Bounded wait for a hand-over flag (about a second of polls); false if it
+// gave up, so every wave always exits.
+__device__ __forceinline__ bool wait_flag(int32_t *p) {
+    for (int it = 0; it < (1 << 20); ++it) {
+        if (dev_load(p) != 0) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
 }
 
 template <typename T>
@@ -158,7 +181,8 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // dimension m, lower triangle only) and the inverse into Vi; a failed pivot
 // lowers *status to g0 + its column.  LDS scratch from the caller: rdg (64
 // entries), Tf and T32 (32 x 33 each), flags (8 ints).  Called by all 256
-// threads of the workgroup.
+// threads of the workgroup.  With publish, the inverse is stored with
+// device-scope atomic stores, for workgroups of the same launch to read.
 //
 // Blocked by 16-column panels with lookahead: wave 0 factors panel p (lane
 // = row, pivots broadcast by readlane) right after bringing its columns up
@@ -171,7 +195,8 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // waves at once.
 template <typename T>
 __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], T (*T32)[33], int *flags, int nb,
-                                          T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int64_t g0) {
+                                          T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int64_t g0,
+                                          bool publish) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
@@ -192,6 +217,10 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
     if (t >= PW * npan && t < NB) rdg[t] = T(1);  // identity rows past the last panel
     __syncthreads();
 #define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
+    auto vi_put = [&](int64_t e, T v) {
+        if (publish) dev_store(Vi + e, v);
+        else Vi[e] = v;
+    };
     // inverse of the 32-column block at o from its two 16-block inverses
     // (one wave): X21 = -X22 L21 X11, kept transposed in the upper triangle
     auto inv16 = [&](int o) {
@@ -363,7 +392,7 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
                 } else {
                     for (int e = lane; e < 32 * nb; e += 64) {
                         const int i = e & 31, k = e >> 5;
-                        Vi[k * nb + i] = SPC_INV(i, k);
+                        vi_put(k * nb + i, SPC_INV(i, k));
                     }
                 }
             }
@@ -386,13 +415,13 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
 #pragma unroll
         for (int q = 0; q < 32 * NB / 256; ++q) {
             const int e = t + 256 * q, i = 32 + e % 32, k = e / 32;
-            if (i < nb && k < nb) Vi[k * nb + i] = SPC_INV(i, k);
+            if (i < nb && k < nb) vi_put(k * nb + i, SPC_INV(i, k));
         }
     } else {
 #pragma unroll
         for (int q = 0; q < NB * NB / 256; ++q) {
             const int e = t + 256 * q, i = e % NB, k = e / NB;
-            if (i < nb && k < nb) Vi[k * nb + i] = SPC_INV(i, k);
+            if (i < nb && k < nb) vi_put(k * nb + i, SPC_INV(i, k));
         }
     }
 #undef SPC_INV
@@ -428,7 +457,7 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
     }
     __syncthreads();
     potrf_lds<T>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
-                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0);
+                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -638,7 +667,11 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 // each wave a 2x2 set of 16x16x4 MFMA blocks; K staged through LDS 16 at a
 // time, the next chunk loaded into registers while the current one is used.
 //   MODE_TRAILING: A, B = panel rows i0.., j0..; P[i][j] -= C for i >= j,
-//                  j < jmax.
+//                  j < jmax.  The diagonal tile of the next column block
+//                  then factors that block (potrf_lds); a tile below it
+//                  with a flag then waits for the block's inverse and
+//                  stores the TRSM result instead: P[i][j] = sum_k
+//                  (P - C)[i][k] (L^{-1})_{jk}.
 //   MODE_SCATTER:  A, B = panel rows i0.., j0..; C (i >= j) scatter-added
 //                  atomically into the ancestors: C[i][j] goes to
 //                  cbase[j] + rel[crel[j] + i].
@@ -649,15 +682,16 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
+__global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
-                                               const int32_t *status_slot) {
+                                               const int32_t *status_slot, int32_t *hflags) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
-    __shared__ T As[KB][TM + 4];
-    __shared__ T Bs[KB][TM + 4];
+    __shared__ T ABs[2][KB][TM + 4];  // A and B chunks, one buffer
     __shared__ T Cs[TM][TM + 1];
     __shared__ int64_t cb[TM], cr[TM];
+    T(*As)[TM + 4] = ABs[0];
+    T(*Bs)[TM + 4] = ABs[1];
     const TileTask tk = tasks[blockIdx.x];
     const int64_t m = tk.m;
     T *P = Lx + tk.loff;
@@ -694,39 +728,70 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
     };
     const int r = tid & 63, cg = tid >> 6;
     const int64_t gi = tk.i0 + r;
-    load(tk.k0);
-    for (int kb = tk.k0; kb < tk.k1; kb += KB) {
-#pragma unroll
-        for (int e = 0; e < KB / 4; ++e) {
-            const int kk = lk + 4 * e;
-            const bool kin = kb + kk < tk.k1;
-            As[kk][lr] = (kin && row_ok) ? ra[e] : T(0);
-            Bs[kk][lr] = (kin && col_ok) ? rb[e] : T(0);
-        }
-        __syncthreads();
-        if (kb + KB < tk.k1) load(kb + KB);
-#pragma unroll
-        for (int kk = 0; kk < KB; kk += 4) {
-            T af[2], bf[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
-        }
-        __syncthreads();
-    }
-    // epilogue: thread = row r, columns cg*16 .. cg*16+15
-    T old[CPT];
-    if (MODE == MODE_TRAILING) {
+    T old[CPT];  // trailing tiles: the tile's values before the update
+    auto load_old = [&] {
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             const int64_t gj = min(tk.j0 + cg * CPT + cc, tk.jmax - 1);
             old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
         }
+    };
+    if (MODE == MODE_TRAILING && tk.blk >= 0 && tk.i0 == tk.j0) {
+        // the diagonal tile of the next block heads the step's critical
+        // path: the tile and its panel rows (A = B) are loaded with one
+        // round trip, TM columns of K at a time, staged in Cs
+        load_old();
+        for (int kb = tk.k0; kb < tk.k1; kb += TM) {
+            T xv[TM / 4];
+#pragma unroll
+            for (int e = 0; e < TM / 4; ++e) xv[e] = pa[(int64_t)min(kb + lk + 4 * e, tk.k1 - 1) * m];
+            if (kb > tk.k0) __syncthreads();
+#pragma unroll
+            for (int e = 0; e < TM / 4; ++e)
+                Cs[lk + 4 * e][lr] = (kb + lk + 4 * e < tk.k1 && row_ok) ? xv[e] : T(0);
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < TM; kk += 4) {
+                T af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = Cs[kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Cs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
+            }
+        }
+        __syncthreads();
+    } else {
+        load(tk.k0);
+        for (int kb = tk.k0; kb < tk.k1; kb += KB) {
+#pragma unroll
+            for (int e = 0; e < KB / 4; ++e) {
+                const int kk = lk + 4 * e;
+                const bool kin = kb + kk < tk.k1;
+                As[kk][lr] = (kin && row_ok) ? ra[e] : T(0);
+                Bs[kk][lr] = (kin && col_ok) ? rb[e] : T(0);
+            }
+            __syncthreads();
+            if (kb + KB < tk.k1) load(kb + KB);
+#pragma unroll
+            for (int kk = 0; kk < KB; kk += 4) {
+                T af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = As[kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::run(af[a], bf[b], acc[a][b]);
+            }
+            __syncthreads();
+        }
+        // epilogue: thread = row r, columns cg*16 .. cg*16+15
+        if (MODE == MODE_TRAILING) load_old();
     }
     int32_t rv[CPT];
     if (MODE == MODE_SCATTER) {
@@ -748,7 +813,7 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
                 Cs[c][rr] = acc[a][b][v];
             }
     __syncthreads();
-    if (MODE == MODE_TRAILING && tk.blk >= 0) {
+    if (MODE == MODE_TRAILING && tk.blk >= 0 && tk.i0 == tk.j0) {
         // diagonal tile of the next column block: its rows r < nb2 form the
         // block, final after this update; factor it here (rows below it are
         // stored as in any other tile)
@@ -777,7 +842,75 @@ __global__ __launch_bounds__(256) void k_tiles(const TileTask *tasks, const int6
         }
         __syncthreads();
         potrf_lds<T>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
-                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk);
+                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk, tk.flag >= 0);
+        if (tk.flag >= 0) {
+            // every thread's inverse stores have completed: tell the tiles
+            // below (raised even after a failed pivot, which the status
+            // word reports, so that no tile waits in vain)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) dev_store(hflags + tk.flag, 1);
+        }
+        return;
+    }
+    if (MODE == MODE_TRAILING && tk.flag >= 0) {
+        // below the diagonal tile of a block factored in this launch: the
+        // updated tile (kept in Cs) times the transposed inverse of the
+        // block, read once the diagonal tile's workgroup has raised the flag
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) Cs[cg * CPT + cc][r] = old[cc] - Cs[cg * CPT + cc][r];
+        if (tid == 0 && !wait_flag(hflags + tk.flag))
+            atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)tk.blk);
+        __syncthreads();
+        // the inverse ((L^{-1})_{jk} at Vi[k * TM + j]) in two halves of K
+        // through the A/B buffer (32 rows of TM + 4), both read at once
+        constexpr int HK = TM / 2, PER = HK * TM / 256;
+        static_assert(HK * (TM + 4) <= 2 * KB * (TM + 4), "half an inverse fits the A/B buffer");
+        const T *Vi = Linv + tk.aux;
+        T *Vb = &ABs[0][0][0];
+        T vh[2][PER];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < PER; ++e) vh[h][e] = dev_load(Vi + h * HK * TM + tid + 256 * e);
+        acc_t xa[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) xa[a][b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int x = tid + 256 * e;
+                Vb[(x / TM) * (TM + 4) + x % TM] = vh[h][e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < HK; kk += 4) {
+                T af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = Cs[h * HK + kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Vb[(kk + (lane >> 4)) * (TM + 4) + wc + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) xa[a][b] = Mfma<T>::run(af[a], bf[b], xa[a][b]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Cs[wc + b * 16 + (lane & 15)][wr + a * 16 + Mfma<T>::row(lane, v)] = xa[a][b][v];
+        __syncthreads();
+        if (gi < m)
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) P[(tk.j0 + cg * CPT + cc) * m + gi] = Cs[cg * CPT + cc][r];
         return;
     }
     if (gi >= m) return;
@@ -1783,9 +1916,10 @@ inline unsigned grid1(int64_t count, int block) {
 
 }  // namespace
 
-void launch_status_reset(unsigned long long *status, int count, hipStream_t st) {
-    if (count <= 0) return;
-    hipLaunchKernelGGL(k_status_reset, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
+void launch_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags, hipStream_t st) {
+    const int n = count > nflags ? count : nflags;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_status_reset, dim3((n + 255) / 256), dim3(256), 0, st, status, count, flags, nflags);
 }
 
 template <typename T>
@@ -1828,18 +1962,18 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st) {
+                  int32_t *hflags, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, hflags);
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr);
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr);
 }
 
 template <typename T>
@@ -2020,7 +2154,7 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
-                                  hipStream_t);                                                             \
+                                  int32_t *, hipStream_t);                                                  \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \

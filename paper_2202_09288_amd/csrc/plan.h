@@ -84,9 +84,16 @@ struct TileTask {
     int32_t k1;
     int32_t jmax;   // columns j >= jmax are outside the update
     int32_t blk;    // TRSM tiles: block id.  Trailing tiles: -1, or, for the
-                    // diagonal tile of the next column block (i0 = j0 = k1),
-                    // that block's global first column: the tile's
-                    // workgroup factors the block after updating it
+                    // tiles of the next column block's columns (j0 = k1),
+                    // that block's global first column: the diagonal tile's
+                    // workgroup (i0 = j0) factors the block after updating it
+    int32_t flag;   // trailing tiles of the next block's columns, when that
+                    // block is a full kNB wide: its block id, the index of a
+                    // flag word.  The diagonal tile raises the flag once the
+                    // block's inverse (at aux) is stored; each tile below it
+                    // waits for the flag and then finishes the block's TRSM
+                    // on its own rows.  -1 otherwise.
+    int32_t pad;
 };
 
 // POTRF of the block of columns c0..c1-1 (c0 a multiple of kNB) of

@@ -449,11 +449,19 @@ int build_schedule(Symbolic &S) {
             // (one column of tiles, K = the group's columns up to b) and
             // factors block b+1 in that column's diagonal tile; the last step
             // of a group updates every column beyond with all of the group's
-            // panels at once (K = kDelay blocks).  Pass 0 emits the columns of
-            // block b+1 (diagonal tile first), pass 1 the columns beyond.
+            // panels at once (K = kDelay blocks).
+            // The trailing launch holds, in this order: the diagonal tiles of
+            // block b+1 (pass 0), the columns beyond block b+1 (pass 1), and
+            // the tiles below block b+1's diagonal (pass 2).  When block b+1
+            // is a full kNB wide, the pass-2 tiles also do its TRSM: they
+            // wait for the diagonal tile's workgroup to store the block's
+            // inverse, so that block gets no TRSM launch of its own.  Every
+            // diagonal tile comes before every tile that waits, so the
+            // waiting tiles can never hold the device while a diagonal tile
+            // is still undispatched.
             const int64_t gb = b - b % kDelay;  // first block of b's group
             const bool bulk = b % kDelay == kDelay - 1;
-            for (int pass = 0; pass < 2; ++pass) {
+            for (int pass = 0; pass < 3; ++pass) {
                 if (pass == 1) st.tm = (int64_t)S.int_tiles.size();
                 for (int32_t s : bylevel[l]) {
                     int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
@@ -467,6 +475,11 @@ int build_schedule(Symbolic &S) {
                     const double kd = (double)(c1 - k0);
                     // the last block of a supernode closes its group too
                     const bool close = bulk || cx >= w;
+                    // block b+1 gets its TRSM from this step's pass-2 tiles;
+                    // block b got it from step b-1's
+                    const bool fuse_next = c1 < w && cx - c1 == kNB;
+                    const bool fused_here = b > 0 && c1 - c0 == kNB;
+                    const int32_t gnext = (int32_t)(S.super_ptr[s] + c1);
                     if (pass == 0) {
                         // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                         // SYRK k n(n+1), GEMM 2 m n k
@@ -474,6 +487,7 @@ int build_schedule(Symbolic &S) {
                         if (c1 < w)  // block b+1's POTRF runs in this step's column update
                             st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
                         st.look_flops += nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd;
+                        if (fuse_next) st.look_flops += (double)(m - cx) * nx * nx;
                         if (close)
                             st.rest_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
                                              (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
@@ -485,24 +499,37 @@ int build_schedule(Symbolic &S) {
                                                               (int32_t)c0, (int32_t)c1,
                                                               (int32_t)(S.super_ptr[s] + c0), 0});
                         }
-                        st.trsm_flops += (double)(m - c1) * nbd * nbd;
-                        for (int64_t r = c1; r < m; r += kTile)
-                            S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r,
-                                                            (int32_t)c0, (int32_t)c0, (int32_t)c1, (int32_t)c1,
-                                                            blk});
-                    }
-                    if (pass == 1 && !close) continue;
-                    // trailing update inside the panel by the group's panels:
-                    // rows [j0, m), columns [j0, ...) with j0 >= c1, K = [k0, c1)
-                    const int64_t j0a = pass == 0 ? c1 : c1 + kTile, j0b = pass == 0 ? cx : w;
-                    for (int64_t j0 = j0a; j0 < j0b; j0 += kTile)
-                        for (int64_t i0 = j0; i0 < m; i0 += kTile) {
-                            const bool fuse = i0 == c1 && j0 == c1;
-                            S.int_tiles.push_back(TileTask{S.lptr[s], fuse ? S.inv_off[blk + 1] : S.rptr[s], s,
-                                                           (int32_t)m, (int32_t)i0, (int32_t)j0, (int32_t)k0,
-                                                           (int32_t)c1, (int32_t)w,
-                                                           fuse ? (int32_t)(S.super_ptr[s] + c1) : -1});
+                        if (!fused_here) {
+                            st.trsm_flops += (double)(m - c1) * nbd * nbd;
+                            for (int64_t r = c1; r < m; r += kTile)
+                                S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
+                                                                (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
+                                                                (int32_t)c1, blk, -1, 0});
                         }
+                        if (c1 < w)
+                            S.int_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk + 1], s, (int32_t)m,
+                                                           (int32_t)c1, (int32_t)c1, (int32_t)k0, (int32_t)c1,
+                                                           (int32_t)w, gnext, fuse_next ? blk + 1 : -1, 0});
+                        continue;
+                    }
+                    if (pass == 1) {
+                        if (!close) continue;
+                        // trailing update of the columns beyond block b+1:
+                        // rows [j0, m), K = [k0, c1)
+                        for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTile)
+                            for (int64_t i0 = j0; i0 < m; i0 += kTile)
+                                S.int_tiles.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
+                                                               (int32_t)j0, (int32_t)k0, (int32_t)c1, (int32_t)w,
+                                                               -1, -1, 0});
+                        continue;
+                    }
+                    // pass 2: block b+1's columns below its diagonal tile
+                    if (c1 >= w) continue;
+                    for (int64_t i0 = c1 + kTile; i0 < m; i0 += kTile)
+                        S.int_tiles.push_back(TileTask{S.lptr[s], fuse_next ? S.inv_off[blk + 1] : S.rptr[s], s,
+                                                       (int32_t)m, (int32_t)i0, (int32_t)c1, (int32_t)k0,
+                                                       (int32_t)c1, (int32_t)w, fuse_next ? gnext : -1,
+                                                       fuse_next ? blk + 1 : -1, 0});
                 }
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
@@ -521,7 +548,7 @@ int build_schedule(Symbolic &S) {
                 for (int64_t i0 = j0; i0 < m; i0 += tsz)
                     (big ? S.ext_tiles_big : S.ext_tiles)
                         .push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0, 0,
-                                            (int32_t)w, (int32_t)m, -1});
+                                            (int32_t)w, (int32_t)m, -1, -1, 0});
         }
         S.ext_tile_ptr[l + 1] = (int64_t)S.ext_tiles.size();
         S.ext_big_ptr[l + 1] = (int64_t)S.ext_tiles_big.size();
