@@ -187,9 +187,11 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // Blocked by 16-column panels with lookahead: wave 0 factors panel p (lane
 // = row, pivots broadcast by readlane) right after bringing its columns up
 // to date with panel p-1 itself (16x16x4 MFMA), while waves 1-3 apply panel
-// p-1 to the columns two panels on and beyond, store its L and invert its
-// 16x16 diagonal triangle, merging a 32-column block's inverse as soon as
-// its two panels are inverted.  The waves hand over through LDS flags, so
+// p-1 to the columns two panels on and beyond; then wave 1 inverts its 16x16
+// diagonal triangle (and merges the second 32-column block's inverse after
+// the last panel), wave 2 merges the first 32-column block's inverse once
+// its two triangles are inverted, and waves 2-3 store L, so that the
+// inverses keep pace with the panels.  The waves hand over through LDS flags, so
 // the panel chain never waits for a whole-workgroup barrier.  Each trailing
 // tile belongs to one wave for all panels, so no tile is updated by two
 // waves at once.
@@ -204,6 +206,7 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
     int *flag_trail = flags + 1;  // [4] trailing waves done with panel p (0..3)
     int &flag_err = flags[5];
     int &flag_x11 = flags[6];     // inverse of the first 32-column block done
+    int &flag_dinv = flags[7];    // diagonal 16x16 triangles 0 .. flag_dinv - 1 inverted
     // T32: L21 X11 of the two 32-column blocks
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -213,6 +216,7 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
         flag_trail[0] = flag_trail[1] = flag_trail[2] = flag_trail[3] = 0;
         flag_err = 0;
         flag_x11 = 0;
+        flag_dinv = 0;
     }
     if (t >= PW * npan && t < NB) rdg[t] = T(1);  // identity rows past the last panel
     __syncthreads();
@@ -334,8 +338,10 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
             if (wv == 1) {
                 // inverse of panel pb's diagonal 16x16 triangle: 2x2 block
                 // formula from the diagonal (rdg = 1/l_jj) up, h = 1, 2, 4, 8;
-                // X21 is kept transposed in the upper triangle
-                T *tf = &Tf[0][0];
+                // X21 is kept transposed in the upper triangle.  Scratch:
+                // rows 16.. of Tf (rows 0..15 belong to the merge of the
+                // first 32-column block, which wave 2 may be running)
+                T *tf = &Tf[16][0];
                 // fixed trip counts (h unrolled, terms masked) so each
                 // level issues its LDS reads together; lanes >= 8 h compute
                 // a clamped copy and store nothing
@@ -362,15 +368,24 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
                     if (lane < nel) A[o + b][o + h + a] = out;
                     wave_lds_sync();
                 }
-                // both 16-blocks of a 32-block inverted (the second may be
-                // identity padding): merge them now, off the panel chain
-                if (nb > PW && ((pb & 1) || pb == npan - 1)) inv16(32 * (pb >> 1));
-                if (pb == 1) lds_flag_store(&flag_x11, 1);
+                lds_flag_store(&flag_dinv, pb + 1);
+                // the second 32-column block (its second 16-block may be
+                // identity padding) is merged right after its last panel
+                if (pb >= 2 && pb == npan - 1) inv16(32);
+            } else {
+                // waves 2 and 3 store L of panel pb (rows >= p0 of its
+                // columns), so that wave 1 keeps up with the panels
+                for (int e = lane + 64 * (wv - 2); e < PW * NB; e += 128) {
+                    const int k = p0 + e / NB, row = e % NB;
+                    if (k < nb && row >= k && row < nb) P[(int64_t)(c0 + k) * m + c0 + row] = A[row][k];
+                }
             }
-            // L of panel pb to the panel store (rows >= p0 of its columns)
-            for (int e = lane + 64 * tw; e < PW * NB; e += 192) {
-                const int k = p0 + e / NB, row = e % NB;
-                if (k < nb && row >= k && row < nb) P[(int64_t)(c0 + k) * m + c0 + row] = A[row][k];
+            if (pb == 1 && wv == 2) {
+                // the first 32-column block: merge its two inverted
+                // 16-blocks once wave 1 has both
+                if (!lds_wait_geq(&flag_dinv, 2)) flag_err = 1;
+                inv16(0);
+                lds_flag_store(&flag_x11, 1);
             }
             if (pb == 1 && nb > 2 * PW && wv >= 2) {
                 // the first 32-column block's inverse X11 is final: wave 2
