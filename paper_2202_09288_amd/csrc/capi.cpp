@@ -52,8 +52,8 @@ struct spc_factor_s {
     void *Lx = nullptr;
     void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
-    // hand-over flags of the trailing launches, one per column block (in
-    // the status allocation, after the status words)
+    // hand-over flags of the trailing launches, one per 16-column panel of
+    // each column block (in the status allocation, after the status words)
     int32_t *hflags = nullptr;
     int nflags = 0;
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
@@ -428,7 +428,7 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     hipError_t e = hipMalloc(&f->Lx, bytes);
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
-    f->nflags = (int)sym->S.sblocks.size();
+    f->nflags = 4 * (int)sym->S.sblocks.size();  // one per 16-column panel of each block
     if (e == hipSuccess)
         e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus + sizeof(int32_t) * f->nflags);
     if (e == hipSuccess) f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus);

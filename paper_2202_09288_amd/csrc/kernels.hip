@@ -181,8 +181,11 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // dimension m, lower triangle only) and the inverse into Vi; a failed pivot
 // lowers *status to g0 + its column.  LDS scratch from the caller: rdg (64
 // entries), Tf and T32 (32 x 33 each), flags (8 ints).  Called by all 256
-// threads of the workgroup.  With publish, the inverse is stored with
-// device-scope atomic stores, for workgroups of the same launch to read.
+// threads of the workgroup.  With pflags (a full block, nb = 64), each
+// panel p is also handed to workgroups of the same launch: its L and the
+// inverse of its 16x16 diagonal triangle go out with device-scope atomic
+// stores, and each of waves 1-3 adds 1 to pflags[p] once its part has
+// completed (3 when the panel is out).
 //
 // Blocked by 16-column panels with lookahead: wave 0 factors panel p (lane
 // = row, pivots broadcast by readlane) right after bringing its columns up
@@ -198,7 +201,7 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 template <typename T>
 __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], T (*T32)[33], int *flags, int nb,
                                           T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int64_t g0,
-                                          bool publish) {
+                                          int32_t *pflags) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
@@ -221,9 +224,11 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
     if (t >= PW * npan && t < NB) rdg[t] = T(1);  // identity rows past the last panel
     __syncthreads();
 #define SPC_INV(a, c) ((c) < (a) ? A[c][a] : ((c) == (a) ? rdg[a] : T(0)))
-    auto vi_put = [&](int64_t e, T v) {
-        if (publish) dev_store(Vi + e, v);
-        else Vi[e] = v;
+    auto vi_put = [&](int64_t e, T v) { Vi[e] = v; };
+    // one wave's part of a panel is out: its stores have completed
+    auto panel_out = [&](int pb) {
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) __hip_atomic_fetch_add(pflags + pb, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     // inverse of the 32-column block at o from its two 16-block inverses
     // (one wave): X21 = -X22 L21 X11, kept transposed in the upper triangle
@@ -369,6 +374,15 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
                     wave_lds_sync();
                 }
                 lds_flag_store(&flag_dinv, pb + 1);
+                if (pflags) {
+                    // the panel's diagonal 16x16 block of the inverse
+#pragma unroll
+                    for (int q = 0; q < PW * PW / 64; ++q) {
+                        const int e = lane + 64 * q, i = p0 + e % PW, k = p0 + e / PW;
+                        dev_store(Vi + k * nb + i, SPC_INV(i, k));
+                    }
+                    panel_out(pb);
+                }
                 // the second 32-column block (its second 16-block may be
                 // identity padding) is merged right after its last panel
                 if (pb >= 2 && pb == npan - 1) inv16(32);
@@ -377,8 +391,13 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
                 // columns), so that wave 1 keeps up with the panels
                 for (int e = lane + 64 * (wv - 2); e < PW * NB; e += 128) {
                     const int k = p0 + e / NB, row = e % NB;
-                    if (k < nb && row >= k && row < nb) P[(int64_t)(c0 + k) * m + c0 + row] = A[row][k];
+                    if (k < nb && row >= k && row < nb) {
+                        T *dst = P + (int64_t)(c0 + k) * m + c0 + row;
+                        if (pflags) dev_store(dst, A[row][k]);
+                        else *dst = A[row][k];
+                    }
                 }
+                if (pflags) panel_out(pb);
             }
             if (pb == 1 && wv == 2) {
                 // the first 32-column block: merge its two inverted
@@ -472,7 +491,7 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
     }
     __syncthreads();
     potrf_lds<T>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
-                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0, false);
+                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,9 +703,9 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 //   MODE_TRAILING: A, B = panel rows i0.., j0..; P[i][j] -= C for i >= j,
 //                  j < jmax.  The diagonal tile of the next column block
 //                  then factors that block (potrf_lds); a tile below it
-//                  with a flag then waits for the block's inverse and
-//                  stores the TRSM result instead: P[i][j] = sum_k
-//                  (P - C)[i][k] (L^{-1})_{jk}.
+//                  with a flag then solves X L^T = P - C for its rows,
+//                  following the block's panels as they are handed out,
+//                  and stores X instead.
 //   MODE_SCATTER:  A, B = panel rows i0.., j0..; C (i >= j) scatter-added
 //                  atomically into the ancestors: C[i][j] goes to
 //                  cbase[j] + rel[crel[j] + i].
@@ -856,72 +875,74 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
             A[r][c] = (r < nb2 && c <= r) ? nv[cc] : (r == c ? T(1) : T(0));
         }
         __syncthreads();
+        // with a flag, each panel goes to the tiles below as it comes out
+        // (also after a failed pivot, which the status word reports, so
+        // that no tile waits in vain)
         potrf_lds<T>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
-                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk, tk.flag >= 0);
-        if (tk.flag >= 0) {
-            // every thread's inverse stores have completed: tell the tiles
-            // below (raised even after a failed pivot, which the status
-            // word reports, so that no tile waits in vain)
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (tid == 0) dev_store(hflags + tk.flag, 1);
-        }
+                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk,
+                     tk.flag >= 0 ? hflags + 4 * tk.flag : nullptr);
         return;
     }
     if (MODE == MODE_TRAILING && tk.flag >= 0) {
         // below the diagonal tile of a block factored in this launch: the
-        // updated tile (kept in Cs) times the transposed inverse of the
-        // block, read once the diagonal tile's workgroup has raised the flag
+        // block's TRSM on this tile, X L^T = C (C the updated tile), 16
+        // columns at a time as the block's panels come out: X_p = C_p
+        // L_pp^{-T}, then C_q -= X_p L_qp^T for the later panels q.  Each
+        // wave owns 16 rows of the tile, so the waves never wait for each
+        // other, only for the panel flags (3 once a panel is out).
+        static_assert(TM == kNB && TM == 64, "four 16-column panels per block");
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) Cs[cg * CPT + cc][r] = old[cc] - Cs[cg * CPT + cc][r];
-        if (tid == 0 && !wait_flag(hflags + tk.flag))
-            atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)tk.blk);
         __syncthreads();
-        // the inverse ((L^{-1})_{jk} at Vi[k * TM + j]) in two halves of K
-        // through the A/B buffer (32 rows of TM + 4), both read at once
-        constexpr int HK = TM / 2, PER = HK * TM / 256;
-        static_assert(HK * (TM + 4) <= 2 * KB * (TM + 4), "half an inverse fits the A/B buffer");
-        const T *Vi = Linv + tk.aux;
-        T *Vb = &ABs[0][0][0];
-        T vh[2][PER];
+        const T *Vi = Linv + tk.aux;                        // (L^{-1})_{jk} at Vi[k * TM + j]
+        const T *Lb = P + (int64_t)tk.j0 * m + tk.j0;       // block-local L[i][k] at Lb[k * m + i]
+        int32_t *pf = hflags + 4 * tk.flag;
+        const int w16 = wave * 16, l16 = lane & 15, lk4 = lane >> 4;
+        bool ok = true;
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < PER; ++e) vh[h][e] = dev_load(Vi + h * HK * TM + tid + 256 * e);
-        acc_t xa[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) xa[a][b] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const int x = tid + 256 * e;
-                Vb[(x / TM) * (TM + 4) + x % TM] = vh[h][e];
+        for (int p = 0; p < 4; ++p) {
+            // wait for panel p (every lane reads the same word: one load)
+            bool ready = false;
+            for (int it = 0; ok && it < (1 << 20); ++it) {
+                if (__builtin_amdgcn_readfirstlane(dev_load(pf + p)) >= 3) {
+                    ready = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            __syncthreads();
+            ok = ok && ready;
+            __asm__ volatile("" ::: "memory");
+            // B operands: the inverse of the panel's diagonal triangle,
+            // B[k][j] = (L^{-1})_{16p+j,16p+k}, and L below it, B[k][j] =
+            // L[16q+j][16p+k]
+            T bi[4], bl[3][4];
 #pragma unroll
-            for (int kk = 0; kk < HK; kk += 4) {
-                T af[2], bf[2];
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 16 * p + 4 * kk + lk4;
+                bi[kk] = dev_load(Vi + k * TM + 16 * p + l16);
 #pragma unroll
-                for (int a = 0; a < 2; ++a) af[a] = Cs[h * HK + kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) bf[b] = Vb[(kk + (lane >> 4)) * (TM + 4) + wc + b * 16 + (lane & 15)];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) xa[a][b] = Mfma<T>::run(af[a], bf[b], xa[a][b]);
+                for (int q = p + 1; q < 4; ++q) bl[q - p - 1][kk] = dev_load(Lb + (int64_t)k * m + 16 * q + l16);
             }
-            __syncthreads();
+            // X_p for this wave's rows, staged over C_p in Cs
+            acc_t x = {0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) x = Mfma<T>::run(Cs[16 * p + 4 * kk + lk4][w16 + l16], bi[kk], x);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Cs[16 * p + l16][w16 + Mfma<T>::row(lane, v)] = x[v];
+            wave_lds_sync();
+#pragma unroll
+            for (int q = p + 1; q < 4; ++q) {
+                acc_t u = {0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    u = Mfma<T>::run(Cs[16 * p + 4 * kk + lk4][w16 + l16], bl[q - p - 1][kk], u);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Cs[16 * q + l16][w16 + Mfma<T>::row(lane, v)] -= u[v];
+            }
+            wave_lds_sync();
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Cs[wc + b * 16 + (lane & 15)][wr + a * 16 + Mfma<T>::row(lane, v)] = xa[a][b][v];
+        if (!ok && lane == 0)
+            atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)tk.blk);
         __syncthreads();
         if (gi < m)
 #pragma unroll

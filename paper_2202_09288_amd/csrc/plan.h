@@ -88,11 +88,13 @@ struct TileTask {
                     // that block's global first column: the diagonal tile's
                     // workgroup (i0 = j0) factors the block after updating it
     int32_t flag;   // trailing tiles of the next block's columns, when that
-                    // block is a full kNB wide: its block id, the index of a
-                    // flag word.  The diagonal tile raises the flag once the
-                    // block's inverse (at aux) is stored; each tile below it
-                    // waits for the flag and then finishes the block's TRSM
-                    // on its own rows.  -1 otherwise.
+                    // block is a full kNB wide: its block id q, which owns
+                    // the flag words 4q..4q+3, one per 16-column panel.  The
+                    // diagonal tile's workgroup hands out each panel (its L
+                    // and the inverse of its diagonal triangle, inside the
+                    // inverse at aux) as soon as it is factored; each tile
+                    // below follows panel by panel with the block's TRSM on
+                    // its own rows.  -1 otherwise.
     int32_t pad;
 };
 

@@ -453,9 +453,9 @@ int build_schedule(Symbolic &S) {
             // The trailing launch holds, in this order: the diagonal tiles of
             // block b+1 (pass 0), the columns beyond block b+1 (pass 1), and
             // the tiles below block b+1's diagonal (pass 2).  When block b+1
-            // is a full kNB wide, the pass-2 tiles also do its TRSM: they
-            // wait for the diagonal tile's workgroup to store the block's
-            // inverse, so that block gets no TRSM launch of its own.  Every
+            // is a full kNB wide, the pass-2 tiles also do its TRSM, panel by
+            // panel as the diagonal tile's workgroup factors the block, so
+            // that block gets no TRSM launch of its own.  Every
             // diagonal tile comes before every tile that waits, so the
             // waiting tiles can never hold the device while a diagonal tile
             // is still undispatched.
