@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per rate")
     ap.add_argument("--capacity-sweep", action="store_true",
                     help="serving: measure capacity (all requests at once), then sweep 0.25-1.1x of it")
+    ap.add_argument("--serving-handover", default="off", choices=["on", "off"],
+                    help="serving: the factorizations' in-launch TRSM hand-over (off: no waits inside a launch)")
     return ap.parse_args()
 
 
@@ -340,7 +342,8 @@ def bench_serving(args):
 
     def one(rate, count):
         reqs = serving.make_requests(count, rate, seed=args.seed)
-        srv = serving.Server(slots=4, hbm_budget=64 << 30, precision="fp32", tol=1e-12, maxit=100)
+        srv = serving.Server(slots=4, hbm_budget=64 << 30, precision="fp32", tol=1e-12, maxit=100,
+                             handover=args.serving_handover == "on")
         t0 = time.perf_counter()
         srv.run(reqs)
         wall = time.perf_counter() - t0

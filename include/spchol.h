@@ -76,10 +76,17 @@ typedef struct spc_options {
      *   solve_persist_max  solve levels from the top with fewer tasks than
      *                     this run as one persistent launch per sweep
      *                     (default 1024)
+     *   handover          1: inside a wide supernode, the tiles below a
+     *                     64-column block that its trailing launch factors
+     *                     take the block's TRSM in the same launch, waiting
+     *                     on device flags for its panels; a negative value
+     *                     gives every block a TRSM launch of its own (no
+     *                     waits inside a launch: for many factorizations
+     *                     sharing the device on several streams).  Default 1.
      * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
     int32_t tiny_w, tiny_m, small_w, small_m;
     int32_t big_min, big_min_k, solve_persist_max;
-    int32_t reserved;
+    int32_t handover;
 } spc_options;
 
 /* Summary numbers of an analysis. */

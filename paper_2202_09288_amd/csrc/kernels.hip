@@ -727,6 +727,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
     T(*As)[TM + 4] = ABs[0];
     T(*Bs)[TM + 4] = ABs[1];
     const TileTask tk = tasks[blockIdx.x];
+    if (MODE == MODE_TRAILING && tk.s < 0) return;  // a no-op entry of the launch layout
     const int64_t m = tk.m;
     T *P = Lx + tk.loff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

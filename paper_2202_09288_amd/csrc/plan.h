@@ -52,6 +52,7 @@ struct Tuning {
     int32_t small_w = kSmallW, small_m = kSmallM;
     int32_t big_min = kBigMin, big_min_k = kBigMinK;
     int32_t solve_persist_max = kSolvePersistMax;
+    int32_t handover = 1;  // fused TRSM with in-launch waits (0: off)
 };
 
 // One pair (source supernode s, ancestor t) of the scatter: rows

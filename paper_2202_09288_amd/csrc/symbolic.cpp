@@ -450,87 +450,117 @@ int build_schedule(Symbolic &S) {
             // factors block b+1 in that column's diagonal tile; the last step
             // of a group updates every column beyond with all of the group's
             // panels at once (K = kDelay blocks).
-            // The trailing launch holds, in this order: the diagonal tiles of
-            // block b+1 (pass 0), the columns beyond block b+1 (pass 1), and
-            // the tiles below block b+1's diagonal (pass 2).  When block b+1
-            // is a full kNB wide, the pass-2 tiles also do its TRSM, panel by
-            // panel as the diagonal tile's workgroup factors the block, so
-            // that block gets no TRSM launch of its own.  Every
-            // diagonal tile comes before every tile that waits, so the
-            // waiting tiles can never hold the device while a diagonal tile
-            // is still undispatched.
+            // The trailing launch holds the diagonal tiles of block b+1 first
+            // (which also factor it), then the columns beyond block b+1, then
+            // the tiles below block b+1's diagonal.  When block b+1 is a full
+            // kNB wide, those tiles also do its TRSM, panel by panel as the
+            // diagonal tile's workgroup factors the block, so that block gets
+            // no TRSM launch of its own.  A tile that waits sits at a launch
+            // index congruent mod 8 to its diagonal tile's and after it:
+            // workgroups go round-robin to the XCDs (whatever XCD a launch
+            // starts on), and each XCD dispatches its share in index order,
+            // so the workgroup it waits for is resident or done, even while
+            // other launches (other streams) fill the device.  Gaps in that
+            // pattern take other tiles, else no-op entries (s = -1).
             const int64_t gb = b - b % kDelay;  // first block of b's group
             const bool bulk = b % kDelay == kDelay - 1;
-            for (int pass = 0; pass < 3; ++pass) {
-                if (pass == 1) st.tm = (int64_t)S.int_tiles.size();
-                for (int32_t s : bylevel[l]) {
-                    int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
-                    int64_t c0 = b * kNB;
-                    if (c0 >= w) continue;
-                    int64_t c1 = std::min<int64_t>(c0 + kNB, w);
-                    int32_t blk = first_blk[s] + (int32_t)b;
-                    const double nbd = (double)(c1 - c0);
-                    const int64_t cx = std::min<int64_t>(c1 + kNB, w);  // end of block b+1
-                    const int64_t k0 = gb * kNB;                         // the group's first column
-                    const double kd = (double)(c1 - k0);
-                    // the last block of a supernode closes its group too
-                    const bool close = bulk || cx >= w;
-                    // block b+1 gets its TRSM from this step's pass-2 tiles;
-                    // block b got it from step b-1's
-                    const bool fuse_next = c1 < w && cx - c1 == kNB;
-                    const bool fused_here = b > 0 && c1 - c0 == kNB;
-                    const int32_t gnext = (int32_t)(S.super_ptr[s] + c1);
-                    if (pass == 0) {
-                        // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
-                        // SYRK k n(n+1), GEMM 2 m n k
-                        const double nx = (double)(cx - c1), tot = (double)(w - c1);
-                        if (c1 < w)  // block b+1's POTRF runs in this step's column update
-                            st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
-                        st.look_flops += nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd;
-                        if (fuse_next) st.look_flops += (double)(m - cx) * nx * nx;
-                        if (close)
-                            st.rest_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
-                                             (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
-                        // block 0 gets a POTRF task; block b+1 is factored by the
-                        // workgroup of its diagonal tile in step b's column update
-                        if (b == 0) {
-                            st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
-                            S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
-                                                              (int32_t)c0, (int32_t)c1,
-                                                              (int32_t)(S.super_ptr[s] + c0), 0});
-                        }
-                        if (!fused_here) {
-                            st.trsm_flops += (double)(m - c1) * nbd * nbd;
-                            for (int64_t r = c1; r < m; r += kTile)
-                                S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m,
-                                                                (int32_t)r, (int32_t)c0, (int32_t)c0, (int32_t)c1,
-                                                                (int32_t)c1, blk, -1, 0});
-                        }
-                        if (c1 < w)
-                            S.int_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk + 1], s, (int32_t)m,
-                                                           (int32_t)c1, (int32_t)c1, (int32_t)k0, (int32_t)c1,
-                                                           (int32_t)w, gnext, fuse_next ? blk + 1 : -1, 0});
-                        continue;
-                    }
-                    if (pass == 1) {
-                        if (!close) continue;
-                        // trailing update of the columns beyond block b+1:
-                        // rows [j0, m), K = [k0, c1)
-                        for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTile)
-                            for (int64_t i0 = j0; i0 < m; i0 += kTile)
-                                S.int_tiles.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
-                                                               (int32_t)j0, (int32_t)k0, (int32_t)c1, (int32_t)w,
-                                                               -1, -1, 0});
-                        continue;
-                    }
-                    // pass 2: block b+1's columns below its diagonal tile
-                    if (c1 >= w) continue;
-                    for (int64_t i0 = c1 + kTile; i0 < m; i0 += kTile)
-                        S.int_tiles.push_back(TileTask{S.lptr[s], fuse_next ? S.inv_off[blk + 1] : S.rptr[s], s,
-                                                       (int32_t)m, (int32_t)i0, (int32_t)c1, (int32_t)k0,
-                                                       (int32_t)c1, (int32_t)w, fuse_next ? gnext : -1,
-                                                       fuse_next ? blk + 1 : -1, 0});
+            std::vector<TileTask> diag, rest, below;
+            std::vector<int32_t> below_diag;  // diagonal tile of each waiting tile (index into diag)
+            for (int32_t s : bylevel[l]) {
+                int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+                int64_t c0 = b * kNB;
+                if (c0 >= w) continue;
+                int64_t c1 = std::min<int64_t>(c0 + kNB, w);
+                int32_t blk = first_blk[s] + (int32_t)b;
+                const double nbd = (double)(c1 - c0);
+                const int64_t cx = std::min<int64_t>(c1 + kNB, w);  // end of block b+1
+                const int64_t k0 = gb * kNB;                         // the group's first column
+                const double kd = (double)(c1 - k0);
+                // the last block of a supernode closes its group too
+                const bool close = bulk || cx >= w;
+                // block b+1 gets its TRSM from this step's tiles below its
+                // diagonal; block b got it from step b-1's
+                const bool fuse_next = tu.handover && c1 < w && cx - c1 == kNB;
+                const bool fused_here = tu.handover && b > 0 && c1 - c0 == kNB;
+                const int32_t gnext = (int32_t)(S.super_ptr[s] + c1);
+                // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
+                // SYRK k n(n+1), GEMM 2 m n k
+                const double nx = (double)(cx - c1), tot = (double)(w - c1);
+                if (c1 < w)  // block b+1's POTRF runs in this step's column update
+                    st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
+                st.look_flops += nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd;
+                if (fuse_next) st.look_flops += (double)(m - cx) * nx * nx;
+                if (close)
+                    st.rest_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
+                                     (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
+                // block 0 gets a POTRF task; block b+1 is factored by the
+                // workgroup of its diagonal tile in step b's column update
+                if (b == 0) {
+                    st.potrf_flops += nbd * nbd * nbd / 3.0 + nbd * nbd / 2.0 + nbd / 6.0;
+                    S.potrf_tasks.push_back(PanelTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)c0,
+                                                      (int32_t)c1, (int32_t)(S.super_ptr[s] + c0), 0});
                 }
+                if (!fused_here) {
+                    st.trsm_flops += (double)(m - c1) * nbd * nbd;
+                    for (int64_t r = c1; r < m; r += kTile)
+                        S.trsm_tiles.push_back(TileTask{S.lptr[s], S.inv_off[blk], s, (int32_t)m, (int32_t)r,
+                                                        (int32_t)c0, (int32_t)c0, (int32_t)c1, (int32_t)c1, blk, -1,
+                                                        0});
+                }
+                if (c1 >= w) continue;
+                const int32_t di = (int32_t)diag.size();
+                diag.push_back(TileTask{S.lptr[s], S.inv_off[blk + 1], s, (int32_t)m, (int32_t)c1, (int32_t)c1,
+                                        (int32_t)k0, (int32_t)c1, (int32_t)w, gnext, fuse_next ? blk + 1 : -1, 0});
+                if (close)
+                    // trailing update of the columns beyond block b+1:
+                    // rows [j0, m), K = [k0, c1)
+                    for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTile)
+                        for (int64_t i0 = j0; i0 < m; i0 += kTile)
+                            rest.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0,
+                                                    (int32_t)k0, (int32_t)c1, (int32_t)w, -1, -1, 0});
+                // block b+1's columns below its diagonal tile
+                for (int64_t i0 = c1 + kTile; i0 < m; i0 += kTile) {
+                    const TileTask tt{S.lptr[s], fuse_next ? S.inv_off[blk + 1] : S.rptr[s], s, (int32_t)m,
+                                      (int32_t)i0, (int32_t)c1, (int32_t)k0, (int32_t)c1, (int32_t)w,
+                                      fuse_next ? gnext : -1, fuse_next ? blk + 1 : -1, 0};
+                    if (fuse_next) {
+                        below.push_back(tt);
+                        below_diag.push_back(di);
+                    } else {
+                        rest.push_back(tt);
+                    }
+                }
+            }
+            // layout: diag | rest not needed for gaps | region where each
+            // waiting tile takes a slot of its diagonal tile's residue
+            const int64_t nd = (int64_t)diag.size();
+            int64_t per[8] = {0, 0, 0, 0, 0, 0, 0, 0}, cmax = 0;
+            for (int32_t di : below_diag) cmax = std::max(cmax, ++per[di % 8]);
+            const int64_t region = 8 * cmax, gaps = region - (int64_t)below.size();
+            const int64_t front = std::max<int64_t>(0, (int64_t)rest.size() - gaps);
+            for (const TileTask &tt : diag) S.int_tiles.push_back(tt);
+            st.tm = (int64_t)S.int_tiles.size();
+            for (int64_t e = 0; e < front; ++e) S.int_tiles.push_back(rest[e]);
+            {
+                std::vector<std::vector<int64_t>> q(8);
+                for (size_t e = 0; e < below.size(); ++e) q[below_diag[e] % 8].push_back((int64_t)e);
+                std::vector<size_t> qi(8, 0);
+                size_t ri = (size_t)front;
+                const TileTask noop{0, 0, -1, 1, 0, 0, 0, 0, 0, -1, -1, 0};
+                std::vector<TileTask> tail;
+                int64_t pending = (int64_t)below.size();
+                for (int64_t pos = nd + front; pending > 0 || ri < rest.size(); ++pos) {
+                    const int r = (int)(pos % 8);
+                    if (qi[r] < q[r].size()) {
+                        tail.push_back(below[q[r][qi[r]++]]);
+                        --pending;
+                    } else if (ri < rest.size()) {
+                        tail.push_back(rest[ri++]);
+                    } else {
+                        tail.push_back(noop);
+                    }
+                }
+                for (const TileTask &tt : tail) S.int_tiles.push_back(tt);
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();

@@ -76,7 +76,7 @@ class Server:
 
     def __init__(self, slots: int = 4, hbm_budget: int = 64 << 30, precision: str = "fp32",
                  tol: float = 1e-12, maxit: int = 50, keep_solutions: bool = False,
-                 max_resident: int = 64):
+                 max_resident: int = 64, handover: bool = False):
         import torch
         from . import spchol
         self.torch = torch
@@ -88,6 +88,10 @@ class Server:
         self.maxit = maxit
         self.keep_solutions = keep_solutions
         self.max_resident = max_resident
+        # in-launch TRSM hand-over (waits inside a launch) for the
+        # factorizations; off by default, since the slots' factorizations
+        # share the device on several streams
+        self.tuning = {"handover": 1 if handover else -1}
         self.sym_cache = {}
         self.sym_lock = threading.Lock()
         self.resident = OrderedDict()      # key -> Resident (LRU order)
@@ -135,7 +139,7 @@ class Server:
         with self.sym_lock:
             sym = self.sym_cache.get(key)
             if sym is None:
-                sym = self.lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+                sym = self.lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, self.tuning)
                 self.sym_cache[key] = sym
         return sym
 

@@ -51,12 +51,12 @@ KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": 
 
 
 # schedule cut-offs of spc_options (0: library default, < 0: path off)
-TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max")
+TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max",
+                 "handover")
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("amalg_z", ctypes.c_double)] + [(k, ctypes.c_int32) for k in TUNING_FIELDS] + \
-        [("reserved", ctypes.c_int32)]
+    _fields_ = [("amalg_z", ctypes.c_double)] + [(k, ctypes.c_int32) for k in TUNING_FIELDS]
 
 
 class _Info(ctypes.Structure):

@@ -37,6 +37,7 @@ GROUPS = [
     ("small", ("small_w", "small_m"), [(32, 128), (16, 64), (32, 64), (-1, -1)]),
     ("big", ("big_min", "big_min_k"), [(256, 128), (128, 64), (512, 128), (256, 256), (-1, -1)]),
     ("persist", ("solve_persist_max",), [(1024,), (256,), (4096,)]),
+    ("handover", ("handover",), [(1,), (-1,)]),
 ]
 
 

@@ -97,6 +97,7 @@ SCHEDULES = {
     "128-tiles everywhere": {"big_min": 1, "big_min_k": 1},
     "no 128-tiles": {"big_min": -1},
     "solve levels only": {"solve_persist_max": -1},
+    "no in-launch TRSM hand-over": {"handover": -1},
     "solve all persistent": {"solve_persist_max": 1 << 30},
 }
 
