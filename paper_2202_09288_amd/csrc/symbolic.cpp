@@ -531,36 +531,57 @@ int build_schedule(Symbolic &S) {
                     }
                 }
             }
-            // layout: diag | rest not needed for gaps | region where each
-            // waiting tile takes a slot of its diagonal tile's residue
+            // layout: the diagonal tiles, then per residue r of the launch
+            // index (mod 8, one XCD) a queue of other tiles followed by the
+            // waiting tiles whose diagonal tile has residue r, emitted by
+            // position; the other tiles are spread so that every residue
+            // holds about as many tiles (water-filling), since the waiting
+            // tiles of a supernode all land on one XCD
             const int64_t nd = (int64_t)diag.size();
-            int64_t per[8] = {0, 0, 0, 0, 0, 0, 0, 0}, cmax = 0;
-            for (int32_t di : below_diag) cmax = std::max(cmax, ++per[di % 8]);
-            const int64_t region = 8 * cmax, gaps = region - (int64_t)below.size();
-            const int64_t front = std::max<int64_t>(0, (int64_t)rest.size() - gaps);
+            std::vector<std::vector<const TileTask *>> qr(8);
+            {
+                int64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int32_t di : below_diag) c[(di % 8)]++;
+                // residues start after the diagonal tiles: position nd is residue nd % 8
+                const int64_t R = (int64_t)rest.size();
+                int64_t lo = 0, hi = R + (int64_t)below.size() + 1;  // smallest T with sum max(0, T - c) >= R
+                while (lo < hi) {
+                    const int64_t T = (lo + hi) / 2;
+                    int64_t sum = 0;
+                    for (int r = 0; r < 8; ++r) sum += std::max<int64_t>(0, T - c[r]);
+                    if (sum >= R) hi = T;
+                    else lo = T + 1;
+                }
+                int64_t take[8], left = R;
+                for (int r = 0; r < 8; ++r) take[r] = std::max<int64_t>(0, lo - 1 - c[r]);
+                for (int r = 0; r < 8; ++r) left -= take[r];
+                for (int r = 0; r < 8 && left > 0; ++r)
+                    if (lo - c[r] > take[r] && lo - c[r] > 0) {
+                        ++take[r];
+                        --left;
+                    }
+                size_t ri = 0;
+                for (int r = 0; r < 8; ++r)
+                    for (int64_t e = 0; e < take[r]; ++e) qr[r].push_back(&rest[ri++]);
+                for (; ri < rest.size(); ++ri) qr[ri % 8].push_back(&rest[ri]);  // (never: the takes add to R)
+                for (size_t e = 0; e < below.size(); ++e) qr[below_diag[e] % 8].push_back(&below[e]);
+            }
             for (const TileTask &tt : diag) S.int_tiles.push_back(tt);
             st.tm = (int64_t)S.int_tiles.size();
-            for (int64_t e = 0; e < front; ++e) S.int_tiles.push_back(rest[e]);
             {
-                std::vector<std::vector<int64_t>> q(8);
-                for (size_t e = 0; e < below.size(); ++e) q[below_diag[e] % 8].push_back((int64_t)e);
-                std::vector<size_t> qi(8, 0);
-                size_t ri = (size_t)front;
                 const TileTask noop{0, 0, -1, 1, 0, 0, 0, 0, 0, -1, -1, 0};
-                std::vector<TileTask> tail;
-                int64_t pending = (int64_t)below.size();
-                for (int64_t pos = nd + front; pending > 0 || ri < rest.size(); ++pos) {
+                std::vector<size_t> qi(8, 0);
+                size_t pending = 0;
+                for (auto &q : qr) pending += q.size();
+                for (int64_t pos = nd; pending > 0; ++pos) {
                     const int r = (int)(pos % 8);
-                    if (qi[r] < q[r].size()) {
-                        tail.push_back(below[q[r][qi[r]++]]);
+                    if (qi[r] < qr[r].size()) {
+                        S.int_tiles.push_back(*qr[r][qi[r]++]);
                         --pending;
-                    } else if (ri < rest.size()) {
-                        tail.push_back(rest[ri++]);
                     } else {
-                        tail.push_back(noop);
+                        S.int_tiles.push_back(noop);
                     }
                 }
-                for (const TileTask &tt : tail) S.int_tiles.push_back(tt);
             }
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
