@@ -128,6 +128,16 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx,
 
 int spc_symbolic_info(spc_symbolic sym, spc_info *out);
 
+/* Check the device schedule of an analysis on the host (no device needed),
+ * for tests and diagnostics: every 64-column block of the blocked path has
+ * the rows below its diagonal solved exactly once (by a TRSM launch, or by
+ * the hand-over tiles of the step before, spc_options.handover), and every
+ * tile that waits inside a trailing launch comes after the tile it waits for
+ * at a launch index congruent to it mod 8, so both run on one XCD and the
+ * wait cannot deadlock.  Returns SPC_OK, or SPC_INVALID_INPUT with the first
+ * violation in spc_last_error_message(); SPC_BAD_HANDLE for a bad handle. */
+int spc_symbolic_verify(spc_symbolic sym);
+
 /* Export one symbolic array to host memory for inspection.
  *   0 perm int32[n]        final order (given order composed with postorder)
  *   1 parent int32[n]      elimination tree of the permuted matrix, -1 root

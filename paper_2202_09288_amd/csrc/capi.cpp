@@ -743,6 +743,14 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     return SPC_OK;
 }
 
+int spc_symbolic_verify(spc_symbolic sym) {
+    if (!sym_ok(sym)) return SPC_BAD_HANDLE;
+    std::string msg;
+    if (spc::verify_schedule(sym->S, msg) == 0) return SPC_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error), "schedule: %s", msg.c_str());
+    return SPC_INVALID_INPUT;
+}
+
 int spc_symbolic_export(spc_symbolic sym, int which, void *h_dst) {
     if (!sym_ok(sym)) return SPC_BAD_HANDLE;
     if (!h_dst) return SPC_INVALID_INPUT;

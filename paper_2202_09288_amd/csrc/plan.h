@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 namespace spc {
@@ -241,6 +242,11 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
             double z, const Tuning &tune, Symbolic &S);
 // Schedule of an analysis whose structural arrays are set.
 int build_schedule(Symbolic &S);
+// Host check of a schedule's invariants: every block of the blocked path
+// has the rows below it solved exactly once (TRSM launch or hand-over
+// tiles), and every tile that waits inside a trailing launch comes after its
+// diagonal tile at a launch index congruent to it mod 8.  0, or -1 with msg.
+int verify_schedule(const Symbolic &S, std::string &msg);
 // Disjoint union of analyses with a schedule over the whole forest; the
 // offsets of each part (columns, panel entries, inverse store, caller
 // entries) are returned, with a final total.

@@ -737,6 +737,61 @@ int build_schedule(Symbolic &S) {
 // panel entries follow those of systems 0..i-1; its caller entries follow
 // theirs too.  The schedule is then built for the whole forest, so level l
 // of the union holds level l of every system.
+int verify_schedule(const Symbolic &S, std::string &msg) {
+    auto fail = [&](const char *what, int64_t a, int64_t b) {
+        char buf[200];
+        std::snprintf(buf, sizeof(buf), "%s (%lld, %lld)", what, (long long)a, (long long)b);
+        msg = buf;
+        return -1;
+    };
+    const int64_t nb = (int64_t)S.sblocks.size();
+    // rows below each block solved by a TRSM launch or by hand-over tiles
+    std::vector<int64_t> solved(nb, 0);
+    std::vector<char> blocked(S.nsuper, 0);
+    for (const PanelTask &pt : S.potrf_tasks) blocked[pt.s] = 1;
+    auto block_of = [&](int32_t s, int64_t c) { return (int64_t)S.first_blk[s] + c / kNB; };
+    auto m_of = [&](int32_t s) { return S.rptr[s + 1] - S.rptr[s]; };
+    for (const TileTask &tt : S.trsm_tiles) {
+        if (tt.s < 0 || tt.s >= S.nsuper || tt.blk < 0 || tt.blk >= nb) return fail("TRSM tile out of range", tt.s, tt.blk);
+        solved[tt.blk] += std::min<int64_t>(tt.i0 + kTile, m_of(tt.s)) - tt.i0;
+    }
+    std::vector<int64_t> dpos(nb, -1);
+    for (const Symbolic::Step &st : S.steps) {
+        for (int64_t t = st.t0; t < st.t1; ++t) {
+            const TileTask &tt = S.int_tiles[t];
+            if (tt.s < 0) {  // no-op entry
+                if (tt.flag != -1 || t < st.tm) return fail("no-op entry misplaced", t, tt.flag);
+                continue;
+            }
+            if (tt.s >= S.nsuper || tt.loff != S.lptr[tt.s] || tt.m != m_of(tt.s))
+                return fail("trailing tile of an unknown supernode", t, tt.s);
+            const bool diag = tt.blk >= 0 && tt.i0 == tt.j0;
+            if (diag) {
+                if (t >= st.tm) return fail("diagonal tile after the others", t, st.tm);
+                if (tt.flag >= 0) {
+                    const int64_t q = block_of(tt.s, tt.j0);
+                    if (tt.flag != q || S.sblocks[q].c1 - S.sblocks[q].c0 != kNB)
+                        return fail("hand-over from a block that is not full", t, tt.flag);
+                    dpos[q] = t;
+                }
+            } else if (tt.flag >= 0) {
+                const int64_t q = tt.flag;
+                if (q >= nb || dpos[q] < st.t0 || dpos[q] >= t) return fail("waiting tile before its diagonal tile", t, q);
+                if ((t - st.t0) % 8 != (dpos[q] - st.t0) % 8) return fail("waiting tile on another XCD", t, dpos[q]);
+                const TileTask &d = S.int_tiles[dpos[q]];
+                if (d.s != tt.s || d.j0 != tt.j0 || tt.i0 < tt.j0 + kTile) return fail("waiting tile of another block", t, q);
+                solved[q] += std::min<int64_t>(tt.i0 + kTile, tt.m) - tt.i0;
+            }
+        }
+    }
+    for (int64_t q = 0; q < nb; ++q) {
+        const SolveBlock &b = S.sblocks[q];
+        if (!blocked[b.s]) continue;
+        if (solved[q] != m_of(b.s) - b.c1) return fail("rows below a block not solved exactly once", q, solved[q]);
+    }
+    return 0;
+}
+
 int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<int64_t> &col_off,
           std::vector<int64_t> &panel_off, std::vector<int64_t> &inv_base, std::vector<int64_t> &val_off) {
     M = Symbolic();

@@ -33,7 +33,7 @@ OK, INVALID_INPUT, NOT_SPD, OUT_OF_MEMORY, NO_CONVERGENCE, DEVICE_ERROR, BAD_HAN
 FP64, FP32 = 0, 1
 _PREC = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
 
-EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_export", "spc_factorize",
+EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbolic_export", "spc_factorize",
            "spc_refactorize", "spc_factorize_batch", "spc_solve", "spc_solve_refined", "spc_sync",
            "spc_factor_export", "spc_factor_last_ms", "spc_factor_set_profiling",
            "spc_factor_kernel_stats", "spc_free_symbolic", "spc_free_factor", "spc_status_string",
@@ -79,6 +79,7 @@ _P = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _lib.spc_analyze.argtypes = [_i64, _P, _P, _P, ctypes.POINTER(_Options), ctypes.POINTER(_P)]
 _lib.spc_symbolic_info.argtypes = [_P, ctypes.POINTER(_Info)]
+_lib.spc_symbolic_verify.argtypes = [_P]
 _lib.spc_symbolic_export.argtypes = [_P, ctypes.c_int, _P]
 _lib.spc_factorize.argtypes = [_P, _P, ctypes.c_int, _P, ctypes.POINTER(_P)]
 _lib.spc_refactorize.argtypes = [_P, _P, _P]
@@ -210,6 +211,13 @@ class Symbolic:
     def n(self) -> int:
         return self.info["n"]
 
+    def verify(self) -> None:
+        """Host check of the schedule's invariants (spc_symbolic_verify);
+        raises SpcError naming the first violation."""
+        rc = _lib.spc_symbolic_verify(self._h)
+        if rc != 0:
+            raise SpcError(rc, "spc_symbolic_verify: " + _lib.spc_last_error_message().decode())
+
     def export(self, name: str) -> np.ndarray:
         if name not in self._cache:
             which, dt, sz = _EXPORT_ARRAYS[name]
@@ -222,7 +230,8 @@ class Symbolic:
         return self._cache[name]
 
     def close(self):
-        if getattr(self, "_h", None):
+        # (at interpreter exit the module's globals may already be gone)
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.spc_free_symbolic(self._h)
             self._h = None
 
@@ -318,7 +327,8 @@ class Factor:
         return res
 
     def close(self):
-        if getattr(self, "_h", None):
+        # (at interpreter exit the module's globals may already be gone)
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.spc_free_factor(self._h)
             self._h = None
 
@@ -403,7 +413,8 @@ class Batch:
         return out
 
     def close(self):
-        if getattr(self, "_h", None):
+        # (at interpreter exit the module's globals may already be gone)
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.spc_free_batch(self._h)
             self._h = None
 
