@@ -286,6 +286,33 @@ def test_refactorize_new_values_wide(torch_dev, lib):
         assert oracle.rel_frobenius(F.export(), refs[k], S.lower_mask()) <= REL_F_FP64
 
 
+def test_handover_concurrent_streams(torch_dev, lib):
+    """Factorizations with the in-launch hand-over on four streams at once,
+    so that trailing launches with waiting tiles share the device: every
+    factor matches the oracle's, refactorization after refactorization.
+    (The waiting tiles sit on the XCD of the tile they wait for, which
+    spc_symbolic_verify checks, so no wait depends on another launch.)"""
+    torch = torch_dev
+    s = grid((30, 28, 26), seed=7)
+    print(f"case concurrent hand-over n={s.n}", flush=True)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"handover": 1})
+    sym.verify()
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    ref = S.factor(s.values)
+    dv = torch.from_numpy(s.values).cuda()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    facs = []
+    for st in streams:
+        facs.append(lib.factorize(sym, dv, "fp64", stream=st))
+    for rep in range(3):
+        for F, st in zip(facs, streams):
+            F.refactorize(dv, stream=st)
+    torch.cuda.synchronize()
+    for F in facs:
+        F.sync()  # raises if a pivot failed or a wait gave up
+        assert oracle.rel_frobenius(F.export(), ref, S.lower_mask()) <= REL_F_FP64
+
+
 def test_zero_rhs_and_empty(torch_dev, lib):
     s = grid((6, 6))
     sym = lib.Symbolic(s.colptr, s.rowidx, s.perm)
