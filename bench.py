@@ -112,7 +112,7 @@ def cpu_baseline(s, target_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: this benchmark runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     modes = {"grid3d60": bench_grid3d, "grid2d64": bench_grid2d, "elast48": bench_elast,
@@ -270,7 +270,7 @@ def bench_elast(args):
 def bench_batch(args):
     """512 independent systems (2D/3D grids, n from ~1k to ~40k), 16 RHS each,
     merged into one forest: one schedule factors them all (FP32), one batched
-    solve; FP64 refinement of all systems together, judged per system."""
+    solve; FP64 refinement of all systems together, checked per system."""
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W

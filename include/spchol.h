@@ -248,7 +248,7 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
  * spc_batch_solve_refined -- spc_solve_refined for every system of a batch
  * at once: one merged solve per step serves all systems, while the norms,
  * the backward error and the conjugate-gradient coefficients are kept per
- * system and right-hand side, so each system converges (and is judged)
+ * system and right-hand side, so each system converges (and is checked)
  * on its own.  A is the matrix of the last spc_batch_factorize.
  *   d_B[i]  system i's right-hand sides (device, n_i x nrhs column-major,
  *           leading dimension ld[i] >= n_i), not modified

@@ -383,7 +383,7 @@ int capture_factor(spc_factor f, const double *d_values) {
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
-    (void)hipGetLastError();  // judge only the launches below
+    (void)hipGetLastError();  // report only the launches below
     if (f->use_graph && !f->profiling) {
         if (!f->gexec || f->graph_values != d_values) {
             int rc = capture_factor(f, d_values);
@@ -825,7 +825,7 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const spc::DevPlan &P = f->sym->dev.plan;
     size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
-    (void)hipGetLastError();  // judge only the launches below
+    (void)hipGetLastError();  // report only the launches below
     constexpr int kChunk = 16;
     const size_t vec = (size_t)S.n * kChunk * esz;
     const size_t cnt_off = (3 * vec + 255) & ~size_t(255);
