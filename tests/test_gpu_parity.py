@@ -243,6 +243,44 @@ def test_not_spd_pivot(torch_dev, lib):
     assert eg.value.column == iperm[7]
 
 
+def test_not_spd_pivot_in_handed_over_block(torch_dev, lib):
+    """A failing pivot inside a 64-column block that a trailing launch
+    factors while handing its panels to the tiles below (blocks 1.. of a wide
+    supernode): the status names the oracle's column, the tiles below do not
+    wait in vain, and the same factor object factors good values again."""
+    torch = torch_dev
+    n = 300
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    r, c = np.tril_indices(n)
+    colptr, rowidx, v0 = W.lower_csc(n, r, c, A[r, c])
+    perm = np.arange(n, dtype=np.int32)
+    S = oracle.Symbolic(colptr, rowidx, perm, 0.05)
+    iperm = np.argsort(S.perm)
+    for handover in (1, -1):
+        sym = lib.Symbolic(colptr, rowidx, perm, 0.05, {"handover": handover})
+        sym.verify()
+        F = None
+        for col in (70, 150, 255, 299):
+            print(f"case not-SPD column {col} handover {handover}", flush=True)
+            v = v0.copy()
+            v[colptr[col]] = -v[colptr[col]]
+            with pytest.raises(oracle.NotSPD) as eo:
+                S.factor(v)
+            dv = torch.from_numpy(v).cuda()
+            if F is None:
+                F = lib.factorize(sym, dv)
+            else:
+                F.refactorize(dv)
+            with pytest.raises(lib.NotSPD) as eg:
+                F.sync()
+            assert eg.value.column == eo.value.column == iperm[col]
+        F.refactorize(torch.from_numpy(v0).cuda())
+        F.sync()
+        assert oracle.rel_frobenius(F.export(), S.factor(v0), S.lower_mask()) <= REL_F_FP64
+
+
 def test_refactorize_and_repeat(torch_dev, lib):
     s = grid((15, 15, 15), seed=4, nrhs=1)
     sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
