@@ -109,6 +109,25 @@ def cpu_baseline(s, target_s):
             "seconds": round(dt, 2), "host_cpus": os.cpu_count()}
 
 
+def host_backward_error(n, colptr, rowidx, values, X, B) -> float:
+    """Normwise backward error of the solution X, max over the right-hand
+    sides: ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf), in FP64 on
+    the host with scipy (A symmetric, given by its lower triangle in CSC)."""
+    import scipy.sparse as sp
+    lower = sp.csc_matrix((np.asarray(values, np.float64), np.asarray(rowidx), np.asarray(colptr)), shape=(n, n))
+    A = (lower + sp.tril(lower, -1).T).tocsr()
+    X = np.asarray(X, np.float64).reshape(n, -1)
+    B = np.asarray(B, np.float64).reshape(n, -1)
+    R = B - A @ X
+    norm_a = float(np.abs(A).sum(axis=1).max()) if n else 0.0
+    worst = 0.0
+    for k in range(X.shape[1]):
+        den = norm_a * float(np.abs(X[:, k]).max()) + float(np.abs(B[:, k]).max())
+        if den > 0:
+            worst = max(worst, float(np.abs(R[:, k]).max()) / den)
+    return worst
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -190,7 +209,6 @@ def bench_grid2d(args):
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W
-    import oracle
     torch.cuda.set_device(0)
     s = W.grid2d_unit(seed=args.seed)
     tuning = cutoffs(args, [s], 1, "fp64")
@@ -205,7 +223,7 @@ def bench_grid2d(args):
     fac = timed(lambda: F.refactorize(dv), steps, warm, torch)
     sol = timed(lambda: (Bw.copy_(B0), F.solve(Bw)), steps, warm, torch)
     F.sync()
-    berr = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Bw.cpu().numpy().T, s.B)
+    berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, Bw.cpu().numpy().T, s.B)
     flops = float(sym.info["flops"])
     out = head(args, round(flops / (fac.mean() * 1e-3) / 1e9, 3), "GFLOP/s", "f64",
                {"workload": "2D 5-point, 64x64 grid, diagonal = degree + 1e-2, geometric nested dissection, "
@@ -226,7 +244,6 @@ def bench_elast(args):
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W
-    import oracle
     torch.cuda.set_device(0)
     s = W.elast48(seed=args.seed)
     tuning = cutoffs(args, [s], 4, "fp32")
@@ -247,7 +264,7 @@ def bench_elast(args):
             info.update(F.solve_refined(dv, B0, X, tol=1e-12, maxit=200))
         sol = timed(solve, max(3, args.steps // 2), 1, torch)
         F.sync()
-        berr = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+        berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
         res[prec] = {"factor_ms": round(float(fac.mean()), 3),
                      "factor_gflops": round(flops / (fac.mean() * 1e-3) / 1e9, 1),
                      "refined_solve_ms_p50": round(float(np.median(sol)), 3),
@@ -274,7 +291,6 @@ def bench_batch(args):
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W
-    import oracle
     torch.cuda.set_device(0)
     systems = W.batch512()
     tuning = cutoffs(args, systems, 16, "fp32")
@@ -313,7 +329,7 @@ def bench_batch(args):
             iters = [r["iterations"] for r in out["systems"]]
             worst = 0.0
             for i, x in enumerate(systems[:64]):
-                worst = max(worst, oracle.backward_error(x.n, x.colptr, x.rowidx, x.values,
+                worst = max(worst, host_backward_error(x.n, x.colptr, x.rowidx, x.values,
                                                          Xs[i].cpu().numpy().T, x.B))
             res[prec].update({"refine_all_ms": round(1e3 * float(np.median(ref)), 3),
                               "refine_converged_all": bool(out["status"] == spchol.OK),
@@ -419,9 +435,8 @@ def bench_grid3d(args):
     fac_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     sol_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
 
-    import oracle
     X = Bw.cpu().numpy().T
-    berr = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X, s.B)
+    berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, X, s.B)
 
     # profiled pass of the same steps: per-launch events around each kernel class
     F.set_profiling(True)
