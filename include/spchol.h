@@ -60,8 +60,8 @@ typedef struct spc_options {
     /* Chain amalgamation tolerance z: a supernode absorbs its only
      * predecessor chain while the explicit zeros stay within z of the stored
      * entries (paper Sec. 2 describes node amalgamation; the exact rule is
-     * this library's).  z < 0 keeps the fundamental supernodes.
-     * Default 0.05. */
+     * this library's).  z < 0 keeps the fundamental supernodes; NaN gives
+     * SPC_INVALID_INPUT.  Default 0.05. */
     double amalg_z;
     /* Schedule cut-offs (the choice between batching small supernodes of a
      * level into one launch and giving a large one the whole device).

@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -679,6 +680,10 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
     spc_symbolic s = new (std::nothrow) spc_symbolic_s;
     if (!s) return SPC_OUT_OF_MEMORY;
     double z = opts ? opts->amalg_z : 0.05;
+    if (std::isnan(z)) {
+        delete s;
+        return SPC_INVALID_INPUT;
+    }
     spc::Tuning tu;
     if (opts) {
         // 0: default; < 0: off; > limit: invalid

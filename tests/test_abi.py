@@ -125,6 +125,13 @@ def test_cutoffs_beyond_kernel_limits_rejected(field, value):
     assert e.value.status == spchol.INVALID_INPUT
 
 
+def test_nan_amalgamation_threshold_rejected():
+    s = W.laplacian((6, 5), "5pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.Symbolic(s.colptr, s.rowidx, s.perm, float("nan"))
+    assert e.value.status == spchol.INVALID_INPUT
+
+
 def test_cutoffs_shape_the_schedule():
     """Schedule cut-offs from the analysis options: turning the one-wave
     path off empties the one-wave solve list; no persistent levels when the
