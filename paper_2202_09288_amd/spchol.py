@@ -171,6 +171,33 @@ def _dev_ptr(t, dtype_name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _values_ptr(sym: "Symbolic", t):
+    """Device pointer of a value array of sym's pattern: float64, at least
+    one entry per stored entry of the lower CSC (the library reads the first
+    nnz(lower A) of them)."""
+    p = _dev_ptr(t, "torch.float64")
+    if t.numel() < sym.info["nnz_a"]:
+        raise ValueError(f"values must hold nnz(lower A) = {sym.info['nnz_a']} entries, got {t.numel()}")
+    return p
+
+
+def _rhs_count(B, n: int, what: str = "B") -> int:
+    """Right-hand sides of a (n,) or (nrhs, n) tensor."""
+    if B.dim() not in (1, 2) or B.shape[-1] != n:
+        raise ValueError(f"{what} must have shape (n,) or (nrhs, n) with n = {n}, got {tuple(B.shape)}")
+    return 1 if B.dim() == 1 else int(B.shape[0])
+
+
+def _batch_rhs(syms, Bs, what: str = "Bs") -> int:
+    """Common right-hand-side count of one tensor per system of a batch."""
+    if len(Bs) != len(syms):
+        raise ValueError(f"{what}: expected {len(syms)} tensors (one per system), got {len(Bs)}")
+    counts = {_rhs_count(b, s.n, f"{what}[{i}]") for i, (s, b) in enumerate(zip(syms, Bs))}
+    if len(counts) > 1:
+        raise ValueError(f"{what}: every system needs the same number of right-hand sides")
+    return counts.pop() if counts else 0
+
+
 _EXPORT_ARRAYS = {"perm": (0, np.int32, "n"), "parent": (1, np.int32, "n"),
                   "colcount": (2, np.int32, "n"), "super_ptr": (3, np.int32, "ns1"),
                   "sparent": (4, np.int32, "ns"), "rptr": (5, np.int64, "ns1"),
@@ -186,6 +213,12 @@ class Symbolic:
         self._rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
         n = self._colptr.size - 1
+        if n < 0:
+            raise ValueError("colptr needs n + 1 entries")
+        if self._rowidx.size < max(int(self._colptr[-1]), 0):
+            raise ValueError("rowidx is shorter than colptr[n]")
+        if self._perm is not None and self._perm.size != n:
+            raise ValueError(f"perm must have n = {n} entries")
         opts = _Options(amalg_z=float(amalg_z))
         self.tuning = dict(tuning or {})
         for k, v in self.tuning.items():
@@ -252,7 +285,7 @@ class Factor:
         return self._h
 
     def refactorize(self, d_values, stream=None):
-        _check(_lib.spc_refactorize(self._h, _dev_ptr(d_values, "torch.float64"), _stream_ptr(stream)),
+        _check(_lib.spc_refactorize(self._h, _values_ptr(self.sym, d_values), _stream_ptr(stream)),
                "spc_refactorize")
 
     def sync(self):
@@ -304,18 +337,18 @@ class Factor:
         """In-place solve. B: float64 device tensor of shape (n,) or (nrhs, n)
         (each row one right-hand side, i.e. column-major n x nrhs)."""
         n = self.sym.n
-        nrhs = 1 if B.dim() == 1 else B.shape[0]
-        if B.shape[-1] != n:
-            raise ValueError("B must have n entries per right-hand side")
+        nrhs = _rhs_count(B, n)
         _check(_lib.spc_solve(self._h, _dev_ptr(B, "torch.float64"), nrhs, n, _stream_ptr(stream)),
                "spc_solve")
         return B
 
     def solve_refined(self, d_values, B, X, tol: float = 1e-12, maxit: int = 10, stream=None):
         n = self.sym.n
-        nrhs = 1 if B.dim() == 1 else B.shape[0]
+        nrhs = _rhs_count(B, n)
+        if tuple(X.shape) != tuple(B.shape):
+            raise ValueError(f"X must have the shape of B {tuple(B.shape)}, got {tuple(X.shape)}")
         info = _RefineInfo()
-        rc = _lib.spc_solve_refined(self._h, _dev_ptr(d_values, "torch.float64"),
+        rc = _lib.spc_solve_refined(self._h, _values_ptr(self.sym, d_values),
                                     _dev_ptr(B, "torch.float64"), _dev_ptr(X, "torch.float64"),
                                     nrhs, n, float(tol), int(maxit), _stream_ptr(stream),
                                     ctypes.byref(info))
@@ -352,7 +385,9 @@ class Batch:
         self.info = {k: int(getattr(info, k)) for k, _ in _Info._fields_}
 
     def factorize(self, d_values_list, stream=None):
-        vs = (_P * len(self.syms))(*[_dev_ptr(v, "torch.float64") for v in d_values_list])
+        if len(d_values_list) != len(self.syms):
+            raise ValueError(f"expected {len(self.syms)} value arrays (one per system), got {len(d_values_list)}")
+        vs = (_P * len(self.syms))(*[_values_ptr(s, v) for s, v in zip(self.syms, d_values_list)])
         _check(_lib.spc_batch_factorize(self._h, vs, _stream_ptr(stream)), "spc_batch_factorize")
 
     def factor(self, i: int) -> "Factor":
@@ -362,7 +397,7 @@ class Batch:
 
     def solve(self, Bs, stream=None):
         """Bs[i]: float64 device tensor (nrhs, n_i), solved in place."""
-        nrhs = 1 if Bs[0].dim() == 1 else Bs[0].shape[0]
+        nrhs = _batch_rhs(self.syms, Bs)
         ptrs = (_P * len(Bs))(*[_dev_ptr(b, "torch.float64") for b in Bs])
         lds = (_i64 * len(Bs))(*[x.n for x in self.syms])
         _check(_lib.spc_batch_solve(self._h, ptrs, nrhs, lds, _stream_ptr(stream)), "spc_batch_solve")
@@ -373,7 +408,9 @@ class Batch:
         factorize): Bs[i], Xs[i] float64 device tensors (nrhs, n_i); returns
         the status and one {iterations, converged, berr} per system."""
         count = len(self.syms)
-        nrhs = 1 if Bs[0].dim() == 1 else Bs[0].shape[0]
+        nrhs = _batch_rhs(self.syms, Bs)
+        if _batch_rhs(self.syms, Xs, "Xs") != nrhs:
+            raise ValueError("Xs must have the right-hand-side count of Bs")
         bp = (_P * count)(*[_dev_ptr(b, "torch.float64") for b in Bs])
         xp = (_P * count)(*[_dev_ptr(x, "torch.float64") for x in Xs])
         lds = (_i64 * count)(*[x.n for x in self.syms])
@@ -429,7 +466,7 @@ def analyze(colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None) -> Sy
 def factorize(sym: Symbolic, d_values, precision="fp64", stream=None) -> Factor:
     prec = _PREC[precision]
     h = _P()
-    _check(_lib.spc_factorize(sym.handle, _dev_ptr(d_values, "torch.float64"), prec,
+    _check(_lib.spc_factorize(sym.handle, _values_ptr(sym, d_values), prec,
                               _stream_ptr(stream), ctypes.byref(h)), "spc_factorize")
     return Factor(sym, h, prec)
 
@@ -437,8 +474,10 @@ def factorize(sym: Symbolic, d_values, precision="fp64", stream=None) -> Factor:
 def factorize_batch(syms, d_values_list, precision="fp64", stream=None):
     prec = _PREC[precision]
     count = len(syms)
+    if len(d_values_list) != count:
+        raise ValueError(f"expected {count} value arrays (one per system), got {len(d_values_list)}")
     hs = (_P * count)(*[s.handle for s in syms])
-    vs = (_P * count)(*[_dev_ptr(v, "torch.float64") for v in d_values_list])
+    vs = (_P * count)(*[_values_ptr(s, v) for s, v in zip(syms, d_values_list)])
     outs = (_P * count)()
     _check(_lib.spc_factorize_batch(count, hs, vs, prec, _stream_ptr(stream), outs),
            "spc_factorize_batch")

@@ -132,6 +132,18 @@ def test_nan_amalgamation_threshold_rejected():
     assert e.value.status == spchol.INVALID_INPUT
 
 
+def test_binding_checks_host_array_sizes():
+    """The binding refuses host arrays shorter than the pattern says (the
+    library reads colptr[n] row indices and n permutation entries)."""
+    s = W.laplacian((6, 5), "5pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
+    with pytest.raises(ValueError):
+        spchol.Symbolic(s.colptr, s.rowidx[:-1], s.perm)
+    with pytest.raises(ValueError):
+        spchol.Symbolic(s.colptr, s.rowidx, s.perm[:-1])
+    with pytest.raises(ValueError):
+        spchol.Symbolic(np.zeros(0, dtype=np.int64), s.rowidx)
+
+
 def test_cutoffs_shape_the_schedule():
     """Schedule cut-offs from the analysis options: turning the one-wave
     path off empties the one-wave solve list; no persistent levels when the

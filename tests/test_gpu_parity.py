@@ -643,3 +643,52 @@ def test_serving_admission_budget(torch_dev, lib):
     assert not bad, bad
     assert max(peak) <= srv.budget
     assert all(r.berr <= 1e-12 for r in out)
+
+
+def test_binding_rejects_mismatched_sizes(torch_dev, lib):
+    """The library takes bare device pointers, so the binding checks every
+    tensor's size against the analysis before a call: a value array shorter
+    than nnz(lower A), right-hand sides whose length is not n, a result
+    of another shape, and batch lists of the wrong length are refused on the
+    host (ValueError) with no launch."""
+    torch = torch_dev
+    s = grid((7, 6), nrhs=2)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm)
+    dv = torch.from_numpy(s.values).cuda()
+    print("binding size checks", flush=True)
+    with pytest.raises(ValueError):
+        lib.factorize(sym, dv[:-1])
+    F = lib.factorize(sym, dv)
+    F.sync()
+    with pytest.raises(ValueError):
+        F.refactorize(dv[:1])
+    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    with pytest.raises(ValueError):
+        F.solve(B[:, :-1].contiguous())
+    with pytest.raises(ValueError):
+        F.solve(B.reshape(1, 2, -1))
+    with pytest.raises(ValueError):
+        F.solve_refined(dv, B, torch.zeros_like(B[:1]))
+    with pytest.raises(ValueError):
+        F.solve_refined(dv[:-1], B, torch.zeros_like(B))
+    batch = lib.Batch([sym, sym])
+    with pytest.raises(ValueError):
+        batch.factorize([dv])
+    with pytest.raises(ValueError):
+        batch.factorize([dv, dv[:-1]])
+    batch.factorize([dv, dv])
+    batch.sync()
+    with pytest.raises(ValueError):
+        batch.solve([B.clone()])
+    with pytest.raises(ValueError):
+        batch.solve([B.clone(), B[:1].clone()])
+    with pytest.raises(ValueError):
+        batch.solve_refined([B, B], [torch.zeros_like(B), torch.zeros_like(B[:1])])
+    with pytest.raises(ValueError):
+        lib.factorize_batch([sym, sym], [dv])
+    # the checked calls still work after the refusals
+    X = B.clone()
+    F.solve(X)
+    Xh = X.cpu().numpy().T
+    assert oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Xh, s.B[:, :2]) <= BERR_FP64
+    batch.close()
