@@ -793,3 +793,34 @@ def test_batch512_full_size(torch_dev, lib):
           f"{max(r['iterations'] for r in out['systems'])}, worst host eta={eta:.3e}", flush=True)
     assert eta <= BERR_FP64
     batch.close()
+
+
+@pytest.mark.timeout(300)
+def test_serving_full_size_mix(torch_dev, lib):
+    """Serving at the full sizes of its mix (batch-mix systems up to 40k
+    unknowns and 50^3 7-point grids, 8 RHS each, 30% re-solves of resident
+    factors), four requests overlapping on the device: every request ends
+    ok, and its solution, checked on the host against the values it was
+    factored with, has a backward error below 1e-12.  Seed 6 is taken
+    because its first 32 requests hold three 50^3 factor requests."""
+    from paper_2202_09288_amd import serving as SV
+    print("serving full-size mix: generating", flush=True)
+    reqs = SV.make_requests(32, 200.0, 6)
+    big = [r.rid for r in reqs if r.kind == "factor" and r.system.n == 50 ** 3]
+    assert len(big) >= 3, big
+    srv = SV.Server(slots=4, keep_solutions=True)
+    print("serving full-size mix: running", flush=True)
+    out = srv.run(reqs, time_scale=1.0)
+    srv.close()
+    systems = {r.rid: r.system for r in reqs if r.kind == "factor"}
+    scales = {r.rid: r.values_scale for r in reqs if r.kind == "factor"}
+    worst = 0.0
+    for r in out:
+        assert r.status == "ok" and r.berr <= 1e-12, (r.rid, r.kind, r.status, r.berr)
+        key = r.rid if r.kind == "factor" else r.target
+        s, sc = systems[key], scales[key]
+        Bh = SV.Server.rhs(r, s).T if r.kind == "resolve" else s.B[:, :r.nrhs]
+        worst = max(worst, oracle.backward_error(s.n, s.colptr, s.rowidx, s.values * sc, r.X, Bh))
+    print(f"serving full-size mix: {len(out)} requests, worst host eta={worst:.3e}", flush=True)
+    assert len(out) == len(reqs)
+    assert worst <= 1e-12
