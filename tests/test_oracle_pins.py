@@ -306,3 +306,50 @@ def test_subtree_factor_matches_full():
             while a != -1 and a < root:
                 a = S.sparent[a]
             assert a == root
+
+
+def test_backward_error_hand_values():
+    """Normwise backward error in the infinity norm on cases worked by hand:
+    A = [2], b = [3], x = [1]: |3 - 2| / (2 * 1 + 3) = 1/5.  A = [[2, -1],
+    [-1, 2]] (||A|| = 3), b = [1, 1]: x = [1, 1] is exact (0); x = [1, 0]
+    leaves r = [-1, 2], so 2 / (3 * 1 + 1) = 1/2.  Several right-hand sides
+    take the largest."""
+    one = (np.array([0, 1], np.int64), np.array([0], np.int32), np.array([2.0]))
+    assert oracle.backward_error(1, *one, np.array([1.0]), np.array([3.0])) == pytest.approx(0.2, abs=1e-16)
+    cp, ri, v = np.array([0, 2, 3], np.int64), np.array([0, 1, 1], np.int32), np.array([2.0, -1.0, 2.0])
+    b = np.array([1.0, 1.0])
+    assert oracle.backward_error(2, cp, ri, v, np.array([1.0, 1.0]), b) == 0.0
+    assert oracle.backward_error(2, cp, ri, v, np.array([1.0, 0.0]), b) == pytest.approx(0.5, abs=1e-16)
+    X = np.column_stack([[1.0, 1.0], [1.0, 0.0]])
+    B = np.column_stack([b, b])
+    assert oracle.backward_error(2, cp, ri, v, X, B) == pytest.approx(0.5, abs=1e-16)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_backward_error_is_the_smallest_consistent_perturbation(seed):
+    """Rigal-Gaches: eta is attained (A + dA) x = b + db with ||dA|| = eta
+    ||A|| and ||db|| = eta ||b||, through dA = c r z^T, db = -d r, with z
+    picking the largest entry of x; and no consistent perturbation is
+    smaller: for (A + E) x = b + f, max(||E||/||A||, ||f||/||b||) >= eta."""
+    s = W.laplacian((6, 5), "5pt", 77, seed, unit=False, shift=1e-2, nrhs=1)
+    A = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values).toarray()
+    b = s.B[:, 0]
+    rng = np.random.default_rng(seed)
+    x = np.linalg.solve(A, b) * (1.0 + 1e-3 * rng.standard_normal(s.n))
+    eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, x, b)
+    nA, nx, nb = np.abs(A).sum(axis=1).max(), np.abs(x).max(), np.abs(b).max()
+    r = b - A @ x
+    k = int(np.argmax(np.abs(x)))
+    z = np.zeros(s.n)
+    z[k] = np.sign(x[k])
+    den = nA * nx + nb
+    dA = (nA / den) * np.outer(r, z)
+    db = -(nb / den) * r
+    assert np.max(np.abs((A + dA) @ x - (b + db))) <= 1e-13 * nA * nx
+    assert np.abs(dA).sum(axis=1).max() == pytest.approx(eta * nA, rel=1e-12)
+    assert np.abs(db).max() == pytest.approx(eta * nb, rel=1e-12)
+    for _ in range(20):
+        E = rng.standard_normal((s.n, s.n)) * 1e-4 * rng.random()
+        f = (A + E) @ x - b
+        eps = max(np.abs(E).sum(axis=1).max() / nA, np.abs(f).max() / nb)
+        assert eps >= eta * (1 - 1e-12)
