@@ -824,3 +824,32 @@ def test_serving_full_size_mix(torch_dev, lib):
     print(f"serving full-size mix: {len(out)} requests, worst host eta={worst:.3e}", flush=True)
     assert len(out) == len(reqs)
     assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims", [(40, 37), (12, 11, 10), (16, 15, 14)])
+def test_factor_componentwise_backward_error(torch_dev, lib, dims, precision):
+    """The computed factor of either precision, independently of the oracle's
+    numbers: Cholesky's componentwise backward error bound (Demmel; Higham,
+    Accuracy and Stability, Thm. 10.3) with k the most nonzeros in a row of
+    L, plus the rounding of A to the working precision:
+    |P^T A P - L L^T| <= gamma_{k+2} (|L| |L^T| + |P^T A P|),
+    gamma_j = j u / (1 - j u), u = 2^-53 or 2^-24 (measured worst entry:
+    about 0.02 of the bound)."""
+    torch = torch_dev
+    s = grid(dims, seed=3)
+    print(f"componentwise bound {dims} {precision}", flush=True)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    F = lib.factorize(sym, torch.from_numpy(s.values).cuda(), precision)
+    F.sync()
+    L = np.tril(S.to_dense_L(F.export()))
+    F.close()
+    A = oracle.full_csr(s.n, s.colptr, s.rowidx, s.values).toarray()
+    Ah = A[np.ix_(S.perm, S.perm)]
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    k = int((L != 0).sum(axis=1).max()) + 2
+    gamma = k * u / (1 - k * u)
+    E = np.abs(Ah - L @ L.T)
+    bound = gamma * (np.abs(L) @ np.abs(L).T + np.abs(Ah))
+    assert np.all(E <= bound), float((E / np.where(bound > 0, bound, np.inf)).max())
