@@ -509,6 +509,7 @@ struct RefineTarget {
     const int32_t *ci = nullptr;
     const double *values = nullptr;
     int64_t n = 0;
+    int64_t nnz = 0;  // entries of the full-A CSR
     const int32_t *seg = nullptr;  // row -> system, or null (one system)
     int nseg = 1;
 };
@@ -575,7 +576,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         return SPC_OK;
     };
     for (;;) {
-        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, q, n, st);  // T = b - A x
+        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, T.nnz, q, n, st);  // T = b - A x
         spc::launch_zero<unsigned long long>(umax, 2 * K, st);
         colmax(Tv, umax);
         colmax(Xw, umax + K);
@@ -626,7 +627,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
             for (int64_t j = 0; j < K; ++j) rho[j] = hdot[j];
             cg_started = true;
         }
-        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Pv, nullptr, Qv, n, q, n, st);  // q = A p
+        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Pv, nullptr, Qv, n, T.nnz, q, n, st);  // q = A p
         if ((rc = dot(Pv, Qv))) return rc;
         for (int64_t j = 0; j < K; ++j) {
             const double a = (!frozen[j] && hdot[j] > 0.0 && std::isfinite(rho[j] / hdot[j])) ? rho[j] / hdot[j] : 0.0;
@@ -887,6 +888,7 @@ int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, d
         T.ci = f->sym->d_csr_col;
         T.values = d_values;
         T.n = n;
+        T.nnz = f->sym->S.csr_ptr.empty() ? 0 : f->sym->S.csr_ptr.back();
         rc = refine_chunk(T, d_B + (int64_t)q0 * ld, d_X + (int64_t)q0 * ld, q, ld, tol, maxit, st, &res);
         if (rc) return rc;
         worst = std::max(worst, res.iterations);
@@ -1204,6 +1206,7 @@ int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const
     T.ci = b->merged->d_csr_col;
     T.values = b->vbuf;
     T.n = n;
+    T.nnz = b->merged->S.csr_ptr.empty() ? 0 : b->merged->S.csr_ptr.back();
     T.seg = b->rowseg;
     T.nseg = cnt;
     std::vector<RefineResult> res(cnt);

@@ -1797,23 +1797,36 @@ __global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy
 // values (valmap), so refinement always uses the values given.  Vectors are
 // n x nrhs column-major with leading dimension ld.
 // ---------------------------------------------------------------------------
-// Y = B - A X (beta = -1, with B) or Y = A X (B == nullptr)
-__global__ void k_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap,
-                       const double *values, const double *X, const double *B, double *Y, int64_t n,
-                       int nrhs, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Y = B - A X (beta = -1, with B) or Y = A X (B == nullptr).  LPR
+// consecutive lanes share a row (LPR a power of two <= 64, so a group never
+// straddles a wave): lane j of the group takes entries j, j + LPR, ... of
+// the row, so a group's index and value loads are contiguous, and the
+// group's partial sums meet by shuffles.
+template <int LPR>
+__global__ __launch_bounds__(256) void k_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap,
+                                              const double *values, const double *X, const double *B, double *Y,
+                                              int64_t n, int nrhs, int64_t ld) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int j = threadIdx.x % LPR;
     double acc[kMaxRhs];
 #pragma unroll
     for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const double a = values[valmap[e]];
-        const int64_t c = colidx[e];
+    if (i < n)
+        for (int64_t e = rowptr[i] + j; e < rowptr[i + 1]; e += LPR) {
+            const double a = values[valmap[e]];
+            const int64_t c = colidx[e];
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q)
-            if (q < nrhs) acc[q] += a * X[c + q * ld];
-    }
-    for (int q = 0; q < nrhs; ++q) Y[i + q * ld] = B ? B[i + q * ld] - acc[q] : acc[q];
+            for (int q = 0; q < kMaxRhs; ++q)
+                if (q < nrhs) acc[q] += a * X[c + q * ld];
+        }
+    // every lane takes part in the shuffles (nrhs is the same for all)
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+        if (q < nrhs)
+#pragma unroll
+            for (int off = LPR / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    if (i < n && j == 0)
+        for (int q = 0; q < nrhs; ++q) Y[i + q * ld] = B ? B[i + q * ld] - acc[q] : acc[q];
 }
 
 // out = max_i sum_j |a_ij| (as the bit pattern of a non-negative double)
@@ -1827,14 +1840,20 @@ __global__ void k_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sum));
 }
 
-// out[q] = max_i |V[i, q]| (bit patterns), grid.y = q
-__global__ void k_colmax(const double *V, int64_t n, int64_t ld, unsigned long long *out) {
+// out[q] = max_i |V[i, q]| (bit patterns), grid.y = q, 256 threads: one
+// atomic per workgroup (same-address atomics serialize at L2)
+__global__ __launch_bounds__(256) void k_colmax(const double *V, int64_t n, int64_t ld, unsigned long long *out) {
+    __shared__ double wmax[4];
     const int q = blockIdx.y;
     double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         mx = fmax(mx, fabs(V[i + q * ld]));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&out[q], (unsigned long long)__double_as_longlong(mx));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(&out[q], (unsigned long long)__double_as_longlong(fmax(fmax(wmax[0], wmax[1]),
+                                                                           fmax(wmax[2], wmax[3]))));
 }
 
 // out[q] += sum_i U[i, q] V[i, q], grid.y = q
@@ -2124,10 +2143,23 @@ void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
 }
 
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
-                 const double *X, const double *B, double *Y, int64_t n, int nrhs, int64_t ld, hipStream_t st) {
+                 const double *X, const double *B, double *Y, int64_t n, int64_t nnz, int nrhs, int64_t ld,
+                 hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_spmv, dim3(grid1(n, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values, X, B, Y, n,
-                       nrhs, ld);
+    // lanes per row: the power of two (4..32) at or above the mean row length
+    const int64_t avg = (nnz + n - 1) / n;
+    if (avg <= 4)
+        hipLaunchKernelGGL(k_spmv<4>, dim3(grid1(n * 4, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values, X,
+                           B, Y, n, nrhs, ld);
+    else if (avg <= 8)
+        hipLaunchKernelGGL(k_spmv<8>, dim3(grid1(n * 8, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values, X,
+                           B, Y, n, nrhs, ld);
+    else if (avg <= 16)
+        hipLaunchKernelGGL(k_spmv<16>, dim3(grid1(n * 16, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values,
+                           X, B, Y, n, nrhs, ld);
+    else
+        hipLaunchKernelGGL(k_spmv<32>, dim3(grid1(n * 32, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values,
+                           X, B, Y, n, nrhs, ld);
 }
 void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
                        unsigned long long *out, hipStream_t st) {
@@ -2140,7 +2172,7 @@ static unsigned red_grid(int64_t n) {
 }
 void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned long long *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL(k_colmax, dim3(red_grid(n), nrhs), dim3(256), 0, st, V, n, ld, out);
+    hipLaunchKernelGGL(k_colmax, dim3(std::min(red_grid(n), 128u), nrhs), dim3(256), 0, st, V, n, ld, out);
 }
 void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
