@@ -518,7 +518,7 @@ struct RefineTarget {
 // solve; then each step computes r = b - A x in FP64 and the backward error
 //   eta_k = ||r_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf)
 // per system and column.  Classical refinement (x += solve(r)) runs while
-// the largest eta at least halves every two steps; after that, conjugate
+// each step cuts the largest eta at least tenfold; after that, conjugate
 // gradients in FP64 preconditioned by the factor (M^{-1} = solve) continue
 // from the current x, with alpha and beta per system and column (the
 // preconditioner is block diagonal over the systems, so the iterations of
@@ -607,7 +607,12 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         eta_hist.push_back(eta);
         if (eta <= tol || it >= maxit) break;
         const size_t h = eta_hist.size();
-        if (!cg && h >= 3 && !(eta_hist[h - 1] <= 0.5 * eta_hist[h - 3])) cg = true;
+        // A classical step contracts eta by about the spectral radius rho of
+        // I - M^{-1} A.  Once a step contracts it by less than 10x, CG takes
+        // over: its rate bound (sqrt(k) - 1) / (sqrt(k) + 1), with
+        // k <= (1 + rho) / (1 - rho), is then well below rho, which pays for
+        // its second SpMV and its dot products.
+        if (!cg && h >= 2 && !(eta_hist[h - 1] <= 0.1 * eta_hist[h - 2])) cg = true;
         ++it;
         if (!cg) {
             spc::launch_copy_cols(Tv, n, Zv, n, n, q, st);
