@@ -1856,14 +1856,19 @@ __global__ __launch_bounds__(256) void k_colmax(const double *V, int64_t n, int6
                                                                            fmax(wmax[2], wmax[3]))));
 }
 
-// out[q] += sum_i U[i, q] V[i, q], grid.y = q
-__global__ void k_coldot(const double *U, const double *V, int64_t n, int64_t ld, double *out) {
+// out[q] += sum_i U[i, q] V[i, q], grid.y = q, 256 threads: one atomic per
+// workgroup, as in k_colmax
+__global__ __launch_bounds__(256) void k_coldot(const double *U, const double *V, int64_t n, int64_t ld,
+                                                double *out) {
+    __shared__ double wsum[4];
     const int q = blockIdx.y;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         acc += U[i + q * ld] * V[i + q * ld];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&out[q], acc);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&out[q], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
 }
 
 // Y[:, q] = a_q X[:, q] + b_q Y[:, q]; a_q = a[q] (device) or a0 when a is
@@ -2176,7 +2181,7 @@ void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned lo
 }
 void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL(k_coldot, dim3(red_grid(n), nrhs), dim3(256), 0, st, U, V, n, ld, out);
+    hipLaunchKernelGGL(k_coldot, dim3(std::min(red_grid(n), 128u), nrhs), dim3(256), 0, st, U, V, n, ld, out);
 }
 void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
                   int nrhs, int64_t ld, hipStream_t st) {
