@@ -1926,35 +1926,78 @@ __global__ void k_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, c
     }
 }
 
-__global__ void k_seg_colmax(const double *V, const int32_t *seg, int64_t n, int64_t ld, int nseg,
-                             unsigned long long *out) {
+// The segmented column reductions give each workgroup of 256 threads
+// kSegRows consecutive rows.  A system's rows are contiguous, so when the
+// first and last row of the chunk belong to one system the whole chunk does:
+// one atomic per workgroup.  A chunk that spans systems falls back to one
+// atomic per wave (or per row where a wave spans systems).
+constexpr int kSegRows = 256 * 8;
+
+__global__ __launch_bounds__(256) void k_seg_colmax(const double *V, const int32_t *seg, int64_t n, int64_t ld,
+                                                    int nseg, unsigned long long *out) {
+    __shared__ double wm[4];
     const int q = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ic = i < n ? i : n - 1;
-    const int s = seg[ic];
-    double mx = i < n ? fabs(V[ic + q * ld]) : 0.0;
-    unsigned long long *o = out + (int64_t)q * nseg + s;
-    if (wave_in_one_segment(s)) {
+    const int64_t base = (int64_t)blockIdx.x * kSegRows;
+    const int64_t last = (base + kSegRows < n ? base + kSegRows : n) - 1;
+    if (seg[base] == seg[last]) {  // the same for every thread of the workgroup
+        double mx = 0.0;
+        for (int r = 0; r < kSegRows / 256; ++r) {
+            const int64_t i = base + r * 256 + threadIdx.x;
+            if (i < n) mx = fmax(mx, fabs(V[i + q * ld]));
+        }
         for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(o, (unsigned long long)__double_as_longlong(mx));
-    } else if (i < n) {
-        atomicMax(o, (unsigned long long)__double_as_longlong(mx));
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(out + (int64_t)q * nseg + seg[base],
+                      (unsigned long long)__double_as_longlong(fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]))));
+        return;
+    }
+    for (int r = 0; r < kSegRows / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+        const int s = seg[ic];
+        double mx = i < n ? fabs(V[ic + q * ld]) : 0.0;
+        unsigned long long *o = out + (int64_t)q * nseg + s;
+        if (wave_in_one_segment(s)) {
+            for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+            if ((threadIdx.x & 63) == 0) atomicMax(o, (unsigned long long)__double_as_longlong(mx));
+        } else if (i < n) {
+            atomicMax(o, (unsigned long long)__double_as_longlong(mx));
+        }
     }
 }
 
-__global__ void k_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n, int64_t ld, int nseg,
-                             double *out) {
+__global__ __launch_bounds__(256) void k_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n,
+                                                    int64_t ld, int nseg, double *out) {
+    __shared__ double ws[4];
     const int q = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ic = i < n ? i : n - 1;
-    const int s = seg[ic];
-    double acc = i < n ? U[ic + q * ld] * V[ic + q * ld] : 0.0;
-    double *o = out + (int64_t)q * nseg + s;
-    if (wave_in_one_segment(s)) {
+    const int64_t base = (int64_t)blockIdx.x * kSegRows;
+    const int64_t last = (base + kSegRows < n ? base + kSegRows : n) - 1;
+    if (seg[base] == seg[last]) {  // the same for every thread of the workgroup
+        double acc = 0.0;
+        for (int r = 0; r < kSegRows / 256; ++r) {
+            const int64_t i = base + r * 256 + threadIdx.x;
+            if (i < n) acc += U[i + q * ld] * V[i + q * ld];
+        }
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if ((threadIdx.x & 63) == 0) atomicAdd(o, acc);
-    } else if (i < n) {
-        atomicAdd(o, acc);
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(out + (int64_t)q * nseg + seg[base], (ws[0] + ws[1]) + (ws[2] + ws[3]));
+        return;
+    }
+    for (int r = 0; r < kSegRows / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+        const int s = seg[ic];
+        double acc = i < n ? U[ic + q * ld] * V[ic + q * ld] : 0.0;
+        double *o = out + (int64_t)q * nseg + s;
+        if (wave_in_one_segment(s)) {
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if ((threadIdx.x & 63) == 0) atomicAdd(o, acc);
+        } else if (i < n) {
+            atomicAdd(o, acc);
+        }
     }
 }
 
@@ -2197,12 +2240,12 @@ void launch_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const d
 void launch_seg_colmax(const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg,
                        unsigned long long *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL(k_seg_colmax, dim3(grid1(n, 256), nrhs), dim3(256), 0, st, V, seg, n, ld, nseg, out);
+    hipLaunchKernelGGL(k_seg_colmax, dim3(grid1(n, kSegRows), nrhs), dim3(256), 0, st, V, seg, n, ld, nseg, out);
 }
 void launch_seg_coldot(const double *U, const double *V, const int32_t *seg, int64_t n, int nrhs, int64_t ld,
                        int nseg, double *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL(k_seg_coldot, dim3(grid1(n, 256), nrhs), dim3(256), 0, st, U, V, seg, n, ld, nseg, out);
+    hipLaunchKernelGGL(k_seg_coldot, dim3(grid1(n, kSegRows), nrhs), dim3(256), 0, st, U, V, seg, n, ld, nseg, out);
 }
 void launch_seg_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y,
                       const int32_t *seg, int64_t n, int nrhs, int64_t ld, int nseg, hipStream_t st) {
