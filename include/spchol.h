@@ -263,8 +263,23 @@ int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const
 
 /* Wait for the factor's work on its stream; SPC_NOT_SPD if a pivot failed,
  * with *bad_pivot (nullable) set to the permuted column of the first
- * failing pivot found, else -1. */
+ * failing pivot found, else -1.  SPC_DEVICE_ERROR (checked first) if a
+ * bounded wait of one workgroup on another gave up during the last
+ * factorization or any solve since (see spc_factor_set_wait_limit): the
+ * factor and those solutions are then unreliable; the condition stays until
+ * the factor is factored again.  spc_solve_refined, spc_batch_solve,
+ * spc_batch_solve_refined and spc_batch_sync report it the same way. */
 int spc_sync(spc_factor f, int64_t *bad_pivot);
+
+/* Polls before a bounded wait of one workgroup on another gives up (the
+ * hand-over inside a trailing launch, the persistent solve sweeps).  Every
+ * such wait is bounded so that every wave exits whatever happens; one that
+ * gives up sets the factor's device-error word, which spc_sync reports as
+ * SPC_DEVICE_ERROR.  Default about a second of polls (2^20).  0 makes every
+ * wait give up at once: the kernels still run to their end and the results
+ * are garbage, which lets a test drive the error path from the host.
+ * SPC_INVALID_INPUT for polls < 0 or a batch view. */
+int spc_factor_set_wait_limit(spc_factor f, int32_t polls);
 
 /* Copy the panels to host as double (lptr layout of spc_symbolic_export;
  * strict upper triangles of the diagonal blocks are zeroed). Synchronous. */

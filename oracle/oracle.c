@@ -19,7 +19,10 @@
  *     supernode is built from A, receives the SYRK/GEMM update of every
  *     earlier supernode that touches its columns, then is factored by a
  *     column Cholesky of the diagonal block and the triangular solve of the
- *     rows below (POTRF + TRSM).
+ *     rows below (POTRF + TRSM).  orc_factor_parallel runs the same steps
+ *     with whole supernodes per host thread, level by level of the
+ *     elimination tree (the one-task-per-supernode scheme of Sec. 3-4), with
+ *     a bit-identical result.
  *   - solve (Sec. 1 and Sec. 2): L y = b then L^T x = y, supernode by
  *     supernode, with the permutation applied at entry and exit.
  *
@@ -31,6 +34,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#define omp_get_num_threads_or_one() omp_get_num_threads()
+#else
+#define omp_get_num_threads_or_one() 1
+#endif
 
 typedef struct orc_sym {
     int64_t n;
@@ -459,83 +468,89 @@ int orc_get(const orc_sym *S, int which, void *dst) {
 }
 
 /*
- * Left-looking supernodal factorization of supernodes s_lo..s_hi (ascending).
- * Lx receives the column-major panels; Lr is a row-major mirror of the same
+ * Left-looking step for one supernode s (Sec. 3, Listing 1): build it from A,
+ * apply the update of every earlier supernode in U_s, then POTRF + TRSM.
+ * Lx receives the column-major panel; Lr is a row-major mirror of the same
  * panels (entry (i, c) of supernode s at lptr[s] + i*w_s + c) so that every
  * inner product below walks contiguous memory.  The mirror changes no
- * arithmetic: each sum still runs over k in ascending order.
+ * arithmetic: each sum still runs over k in ascending order.  pos is n+1
+ * ints of scratch.  Returns 0, or -2 with *bad_col set.
  */
+static int factor_one(const orc_sym *S, const double *values, double *Lx, double *Lr, int32_t s,
+                      int32_t *pos, int64_t *bad_col) {
+    int32_t f = S->super_ptr[s], l = S->super_ptr[s + 1] - 1;
+    int64_t w = l - f + 1, m = S->rptr[s + 1] - S->rptr[s];
+    const int32_t *R = S->rows + S->rptr[s];
+    double *B = Lr + S->lptr[s]; /* row-major m x w */
+    for (int64_t k = 0; k < m; ++k) pos[R[k]] = (int32_t)k;
+    /* construction of the supernode from A */
+    memset(B, 0, sizeof(double) * (size_t)(m * w));
+    for (int32_t j = f; j <= l; ++j)
+        for (int64_t k = S->Ap[j]; k < S->Ap[j + 1]; ++k)
+            B[(int64_t)pos[S->Ai[k]] * w + (j - f)] = values[S->Amap[k]];
+    /* updates from every earlier supernode d that touches cols(s):
+     * B[rel(R_d[r]), rel(R_d[c])] -= sum_k L_d[r,k] L_d[c,k],
+     * for c in [i0, i1) (the rows of R_d inside cols(s)) and r >= c */
+    for (int64_t u = S->uptr[s]; u < S->uptr[s + 1]; ++u) {
+        int32_t d = S->ulist[u];
+        int64_t md = S->rptr[d + 1] - S->rptr[d];
+        int64_t wd = S->super_ptr[d + 1] - S->super_ptr[d];
+        const int32_t *Rd = S->rows + S->rptr[d];
+        const double *Ld = Lr + S->lptr[d];
+        int64_t i0 = 0, i1;
+        while (i0 < md && Rd[i0] < f) ++i0;
+        i1 = i0;
+        while (i1 < md && Rd[i1] <= l) ++i1;
+        for (int64_t c = i0; c < i1; ++c) {
+            int64_t col = Rd[c] - f;
+            const double *lc = Ld + c * wd;
+            for (int64_t r = c; r < md; ++r) {
+                const double *lr = Ld + r * wd;
+                double sum = 0.0;
+                for (int64_t k = 0; k < wd; ++k) sum += lr[k] * lc[k];
+                B[(int64_t)pos[Rd[r]] * w + col] -= sum;
+            }
+        }
+    }
+    /* column Cholesky of the diagonal block (POTRF) and of the rows
+     * below it (TRSM by forward substitution):
+     *   d    = b_jj - sum_{k<j} l_jk^2,  NOT_SPD unless d > 0 and finite
+     *   l_jj = sqrt(d),  l_ij = (b_ij - sum_{k<j} l_ik l_jk) / l_jj */
+    for (int64_t j = 0; j < w; ++j) {
+        const double *lj = B + j * w;
+        double d = lj[j];
+        for (int64_t k = 0; k < j; ++k) d -= lj[k] * lj[k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (bad_col) *bad_col = f + j;
+            return -2;
+        }
+        double ljj = sqrt(d);
+        B[j * w + j] = ljj;
+        for (int64_t i = j + 1; i < m; ++i) {
+            double *li = B + i * w;
+            double v = li[j];
+            for (int64_t k = 0; k < j; ++k) v -= li[k] * lj[k];
+            li[j] = v / ljj;
+        }
+    }
+    /* strict upper triangle of the diagonal block is not part of L */
+    for (int64_t i = 0; i < w; ++i)
+        for (int64_t c = i + 1; c < w; ++c) B[i * w + c] = 0.0;
+    double *C = Lx + S->lptr[s];
+    for (int64_t c = 0; c < w; ++c)
+        for (int64_t i = 0; i < m; ++i) C[c * m + i] = B[i * w + c];
+    return 0;
+}
+
+/* The left-looking loop over supernodes s_lo..s_hi in ascending order. */
 static int factor_range(const orc_sym *S, const double *values, double *Lx, double *Lr,
                         int32_t s_lo, int32_t s_hi, int64_t *bad_col) {
-    int64_t n = S->n;
-    int32_t *pos = xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *pos = xmalloc(sizeof(int32_t) * (size_t)(S->n + 1));
+    int rc = 0;
     if (bad_col) *bad_col = -1;
-    for (int32_t s = s_lo; s <= s_hi; ++s) {
-        int32_t f = S->super_ptr[s], l = S->super_ptr[s + 1] - 1;
-        int64_t w = l - f + 1, m = S->rptr[s + 1] - S->rptr[s];
-        const int32_t *R = S->rows + S->rptr[s];
-        double *B = Lr + S->lptr[s]; /* row-major m x w */
-        for (int64_t k = 0; k < m; ++k) pos[R[k]] = (int32_t)k;
-        /* construction of the supernode from A */
-        memset(B, 0, sizeof(double) * (size_t)(m * w));
-        for (int32_t j = f; j <= l; ++j)
-            for (int64_t k = S->Ap[j]; k < S->Ap[j + 1]; ++k)
-                B[(int64_t)pos[S->Ai[k]] * w + (j - f)] = values[S->Amap[k]];
-        /* updates from every earlier supernode d that touches cols(s):
-         * B[rel(R_d[r]), rel(R_d[c])] -= sum_k L_d[r,k] L_d[c,k],
-         * for c in [i0, i1) (the rows of R_d inside cols(s)) and r >= c */
-        for (int64_t u = S->uptr[s]; u < S->uptr[s + 1]; ++u) {
-            int32_t d = S->ulist[u];
-            int64_t md = S->rptr[d + 1] - S->rptr[d];
-            int64_t wd = S->super_ptr[d + 1] - S->super_ptr[d];
-            const int32_t *Rd = S->rows + S->rptr[d];
-            const double *Ld = Lr + S->lptr[d];
-            int64_t i0 = 0, i1;
-            while (i0 < md && Rd[i0] < f) ++i0;
-            i1 = i0;
-            while (i1 < md && Rd[i1] <= l) ++i1;
-            for (int64_t c = i0; c < i1; ++c) {
-                int64_t col = Rd[c] - f;
-                const double *lc = Ld + c * wd;
-                for (int64_t r = c; r < md; ++r) {
-                    const double *lr = Ld + r * wd;
-                    double sum = 0.0;
-                    for (int64_t k = 0; k < wd; ++k) sum += lr[k] * lc[k];
-                    B[(int64_t)pos[Rd[r]] * w + col] -= sum;
-                }
-            }
-        }
-        /* column Cholesky of the diagonal block (POTRF) and of the rows
-         * below it (TRSM by forward substitution):
-         *   d    = b_jj - sum_{k<j} l_jk^2,  NOT_SPD unless d > 0 and finite
-         *   l_jj = sqrt(d),  l_ij = (b_ij - sum_{k<j} l_ik l_jk) / l_jj */
-        for (int64_t j = 0; j < w; ++j) {
-            const double *lj = B + j * w;
-            double d = lj[j];
-            for (int64_t k = 0; k < j; ++k) d -= lj[k] * lj[k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                if (bad_col) *bad_col = f + j;
-                free(pos);
-                return -2;
-            }
-            double ljj = sqrt(d);
-            B[j * w + j] = ljj;
-            for (int64_t i = j + 1; i < m; ++i) {
-                double *li = B + i * w;
-                double v = li[j];
-                for (int64_t k = 0; k < j; ++k) v -= li[k] * lj[k];
-                li[j] = v / ljj;
-            }
-        }
-        /* strict upper triangle of the diagonal block is not part of L */
-        for (int64_t i = 0; i < w; ++i)
-            for (int64_t c = i + 1; c < w; ++c) B[i * w + c] = 0.0;
-        double *C = Lx + S->lptr[s];
-        for (int64_t c = 0; c < w; ++c)
-            for (int64_t i = 0; i < m; ++i) C[c * m + i] = B[i * w + c];
-    }
+    for (int32_t s = s_lo; s <= s_hi && rc == 0; ++s) rc = factor_one(S, values, Lx, Lr, s, pos, bad_col);
     free(pos);
-    return 0;
+    return rc;
 }
 
 /*
@@ -552,6 +567,76 @@ int orc_factor(const orc_sym *S, const double *values, double *Lx, int64_t *bad_
     double *Lr = xmalloc(sizeof(double) * (size_t)(S->lptr[S->nsuper] + 1));
     int rc = factor_range(S, values, Lx, Lr, 0, S->nsuper - 1, bad_col);
     free(Lr);
+    return rc;
+}
+
+/*
+ * orc_factor_parallel: the same factorization on `nthreads` host threads
+ * (OpenMP), each thread owning whole supernodes, in the order of the
+ * elimination tree: level by level (a supernode's level exceeds those of all
+ * its descendants, which are all the supernodes its updates come from, Sec. 3
+ * and Fig. 1).  This is the paper's one-task-per-supernode scheme without
+ * nested tasks (NONESTED, Sec. 3-4).  Every supernode runs exactly the steps
+ * of the sequential loop on the same inputs, so the result is bit-identical
+ * to orc_factor for any thread count.  A supernode with a failed descendant
+ * is skipped; the failure reported is the one of the lowest supernode, the
+ * one the sequential loop stops at.  Returns the thread count used in
+ * *used (nullable).
+ */
+int orc_factor_parallel(const orc_sym *S, const double *values, double *Lx, int64_t *bad_col, int nthreads,
+                        int *used) {
+    int32_t ns = S->nsuper;
+    double *Lr = xmalloc(sizeof(double) * (size_t)(S->lptr[ns] + 1));
+    /* supernodes grouped by level */
+    int32_t nl = S->nlevels;
+    int64_t *lptr = xcalloc((size_t)nl + 2, sizeof(int64_t));
+    int32_t *bylev = xmalloc(sizeof(int32_t) * (size_t)(ns + 1));
+    for (int32_t s = 0; s < ns; ++s) lptr[S->level[s] + 1]++;
+    for (int32_t v = 0; v < nl; ++v) lptr[v + 1] += lptr[v];
+    {
+        int64_t *fill = xmalloc(sizeof(int64_t) * (size_t)(nl + 1));
+        for (int32_t v = 0; v <= nl; ++v) fill[v] = lptr[v];
+        for (int32_t s = 0; s < ns; ++s) bylev[fill[S->level[s]]++] = s;
+        free(fill);
+    }
+    /* failed[s]: s or one of its descendants failed */
+    char *failed = xcalloc((size_t)ns + 1, 1);
+    int64_t *badc = xmalloc(sizeof(int64_t) * (size_t)(ns + 1));
+    int nt = nthreads > 0 ? nthreads : 1, got = 1;
+    for (int32_t v = 0; v < nl; ++v) {
+#pragma omp parallel num_threads(nt)
+        {
+#pragma omp single
+            got = omp_get_num_threads_or_one();
+            int32_t *pos = xmalloc(sizeof(int32_t) * (size_t)(S->n + 1));
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t q = lptr[v]; q < lptr[v + 1]; ++q) {
+                int32_t s = bylev[q];
+                if (failed[s]) continue;
+                int64_t bc = -1;
+                if (factor_one(S, values, Lx, Lr, s, pos, &bc) != 0) {
+                    failed[s] = 2; /* the supernode itself failed */
+                    badc[s] = bc;
+                }
+            }
+            free(pos);
+        }
+        /* a failure makes every ancestor skip */
+        for (int64_t q = lptr[v]; q < lptr[v + 1]; ++q) {
+            int32_t s = bylev[q], p = S->sparent[s];
+            if (failed[s] && p >= 0 && !failed[p]) failed[p] = 1;
+        }
+    }
+    int rc = 0;
+    if (bad_col) *bad_col = -1;
+    for (int32_t s = 0; s < ns; ++s)
+        if (failed[s] == 2) {
+            rc = -2;
+            if (bad_col) *bad_col = badc[s];
+            break;
+        }
+    if (used) *used = got;
+    free(failed); free(badc); free(bylev); free(lptr); free(Lr);
     return rc;
 }
 

@@ -53,8 +53,13 @@ struct spc_factor_s {
     void *Lx = nullptr;
     void *Linv = nullptr;       // inverses of the diagonal blocks (factor precision)
     unsigned long long *status = nullptr;
+    // device-error word: set by a bounded wait on another workgroup that gave
+    // up (factor hand-over, persistent solve sweeps), cleared by every
+    // factorization; after the status words in their allocation
+    int32_t *deverr = nullptr;
+    int32_t spin = spc::kSpinDefault;  // polls before such a wait gives up
     // hand-over flags of the trailing launches, one per 16-column panel of
-    // each column block (in the status allocation, after the status words)
+    // each column block (in the status allocation, after the error word)
     int32_t *hflags = nullptr;
     int nflags = 0;
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
@@ -124,6 +129,26 @@ int record_error(hipError_t e, const char *what, int line) {
     } while (0)
 
 bool sym_ok(spc_symbolic s) { return s && s->magic == kSymMagic; }
+
+// The factor whose storage, status words and device-error word a handle
+// uses: itself, or for a view into a batch, the batch's merged factor.
+spc_factor_s *owner_of(spc_factor_s *f) { return f->batch ? f->batch->F : f; }
+spc::WaitCtl wait_of(spc_factor_s *f) {
+    spc_factor_s *o = owner_of(f);
+    return spc::WaitCtl{o->deverr, o->spin};
+}
+
+// SPC_DEVICE_ERROR if a bounded wait of f's work gave up (the stream must
+// have drained), else SPC_OK.
+int check_deverr(spc_factor_s *f) {
+    int32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, owner_of(f)->deverr, sizeof(v), hipMemcpyDeviceToHost));
+    if (v == 0) return SPC_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "a wait on another workgroup gave up after its poll limit; the factor and the solves since "
+                  "its factorization are unreliable until it is factored again");
+    return SPC_DEVICE_ERROR;
+}
 bool fac_ok(spc_factor f) { return f && f->magic == kFacMagic && sym_ok(f->sym); }
 
 void sym_release(spc_symbolic_s *s) {
@@ -262,7 +287,7 @@ struct Prof {
 // factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, int32_t *hflags, hipStream_t st, Prof &prof) {
+                    unsigned long long *status, int32_t *hflags, spc::WaitCtl wc, hipStream_t st, Prof &prof) {
     prof.run(SPC_K_ASSEMBLE, 0.0, st, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
@@ -281,14 +306,14 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
             const auto &stp = S.steps[k];
             if (stp.f1 > stp.f0)
                 prof.run(SPC_K_POTRF, stp.potrf_flops, st,
-                         [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, st); });
+                         [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, wc.err, st); });
             if (stp.p1 > stp.p0)
                 prof.run(SPC_K_TRSM, stp.trsm_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, nullptr, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, nullptr, wc, st);
                 });
             if (stp.t1 > stp.t0)
                 prof.run(SPC_K_TRAILING, stp.look_flops + stp.rest_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, wc, st);
                 });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
@@ -298,7 +323,7 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], st, [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     status, nullptr, st);
+                                     status, nullptr, wc, st);
             });
     }
 }
@@ -308,23 +333,14 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
 // one launch per wide block-tree level, and the narrow levels at the top
 // (levels solve_split..) as one persistent launch per sweep, which removes
 // a launch per level from the long chains of the top supernodes.
-// SPC_SOLVE_LEVELS=1 in the environment runs every level as its own launch.
-bool solve_persistent() {
-    static const bool v = [] {
-        const char *e = std::getenv("SPC_SOLVE_LEVELS");
-        return !(e && e[0] == '1');
-    }();
-    return v;
-}
-
 template <typename T>
 void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, const T *Linv, T *Y, T *X,
-                   T *Acc, int32_t *sync, int nrhs, hipStream_t st) {
+                   T *Acc, int32_t *sync, spc::WaitCtl wc, int nrhs, hipStream_t st) {
     const int64_t n = S.n, nb = (int64_t)S.sblocks.size(), nt = (int64_t)S.stasks.size();
-    const spc::SolveSync sy = spc::make_solve_sync(sync, nb);
+    const spc::SolveSync sy = spc::make_solve_sync(sync, nb, wc);
     spc::launch_zero<T>(Acc, n * nrhs, st);
     spc::launch_solve_reset(P, nb, sy, st);
-    const int32_t split = solve_persistent() ? S.solve_split : S.nslevels;
+    const int32_t split = S.solve_split;
     // below solve_split the tiny supernodes of a level have their own
     // (one-wave) launch beside the level's task launch
     const int32_t tsplit = S.solve_split;
@@ -360,13 +376,14 @@ int capture_factor(spc_factor f, const double *d_values) {
     drop_graph(f);
     if (!f->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal));
-    spc::launch_status_reset(f->status, f->nstatus, f->hflags, f->nflags, f->cap_stream);
+    spc::launch_status_reset(f->status, f->nstatus, f->deverr, f->hflags, f->nflags, f->cap_stream);
     Prof none{nullptr};
+    const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags,
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc,
                                f->cap_stream, none);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags,
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc,
                               f->cap_stream, none);
     hipGraph_t g = nullptr;
     const hipError_t e0 = hipGetLastError();
@@ -396,14 +413,17 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
         f->stream = st;
         return SPC_OK;
     }
-    spc::launch_status_reset(f->status, f->nstatus, f->hflags, f->nflags, st);
+    spc::launch_status_reset(f->status, f->nstatus, f->deverr, f->hflags, f->nflags, st);
     HIP_TRY(hipEventRecord(f->ev0, st));
     f->prof_used = 0;
     Prof prof{f};
+    const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc, st,
+                               prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc, st,
+                              prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -430,9 +450,13 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
     f->nflags = 4 * (int)sym->S.sblocks.size();  // one per 16-column panel of each block
+    // status words, the device-error word (padded to 8 bytes), hand-over flags
     if (e == hipSuccess)
-        e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * nstatus + sizeof(int32_t) * f->nflags);
-    if (e == hipSuccess) f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus);
+        e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * (nstatus + 1) + sizeof(int32_t) * f->nflags);
+    if (e == hipSuccess) {
+        f->deverr = reinterpret_cast<int32_t *>(f->status + nstatus);
+        f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus + 1);
+    }
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
 
@@ -583,6 +607,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         HIP_TRY(hipMemcpyAsync(hb.data(), umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                st));
         HIP_TRY(hipStreamSynchronize(st));
+        if ((rc = check_deverr(T.f))) return rc;
         double eta = 0.0;
         std::fill(eta_s.begin(), eta_s.end(), 0.0);
         for (int k = 0; k < q; ++k)
@@ -593,7 +618,11 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
                              bn = bits_to_double(hb[2 * K + j]);
                 const double den = normA * xn + bn;
                 double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
-                if (std::isnan(e)) e = INFINITY;
+                // a NaN or Inf anywhere (the maxima carry NaN as +Inf) is
+                // never converged
+                if (std::isnan(e) || !std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(bn) ||
+                    !std::isfinite(normA))
+                    e = INFINITY;
                 frozen[j] = e <= tol;
                 eta_s[sg] = std::max(eta_s[sg], e);
                 eta = std::max(eta, e);
@@ -845,18 +874,21 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
     if (rc) return rc;
     char *base = (char *)f->work;
     int32_t *counters = (int32_t *)(base + cnt_off);
+    const spc::WaitCtl wc = wait_of(f);
     for (int q0 = 0; q0 < nrhs; q0 += kChunk) {
         int q = std::min(kChunk, nrhs - q0);
         double *B = d_B + (int64_t)q0 * ldb;
         if (f->precision == SPC_FP64) {
             double *Y = (double *)base, *X = (double *)(base + vec), *Acc = (double *)(base + 2 * vec);
             spc::launch_perm_in<double>(P, S.n, q, B, ldb, Y, st);
-            enqueue_solve<double>(S, P, (const double *)f->Lx, (const double *)f->Linv, Y, X, Acc, counters, q, st);
+            enqueue_solve<double>(S, P, (const double *)f->Lx, (const double *)f->Linv, Y, X, Acc, counters, wc, q,
+                                  st);
             spc::launch_perm_out<double>(P, S.n, q, X, B, ldb, st);
         } else {
             float *Y = (float *)base, *X = (float *)(base + vec), *Acc = (float *)(base + 2 * vec);
             spc::launch_perm_in<float>(P, S.n, q, B, ldb, Y, st);
-            enqueue_solve<float>(S, P, (const float *)f->Lx, (const float *)f->Linv, Y, X, Acc, counters, q, st);
+            enqueue_solve<float>(S, P, (const float *)f->Lx, (const float *)f->Linv, Y, X, Acc, counters, wc, q,
+                                 st);
             spc::launch_perm_out<float>(P, S.n, q, X, B, ldb, st);
         }
     }
@@ -912,6 +944,8 @@ int spc_sync(spc_factor f, int64_t *bad_pivot) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
+    int rc = check_deverr(f);
+    if (rc) return rc;
     unsigned long long v = 0;
     HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
     if (v != ~0ull) {
@@ -1033,6 +1067,14 @@ int spc_factor_set_graph(spc_factor f, int on) {
     if (f->batch) return SPC_INVALID_INPUT;  // a batch view: spc_batch_set_graph
     f->use_graph = on != 0;
     if (!f->use_graph) drop_graph(f);
+    return SPC_OK;
+}
+
+int spc_factor_set_wait_limit(spc_factor f, int32_t polls) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (f->batch || polls < 0) return SPC_INVALID_INPUT;
+    f->spin = polls;
+    drop_graph(f);  // a captured graph holds the old limit
     return SPC_OK;
 }
 
@@ -1160,7 +1202,7 @@ int spc_batch_solve(spc_batch b, double *const *d_B, int nrhs, const int64_t *ld
     // the pointer tables are read by the kernels above: wait before returning
     // so the caller may reuse its host arrays
     HIP_TRY(hipStreamSynchronize(st));
-    return SPC_OK;
+    return check_deverr(b->F);
 }
 
 int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const *d_X, int nrhs, const int64_t *ld,
@@ -1244,6 +1286,8 @@ int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {
     if (bad_system) *bad_system = -1;
     if (bad_pivot) *bad_pivot = -1;
     HIP_TRY(hipStreamSynchronize(b->F->stream));
+    int rc = check_deverr(b->F);
+    if (rc) return rc;
     std::vector<unsigned long long> v(b->count);
     HIP_TRY(hipMemcpy(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
     for (int i = 0; i < b->count; ++i)

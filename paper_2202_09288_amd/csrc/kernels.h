@@ -31,32 +31,45 @@ struct DevPlan {
     const int32_t *bwd_order;    // task order of the backward sweep
 };
 
+// Bounded waits on other workgroups: `err` is the factor's device-error
+// word (set when a wait gives up, cleared by a factorization), `spin` the
+// polls before a wait gives up.
+struct WaitCtl {
+    int32_t *err;
+    int32_t spin;
+};
+// Polls of a bounded wait by default: about a second.
+constexpr int32_t kSpinDefault = 1 << 20;
+
 // Device state of one persistent solve (in the caller's workspace):
-// kSolveSyncInts(nblocks) int32 words.
+// kSolveSyncInts(nblocks) int32 words, plus the factor's error word.
 struct SolveSync {
     int32_t *dep;    // [nblocks] forward contributions still due
     int32_t *done;   // [nblocks] 1 once x of the block is final (backward)
     int32_t *cnt;    // [nblocks] backward tasks of the block that arrived
     int32_t *queue;  // [2] work counters of the two sweeps
-    int32_t *err;    // [1] nonzero when a wait gave up
+    int32_t *err;    // the factor's device-error word: nonzero once a wait gave up
+    int32_t spin;    // polls before a wait gives up
 };
-inline int64_t kSolveSyncInts(int64_t nblocks) { return 3 * nblocks + 4; }
-inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks) {
-    return SolveSync{base, base + nblocks, base + 2 * nblocks, base + 3 * nblocks, base + 3 * nblocks + 2};
+inline int64_t kSolveSyncInts(int64_t nblocks) { return 3 * nblocks + 2; }
+inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks, WaitCtl wc) {
+    return SolveSync{base, base + nblocks, base + 2 * nblocks, base + 3 * nblocks, wc.err, wc.spin};
 }
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
 // status word: lowest permuted column whose pivot failed, or ~0ull; the
-// hand-over flags of the trailing launches (one per column block) to 0
-void launch_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags, hipStream_t st);
+// device-error word and the hand-over flags of the trailing launches (one
+// per 16-column panel of each column block) to 0
+void launch_status_reset(unsigned long long *status, int count, int32_t *deverr, int32_t *flags, int nflags,
+                         hipStream_t st);
 template <typename T>
 void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
 void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx, hipStream_t st);
 template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st);
+                  int32_t *deverr, hipStream_t st);
 template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   hipStream_t st);
@@ -65,7 +78,7 @@ void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsig
                  hipStream_t st);
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *hflags, hipStream_t st);
+                  int32_t *hflags, WaitCtl wc, hipStream_t st);
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);

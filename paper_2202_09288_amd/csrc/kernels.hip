@@ -61,10 +61,11 @@ __global__ void k_zero(T *x, int64_t count) {
     for (; i < count; i += stride) x[i] = T(0);
 }
 
-__global__ void k_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags) {
+__global__ void k_status_reset(unsigned long long *status, int count, int32_t *deverr, int32_t *flags, int nflags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) status[i] = ~0ull;
     if (i < nflags) flags[i] = 0;
+    if (i == 0) deverr[0] = 0;
 }
 
 // Data handed from one workgroup to another inside a launch (which may run
@@ -79,14 +80,13 @@ template <typename T>
 __device__ __forceinline__ void dev_store(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Bounded wait for a hand-over flag (about a second of polls); false if it
-// gave up, so every wave always exits.
-__device__ __forceinline__ bool wait_flag(int32_t *p) {
-    for (int it = 0; it < (1 << 20); ++it) {
-        if (dev_load(p) != 0) return true;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return false;
+// Every wait on another workgroup is bounded: after a number of polls
+// chosen by the host (about a second's worth by default) it gives up, sets
+// the factor's device-error word and goes on, so every wave always exits;
+// the host then reports SPC_DEVICE_ERROR.  The pivot status word is never
+// used for this.
+__device__ __forceinline__ void flag_device_error(int32_t *deverr) {
+    __hip_atomic_fetch_or(deverr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
@@ -200,8 +200,8 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // waves at once.
 template <typename T>
 __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], T (*T32)[33], int *flags, int nb,
-                                          T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int64_t g0,
-                                          int32_t *pflags) {
+                                          T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int32_t *deverr,
+                                          int64_t g0, int32_t *pflags) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
@@ -433,7 +433,10 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
         }
     }
     __syncthreads();
-    if (wv == 0 && lane == 0 && (bad >= 0 || flag_err)) atomicMin(status, (unsigned long long)(g0 + (bad >= 0 ? bad : 0)));
+    if (wv == 0 && lane == 0) {
+        if (bad >= 0) atomicMin(status, (unsigned long long)(g0 + bad));
+        if (flag_err) flag_device_error(deverr);
+    }
     if (nb > 32) {
         // the two 32-blocks: X21 = -X22 (L21 X11), wave w the 16x16 tile
         // (w / 2, w % 2); the first 32 rows of the inverse are stored already
@@ -463,7 +466,8 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T *Linv,
-                                               unsigned long long *status, const int32_t *status_slot) {
+                                               unsigned long long *status, const int32_t *status_slot,
+                                               int32_t *deverr) {
     constexpr int NB = kNB;
     __shared__ T A[NB][NB + 1];
     __shared__ T rdg[NB];
@@ -491,7 +495,7 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
     }
     __syncthreads();
     potrf_lds<T>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
-                 status + (status_slot ? status_slot[tk.s] : 0), tk.g0, nullptr);
+                 status + (status_slot ? status_slot[tk.s] : 0), deverr, tk.g0, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -718,7 +722,7 @@ enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 template <typename T, int MODE>
 __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
-                                               const int32_t *status_slot, int32_t *hflags) {
+                                               const int32_t *status_slot, int32_t *hflags, WaitCtl wctl) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T ABs[2][KB][TM + 4];  // A and B chunks, one buffer
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
         // (also after a failed pivot, which the status word reports, so
         // that no tile waits in vain)
         potrf_lds<T>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
-                     status + (status_slot ? status_slot[tk.s] : 0), tk.blk,
+                     status + (status_slot ? status_slot[tk.s] : 0), wctl.err, tk.blk,
                      tk.flag >= 0 ? hflags + 4 * tk.flag : nullptr);
         return;
     }
@@ -904,7 +908,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
         for (int p = 0; p < 4; ++p) {
             // wait for panel p (every lane reads the same word: one load)
             bool ready = false;
-            for (int it = 0; ok && it < (1 << 20); ++it) {
+            for (int it = 0; ok && it < wctl.spin; ++it) {
                 if (__builtin_amdgcn_readfirstlane(dev_load(pf + p)) >= 3) {
                     ready = true;
                     break;
@@ -942,8 +946,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
             }
             wave_lds_sync();
         }
-        if (!ok && lane == 0)
-            atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)tk.blk);
+        if (!ok && lane == 0) flag_device_error(wctl.err);
         __syncthreads();
         if (gi < m)
 #pragma unroll
@@ -1112,45 +1115,34 @@ constexpr int kMaxRhs = 16;
 // a block's tasks wait until every task updating its rows has counted down
 // dep[block]; backward: a task waits until the blocks owning its rows are
 // done (bounded waits, wait_value).
-// Bounded waits: poll an int until it holds `want`; after kSpinLimit polls
-// (about a second) give up, flag err and go on, so every wave always exits.
-// Once any wait has given up, the others stop waiting too.
-constexpr int kSpinLimit = 1 << 20;
-
-__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err) {
-    for (int it = 0; it < kSpinLimit; ++it) {
+// Bounded waits: poll an int until it holds `want`; after `spin` polls
+// (about a second by default) give up, flag err and go on, so every wave
+// always exits.  Once any wait has given up, the others stop waiting too.
+__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err, int32_t spin) {
+    for (int it = 0; it < spin; ++it) {
         if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
         // once any wait has given up, the others stop waiting too
         if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         __builtin_amdgcn_s_sleep(2);
     }
-    atomicExch(err, 1);
+    flag_device_error(err);
 }
 
 // Data handed between workgroups of one persistent sweep moves through
 // device-scope atomics (loads after a wait, stores before a flag is raised),
 // and a workgroup raises a flag after waiting for its own memory operations;
 // no cache-wide fences, whose writeback and invalidation cost more than the
-// data.  SPC_SOLVE_FENCES=1 restores the fences.
-#ifndef SPC_SOLVE_FENCES
-#define SPC_SOLVE_FENCES 0
-#endif
+// data.
 template <typename T>
 __device__ __forceinline__ T shared_load(const T *p) {
-    return SPC_SOLVE_FENCES ? *p : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ __forceinline__ void shared_store(T *p, T v) {
-    if (SPC_SOLVE_FENCES) *p = v;
-    else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void release_own() {
-    if (SPC_SOLVE_FENCES) __threadfence();
-    else __builtin_amdgcn_s_waitcnt(0);
-}
-__device__ __forceinline__ void acquire_after_wait() {
-    if (SPC_SOLVE_FENCES) __threadfence();
-}
+__device__ __forceinline__ void release_own() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ void acquire_after_wait() {}
 
 // Next task of a workgroup: the persistent grid takes it from the work
 // counter (through `order` when given), the level-launch grid takes its
@@ -1206,7 +1198,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
         if (PERSIST) {
             const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
             if (tid < te - tb) my_tgt = tgt[tb + tid];
-            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
+            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err, sy.spin);
             __syncthreads();
             acquire_after_wait();
         }
@@ -1299,7 +1291,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
             // at most one target block per row of the task
             const int64_t tb = tgt_ptr[t], te = tgt_ptr[t + 1];
             if (tid < te - tb) my_tgt = tgt[tb + tid];
-            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err);
+            if (tid == 0) wait_value(&sy.dep[tk.blk], 0, sy.err, sy.spin);
             __syncthreads();
             acquire_after_wait();
         }
@@ -1434,7 +1426,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
         const bool finisher = PERSIST && tk.first && tk.ntasks > 1;
         if (finisher) {
             // every other task of the block was dequeued before this one
-            if (tid == 0) wait_value(&sy.cnt[tk.blk], tk.ntasks - 1, sy.err);
+            if (tid == 0) wait_value(&sy.cnt[tk.blk], tk.ntasks - 1, sy.err, sy.spin);
             __syncthreads();
             acquire_after_wait();
             for (int e = tid; e < nb * nrhs; e += 256) {
@@ -1444,7 +1436,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
             }
         }
         if (PERSIST) {
-            if (my_tgt >= 0) wait_value(&sy.done[my_tgt], 1, sy.err);
+            if (my_tgt >= 0) wait_value(&sy.done[my_tgt], 1, sy.err, sy.spin);
             __syncthreads();
             acquire_after_wait();
         }
@@ -1778,8 +1770,9 @@ __global__ __launch_bounds__(256) void k_solve_tiny_bwd(const SmallTask *tasks, 
     }
 }
 
-// Per solve: dep <- the forward counts, done and cnt <- 0, queues and the
-// error word <- 0.
+// Per solve: dep <- the forward counts, done and cnt <- 0, queues <- 0.  The
+// error word is the factor's, cleared only by a factorization, so a wait
+// that gave up stays reported.
 __global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nblocks) {
@@ -1788,8 +1781,13 @@ __global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy
         sy.cnt[i] = 0;
     }
     if (i < 2) sy.queue[i] = 0;
-    if (i == 0) sy.err[0] = 0;
 }
+
+// |v| for the maxima of refinement, with NaN mapped to +Inf: fmax drops a
+// NaN operand, and a NaN in a residual or solution must not vanish from
+// its norm (the bit patterns of non-negative doubles order as unsigned
+// integers, so the maxima run as integer atomicMax on them).
+__device__ __forceinline__ double abs_key(double v) { return v != v ? __longlong_as_double(0x7ff0000000000000ll) : fabs(v); }
 
 // ---------------------------------------------------------------------------
 // FP64 kernels of iterative refinement.  A is applied in full through a CSR
@@ -1836,6 +1834,7 @@ __global__ void k_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const
     double sum = 0.0;
     if (i < n)
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) sum += fabs(values[valmap[e]]);
+    sum = abs_key(sum);
     for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sum));
 }
@@ -1847,7 +1846,7 @@ __global__ __launch_bounds__(256) void k_colmax(const double *V, int64_t n, int6
     const int q = blockIdx.y;
     double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        mx = fmax(mx, fabs(V[i + q * ld]));
+        mx = fmax(mx, abs_key(V[i + q * ld]));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -1918,6 +1917,7 @@ __global__ void k_seg_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, c
     double sum = 0.0;
     if (i < n)
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) sum += fabs(values[valmap[e]]);
+    sum = abs_key(sum);
     if (wave_in_one_segment(s)) {
         for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
         if ((threadIdx.x & 63) == 0) atomicMax(&out[s], (unsigned long long)__double_as_longlong(sum));
@@ -1943,7 +1943,7 @@ __global__ __launch_bounds__(256) void k_seg_colmax(const double *V, const int32
         double mx = 0.0;
         for (int r = 0; r < kSegRows / 256; ++r) {
             const int64_t i = base + r * 256 + threadIdx.x;
-            if (i < n) mx = fmax(mx, fabs(V[i + q * ld]));
+            if (i < n) mx = fmax(mx, abs_key(V[i + q * ld]));
         }
         for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
         if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
@@ -1957,7 +1957,7 @@ __global__ __launch_bounds__(256) void k_seg_colmax(const double *V, const int32
         const int64_t i = base + r * 256 + threadIdx.x;
         const int64_t ic = i < n ? i : n - 1;
         const int s = seg[ic];
-        double mx = i < n ? fabs(V[ic + q * ld]) : 0.0;
+        double mx = i < n ? abs_key(V[ic + q * ld]) : 0.0;
         unsigned long long *o = out + (int64_t)q * nseg + s;
         if (wave_in_one_segment(s)) {
             for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
@@ -2020,10 +2020,11 @@ inline unsigned grid1(int64_t count, int block) {
 
 }  // namespace
 
-void launch_status_reset(unsigned long long *status, int count, int32_t *flags, int nflags, hipStream_t st) {
+void launch_status_reset(unsigned long long *status, int count, int32_t *deverr, int32_t *flags, int nflags,
+                         hipStream_t st) {
     const int n = count > nflags ? count : nflags;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_status_reset, dim3((n + 255) / 256), dim3(256), 0, st, status, count, flags, nflags);
+    hipLaunchKernelGGL(k_status_reset, dim3((n + 255) / 256), dim3(256), 0, st, status, count, deverr, flags, nflags);
 }
 
 template <typename T>
@@ -2042,10 +2043,10 @@ void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx,
 
 template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st) {
+                  int32_t *deverr, hipStream_t st) {
     if (t1 <= t0) return;
     hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0, Lx, Linv,
-                       status, P.status_slot);
+                       status, P.status_slot, deverr);
 }
 
 template <typename T>
@@ -2066,18 +2067,18 @@ void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *hflags, hipStream_t st) {
+                  int32_t *hflags, WaitCtl wc, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, hflags);
+                           Linv, Lx, status, P.status_slot, hflags, wc);
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc);
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc);
 }
 
 template <typename T>
@@ -2269,9 +2270,9 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_zero<T>(T *, int64_t, hipStream_t);                                                \
     template void launch_assemble<T>(const DevPlan &, int64_t, const double *, T *, hipStream_t);           \
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
-                                  hipStream_t);                                                             \
-    template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
                                   int32_t *, hipStream_t);                                                  \
+    template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
+                                  int32_t *, WaitCtl, hipStream_t);                                         \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   hipStream_t);                                                             \
     template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \

@@ -13,8 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SPCHOL_LIBRARY names another build of the same library (A/B timing)
-LIB_PATH = os.environ.get("SPCHOL_LIBRARY") or os.path.join(_HERE, "libspchol.so")
+LIB_PATH = os.path.join(_HERE, "libspchol.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_09288_amd/build.py "
@@ -40,7 +39,8 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
            "spc_last_error_message", "spc_batch_create", "spc_batch_factorize", "spc_batch_factor",
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
-           "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats")
+           "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats",
+           "spc_factor_set_wait_limit")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -101,6 +101,7 @@ _lib.spc_batch_solve_refined.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(
                                          ctypes.POINTER(_i64), ctypes.c_double, ctypes.c_int, _P,
                                          ctypes.POINTER(_RefineInfo)]
 _lib.spc_factor_set_graph.argtypes = [_P, ctypes.c_int]
+_lib.spc_factor_set_wait_limit.argtypes = [_P, ctypes.c_int32]
 _lib.spc_factor_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
 _lib.spc_batch_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
 _lib.spc_batch_set_graph.argtypes = [_P, ctypes.c_int]
@@ -322,6 +323,11 @@ class Factor:
     def set_graph(self, on: bool = True):
         """Capture the factorization into a HIP graph and replay it."""
         _check(_lib.spc_factor_set_graph(self._h, 1 if on else 0), "spc_factor_set_graph")
+
+    def set_wait_limit(self, polls: int):
+        """Polls before a bounded wait on another workgroup gives up
+        (spc_factor_set_wait_limit; 0: every such wait gives up at once)."""
+        _check(_lib.spc_factor_set_wait_limit(self._h, int(polls)), "spc_factor_set_wait_limit")
 
     def kernel_stats(self) -> dict:
         """Per kernel class: launches, total device ms and algorithmic flops of

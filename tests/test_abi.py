@@ -10,7 +10,7 @@ import pytest
 
 from paper_2202_09288_amd import workloads as W
 
-spchol = pytest.importorskip("paper_2202_09288_amd.spchol")
+from paper_2202_09288_amd import spchol  # noqa: E402  (conftest builds it when missing)
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 

@@ -353,3 +353,105 @@ def test_backward_error_is_the_smallest_consistent_perturbation(seed):
         f = (A + E) @ x - b
         eps = max(np.abs(E).sum(axis=1).max() / nA, np.abs(f).max() / nb)
         assert eps >= eta * (1 - 1e-12)
+
+
+def test_rel_frobenius_hand_values():
+    """relF = ||L - L_ref||_F / ||L_ref||_F over the masked entries, worked
+    by hand: L_ref = [3, 4, 0, 12], L = [3, 4, 99, 25] with entry 2 masked
+    out leaves the difference [0, 0, 13] against ||[3, 4, 12]|| = 13, so
+    relF = 1; without the mask the difference is [0, 0, 99, 13], so relF =
+    sqrt(99^2 + 13^2) / 13.  An all-zero reference gives ||L||_F, and
+    L = 2 L_ref gives 1."""
+    ref = np.array([3.0, 4.0, 0.0, 12.0])
+    got = np.array([3.0, 4.0, 99.0, 25.0])
+    mask = np.array([True, True, False, True])
+    assert oracle.rel_frobenius(got, ref, mask) == 1.0
+    assert oracle.rel_frobenius(got, ref) == pytest.approx(np.sqrt(99.0 ** 2 + 13.0 ** 2) / 13.0, rel=1e-15)
+    assert oracle.rel_frobenius(np.array([3.0, 4.0]), np.zeros(2)) == 5.0
+    assert oracle.rel_frobenius(2 * ref, ref) == 1.0
+    assert oracle.rel_frobenius(ref, ref, mask) == 0.0
+
+
+def test_lower_mask_hand_values():
+    """The mask keeps each panel's lower trapezoid and drops the strict upper
+    triangle of its diagonal block.  A dense 3x3 matrix is one supernode, a
+    3x3 column-major panel: entries (row, col) = (0,1), (0,2), (1,2) are out.
+    On a grid the mask holds sum_s (m_s w_s - w_s (w_s - 1) / 2) entries."""
+    A = np.array([[4.0, 1.0, 1.0], [1.0, 4.0, 1.0], [1.0, 1.0, 4.0]])
+    colptr, rowidx, values = lower_from_dense_pattern(np.ones((3, 3), bool), A)
+    S = oracle.Symbolic(colptr, rowidx, np.arange(3, dtype=np.int32), 0.05)
+    assert S.nsuper == 1
+    assert S.lower_mask().tolist() == [True, True, True, False, True, True, False, False, True]
+    s = W.laplacian((7, 6, 5), "7pt", 77, 0, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    w = np.diff(S.super_ptr).astype(np.int64)
+    m = np.diff(S.rptr).astype(np.int64)
+    assert int(S.lower_mask().sum()) == int(np.sum(m * w - w * (w - 1) // 2))
+
+
+def test_supernode_rel_errors_hand_values():
+    """Per-supernode relative error, by hand: panels [0, 2) and [2, 6) with
+    L_ref = [1, 0 | 3, 4, 0, 0] and L = [1, 0 | 3, 4, 0, 5]: supernode 0 is
+    exact, supernode 1 differs by 5 against ||[3, 4]|| = 5, so 1.  A
+    supernode whose reference is zero reports ||L_s||."""
+    lptr = np.array([0, 2, 6])
+    ref = np.array([1.0, 0.0, 3.0, 4.0, 0.0, 0.0])
+    got = np.array([1.0, 0.0, 3.0, 4.0, 0.0, 5.0])
+    assert oracle.supernode_rel_errors(got, ref, lptr).tolist() == [0.0, 1.0]
+    mask = np.array([True, True, True, True, True, False])
+    assert oracle.supernode_rel_errors(got, ref, lptr, mask).tolist() == [0.0, 0.0]
+    assert oracle.supernode_rel_errors(np.array([0.5, 2.0]), np.array([0.0, 2.0]),
+                                       np.array([0, 1, 2])).tolist() == [0.5, 0.0]
+    # an empty supernode (no entries) reports 0
+    assert oracle.supernode_rel_errors(np.array([2.0]), np.array([2.0]), np.array([0, 0, 1])).tolist() == [0.0, 0.0]
+
+
+def test_supernode_errors_expose_a_local_error():
+    """A relative error of 1e-8 planted in one entry of the smallest-norm
+    supernode of a grid factor stays below the 1e-10 bar in the global relF
+    but shows above it in that supernode's error, which is what the
+    per-supernode bar of the GPU tests is for."""
+    s = W.laplacian((14, 13, 12), "7pt", 77, 1, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lref = S.factor(s.values)
+    mask = S.lower_mask()
+    lp = S.lptr
+    norms = np.sqrt(np.add.reduceat(np.where(mask, Lref, 0.0) ** 2, lp[:-1]))
+    t = int(np.argmin(norms))
+    Lbad = Lref.copy()
+    Lbad[lp[t]] *= 1.0 + 1e-8  # the diagonal entry of its first column
+    assert oracle.rel_frobenius(Lbad, Lref, mask) < 1e-10
+    e = oracle.supernode_rel_errors(Lbad, Lref, lp, mask)
+    assert e[t] > 1e-9 and np.count_nonzero(e) == 1
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_oracle_is_bit_identical(threads):
+    """The multi-threaded mode (whole supernodes per thread, level by level)
+    runs each supernode's steps on the same inputs as the sequential loop,
+    so its factor equals the sequential one bit for bit."""
+    for dims in [(9, 8, 7), (33, 31)]:
+        s = W.laplacian(dims, "5pt" if len(dims) == 2 else "7pt", 77, 2, unit=False, shift=1e-2, nrhs=1)
+        S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        assert np.array_equal(S.factor(s.values), S.factor(s.values, threads=threads))
+
+
+def test_parallel_oracle_not_spd_same_column():
+    """A failing pivot is reported at the column the sequential loop stops
+    at, also when a later supernode on another branch fails too."""
+    s = W.laplacian((9, 9, 9), "7pt", 77, 3, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    v = s.values.copy()
+    # make two diagonal entries negative: permuted columns a < b on different branches
+    iperm = np.empty(S.n, dtype=np.int64)
+    iperm[S.perm] = np.arange(S.n)
+    lev0 = np.nonzero(S.level == 0)[0]
+    cols = [int(S.super_ptr[lev0[3]]), int(S.super_ptr[lev0[-2]])]
+    for pc in cols:
+        j = int(S.perm[pc])
+        v[s.colptr[j]] = -1.0  # first entry of column j is its diagonal
+    with pytest.raises(oracle.NotSPD) as e1:
+        S.factor(v)
+    with pytest.raises(oracle.NotSPD) as e2:
+        S.factor(v, threads=4)
+    assert e1.value.column == e2.value.column == min(cols)

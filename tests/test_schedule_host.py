@@ -10,7 +10,7 @@ import pytest
 
 from paper_2202_09288_amd import workloads as W
 
-spchol = pytest.importorskip("paper_2202_09288_amd.spchol")
+from paper_2202_09288_amd import spchol  # noqa: E402  (conftest builds it when missing)
 
 TUNINGS = [None, {"handover": -1}, {"tiny_w": -1, "small_w": -1}, {"big_min": 1, "big_min_k": 1},
            {"tiny_w": 4, "tiny_m": 32, "small_w": 16, "small_m": 64}]
