@@ -222,6 +222,24 @@ void spc_free_batch(spc_batch b);
  */
 int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream);
 
+/*
+ * spc_solve_noalloc -- spc_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same result, but the work
+ * vectors live in a fixed scratch array inside the library (64 MiB of device
+ * memory per device the library runs on, held until the process ends)
+ * instead of the factor's own work area, so the call allocates nothing.
+ * The right-hand sides are solved in chunks of as many columns as fit the
+ * array (at most 16; 3 * n * 8 bytes per column in FP64, 3 * n * 4 in FP32).
+ *   arguments as for spc_solve
+ * Every call on one device shares that device's array: calls that overlap on
+ * the device race (queue them on one stream).  The array keeps the last
+ * call's contents; each call clears what it needs.
+ * Errors: as spc_solve; SPC_INVALID_INPUT (with spc_last_error_message) when
+ * even one right-hand side does not fit the array.
+ */
+int spc_solve_noalloc(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream);
+
 /* Result of iterative refinement. */
 typedef struct spc_refine_info {
     int32_t iterations;       /* refinement steps taken */

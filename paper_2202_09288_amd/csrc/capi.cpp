@@ -689,6 +689,50 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
 }
 
 
+// ---------------------------------------------------------------------------
+// Triangular solves in chunks of right-hand sides over a work area of
+// solve_work_bytes(S, chunk, esz): Y, X, Acc (n x chunk each, factor
+// precision) then the persistent sweeps' counters.  The kernels clear what
+// they need (Acc and the counters) at the start of every chunk.
+// ---------------------------------------------------------------------------
+constexpr int kSolveChunk = 16;
+
+size_t solve_vec_bytes(const spc::Symbolic &S, int chunk, size_t esz) { return (size_t)S.n * chunk * esz; }
+size_t solve_work_bytes(const spc::Symbolic &S, int chunk, size_t esz) {
+    const size_t cnt_off = (3 * solve_vec_bytes(S, chunk, esz) + 255) & ~size_t(255);
+    return cnt_off + sizeof(int32_t) * spc::kSolveSyncInts((int64_t)S.sblocks.size());
+}
+
+int solve_chunks(spc_factor f, double *d_B, int nrhs, int64_t ldb, hipStream_t st, char *base, int chunk) {
+    const spc::Symbolic &S = f->sym->S;
+    const spc::DevPlan &P = f->sym->dev.plan;
+    const size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    (void)hipGetLastError();  // report only the launches below
+    const size_t vec = solve_vec_bytes(S, chunk, esz);
+    const size_t cnt_off = (3 * vec + 255) & ~size_t(255);
+    int32_t *counters = (int32_t *)(base + cnt_off);
+    const spc::WaitCtl wc = wait_of(f);
+    for (int q0 = 0; q0 < nrhs; q0 += chunk) {
+        const int q = std::min(chunk, nrhs - q0);
+        double *B = d_B + (int64_t)q0 * ldb;
+        if (f->precision == SPC_FP64) {
+            double *Y = (double *)base, *X = (double *)(base + vec), *Acc = (double *)(base + 2 * vec);
+            spc::launch_perm_in<double>(P, S.n, q, B, ldb, Y, st);
+            enqueue_solve<double>(S, P, (const double *)f->Lx, (const double *)f->Linv, Y, X, Acc, counters, wc, q,
+                                  st);
+            spc::launch_perm_out<double>(P, S.n, q, X, B, ldb, st);
+        } else {
+            float *Y = (float *)base, *X = (float *)(base + vec), *Acc = (float *)(base + 2 * vec);
+            spc::launch_perm_in<float>(P, S.n, q, B, ldb, Y, st);
+            enqueue_solve<float>(S, P, (const float *)f->Lx, (const float *)f->Linv, Y, X, Acc, counters, wc, q,
+                                 st);
+            spc::launch_perm_out<float>(P, S.n, q, X, B, ldb, st);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return SPC_OK;
+}
+
 void batch_release(spc_batch_s *b) {
     if (!b || b->refs.fetch_sub(1) != 1) return;
     if (b->F) spc_free_factor(b->F);
@@ -862,38 +906,37 @@ int spc_solve(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
     const spc::Symbolic &S = f->sym->S;
     if (nrhs < 0 || ldb < S.n || (!d_B && nrhs > 0 && S.n > 0)) return SPC_INVALID_INPUT;
     if (nrhs == 0 || S.n == 0) return SPC_OK;
-    hipStream_t st = (hipStream_t)stream;
-    const spc::DevPlan &P = f->sym->dev.plan;
-    size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
-    (void)hipGetLastError();  // report only the launches below
-    constexpr int kChunk = 16;
-    const size_t vec = (size_t)S.n * kChunk * esz;
-    const size_t cnt_off = (3 * vec + 255) & ~size_t(255);
-    int rc = ensure_bytes(&f->work, &f->work_bytes,
-                          cnt_off + sizeof(int32_t) * spc::kSolveSyncInts((int64_t)S.sblocks.size()));
+    const size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t need = solve_work_bytes(S, kSolveChunk, esz);
+    int rc = ensure_bytes(&f->work, &f->work_bytes, need);
     if (rc) return rc;
-    char *base = (char *)f->work;
-    int32_t *counters = (int32_t *)(base + cnt_off);
-    const spc::WaitCtl wc = wait_of(f);
-    for (int q0 = 0; q0 < nrhs; q0 += kChunk) {
-        int q = std::min(kChunk, nrhs - q0);
-        double *B = d_B + (int64_t)q0 * ldb;
-        if (f->precision == SPC_FP64) {
-            double *Y = (double *)base, *X = (double *)(base + vec), *Acc = (double *)(base + 2 * vec);
-            spc::launch_perm_in<double>(P, S.n, q, B, ldb, Y, st);
-            enqueue_solve<double>(S, P, (const double *)f->Lx, (const double *)f->Linv, Y, X, Acc, counters, wc, q,
-                                  st);
-            spc::launch_perm_out<double>(P, S.n, q, X, B, ldb, st);
-        } else {
-            float *Y = (float *)base, *X = (float *)(base + vec), *Acc = (float *)(base + 2 * vec);
-            spc::launch_perm_in<float>(P, S.n, q, B, ldb, Y, st);
-            enqueue_solve<float>(S, P, (const float *)f->Lx, (const float *)f->Linv, Y, X, Acc, counters, wc, q,
-                                 st);
-            spc::launch_perm_out<float>(P, S.n, q, X, B, ldb, st);
-        }
+    return solve_chunks(f, d_B, nrhs, ldb, (hipStream_t)stream, (char *)f->work, kSolveChunk);
+}
+
+int spc_solve_noalloc(spc_factor f, double *d_B, int nrhs, int64_t ldb, void *stream) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    const spc::Symbolic &S = f->sym->S;
+    if (nrhs < 0 || ldb < S.n || (!d_B && nrhs > 0 && S.n > 0)) return SPC_INVALID_INPUT;
+    if (nrhs == 0 || S.n == 0) return SPC_OK;
+    const size_t esz = f->precision == SPC_FP64 ? sizeof(double) : sizeof(float);
+    // the most right-hand sides per chunk whose work fits the scratch array
+    int chunk = 0;
+    while (chunk < kSolveChunk && solve_work_bytes(S, chunk + 1, esz) <= spc::kScratchBytes) ++chunk;
+    if (chunk == 0) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "spc_solve_noalloc: one right-hand side needs %zu bytes of work, more than the %zu-byte "
+                      "scratch array",
+                      solve_work_bytes(S, 1, esz), (size_t)spc::kScratchBytes);
+        return SPC_INVALID_INPUT;
     }
-    HIP_TRY(hipGetLastError());
-    return SPC_OK;
+    void *scratch = nullptr;
+    int rc = spc::scratch_address(f->device, &scratch);
+    if (rc) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "spc_solve_noalloc: hipGetSymbolAddress of the scratch "
+                                                          "array failed on device %d", f->device);
+        return rc;
+    }
+    return solve_chunks(f, d_B, nrhs, ldb, (hipStream_t)stream, (char *)scratch, chunk);
 }
 
 int spc_solve_refined(spc_factor f, const double *d_values, const double *d_B, double *d_X, int nrhs,

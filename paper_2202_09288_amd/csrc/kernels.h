@@ -58,6 +58,13 @@ inline SolveSync make_solve_sync(int32_t *base, int64_t nblocks, WaitCtl wc) {
 
 enum { kTilesTrailing = 0, kTilesScatter = 1, kTilesTrsm = 2 };
 
+// Bytes of the per-device scratch array that spc_solve_noalloc works in.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of the scratch array on `device` (looked up once per device,
+// with that device current; the array's name in host code is only a stand-in
+// for the symbol).  SPC_OK or SPC_DEVICE_ERROR.
+int scratch_address(int device, void **out);
+
 // status word: lowest permuted column whose pivot failed, or ~0ull; the
 // device-error word and the hand-over flags of the trailing launches (one
 // per 16-column panel of each column block) to 0

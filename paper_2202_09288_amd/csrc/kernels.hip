@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -2292,5 +2293,35 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
                                            int64_t, int, hipStream_t);
 SPC_INSTANTIATE(double)
 SPC_INSTANTIATE(float)
+
+// ---------------------------------------------------------------------------
+// Scratch for callers that cannot allocate (spc_solve_noalloc): a fixed
+// array in device memory, one copy per device, held until the process ends.
+// Every call on a device shares it.
+// ---------------------------------------------------------------------------
+}  // namespace spc
+
+static __device__ __align__(256) unsigned char scratch[spc::kScratchBytes];
+
+namespace spc {
+
+int scratch_address(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    if (device < 0 || device >= 64) return -5;  // SPC_DEVICE_ERROR
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return -5;
+        if (cur != device && hipSetDevice(device) != hipSuccess) return -5;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return -5;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return 0;
+}
 
 }  // namespace spc

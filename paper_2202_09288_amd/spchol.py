@@ -40,7 +40,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
            "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats",
-           "spc_factor_set_wait_limit")
+           "spc_factor_set_wait_limit", "spc_solve_noalloc")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -86,6 +86,7 @@ _lib.spc_refactorize.argtypes = [_P, _P, _P]
 _lib.spc_factorize_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int,
                                      _P, ctypes.POINTER(_P)]
 _lib.spc_solve.argtypes = [_P, _P, ctypes.c_int, _i64, _P]
+_lib.spc_solve_noalloc.argtypes = [_P, _P, ctypes.c_int, _i64, _P]
 _lib.spc_solve_refined.argtypes = [_P, _P, _P, _P, ctypes.c_int, _i64, ctypes.c_double, ctypes.c_int, _P,
                                    ctypes.POINTER(_RefineInfo)]
 _lib.spc_sync.argtypes = [_P, ctypes.POINTER(_i64)]
@@ -346,6 +347,16 @@ class Factor:
         nrhs = _rhs_count(B, n)
         _check(_lib.spc_solve(self._h, _dev_ptr(B, "torch.float64"), nrhs, n, _stream_ptr(stream)),
                "spc_solve")
+        return B
+
+    def solve_noalloc(self, B, stream=None):
+        """spc_solve_noalloc: the in-place solve of solve(), with its work in
+        the library's fixed scratch array (no device allocation)."""
+        n = self.sym.n
+        nrhs = _rhs_count(B, n)
+        rc = _lib.spc_solve_noalloc(self._h, _dev_ptr(B, "torch.float64"), nrhs, n, _stream_ptr(stream))
+        if rc != OK:
+            raise SpcError(rc, "spc_solve_noalloc: " + _lib.spc_last_error_message().decode())
         return B
 
     def solve_refined(self, d_values, B, X, tol: float = 1e-12, maxit: int = 10, stream=None):
