@@ -1,19 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark: numeric supernodal Cholesky factor + solve on one MI355X.
 
-Workload: the 3D 7-point operator on a 60^3 grid (n = 216,000), edge
-conductances log-uniform in [1e-2, 1e2], diagonal shift 1e-6, geometric
-nested dissection, one right-hand side; plain FP64 factorization + solve.
+Default workload (the headline): the 3D 27-point, 3-dof elasticity-like
+operator on a 48^3 grid (n = 331,776, 2.11e12 flops, kappa ~1e8), 4
+right-hand sides, geometric nested dissection.  One step = a plain FP64
+refactorization from the values resident in HBM (assemble, panel POTRF/TRSM,
+trailing and scatter SYRK/GEMM updates) + the forward and backward solves of
+the 4 right-hand sides.  value = FP64 factor GFLOP/s = sum_j colcount_j^2 /
+mean factor device time.  Beside it ("vs plain FP64"): the FP32
+factorization with FP64 iterative refinement to a backward error of 1e-12
+(factor ms, refined-solve p50/p99, steps, backward error).
 
-One step = refactorize (all numeric kernels: assemble, panel POTRF/TRSM,
-trailing and scatter SYRK/GEMM updates) + the forward and backward solves,
-with A's values and the right-hand side already resident in HBM.
+The printed JSON line also carries a live roofline of the dominant kernel
+class (HIP events around each of its launches, in a profiled pass of the
+same steps) and the CPU oracle timed on a bounded sample of the same matrix
+(whole subtrees of its elimination tree), on all the host's cores (the
+oracle's deterministic multi-threaded mode) and on one.
 
-value = factor GFLOP/s = sum_j colcount_j^2 / mean factor device time.
-The printed JSON line also carries solve p50/p99, the backward error of the
-last solve (host FP64), a live roofline of the dominant kernel class (HIP
-events around each of its launches, in a profiled pass of the same steps)
-and the CPU oracle timed on a bounded sample of the same workload.
+Other workloads: --workload grid3d60 (the 60^3 7-point operator, FP64),
+grid2d64, batch512, serving, copy (counter calibration).
 """
 import argparse
 import json
@@ -39,12 +44,14 @@ def parse():
     ap.add_argument("--grid", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", default="grid3d60",
-                    choices=["grid3d60", "grid2d64", "elast48", "batch512", "serving", "copy"],
-                    help="grid3d60: the headline FP64 factor + solve (default); grid2d64: small-system "
-                         "latency; elast48: FP32 factor + FP64 refinement on the 48^3 elasticity "
-                         "operator; batch512: 512 systems in one schedule; serving: request loop")
+                    help="target wall time of the oracle's all-cores sample (the one-core sample takes about "
+                         "a third of it)")
+    ap.add_argument("--workload", default="elast48",
+                    choices=["elast48", "grid3d60", "grid2d64", "batch512", "serving", "copy"],
+                    help="elast48: the headline, 48^3 elasticity, FP64 factor + solve with the FP32 + FP64 "
+                         "refinement leg beside it (default); grid3d60: 60^3 7-point FP64 factor + solve; "
+                         "grid2d64: small-system latency; batch512: 512 systems in one schedule; "
+                         "serving: request loop")
     ap.add_argument("--tuning", default="auto", choices=["auto", "default"],
                     help="schedule cut-offs: the autotuner's cache entry for this workload (auto), else defaults")
     ap.add_argument("--seed", type=int, default=0, help="seed of the synthetic inputs (configs 1-3)")
@@ -59,54 +66,86 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(s, target_s):
-    """Oracle (plain C, one thread) on disjoint subtrees of the same matrix.
+def _subtree_firsts(S):
+    """First supernode of each supernode's subtree (a contiguous range in
+    postorder ending at the supernode)."""
+    sparent = S.sparent
+    first = np.arange(S.nsuper, dtype=np.int64)
+    for t in range(S.nsuper):
+        p = int(sparent[t])
+        if p >= 0 and first[t] < first[p]:
+            first[p] = first[t]
+    return first
 
-    Subtrees are the whole subtrees rooted at supernodes of one level, taken
-    in order until their flops reach ~target_s at the oracle's rate; the rate
-    is their flops (sum of squared column counts over their columns) divided
-    by the oracle's wall time.
-    """
+
+def cpu_baseline(s, target_s, name):
+    """The oracle (plain C, FP64, no BLAS) on whole subtrees of the same
+    matrix's elimination tree: (a) on all host cores (its deterministic
+    multi-threaded mode: whole supernodes per thread, level by level), on the
+    subtrees of one etree level whose flops fill about target_s; (b) on one
+    core, on one subtree of about target_s / 3.  The rate is the sample's
+    flops (sum of squared column counts over its columns) over wall time."""
     import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
     cc = S.colcount.astype(np.float64)
+    cum = np.concatenate([[0.0], np.cumsum(cc ** 2)])
     sp = S.super_ptr
+    first = _subtree_firsts(S)
+    sub_flops = cum[sp[1:]] - cum[sp[first]]
     lev = S.level
-    # estimate of the oracle's rate to size the sample (~10 GFLOP/s on one core)
-    budget = target_s * 1.0e10
-    best = None
-    for L in range(S.sizes["nlevels"] - 1, -1, -1):
-        roots = np.nonzero(lev == L)[0]
-        if roots.size == 0:
-            continue
-        picks, fl = [], 0.0
-        for r in roots:
-            # subtree columns: contiguous range ending at the root's last column
-            first = r
-            while first > 0:
-                a = first - 1
-                while a != -1 and a < r:
-                    a = S.sparent[a]
-                if a != r:
+    one_rate = 6.0e9                     # about what one core reaches on the lower levels
+    all_rate = one_rate * threads * 0.5  # level sync and the top of each subtree cost parallelism
+
+    def pick(budget, min_roots):
+        for L in range(S.sizes["nlevels"] - 1, -1, -1):
+            roots = np.nonzero(lev == L)[0]
+            if roots.size < min_roots:
+                continue
+            picks, fl = [], 0.0
+            for r in roots:
+                if fl + sub_flops[r] > budget and picks:
                     break
-                first -= 1
-            f = float(np.sum(cc[sp[first]:sp[r + 1]] ** 2))
-            if fl + f > budget and picks:
-                break
-            picks.append(int(r))
-            fl += f
-        if fl <= budget * 1.2 and fl > 0:
-            best = (L, picks, fl)
-            break
-    L, picks, fl = best
+                picks.append(int(r))
+                fl += sub_flops[r]
+            if fl <= budget * 1.3 and len(picks) >= min_roots:
+                return L, picks, fl
+        return None
+
+    L, roots, fl = pick(target_s * all_rate, min(threads, 8))
     t0 = time.perf_counter()
-    for r in picks:
-        S.factor_subtree(s.values, r)
+    S.factor_forest(s.values, roots, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(fl / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(picks)} whole subtrees rooted at level {L} of the 60^3 etree, "
-                      f"{fl:.3e} flops (sum of squared column counts), {dt:.1f} s single-threaded",
-            "seconds": round(dt, 2), "host_cpus": os.cpu_count()}
+    used = S.threads_used
+    L1, roots1, fl1 = pick(target_s / 3 * one_rate, 1)
+    r1 = roots1[:1]
+    fl1 = float(sub_flops[r1[0]])
+    t0 = time.perf_counter()
+    S.factor_subtree(s.values, r1[0])
+    dt1 = time.perf_counter() - t0
+    import platform
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(fl / dt / 1e9, 4), "unit": "GFLOP/s", "cores": used, "kind": "oracle",
+            "sample": f"{len(roots)} whole subtrees rooted at level {L} of the {name} elimination tree, "
+                      f"{fl:.3e} flops (sum of squared column counts), {dt:.1f} s on {used} threads "
+                      f"(deterministic multi-threaded mode)",
+            "seconds": round(dt, 2), "host_cpus": os.cpu_count(), "cpu_model": cpu_model or platform.processor(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "single_core": {"value": round(fl1 / dt1 / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+                            "sample": f"1 whole subtree rooted at level {L1}, {fl1:.3e} flops, {dt1:.1f} s",
+                            "seconds": round(dt1, 2)}}
+
+
+def progress(msg):
+    """A line on stderr as each stage of the run ends."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def host_backward_error(n, colptr, rowidx, values, X, B) -> float:
@@ -153,12 +192,12 @@ def bench_copy(args):
                       "ms_per_launch": round(float(np.median(t)), 4), "GB/s": round(gbs, 1)}), flush=True)
 
 
-def counted_traffic(kernel: str, precision: str):
+def counted_traffic(kernel: str, precision: str, workload: str = "grid3d60"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
     there is none for it or the kernel source changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"counters_grid3d60_{precision}.md")
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}_{precision}.md")
     try:
         txt = open(path).read()
         src = open(os.path.join(ROOT, "paper_2202_09288_amd", "csrc", "kernels.hip"), "rb").read()
@@ -193,6 +232,51 @@ def timed(fn, steps, warmup, torch):
         out.append((e0, e1))
     torch.cuda.synchronize()
     return np.array([a.elapsed_time(b) for a, b in out])
+
+
+def profiled_pass(F, step, nprof):
+    """Per kernel class and per etree level: launches, device ms and flops of
+    nprof profiled steps (events around every launch on its stream)."""
+    F.set_profiling(True)
+    prof, lv = {}, None
+    for _ in range(nprof):
+        step()
+        for name, v in F.kernel_stats().items():
+            p = prof.setdefault(name, {"launches": 0, "ms": 0.0, "flops": 0.0})
+            for key in p:
+                p[key] += v[key]
+        ls = F.level_stats()
+        lv = ls if lv is None else [dict(a, ms=a["ms"] + b["ms"]) for a, b in zip(lv, ls)]
+    F.set_profiling(False)
+    return prof, lv
+
+
+def roofline_of(prof, nprof, precision, workload, kernel_names):
+    """The dominant kernel class (most device time, assembly aside): its
+    algorithmic flops over its summed launch durations, against the dense
+    MFMA peak of the precision."""
+    dom = max((n for n in prof if n != "assemble"), key=lambda n: prof[n]["ms"])
+    peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+    d = prof[dom]
+    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+    tname = "double" if precision == "fp64" else "float"
+    kname = kernel_names[dom].format(t=tname)
+    tr = counted_traffic(kname, precision, workload)
+    return {"bound": "mfma", "kernel": kname,
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_read_written": [tr["read"], tr["written"]] if tr else None,
+            "launches_per_step": d["launches"] // nprof,
+            "avg_launch_ms": round(d["ms"] / max(1, d["launches"]), 4),
+            "flops_per_launch": round(d["flops"] / max(1, d["launches"])),
+            "classes_ms_per_step": {n: round(v["ms"] / nprof, 3) for n, v in prof.items()}}
+
+
+def level_rows(lv, nprof):
+    """Per etree level (-1: assembly): launches, device ms and TFLOP/s of one factorization."""
+    return [[v["level"], v["launches"] // nprof, round(v["ms"] / nprof, 3),
+             round(v["flops"] / (v["ms"] / nprof * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0] for v in lv]
 
 
 def cutoffs(args, systems, nrhs, precision):
@@ -239,48 +323,131 @@ def bench_grid2d(args):
 
 
 def bench_elast(args):
-    """48^3 27-point 3-dof elasticity operator (kappa ~ 1e8), 4 RHS: FP32
-    factorization + FP64 refinement to eta <= 1e-12, next to plain FP64."""
+    """The headline: 48^3 27-point 3-dof elasticity operator (kappa ~ 1e8),
+    4 RHS.  Timed steps: plain FP64 refactorization + solve.  Beside it, the
+    FP32 factorization with FP64 refinement to a backward error <= 1e-12."""
     import torch
     from paper_2202_09288_amd import spchol
     from paper_2202_09288_amd import workloads as W
     torch.cuda.set_device(0)
     s = W.elast48(seed=args.seed)
-    tuning = cutoffs(args, [s], 4, "fp32")
-    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tuning)
-    flops = float(sym.info["flops"])
+    nrhs = s.B.shape[1]
+    progress(f"48^3 elasticity generated, n = {s.n}")
+    t0 = time.perf_counter()
+    tun64 = cutoffs(args, [s], nrhs, "fp64")
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tun64)
+    t_analyze = time.perf_counter() - t0
+    info = sym.info
+    flops = float(info["flops"])
     dv = torch.from_numpy(s.values).cuda()
     B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
-    res = {}
-    for prec in ("fp32", "fp64"):
-        F = spchol.factorize(sym, dv, prec)
-        F.sync()
-        F.set_graph(args.graph == "on")
-        fac = timed(lambda: F.refactorize(dv), args.steps, args.warmup, torch)
-        X = torch.zeros_like(B0)
-        info = {}
+    Bw = torch.empty_like(B0)
+    stream = torch.cuda.current_stream()
 
-        def solve():
-            info.update(F.solve_refined(dv, B0, X, tol=1e-12, maxit=200))
-        sol = timed(solve, max(3, args.steps // 2), 1, torch)
-        F.sync()
+    # ---- plain FP64: the timed steps
+    F = spchol.factorize(sym, dv, "fp64")
+    F.sync()
+    F.set_graph(args.graph == "on")
+
+    def step(ev=None):
+        Bw.copy_(B0)
+        if ev:
+            ev[0].record(stream)
+        F.refactorize(dv)
+        if ev:
+            ev[1].record(stream)
+        F.solve(Bw)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    F.sync()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    F.sync()  # raises if a pivot failed
+    fac_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    sol_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    berr64 = host_backward_error(s.n, s.colptr, s.rowidx, s.values, Bw.cpu().numpy().T, s.B)
+    nprof = max(1, min(args.steps, 2))
+    progress(f"plain FP64: {args.steps} steps, factor {fac_ms.mean():.2f} ms")
+    prof, lv = profiled_pass(F, step, nprof)
+    roofline = roofline_of(prof, nprof, "fp64", "elast48", spchol.KERNEL_NAMES)
+    F.close()
+    fac_mean = float(fac_ms.mean())
+    value = flops / (fac_mean * 1e-3) / 1e9
+
+    # ---- FP32 (and BF16-update) factorization + FP64 refinement (the same
+    # matrix and right-hand sides)
+    tun32 = cutoffs(args, [s], nrhs, "fp32")
+    sym32 = sym if tun32 == tun64 else spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tun32)
+
+    def refined_leg(prec):
+        F32 = spchol.factorize(sym32, dv, prec)
+        F32.sync()
+        F32.set_graph(args.graph == "on")
+        fac32 = timed(lambda: F32.refactorize(dv), args.steps, args.warmup, torch)
+        X = torch.zeros_like(B0)
+        rinfo = {}
+
+        def refined():
+            rinfo.update(F32.solve_refined(dv, B0, X, tol=1e-12, maxit=200))
+        ref = timed(refined, max(3, args.steps // 2), 1, torch)
+        F32.sync()
         berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
-        res[prec] = {"factor_ms": round(float(fac.mean()), 3),
-                     "factor_gflops": round(flops / (fac.mean() * 1e-3) / 1e9, 1),
-                     "refined_solve_ms_p50": round(float(np.median(sol)), 3),
-                     "iterations": info.get("iterations"), "converged": info.get("converged"),
-                     "berr": berr, "berr_ok": bool(berr <= 1e-12)}
-        F.close()
-    r32 = res["fp32"]
-    out = head(args, r32["factor_gflops"], "GFLOP/s", "f32",
+        raised = F32.pivot_floors()
+        F32.close()
+        f_ms = float(fac32.mean())
+        return {"factor_ms": round(f_ms, 3),
+                "factor_gflops": round(flops / (f_ms * 1e-3) / 1e9, 1),
+                "factor_frac_of_fp32_peak": round(flops / (f_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                "refined_solve_ms_p50": round(float(np.median(ref)), 3),
+                "refined_solve_ms_p99": round(float(np.percentile(ref, 99)), 3),
+                "refinement_steps": rinfo.get("iterations"), "converged": rinfo.get("converged"),
+                "status": spchol._lib.spc_status_string(rinfo.get("status", 0)).decode(),
+                "berr": berr, "berr_ok": bool(berr <= 1e-12), "pivots_raised_to_floor": raised,
+                "factor_plus_refined_solve_ms": round(f_ms + float(np.median(ref)), 3),
+                "schedule_cutoffs": tun32 or "library defaults"}
+
+    leg32 = refined_leg("fp32")
+    progress(f"FP32 + refinement: {leg32['factor_ms']} ms + {leg32['refined_solve_ms_p50']} ms")
+    try:
+        leg16 = refined_leg("bf16upd")
+    except spchol.NotSPD as e:
+        leg16 = {"status": "not SPD", "detail": str(e)}
+    progress(f"BF16 updates + refinement: {leg16}")
+    plain = {"factor_ms": round(fac_mean, 3), "solve_ms_p50": round(float(np.median(sol_ms)), 3),
+             "factor_plus_solve_ms": round(fac_mean + float(np.median(sol_ms)), 3)}
+    out = head(args, round(value, 2), "GFLOP/s", "f64",
                {"workload": "3D 27-point 3-dof elasticity-like operator, 48^3 grid, kappa ~1e8, 4 RHS, "
-                            "FP32 factor + FP64 refinement to 1e-12", "n": s.n, "nnz_lower": s.nnz,
-                "flops": int(flops), "nnz_L": sym.info["nnz_l"],
-                "schedule_cutoffs": tuning or "library defaults"},
-               round(r32["factor_ms"] + r32["refined_solve_ms_p50"], 3))
-    out.update({"fp32": res["fp32"], "fp64": res["fp64"],
-                "fp32_factor_frac_of_peak": round(r32["factor_gflops"] / (FP32_PEAK_TFLOPS * 1e3), 4),
-                "fp64_factor_frac_of_peak": round(res["fp64"]["factor_gflops"] / (FP64_PEAK_TFLOPS * 1e3), 4)})
+                            "geometric nested dissection; plain FP64 supernodal factor + solve",
+                "n": s.n, "nnz_lower": s.nnz, "flops": int(flops), "nnz_L": info["nnz_l"],
+                "nsuper": info["nsuper"], "levels": info["levels"], "amalg_z": 0.05,
+                "schedule_cutoffs": tun64 or "library defaults", "precision": "fp64", "nrhs": nrhs},
+               round(wall * 1e3 / args.steps, 3))
+    out.update({
+        "factor_ms_mean": round(fac_mean, 3),
+        "factor_ms_p50": round(float(np.median(fac_ms)), 3),
+        "solve_ms_p50": round(float(np.percentile(sol_ms, 50)), 3),
+        "solve_ms_p99": round(float(np.percentile(sol_ms, 99)), 3),
+        "berr": berr64, "berr_ok": bool(berr64 <= 1e-12),
+        "frac_of_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
+        "analyze_s": round(t_analyze, 2),
+        "roofline": roofline,
+        "factor_levels": {"columns": ["etree level (-1: assembly)", "launches", "device ms", "TFLOP/s"],
+                          "rows": level_rows(lv, nprof)},
+        "vs_plain_fp64": {"plain_fp64": plain, "fp32_refined": leg32, "bf16upd_refined": leg16,
+                          "speedup_factor_plus_solve": round(plain["factor_plus_solve_ms"] /
+                                                             leg32["factor_plus_refined_solve_ms"], 3)},
+    })
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, "48^3 elasticity")
+        progress("CPU oracle sample done")
     print(json.dumps(out), flush=True)
 
 
@@ -438,40 +605,11 @@ def bench_grid3d(args):
     X = Bw.cpu().numpy().T
     berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, X, s.B)
 
-    # profiled pass of the same steps: per-launch events around each kernel class
-    F.set_profiling(True)
-    prof = {}
-    lv_ms = None
-    for k in range(max(1, min(args.steps, 3))):
-        step([torch.cuda.Event(enable_timing=True) for _ in range(3)])
-        ks = F.kernel_stats()
-        for name, v in ks.items():
-            p = prof.setdefault(name, {"launches": 0, "ms": 0.0, "flops": 0.0})
-            for key in p:
-                p[key] += v[key]
-        ls = F.level_stats()
-        lv_ms = ls if lv_ms is None else [dict(a, ms=a["ms"] + b["ms"]) for a, b in zip(lv_ms, ls)]
-    F.set_profiling(False)
     nprof = max(1, min(args.steps, 3))
-    dom = max((n for n in prof if n != "assemble"), key=lambda n: prof[n]["ms"])
+    prof, lv_ms = profiled_pass(F, lambda: step([torch.cuda.Event(enable_timing=True) for _ in range(3)]), nprof)
     peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
-    d = prof[dom]
-    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-    tname = "double" if args.precision == "fp64" else "float"
-    kname = spchol.KERNEL_NAMES[dom].format(t=tname)
-    tr = counted_traffic(kname, args.precision) if args.grid == 60 else None
-    roofline = {"bound": "mfma", "kernel": kname,
-                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_read_written": [tr["read"], tr["written"]] if tr else None,
-                "launches_per_step": d["launches"] // nprof,
-                "avg_launch_ms": round(d["ms"] / max(1, d["launches"]), 4),
-                "flops_per_launch": round(d["flops"] / max(1, d["launches"])),
-                "classes_ms_per_step": {n: round(v["ms"] / nprof, 3) for n, v in prof.items()}}
-    # per etree level (-1: assembly): launches, device ms and TFLOP/s of one factorization
-    levels = [[v["level"], v["launches"], round(v["ms"] / nprof, 3),
-               round(v["flops"] / (v["ms"] / nprof * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0] for v in lv_ms]
+    roofline = roofline_of(prof, nprof, args.precision, f"grid3d{args.grid}", spchol.KERNEL_NAMES)
+    levels = level_rows(lv_ms, nprof)
 
     fac_mean = float(fac_ms.mean())
     value = flops / (fac_mean * 1e-3) / 1e9
@@ -507,7 +645,7 @@ def bench_grid3d(args):
                           "rows": levels},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, f"{args.grid}^3")
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,15 @@ enum spc_status {
 
 enum spc_precision {
     SPC_FP64 = 0,             /* panels, updates and solves in double */
-    SPC_FP32 = 1              /* panels, updates and solves in float, float accumulation */
+    SPC_FP32 = 1,             /* panels, updates and solves in float, float accumulation */
+    SPC_FP32_BF16UPD = 2      /* as SPC_FP32, but the SYRK/GEMM Schur-complement updates of the
+                               * tiled paths (the trailing update inside a wide supernode, except
+                               * the diagonal tile of the block factored next, and the scatter
+                               * updates into ancestors) multiply operands rounded to BF16 on
+                               * BF16 MFMA with FP32 accumulation; POTRF, TRSM, the block
+                               * inverses, the small-supernode paths and the solves stay FP32.
+                               * Not in the paper: an experiment in how little precision the
+                               * updates need when FP64 refinement (spc_solve_refined) follows. */
 };
 
 typedef struct spc_symbolic_s *spc_symbolic;
@@ -288,6 +296,18 @@ int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const
  * the factor is factored again.  spc_solve_refined, spc_batch_solve,
  * spc_batch_solve_refined and spc_batch_sync report it the same way. */
 int spc_sync(spc_factor f, int64_t *bad_pivot);
+
+/* SPC_FP32_BF16UPD: the number of pivots of the last factorization (of the
+ * whole batch, for a batch view) that were raised to their floor, else 0.
+ * With BF16-rounded Schur updates the computed Schur complement of an
+ * ill-conditioned matrix can lose definiteness (the rounding perturbs it by
+ * about 2^-8 of |L||L^T|); a pivot d_j below theta * a_jj, with theta = 2^-8
+ * (BF16's unit roundoff) and a_jj the column's diagonal entry in A, is then
+ * replaced by theta * a_jj (static pivot perturbation: the factor is that of
+ * A plus a non-negative diagonal), so the factorization completes and the
+ * FP64 refinement (whose residual uses A itself) corrects for it.  NaN or
+ * Inf pivots still give SPC_NOT_SPD.  Synchronizes. */
+int spc_factor_pivot_floors(spc_factor f, int64_t *raised);
 
 /* Polls before a bounded wait of one workgroup on another gives up (the
  * hand-over inside a trailing launch, the persistent solve sweeps).  Every

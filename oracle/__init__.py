@@ -53,7 +53,7 @@ def _load():
         lib.orc_factor.restype = ctypes.c_int
         lib.orc_solve.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64]
         lib.orc_solve.restype = None
-        lib.orc_factor_parallel.argtypes = [P, P, P, P, ctypes.c_int, P]
+        lib.orc_factor_parallel.argtypes = [P, P, P, P, ctypes.c_int, P, P, ctypes.c_int32]
         lib.orc_factor_parallel.restype = ctypes.c_int
         lib.orc_factor_subtree.argtypes = [P, P, ctypes.c_int32, P, P, P]
         lib.orc_factor_subtree.restype = ctypes.c_int
@@ -144,7 +144,8 @@ class Symbolic:
         bad = np.zeros(1, dtype=np.int64)
         if threads > 0:
             used = np.zeros(1, dtype=np.int32)
-            rc = _load().orc_factor_parallel(self._h, _ptr(v), _ptr(Lx), _ptr(bad), int(threads), _ptr(used))
+            rc = _load().orc_factor_parallel(self._h, _ptr(v), _ptr(Lx), _ptr(bad), int(threads), _ptr(used),
+                                             None, 0)
             self.threads_used = int(used[0])
         else:
             rc = _load().orc_factor(self._h, _ptr(v), _ptr(Lx), _ptr(bad))
@@ -170,6 +171,24 @@ class Symbolic:
         if rc != 0:
             raise ValueError("bad subtree root")
         return Lx[: self.sizes["panel_entries"]], int(first[0])
+
+    def factor_forest(self, values, roots, threads: int = 1):
+        """Panels of the subtrees of the supernodes ``roots`` (the rest of
+        the returned array is zero), factored by the multi-threaded mode on
+        ``threads`` threads; self.threads_used holds the count it ran with."""
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        r = np.ascontiguousarray(roots, dtype=np.int32)
+        Lx = np.zeros(max(self.sizes["panel_entries"], 1), dtype=np.float64)
+        bad = np.zeros(1, dtype=np.int64)
+        used = np.zeros(1, dtype=np.int32)
+        rc = _load().orc_factor_parallel(self._h, _ptr(v), _ptr(Lx), _ptr(bad), int(threads), _ptr(used),
+                                         _ptr(r), int(r.size))
+        self.threads_used = int(used[0])
+        if rc == NOT_SPD:
+            raise NotSPD(int(bad[0]))
+        if rc != 0:
+            raise ValueError("bad subtree root")
+        return Lx[: self.sizes["panel_entries"]]
 
     def solve(self, Lx: np.ndarray, B: np.ndarray) -> np.ndarray:
         """Return A^{-1} B; B is (n, nrhs) or (n,)."""

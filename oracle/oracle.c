@@ -581,11 +581,24 @@ int orc_factor(const orc_sym *S, const double *values, double *Lx, int64_t *bad_
  * to orc_factor for any thread count.  A supernode with a failed descendant
  * is skipped; the failure reported is the one of the lowest supernode, the
  * one the sequential loop stops at.  Returns the thread count used in
- * *used (nullable).
+ * *used (nullable).  With roots (nroots of them) only the subtrees of those
+ * supernodes are factored (a forest whose panels equal those of the whole
+ * factorization, as in orc_factor_subtree); roots == NULL: all supernodes.
  */
+static int32_t subtree_first(const orc_sym *S, int32_t root);
+
 int orc_factor_parallel(const orc_sym *S, const double *values, double *Lx, int64_t *bad_col, int nthreads,
-                        int *used) {
+                        int *used, const int32_t *roots, int32_t nroots) {
     int32_t ns = S->nsuper;
+    char *active = xcalloc((size_t)ns + 1, 1);
+    if (roots) {
+        for (int32_t q = 0; q < nroots; ++q) {
+            if (roots[q] < 0 || roots[q] >= ns) { free(active); return -1; }
+            for (int32_t t = subtree_first(S, roots[q]); t <= roots[q]; ++t) active[t] = 1;
+        }
+    } else {
+        memset(active, 1, (size_t)ns);
+    }
     double *Lr = xmalloc(sizeof(double) * (size_t)(S->lptr[ns] + 1));
     /* supernodes grouped by level */
     int32_t nl = S->nlevels;
@@ -612,7 +625,7 @@ int orc_factor_parallel(const orc_sym *S, const double *values, double *Lx, int6
 #pragma omp for schedule(dynamic, 1)
             for (int64_t q = lptr[v]; q < lptr[v + 1]; ++q) {
                 int32_t s = bylev[q];
-                if (failed[s]) continue;
+                if (failed[s] || !active[s]) continue;
                 int64_t bc = -1;
                 if (factor_one(S, values, Lx, Lr, s, pos, &bc) != 0) {
                     failed[s] = 2; /* the supernode itself failed */
@@ -636,8 +649,22 @@ int orc_factor_parallel(const orc_sym *S, const double *values, double *Lx, int6
             break;
         }
     if (used) *used = got;
-    free(failed); free(badc); free(bylev); free(lptr); free(Lr);
+    free(failed); free(badc); free(bylev); free(lptr); free(Lr); free(active);
     return rc;
+}
+
+/* First supernode of the subtree of `root` (its descendants and itself are a
+ * contiguous range in postorder): walk down while the supernode just below
+ * the range still descends from root. */
+static int32_t subtree_first(const orc_sym *S, int32_t root) {
+    int32_t lo = root;
+    for (int32_t s = root - 1; s >= 0; --s) {
+        int32_t a = s;
+        while (a != -1 && a < root) a = S->sparent[a];
+        if (a != root) break;
+        lo = s;
+    }
+    return lo;
 }
 
 /*
@@ -651,16 +678,7 @@ int orc_factor_parallel(const orc_sym *S, const double *values, double *Lx, int6
 int orc_factor_subtree(const orc_sym *S, const double *values, int32_t root, double *Lx,
                        int64_t *bad_col, int32_t *first) {
     if (root < 0 || root >= S->nsuper) return -1;
-    int32_t lo = root;
-    /* descendants of root form the range (lo, root]; walk down the first
-     * child chain: in a postorder the smallest descendant of a node is the
-     * smallest descendant of its smallest child */
-    for (int32_t s = root - 1; s >= 0; --s) {
-        int32_t a = s;
-        while (a != -1 && a < root) a = S->sparent[a];
-        if (a != root) break;
-        lo = s;
-    }
+    int32_t lo = subtree_first(S, root);
     if (first) *first = lo;
     double *Lr = xmalloc(sizeof(double) * (size_t)(S->lptr[S->nsuper] + 1));
     int rc = factor_range(S, values, Lx, Lr, lo, root, bad_col);

@@ -58,6 +58,9 @@ struct spc_factor_s {
     // factorization; after the status words in their allocation
     int32_t *deverr = nullptr;
     int32_t spin = spc::kSpinDefault;  // polls before such a wait gives up
+    // BF16 updates: pivot floors (n entries, factor precision); the count of
+    // pivots raised to their floor is the word after deverr
+    void *pfloor = nullptr;
     // hand-over flags of the trailing launches, one per 16-column panel of
     // each column block (in the status allocation, after the error word)
     int32_t *hflags = nullptr;
@@ -199,6 +202,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.crel.data(), bytes_of(S.crel), (const void **)&P.crel},
         {S.amap.data(), bytes_of(S.amap), (const void **)&P.amap},
         {S.perm.data(), bytes_of(S.perm), (const void **)&P.perm},
+        {S.dsrc.data(), bytes_of(S.dsrc), (const void **)&P.dsrc},
         {S.potrf_tasks.data(), bytes_of(S.potrf_tasks), (const void **)&P.potrf_tasks},
         {S.small_tasks.data(), bytes_of(S.small_tasks), (const void **)&P.small_tasks},
         {S.tiny_tasks.data(), bytes_of(S.tiny_tasks), (const void **)&P.tiny_tasks},
@@ -239,7 +243,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 
 size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
-           bytes_of(S.perm) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
+           bytes_of(S.perm) + bytes_of(S.dsrc) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
            bytes_of(S.stasks) + bytes_of(S.stiny) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
            bytes_of(S.fdep) + bytes_of(S.bwd_order);
@@ -287,43 +291,52 @@ struct Prof {
 // factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, int32_t *hflags, spc::WaitCtl wc, hipStream_t st, Prof &prof) {
+                    unsigned long long *status, int32_t *hflags, spc::WaitCtl wc, bool bf16, T *pfloor,
+                    hipStream_t st, Prof &prof) {
+    spc::PivotFloor<T> pfl;
+    if (bf16) {
+        pfl.v = pfloor;
+        pfl.count = wc.err + 1;
+    }
     prof.run(SPC_K_ASSEMBLE, 0.0, st, [&] {
         spc::launch_zero<T>(Lx, S.panel_entries(), st);
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
+        if (bf16) spc::launch_pivot_floor<T>(P, S.n, d_values, spc::kBf16PivotTheta, pfloor, st);
     });
     for (int32_t l = 0; l < S.nlevels; ++l) {
         prof.level = l;
         if (S.tiny_ptr[l + 1] > S.tiny_ptr[l])
             prof.run(SPC_K_TINY, S.tiny_flops[l], st, [&] {
-                spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_ptr[l + 1], Lx, Linv, status, st);
+                spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_ptr[l + 1], Lx, Linv, status, pfl, st);
             });
         if (S.small_ptr[l + 1] > S.small_ptr[l])
             prof.run(SPC_K_SMALL, S.small_flops[l], st, [&] {
-                spc::launch_small<T>(P, S.small_ptr[l], S.small_ptr[l + 1], Lx, Linv, status, st);
+                spc::launch_small<T>(P, S.small_ptr[l], S.small_ptr[l + 1], Lx, Linv, status, pfl, st);
             });
         for (int64_t k = S.level_step_ptr[l]; k < S.level_step_ptr[l + 1]; ++k) {
             const auto &stp = S.steps[k];
             if (stp.f1 > stp.f0)
                 prof.run(SPC_K_POTRF, stp.potrf_flops, st,
-                         [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, wc.err, st); });
+                         [&] { spc::launch_potrf<T>(P, stp.f0, stp.f1, Lx, Linv, status, wc.err, pfl, st); });
             if (stp.p1 > stp.p0)
                 prof.run(SPC_K_TRSM, stp.trsm_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, nullptr, wc, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrsm, stp.p0, stp.p1, Lx, Linv, status, nullptr, wc, false, pfl,
+                                         st);
                 });
             if (stp.t1 > stp.t0)
                 prof.run(SPC_K_TRAILING, stp.look_flops + stp.rest_flops, st, [&] {
-                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, wc, st);
+                    spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, wc, bf16,
+                                         pfl, st);
                 });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
             prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], st, [&] {
-                spc::launch_tiles128<T>(P, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, st);
+                spc::launch_tiles128<T>(P, S.ext_big_ptr[l], S.ext_big_ptr[l + 1], Lx, bf16, st);
             });
         if (S.ext_tile_ptr[l + 1] > S.ext_tile_ptr[l])
             prof.run(SPC_K_SCATTER, S.ext_flops[l], st, [&] {
                 spc::launch_tiles<T>(P, spc::kTilesScatter, S.ext_tile_ptr[l], S.ext_tile_ptr[l + 1], Lx, Linv,
-                                     status, nullptr, wc, st);
+                                     status, nullptr, wc, bf16, pfl, st);
             });
     }
 }
@@ -381,10 +394,10 @@ int capture_factor(spc_factor f, const double *d_values) {
     const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
         enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc,
-                               f->cap_stream, none);
+                               false, nullptr, f->cap_stream, none);
     else
         enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc,
-                              f->cap_stream, none);
+                              f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, f->cap_stream, none);
     hipGraph_t g = nullptr;
     const hipError_t e0 = hipGetLastError();
     const hipError_t e1 = hipStreamEndCapture(f->cap_stream, &g);
@@ -419,11 +432,11 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     Prof prof{f};
     const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc, st,
-                               prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc, false,
+                               nullptr, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc, st,
-                              prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc,
+                              f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -431,7 +444,7 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
 }
 
 int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus = 1) {
-    if (precision != SPC_FP64 && precision != SPC_FP32) return SPC_INVALID_INPUT;
+    if (precision != SPC_FP64 && precision != SPC_FP32 && precision != SPC_FP32_BF16UPD) return SPC_INVALID_INPUT;
     int dev = -1;
     int rc = check_device(&dev);
     if (rc) return rc;
@@ -457,6 +470,8 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
         f->deverr = reinterpret_cast<int32_t *>(f->status + nstatus);
         f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus + 1);
     }
+    if (e == hipSuccess && precision == SPC_FP32_BF16UPD)
+        e = hipMalloc(&f->pfloor, std::max<size_t>(1, (size_t)sym->S.n) * sizeof(float));
     if (e == hipSuccess) e = hipEventCreate(&f->ev0);
     if (e == hipSuccess) e = hipEventCreate(&f->ev1);
 
@@ -1091,6 +1106,7 @@ void spc_free_factor(spc_factor f) {
     if (f->stream || f->Lx) (void)hipStreamSynchronize(f->stream);
     if (f->Lx) (void)hipFree(f->Lx);
     if (f->Linv) (void)hipFree(f->Linv);
+    if (f->pfloor) (void)hipFree(f->pfloor);
     if (f->status) (void)hipFree(f->status);
     if (f->work) (void)hipFree(f->work);
     if (f->refine) (void)hipFree(f->refine);
@@ -1113,6 +1129,19 @@ int spc_factor_set_graph(spc_factor f, int on) {
     return SPC_OK;
 }
 
+int spc_factor_pivot_floors(spc_factor f, int64_t *raised) {
+    if (!fac_ok(f)) return SPC_BAD_HANDLE;
+    if (!raised) return SPC_INVALID_INPUT;
+    *raised = 0;
+    spc_factor_s *o = owner_of(f);
+    if (o->precision != SPC_FP32_BF16UPD) return SPC_OK;
+    HIP_TRY(hipStreamSynchronize(o->stream));
+    int32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, o->deverr + 1, sizeof(v), hipMemcpyDeviceToHost));
+    *raised = v;
+    return SPC_OK;
+}
+
 int spc_factor_set_wait_limit(spc_factor f, int32_t polls) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
     if (f->batch || polls < 0) return SPC_INVALID_INPUT;
@@ -1132,7 +1161,8 @@ int spc_batch_set_graph(spc_batch b, int on) {
 int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_batch *out) {
     if (!out) return SPC_INVALID_INPUT;
     *out = nullptr;
-    if (count <= 0 || !syms || (precision != SPC_FP64 && precision != SPC_FP32)) return SPC_INVALID_INPUT;
+    if (count <= 0 || !syms || (precision != SPC_FP64 && precision != SPC_FP32 && precision != SPC_FP32_BF16UPD))
+        return SPC_INVALID_INPUT;
     for (int i = 0; i < count; ++i)
         if (!sym_ok(syms[i])) return SPC_BAD_HANDLE;
     int dev = -1;

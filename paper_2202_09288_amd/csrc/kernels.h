@@ -15,6 +15,7 @@ struct DevPlan {
     const int64_t *crel;        // per row position: offset into rel
     const int64_t *amap;        // caller entry -> panel entry
     const int32_t *perm;
+    const int64_t *dsrc;        // permuted column -> caller entry of its diagonal
     const PanelTask *potrf_tasks;
     const SmallTask *small_tasks;
     const SmallTask *tiny_tasks;
@@ -38,6 +39,17 @@ struct WaitCtl {
     int32_t *err;
     int32_t spin;
 };
+// Pivot floors of a factorization with BF16 updates: a pivot below v[g]
+// (global permuted column g; v = theta * the column's diagonal entry of A)
+// is raised to v[g], and *count counts them.  v == nullptr: off.
+template <typename T>
+struct PivotFloor {
+    const T *v = nullptr;
+    int32_t *count = nullptr;
+};
+// theta: the unit roundoff of BF16 (8 significant bits), 2^-8.
+constexpr double kBf16PivotTheta = 1.0 / 256.0;
+
 // Polls of a bounded wait by default: about a second.
 constexpr int32_t kSpinDefault = 1 << 20;
 
@@ -74,21 +86,26 @@ template <typename T>
 void launch_zero(T *x, int64_t count, hipStream_t st);
 template <typename T>
 void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx, hipStream_t st);
+// floor[j] = theta * A's diagonal entry of permuted column j (BF16 updates)
+template <typename T>
+void launch_pivot_floor(const DevPlan &P, int64_t n, const double *values, double theta, T *floor, hipStream_t st);
 template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *deverr, hipStream_t st);
+                  int32_t *deverr, PivotFloor<T> pfl, hipStream_t st);
 template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st);
+                  PivotFloor<T> pfl, hipStream_t st);
 template <typename T>
 void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                 hipStream_t st);
+                 PivotFloor<T> pfl, hipStream_t st);
 template <typename T>
+// bf16: (float panels only) the trailing and scatter updates multiply
+// operands rounded to BF16 on BF16 MFMA with FP32 accumulation
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *hflags, WaitCtl wc, hipStream_t st);
+                  int32_t *hflags, WaitCtl wc, bool bf16, PivotFloor<T> pfl, hipStream_t st);
 
 template <typename T>
-void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st);
+void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st);
 
 template <typename T>
 void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <climits>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -52,6 +53,24 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// BF16 updates (SPC_FP32_BF16UPD): D(16x16, FP32) += A(16x32) B(32x16) with
+// both operands rounded to BF16 (round to nearest even).  Lane l supplies
+// eight consecutive k of row l%16 of A and of column l%16 of B, k = 8 (l/16)
+// .. 8 (l/16) + 7; the same k order for A and B is all a sum over k needs.
+// D is laid out as in the FP32 16x16x4 shape: element v of lane l is
+// D[4 (l/16) + v][l%16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// Eight FP32 values as eight BF16 (16 bytes) for an LDS row of k.
+__device__ __forceinline__ bf16x8 to_bf16x8(const float *v) {
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[e];
+    return r;
+}
+
 __device__ __forceinline__ bool finite_pos(double d) { return d > 0.0 && d <= 1.7976931348623157e308; }
 __device__ __forceinline__ bool finite_pos(float d) { return d > 0.0f && d <= 3.402823466e38f; }
 
@@ -66,7 +85,7 @@ __global__ void k_status_reset(unsigned long long *status, int count, int32_t *d
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) status[i] = ~0ull;
     if (i < nflags) flags[i] = 0;
-    if (i == 0) deverr[0] = 0;
+    if (i < 2) deverr[i] = 0;  // the device-error word and the raised-pivot count
 }
 
 // Data handed from one workgroup to another inside a launch (which may run
@@ -94,6 +113,14 @@ template <typename T>
 __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *values, T *Lx) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nnz) Lx[amap[k]] = (T)values[k];
+}
+
+// Pivot floors of the BF16-update factorization: theta times the diagonal
+// entry of A of each permuted column.
+template <typename T>
+__global__ void k_pivot_floor(const int64_t *dsrc, int64_t n, const double *values, double theta, T *floor) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) floor[j] = (T)(theta * values[dsrc[j]]);
 }
 
 // ---------------------------------------------------------------------------
@@ -199,10 +226,10 @@ __device__ __forceinline__ void lds_flag_add(int *f) {
 // the panel chain never waits for a whole-workgroup barrier.  Each trailing
 // tile belongs to one wave for all panels, so no tile is updated by two
 // waves at once.
-template <typename T>
+template <typename T, bool BOOST = false>
 __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], T (*T32)[33], int *flags, int nb,
                                           T *P, int64_t m, int c0, T *Vi, unsigned long long *status, int32_t *deverr,
-                                          int64_t g0, int32_t *pflags) {
+                                          int64_t g0, int32_t *pflags, PivotFloor<T> pfl = {}) {
     constexpr int NB = kNB, PW = 16;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
@@ -253,8 +280,11 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
         wave_lds_sync();
     };
     int bad = -1;  // wave 0: first pivot (block column) that failed
+    int boosted = 0;
     if (wv == 0) {
         const int i = lane;
+        // pivot floors of this block's columns (lane = column), read off the chain
+        const T flo = BOOST ? pfl.v[g0 + min(lane, nb - 1)] : T(0);
         for (int pb = 0; pb < npan; ++pb) {
             const int p0 = PW * pb;
             if (pb >= 2 && !lds_wait_geq(&flag_trail[pb - 2], 3)) flag_err = 1;
@@ -299,7 +329,14 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
                 const int j = p0 + c;
-                const T d = lane_read(r[c], j);
+                T d = lane_read(r[c], j);
+                if (BOOST) {
+                    const T fj = lane_read(flo, j);
+                    if (d < fj && j < nb) {  // a NaN compares false and still fails below
+                        d = fj;
+                        ++boosted;
+                    }
+                }
                 if (bad < 0 && j < nb && !finite_pos(d)) bad = j;
                 const T rs = rsqrt_nr(d);
                 if (i == j) rdg[j] = rs;
@@ -437,6 +474,7 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
     if (wv == 0 && lane == 0) {
         if (bad >= 0) atomicMin(status, (unsigned long long)(g0 + bad));
         if (flag_err) flag_device_error(deverr);
+        if (BOOST && boosted) atomicAdd(pfl.count, boosted);
     }
     if (nb > 32) {
         // the two 32-blocks: X21 = -X22 (L21 X11), wave w the 16x16 tile
@@ -465,10 +503,10 @@ __device__ __forceinline__ void potrf_lds(T (*A)[kNB + 1], T *rdg, T (*Tf)[33], 
 #undef SPC_INV
 }
 
-template <typename T>
+template <typename T, bool BOOST>
 __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T *Linv,
                                                unsigned long long *status, const int32_t *status_slot,
-                                               int32_t *deverr) {
+                                               int32_t *deverr, PivotFloor<T> pfl) {
     constexpr int NB = kNB;
     __shared__ T A[NB][NB + 1];
     __shared__ T rdg[NB];
@@ -495,8 +533,8 @@ __global__ __launch_bounds__(256) void k_potrf(const PanelTask *tasks, T *Lx, T 
         }
     }
     __syncthreads();
-    potrf_lds<T>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
-                 status + (status_slot ? status_slot[tk.s] : 0), deverr, tk.g0, nullptr);
+    potrf_lds<T, BOOST>(A, rdg, Tf, T32, flags, nb, P, m, c0, Linv + tk.ioff,
+                        status + (status_slot ? status_slot[tk.s] : 0), deverr, tk.g0, nullptr, pfl);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,7 +559,8 @@ __device__ __forceinline__ int64_t lane_read_i64(int64_t v, int src) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t ntasks, const int64_t *cbase,
                                               const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
-                                              unsigned long long *status, const int32_t *status_slot) {
+                                              unsigned long long *status, const int32_t *status_slot,
+                                              PivotFloor<T> pfl) {
     constexpr int WT = kTinyW, CB = 8;  // CB: update columns per batch of loads
     const int lane = threadIdx.x & 63;
     const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -537,12 +576,20 @@ __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t nt
     const int64_t kpos = tk.roff + min(max(lane, w), m - 1);
     const int64_t my_cb = cbase[kpos], my_cr = crel[kpos];
     // 1. column Cholesky
-    int bad = -1;
+    int bad = -1, boosted = 0;
     T rdg[WT];
+    const T flo = pfl.v ? pfl.v[tk.g0 + min(lane, w - 1)] : T(0);
 #pragma unroll
     for (int c = 0; c < WT; ++c) {
         if (c < w) {
-            const T d = lane_read(r[c], c);
+            T d = lane_read(r[c], c);
+            if (pfl.v) {
+                const T fc = lane_read(flo, c);
+                if (d < fc) {
+                    d = fc;
+                    ++boosted;
+                }
+            }
             if (bad < 0 && !finite_pos(d)) bad = c;
             const T rs = rsqrt_nr(d);
             rdg[c] = rs;
@@ -555,6 +602,7 @@ __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t nt
     }
     if (lane == 0 && bad >= 0)
         atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
+    if (lane == 0 && boosted) atomicAdd(pfl.count, boosted);
     if (lane < m)
 #pragma unroll
         for (int c = 0; c < WT; ++c)
@@ -615,7 +663,7 @@ __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t nt
 template <typename T>
 __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
-                                               const int32_t *status_slot) {
+                                               const int32_t *status_slot, PivotFloor<T> pfl) {
     constexpr int MS = kSmallM, WS = kSmallW, LPT = WS * MS / 256, SB = 8;
     __shared__ T A[WS][MS + 1];   // A[c][i] = panel entry (row i, column c)
     __shared__ T Vt[WS][WS + 1];  // inverse, Vt[c][a] = (L^{-1})_ac
@@ -643,9 +691,16 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
         }
     }
     __syncthreads();
-    int bad = -1;
+    int bad = -1, boosted = 0;
     for (int j = 0; j < w; ++j) {
-        const T d = A[j][j];
+        T d = A[j][j];
+        if (pfl.v) {
+            const T fj = pfl.v[tk.g0 + j];
+            if (d < fj) {
+                d = fj;
+                ++boosted;
+            }
+        }
         if (bad < 0 && !finite_pos(d)) bad = j;
         const T ljj = sqrt(d);
         __syncthreads();  // every thread has read d
@@ -660,6 +715,7 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
     }
     if (tid == 0 && bad >= 0)
         atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
+    if (tid == 0 && boosted) atomicAdd(pfl.count, boosted);
     for (int e = tid; e < w * MS; e += 256) {
         const int i = e % MS, c = e / MS;
         if (i < m && i >= c) P[(int64_t)c * m + i] = A[c][i];
@@ -720,10 +776,11 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 // ---------------------------------------------------------------------------
 enum { MODE_TRAILING = 0, MODE_SCATTER = 1, MODE_TRSM = 2 };
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool BF = false>
 __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                const int32_t *rel, T *Linv, T *Lx, unsigned long long *status,
-                                               const int32_t *status_slot, int32_t *hflags, WaitCtl wctl) {
+                                               const int32_t *status_slot, int32_t *hflags, WaitCtl wctl,
+                                               PivotFloor<T> pfl) {
     constexpr int TM = kTile, KB = 16, CPT = 16;
     using acc_t = typename Mfma<T>::acc;
     __shared__ T ABs[2][KB][TM + 4];  // A and B chunks, one buffer
@@ -804,6 +861,53 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
             }
         }
         __syncthreads();
+    } else if constexpr (BF) {
+        // BF16 operands, FP32 accumulation, K staged 32 at a time: thread
+        // (row lr, quarter lk) loads k = 8 lk .. 8 lk + 7 of its row of A
+        // and of B, rounds them to BF16 and writes each as 16 bytes of an
+        // LDS row (k contiguous), which a lane then reads with one load
+        static_assert(sizeof(T) == 4, "BF16 updates are for FP32 panels");
+        constexpr int KBB = 32, RS = KBB + 8;  // row stride in bf16 (16 bytes of padding)
+        // staged in Cs, which the epilogue needs only after the last chunk
+        __bf16 *Ab = reinterpret_cast<__bf16 *>(&Cs[0][0]);
+        __bf16 *Bb = Ab + TM * RS;
+        static_assert(2 * TM * RS * sizeof(__bf16) <= sizeof(Cs), "bf16 staging fits the output tile buffer");
+        float fa[8], fb[8];
+        auto loadb = [&](int kb) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = min(kb + 8 * lk + e, tk.k1 - 1);
+                fa[e] = pa[(int64_t)k * m];
+                fb[e] = pb[(int64_t)k * m];
+            }
+        };
+        loadb(tk.k0);
+        for (int kb = tk.k0; kb < tk.k1; kb += KBB) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool kin = kb + 8 * lk + e < tk.k1;
+                fa[e] = (kin && row_ok) ? fa[e] : 0.0f;
+                fb[e] = (kin && col_ok) ? fb[e] : 0.0f;
+            }
+            *reinterpret_cast<bf16x8 *>(Ab + lr * RS + 8 * lk) = to_bf16x8(fa);
+            *reinterpret_cast<bf16x8 *>(Bb + lr * RS + 8 * lk) = to_bf16x8(fb);
+            __syncthreads();
+            if (kb + KBB < tk.k1) loadb(kb + KBB);
+            bf16x8 af[2], bf[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                af[a] = *reinterpret_cast<const bf16x8 *>(Ab + (wr + a * 16 + (lane & 15)) * RS + 8 * (lane >> 4));
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bf[b] = *reinterpret_cast<const bf16x8 *>(Bb + (wc + b * 16 + (lane & 15)) * RS + 8 * (lane >> 4));
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = mfma_bf16(af[a], bf[b], acc[a][b]);
+            __syncthreads();
+        }
+        if (MODE == MODE_TRAILING) load_old();
     } else {
         load(tk.k0);
         for (int kb = tk.k0; kb < tk.k1; kb += KB) {
@@ -884,9 +988,9 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
         // with a flag, each panel goes to the tiles below as it comes out
         // (also after a failed pivot, which the status word reports, so
         // that no tile waits in vain)
-        potrf_lds<T>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
-                     status + (status_slot ? status_slot[tk.s] : 0), wctl.err, tk.blk,
-                     tk.flag >= 0 ? hflags + 4 * tk.flag : nullptr);
+        potrf_lds<T, BF>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
+                         status + (status_slot ? status_slot[tk.s] : 0), wctl.err, tk.blk,
+                         tk.flag >= 0 ? hflags + 4 * tk.flag : nullptr, pfl);
         return;
     }
     if (MODE == MODE_TRAILING && tk.flag >= 0) {
@@ -979,12 +1083,14 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
 // time with the next chunk in registers while the current one is consumed.
 // The epilogue goes through LDS in four passes of 32 columns.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool BF = false>
 __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                   const int32_t *rel, T *Lx) {
     constexpr int TM = 128, KB = 16, PADA = 4, CPT = 8, NT = 512;
+    constexpr int KBB = 32, RS = KBB + 8;  // BF16: K per chunk, LDS row stride (bf16)
     using acc_t = typename Mfma<T>::acc;
-    __shared__ T smem[2 * KB * (TM + PADA)];
+    constexpr int kSmem = BF ? (2 * TM * RS * 2 + sizeof(T) - 1) / sizeof(T) : 2 * KB * (TM + PADA);
+    __shared__ T smem[kSmem];
     __shared__ int64_t cb[TM], cr[TM];
     T(*As)[TM + PADA] = reinterpret_cast<T(*)[TM + PADA]>(smem);
     T(*Bs)[TM + PADA] = reinterpret_cast<T(*)[TM + PADA]>(smem + KB * (TM + PADA));
@@ -1009,6 +1115,48 @@ __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const i
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
     }
+    if constexpr (BF) {
+        // BF16 operands, FP32 accumulation (as in k_tiles): thread (row lr,
+        // quarter lk) stages k = 8 lk .. 8 lk + 7 of its rows of A and B
+        static_assert(sizeof(T) == 4, "BF16 updates are for FP32 panels");
+        __bf16 *Ab = reinterpret_cast<__bf16 *>(smem);
+        __bf16 *Bb = Ab + TM * RS;
+        float fa[8], fb[8];
+        auto loadb = [&](int kb) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t k = min(kb + 8 * lk + e, tk.k1 - 1);
+                fa[e] = pa[k * m];
+                fb[e] = pb[k * m];
+            }
+        };
+        loadb(tk.k0);
+        for (int kb = tk.k0; kb < tk.k1; kb += KBB) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool kin = kb + 8 * lk + e < tk.k1;
+                fa[e] = (kin && row_ok) ? fa[e] : 0.0f;
+                fb[e] = (kin && col_ok) ? fb[e] : 0.0f;
+            }
+            *reinterpret_cast<bf16x8 *>(Ab + lr * RS + 8 * lk) = to_bf16x8(fa);
+            *reinterpret_cast<bf16x8 *>(Bb + lr * RS + 8 * lk) = to_bf16x8(fb);
+            __syncthreads();
+            if (kb + KBB < tk.k1) loadb(kb + KBB);
+            bf16x8 af[4], bf[2];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                af[a] = *reinterpret_cast<const bf16x8 *>(Ab + (wr + a * 16 + (lane & 15)) * RS + 8 * (lane >> 4));
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bf[b] = *reinterpret_cast<const bf16x8 *>(Bb + (wc + b * 16 + (lane & 15)) * RS + 8 * (lane >> 4));
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = mfma_bf16(af[a], bf[b], acc[a][b]);
+            __syncthreads();
+        }
+    } else {
     T ra[KB / 4], rb[KB / 4];
     auto load = [&](int kb) {
 #pragma unroll
@@ -1042,9 +1190,11 @@ __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const i
         }
         __syncthreads();
     }
+    }
     // epilogue: 4 passes of 32 columns staged as Cs[32][128 + 1]; in pass p
     // the two waves with wc = 32 p stage their columns, then thread (row r,
     // quarter cq) adds 8 of them
+    static_assert(32 * (TM + 1) <= kSmem, "the epilogue's staging fits");
     T(*Cs)[TM + 1] = reinterpret_cast<T(*)[TM + 1]>(smem);
     const int r = tid & 127, cq = tid >> 7;
     const int64_t gi = tk.i0 + r;
@@ -2043,49 +2193,78 @@ void launch_assemble(const DevPlan &P, int64_t nnz, const double *values, T *Lx,
 }
 
 template <typename T>
+void launch_pivot_floor(const DevPlan &P, int64_t n, const double *values, double theta, T *floor, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pivot_floor<T>, dim3(grid1(n, 256)), dim3(256), 0, st, P.dsrc, n, values, theta, floor);
+}
+
+template <typename T>
 void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *deverr, hipStream_t st) {
+                  int32_t *deverr, PivotFloor<T> pfl, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0, Lx, Linv,
-                       status, P.status_slot, deverr);
+    if (pfl.v)
+        hipLaunchKernelGGL((k_potrf<T, true>), dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0, Lx,
+                           Linv, status, P.status_slot, deverr, pfl);
+    else
+        hipLaunchKernelGGL((k_potrf<T, false>), dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.potrf_tasks + t0, Lx,
+                           Linv, status, P.status_slot, deverr, pfl);
 }
 
 template <typename T>
 void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                 hipStream_t st) {
+                 PivotFloor<T> pfl, hipStream_t st) {
     if (t1 <= t0) return;
     hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(256), 0, st, P.tiny_tasks + t0, t1 - t0,
-                       P.cbase, P.crel, P.rel, Lx, Linv, status, P.status_slot);
+                       P.cbase, P.crel, P.rel, Lx, Linv, status, P.status_slot, pfl);
 }
 
 template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  hipStream_t st) {
+                  PivotFloor<T> pfl, hipStream_t st) {
     if (t1 <= t0) return;
     hipLaunchKernelGGL(k_small<T>, dim3((unsigned)(t1 - t0)), dim3(256), 0, st, P.small_tasks + t0, P.cbase,
-                       P.crel, P.rel, Lx, Linv, status, P.status_slot);
+                       P.crel, P.rel, Lx, Linv, status, P.status_slot, pfl);
 }
 
 template <typename T>
 void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                  int32_t *hflags, WaitCtl wc, hipStream_t st) {
+                  int32_t *hflags, WaitCtl wc, bool bf16, PivotFloor<T> pfl, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g((unsigned)(t1 - t0)), b(256);
+    if constexpr (std::is_same<T, float>::value) {
+        if (bf16 && mode == kTilesTrailing) {
+            hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING, true>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel,
+                               P.rel, Linv, Lx, status, P.status_slot, hflags, wc, pfl);
+            return;
+        }
+        if (bf16 && mode == kTilesScatter) {
+            hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER, true>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel,
+                               P.rel, Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc, pfl);
+            return;
+        }
+    }
     if (mode == kTilesTrailing)
         hipLaunchKernelGGL((k_tiles<T, MODE_TRAILING>), g, b, 0, st, P.int_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, hflags, wc);
+                           Linv, Lx, status, P.status_slot, hflags, wc, PivotFloor<T>{});
     else if (mode == kTilesScatter)
         hipLaunchKernelGGL((k_tiles<T, MODE_SCATTER>), g, b, 0, st, P.ext_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc, PivotFloor<T>{});
     else
         hipLaunchKernelGGL((k_tiles<T, MODE_TRSM>), g, b, 0, st, P.trsm_tiles + t0, P.cbase, P.crel, P.rel,
-                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc);
+                           Linv, Lx, status, P.status_slot, (int32_t *)nullptr, wc, PivotFloor<T>{});
 }
 
 template <typename T>
-void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, hipStream_t st) {
+void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_tiles128<T>, dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
+    if constexpr (std::is_same<T, float>::value) {
+        if (bf16) {
+            hipLaunchKernelGGL((k_tiles128<T, true>), dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
+                               P.ext_tiles_big + t0, P.cbase, P.crel, P.rel, Lx);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_tiles128<T, false>), dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
                        P.ext_tiles_big + t0, P.cbase, P.crel, P.rel, Lx);
 }
 
@@ -2271,14 +2450,15 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_zero<T>(T *, int64_t, hipStream_t);                                                \
     template void launch_assemble<T>(const DevPlan &, int64_t, const double *, T *, hipStream_t);           \
     template void launch_potrf<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
-                                  int32_t *, hipStream_t);                                                  \
+                                  int32_t *, PivotFloor<T>, hipStream_t);                                   \
+    template void launch_pivot_floor<T>(const DevPlan &, int64_t, const double *, double, T *, hipStream_t); \
     template void launch_tiles<T>(const DevPlan &, int, int64_t, int64_t, T *, T *, unsigned long long *,    \
-                                  int32_t *, WaitCtl, hipStream_t);                                         \
+                                  int32_t *, WaitCtl, bool, PivotFloor<T>, hipStream_t);                    \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
-                                  hipStream_t);                                                             \
+                                  PivotFloor<T>, hipStream_t);                                              \
     template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \
-                                 hipStream_t);                                                              \
-    template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, hipStream_t);                  \
+                                 PivotFloor<T>, hipStream_t);                                               \
+    template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, bool, hipStream_t);            \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \
                                     hipStream_t);                                                           \
     template void launch_perm_out<T>(const DevPlan &, int64_t, int, const T *, double *, int64_t,           \

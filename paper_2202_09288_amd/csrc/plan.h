@@ -159,6 +159,7 @@ struct Symbolic {
     int64_t flops = 0, nnzL = 0, max_w = 0, max_m = 0;
     int32_t nlevels = 0;
     std::vector<int64_t> amap;  // caller entry k -> panel offset
+    std::vector<int64_t> dsrc;  // permuted column j -> caller entry of its diagonal
     // full symmetric A in the caller's ordering (CSR), entries pointing into
     // the caller's lower-CSC values; used by iterative refinement
     std::vector<int64_t> csr_ptr, csr_val;

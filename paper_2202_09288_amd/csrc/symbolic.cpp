@@ -263,9 +263,11 @@ int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32
 
     // ---- assembly map -------------------------------------------------------
     S.amap.resize(S.nnzA);
+    S.dsrc.assign(n, 0);
     for (int64_t c = 0; c < n; ++c)
         for (int64_t k = colptr[c]; k < colptr[c + 1]; ++k) {
             int32_t a = S.iperm[rowidx[k]], b = S.iperm[c];
+            if (a == b) S.dsrc[a] = k;
             int32_t row = std::max(a, b), col = std::min(a, b);
             int32_t s = S.snode[col];
             int64_t m = S.rptr[s + 1] - S.rptr[s];
@@ -826,6 +828,7 @@ int merge(const std::vector<const Symbolic *> &parts, Symbolic &M, std::vector<i
         for (int32_t r : S.rows) M.rows.push_back((int32_t)(c0 + r));
         for (int32_t s = 0; s < S.nsuper; ++s) M.status_slot.push_back((int32_t)i);
         for (int64_t a : S.amap) M.amap.push_back(p0 + a);
+        for (int64_t d : S.dsrc) M.dsrc.push_back(val_off[i] + d);
         // the full-A CSR of the union: rows and columns shifted by the
         // part's first column, entries by its first caller value
         const int64_t e0 = M.csr_ptr.back();

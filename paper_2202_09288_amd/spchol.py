@@ -29,8 +29,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, INVALID_INPUT, NOT_SPD, OUT_OF_MEMORY, NO_CONVERGENCE, DEVICE_ERROR, BAD_HANDLE, NO_DEVICE = \
     0, -1, -2, -3, -4, -5, -6, -7
-FP64, FP32 = 0, 1
-_PREC = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
+FP64, FP32, FP32_BF16UPD = 0, 1, 2
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16upd": FP32_BF16UPD, FP64: FP64, FP32: FP32, FP32_BF16UPD: FP32_BF16UPD}
 
 EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbolic_export", "spc_factorize",
            "spc_refactorize", "spc_factorize_batch", "spc_solve", "spc_solve_refined", "spc_sync",
@@ -40,7 +40,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
            "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats",
-           "spc_factor_set_wait_limit", "spc_solve_noalloc")
+           "spc_factor_set_wait_limit", "spc_solve_noalloc", "spc_factor_pivot_floors")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -103,6 +103,7 @@ _lib.spc_batch_solve_refined.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(
                                          ctypes.POINTER(_RefineInfo)]
 _lib.spc_factor_set_graph.argtypes = [_P, ctypes.c_int]
 _lib.spc_factor_set_wait_limit.argtypes = [_P, ctypes.c_int32]
+_lib.spc_factor_pivot_floors.argtypes = [_P, ctypes.POINTER(_i64)]
 _lib.spc_factor_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
 _lib.spc_batch_level_stats.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_KernelStats)]
 _lib.spc_batch_set_graph.argtypes = [_P, ctypes.c_int]
@@ -324,6 +325,13 @@ class Factor:
     def set_graph(self, on: bool = True):
         """Capture the factorization into a HIP graph and replay it."""
         _check(_lib.spc_factor_set_graph(self._h, 1 if on else 0), "spc_factor_set_graph")
+
+    def pivot_floors(self) -> int:
+        """BF16 updates: pivots of the last factorization raised to their
+        floor (spc_factor_pivot_floors)."""
+        v = _i64(0)
+        _check(_lib.spc_factor_pivot_floors(self._h, ctypes.byref(v)), "spc_factor_pivot_floors")
+        return int(v.value)
 
     def set_wait_limit(self, polls: int):
         """Polls before a bounded wait on another workgroup gives up

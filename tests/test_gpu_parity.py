@@ -981,3 +981,58 @@ def test_refined_nan_rhs_is_not_converged(torch_dev, lib):
     assert out["status"] == lib.NO_CONVERGENCE
     assert not out["systems"][1]["converged"]
     assert out["systems"][0]["converged"] and out["systems"][2]["converged"]
+
+
+# ---- BF16 Schur updates (SPC_FP32_BF16UPD) + FP64 refinement ----------------
+
+def test_bf16upd_factor_error_vs_oracle(torch_dev, lib):
+    """The BF16-update factor against the FP64 oracle on a grid whose big
+    supernodes go through the BF16 tile kernels (64- and 128-tiles).  Parity
+    unpinned: no closed form bounds it; BF16 rounds each operand to 8
+    significant bits (unit roundoff 2^-9), so relF of a few 1e-3 is what the
+    operands' rounding alone gives, and a wrong MFMA operand layout would
+    give relF of order 1.  Refined in FP64 it meets the 1e-12 bar."""
+    torch = torch_dev
+    s = grid((30, 30, 30), nrhs=3)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lref = S.factor(s.values)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, tuning={"small_w": -1, "tiny_w": -1, "big_min": 64,
+                                                                 "big_min_k": 32})
+    dv = torch.from_numpy(s.values).cuda()
+    res = {}
+    for prec in ("fp32", "bf16upd"):
+        F = lib.factorize(sym, dv, prec)
+        F.sync()
+        res[prec] = oracle.rel_frobenius(F.export(), Lref, S.lower_mask())
+        B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+        X = torch.zeros_like(B)
+        info = F.solve_refined(dv, B, X, tol=1e-12, maxit=50)
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+        print(f"30^3 {prec}: relF vs oracle {res[prec]:.3e}, refinement {info}, host eta {eta:.3e}", flush=True)
+        assert info["converged"] and eta <= BERR_FP64
+    assert res["bf16upd"] <= 2e-2
+    assert res["bf16upd"] > res["fp32"]  # the BF16 path really ran
+
+
+def test_bf16upd_refined_elasticity_kappa1e6(torch_dev, lib):
+    """A kappa = 1e6 elasticity case (3x3 blocks of random orientation):
+    the BF16-update factor (pivots below 2^-8 of their diagonal entry raised
+    to it) refined in FP64 (classical steps, then CG) to a backward error of
+    1e-12 on 4 right-hand sides.  Its distance from the oracle's factor is
+    reported (parity unpinned)."""
+    torch = torch_dev
+    s = W.elasticity27((14, 13, 12), 88, 1, kappa=1e6, nrhs=4, power_iters=30)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv, "bf16upd")
+    F.sync()
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    relF = oracle.rel_frobenius(F.export(), S.factor(s.values), S.lower_mask())
+    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    X = torch.zeros_like(B)
+    info = F.solve_refined(dv, B, X, tol=1e-12, maxit=200)
+    eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+    print(f"elasticity kappa 1e6 n={s.n} bf16upd: relF vs oracle {relF:.3e}, {F.pivot_floors()} pivots raised "
+          f"to their floor, {info}, host eta {eta:.3e}", flush=True)
+    assert info["converged"] and info["status"] == lib.OK
+    assert eta <= BERR_FP64

@@ -455,3 +455,17 @@ def test_parallel_oracle_not_spd_same_column():
     with pytest.raises(oracle.NotSPD) as e2:
         S.factor(v, threads=4)
     assert e1.value.column == e2.value.column == min(cols)
+
+
+def test_parallel_forest_matches_subtrees():
+    """The multi-threaded mode restricted to a forest of subtrees gives the
+    panels of each subtree exactly as the full sequential factorization."""
+    s = W.laplacian((10, 9, 8), "7pt", 77, 5, unit=False, shift=1e-2, nrhs=1)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lx = S.factor(s.values)
+    roots = np.nonzero(S.level == 2)[0]
+    Lf = S.factor_forest(s.values, roots, threads=4)
+    for r in roots:
+        _, first = S.factor_subtree(s.values, int(r))
+        sl = slice(S.lptr[first], S.lptr[r + 1])
+        assert np.array_equal(Lf[sl], Lx[sl])
