@@ -94,8 +94,8 @@ def cpu_baseline(s, target_s, name):
     first = _subtree_firsts(S)
     sub_flops = cum[sp[1:]] - cum[sp[first]]
     lev = S.level
-    one_rate = 6.0e9                     # about what one core reaches on the lower levels
-    all_rate = one_rate * threads * 0.5  # level sync and the top of each subtree cost parallelism
+    one_rate = 1.0e10                    # about what one core reaches on these levels
+    all_rate = one_rate * threads * 0.8  # level sync and the top of each subtree cost some parallelism
 
     def pick(budget, min_roots):
         for L in range(S.sizes["nlevels"] - 1, -1, -1):

@@ -91,10 +91,17 @@ typedef struct spc_options {
      *                     gives every block a TRSM launch of its own (no
      *                     waits inside a launch: for many factorizations
      *                     sharing the device on several streams).  Default 1.
+     *   delay             column blocks per bulk trailing update inside a wide
+     *                     supernode: the columns beyond a group of `delay`
+     *                     64-column blocks receive the group's update once,
+     *                     with K = 64 * delay, while each next block inside
+     *                     the group is brought up to date on its own; at most
+     *                     8 (default 1; a negative value keeps 1)
      * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
     int32_t tiny_w, tiny_m, small_w, small_m;
     int32_t big_min, big_min_k, solve_persist_max;
     int32_t handover;
+    int32_t delay;
 } spc_options;
 
 /* Summary numbers of an analysis. */

@@ -796,7 +796,8 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
                         pick(opts->big_min, spc::kBigMin, kNone, kNone, &tu.big_min) &&
                         pick(opts->big_min_k, spc::kBigMinK, kNone, kNone, &tu.big_min_k) &&
                         pick(opts->solve_persist_max, spc::kSolvePersistMax, kNone, 0, &tu.solve_persist_max) &&
-                        pick(opts->handover, 1, 1, 0, &tu.handover);
+                        pick(opts->handover, 1, 1, 0, &tu.handover) &&
+                        pick(opts->delay, spc::kDelay, spc::kDelayMax, spc::kDelay, &tu.delay);
         if (!ok) {
             delete s;
             return SPC_INVALID_INPUT;

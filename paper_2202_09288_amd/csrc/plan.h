@@ -27,13 +27,16 @@ constexpr int kTinyM = 64;
 // triangle gets an explicit inverse in the inverse store.
 constexpr int kNB = 64;
 constexpr int kPanelNB = kNB;
-// Column blocks per bulk trailing update: the columns beyond a group of
-// kDelay blocks are updated once, with all of the group's panels (K =
-// kDelay * kNB), while each next block inside the group is brought up to
-// date on its own just before it is factored.  Measured on the 60^3 grid:
-// 1 -> 16.3 ms, 2 -> 16.6, 3 -> 17.0, 4 -> 17.3 (the column-only launches
-// lengthen the chain of dependent steps more than the deeper updates save).
+// Column blocks per bulk trailing update (default; a tuning option): the
+// columns beyond a group of `delay` blocks are updated once, with all of the
+// group's panels (K = delay * kNB), while each next block inside the group
+// is brought up to date on its own just before it is factored.  Measured on
+// the 60^3 grid: 1 -> 16.3 ms, 2 -> 16.6, 3 -> 17.0, 4 -> 17.3 (the
+// column-only launches lengthen the chain of dependent steps more than the
+// deeper updates save); workloads whose top supernodes are bound by the
+// trailing update's memory traffic rather than by that chain can gain.
 constexpr int kDelay = 1;
+constexpr int kDelayMax = 8;
 constexpr int kSolveNB = kNB;
 // Rows of one solve-update task.
 constexpr int kSolveRows = 256;
@@ -54,6 +57,7 @@ struct Tuning {
     int32_t big_min = kBigMin, big_min_k = kBigMinK;
     int32_t solve_persist_max = kSolvePersistMax;
     int32_t handover = 1;  // fused TRSM with in-launch waits (0: off)
+    int32_t delay = kDelay;  // column blocks per bulk trailing update
 };
 
 // One pair (source supernode s, ancestor t) of the scatter: rows

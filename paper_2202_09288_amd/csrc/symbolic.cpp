@@ -446,12 +446,12 @@ int build_schedule(Symbolic &S) {
             st.f0 = (int64_t)S.potrf_tasks.size();
             st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
-            // Blocks go in groups of kDelay.  Inside a group, step b brings
+            // Blocks go in groups of tu.delay.  Inside a group, step b brings
             // block b+1's columns up to date with the group's panels so far
             // (one column of tiles, K = the group's columns up to b) and
             // factors block b+1 in that column's diagonal tile; the last step
             // of a group updates every column beyond with all of the group's
-            // panels at once (K = kDelay blocks).
+            // panels at once (K = tu.delay blocks).
             // The trailing launch holds the diagonal tiles of block b+1 first
             // (which also factor it), then the columns beyond block b+1, then
             // the tiles below block b+1's diagonal.  When block b+1 is a full
@@ -464,8 +464,8 @@ int build_schedule(Symbolic &S) {
             // so the workgroup it waits for is resident or done, even while
             // other launches (other streams) fill the device.  Gaps in that
             // pattern take other tiles, else no-op entries (s = -1).
-            const int64_t gb = b - b % kDelay;  // first block of b's group
-            const bool bulk = b % kDelay == kDelay - 1;
+            const int64_t gb = b - b % tu.delay;  // first block of b's group
+            const bool bulk = b % tu.delay == tu.delay - 1;
             std::vector<TileTask> diag, rest, below;
             std::vector<int32_t> below_diag;  // diagonal tile of each waiting tile (index into diag)
             for (int32_t s : bylevel[l]) {

@@ -38,6 +38,7 @@ GROUPS = [
     ("big", ("big_min", "big_min_k"), [(256, 128), (128, 64), (512, 128), (256, 256), (-1, -1)]),
     ("persist", ("solve_persist_max",), [(1024,), (256,), (4096,)]),
     ("handover", ("handover",), [(1,), (-1,)]),
+    ("delay", ("delay",), [(1,), (2,), (3,), (4,)]),
 ]
 
 
@@ -166,7 +167,7 @@ def tune(systems, nrhs: int, precision: str = "fp64", reps: int = 5, log=print) 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", default="grid3d60", choices=["grid3d60", "grid2d64", "elast48", "batch512"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16upd"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args(argv)

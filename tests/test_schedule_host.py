@@ -13,7 +13,8 @@ from paper_2202_09288_amd import workloads as W
 from paper_2202_09288_amd import spchol  # noqa: E402  (conftest builds it when missing)
 
 TUNINGS = [None, {"handover": -1}, {"tiny_w": -1, "small_w": -1}, {"big_min": 1, "big_min_k": 1},
-           {"tiny_w": 4, "tiny_m": 32, "small_w": 16, "small_m": 64}]
+           {"tiny_w": 4, "tiny_m": 32, "small_w": 16, "small_m": 64}, {"delay": 2}, {"delay": 3},
+           {"delay": 4, "handover": -1}]
 
 
 @pytest.mark.parametrize("dims", [(20, 20, 20), (30, 24, 28), (37, 23), (200, 150), (12, 9, 11)])
@@ -34,7 +35,7 @@ def test_schedule_invariants_dense(n):
     A = X @ X.T + n * np.eye(n)
     colptr, rowidx, v = W.lower_csc(n, r, c, A[r, c])
     perm = np.arange(n, dtype=np.int32)
-    for tuning in (None, {"handover": -1}, {"tiny_w": -1, "small_w": -1}):
+    for tuning in (None, {"handover": -1}, {"tiny_w": -1, "small_w": -1}, {"delay": 2}, {"delay": 4}):
         spchol.Symbolic(colptr, rowidx, perm, 0.05, tuning).verify()
 
 
