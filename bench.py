@@ -274,7 +274,8 @@ def roofline_of(prof, nprof, precision, workload, kernel_names):
 
 
 def level_rows(lv, nprof):
-    """Per etree level (-1: assembly): launches, device ms and TFLOP/s of one factorization."""
+    """Per etree level (-2: the small-subtree launch, -1: assembly): launches, device ms and TFLOP/s of one
+    factorization."""
     return [[v["level"], v["launches"] // nprof, round(v["ms"] / nprof, 3),
              round(v["flops"] / (v["ms"] / nprof * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0] for v in lv]
 
@@ -439,7 +440,8 @@ def bench_elast(args):
         "frac_of_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
         "analyze_s": round(t_analyze, 2),
         "roofline": roofline,
-        "factor_levels": {"columns": ["etree level (-1: assembly)", "launches", "device ms", "TFLOP/s"],
+        "factor_levels": {"columns": ["etree level (-2: the persistent launch over the small subtrees, -1: assembly)",
+                                      "launches", "device ms", "TFLOP/s"],
                           "rows": level_rows(lv, nprof)},
         "vs_plain_fp64": {"plain_fp64": plain, "fp32_refined": leg32, "bf16upd_refined": leg16,
                           "speedup_factor_plus_solve": round(plain["factor_plus_solve_ms"] /
@@ -641,7 +643,8 @@ def bench_grid3d(args):
         "frac_of_peak": round(value / (peak * 1e3), 4),
         "analyze_s": round(t_analyze, 2),
         "roofline": roofline,
-        "factor_levels": {"columns": ["etree level (-1: assembly)", "launches", "device ms", "TFLOP/s"],
+        "factor_levels": {"columns": ["etree level (-2: the persistent launch over the small subtrees, -1: assembly)",
+                                      "launches", "device ms", "TFLOP/s"],
                           "rows": levels},
     }
     if not args.no_cpu_baseline:

@@ -97,11 +97,19 @@ typedef struct spc_options {
      *                     with K = 64 * delay, while each next block inside
      *                     the group is brought up to date on its own; at most
      *                     8 (default 1; a negative value keeps 1)
+     *   persist           1: every small subtree (a supernode whose whole
+     *                     subtree is within the one-wave or one-workgroup
+     *                     limits), of every system of a batch, is factored by
+     *                     one persistent launch across all its levels, with
+     *                     device-side dependency counters; a negative value
+     *                     (the default, 0) launches those supernodes level by
+     *                     level, which measured faster on the workloads here.
      * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
     int32_t tiny_w, tiny_m, small_w, small_m;
     int32_t big_min, big_min_k, solve_persist_max;
     int32_t handover;
     int32_t delay;
+    int32_t persist;
 } spc_options;
 
 /* Summary numbers of an analysis. */
@@ -346,7 +354,8 @@ enum spc_kernel_class {
     SPC_K_SCATTER_BIG = 5,    /* the same on 128x128 tiles (large supernodes) */
     SPC_K_SMALL = 6,          /* whole small supernodes: POTRF, TRSM, inverse, scatter */
     SPC_K_TINY = 7,           /* the same for tiny supernodes, one wave each */
-    SPC_K_COUNT = 8
+    SPC_K_SMALL_TREES = 8,    /* the persistent launch over the small subtrees (all their levels) */
+    SPC_K_COUNT = 9
 };
 
 typedef struct spc_kernel_stats {
@@ -377,7 +386,8 @@ int spc_batch_set_profiling(spc_batch b, int on);
 int spc_batch_kernel_stats(spc_batch b, int kernel_class, spc_kernel_stats *out);
 
 /* The same totals per elimination-tree level of the schedule (0 = leaves,
- * up to spc_info.levels - 1; -1 = the assembly of A), over all classes. */
+ * up to spc_info.levels - 1; -1 = the assembly of A; -2 = the persistent
+ * launch over the small subtrees, which spans levels), over all classes. */
 int spc_factor_level_stats(spc_factor f, int level, spc_kernel_stats *out);
 int spc_batch_level_stats(spc_batch b, int level, spc_kernel_stats *out);
 

@@ -65,6 +65,10 @@ struct spc_factor_s {
     // each column block (in the status allocation, after the error word)
     int32_t *hflags = nullptr;
     int nflags = 0;
+    // persistent launch over the small subtrees: its work counter and one
+    // dependency counter per supernode (after the flags)
+    int32_t *qctr = nullptr;
+    int32_t *pdep = nullptr;
     void *work = nullptr;       // solve vectors Y, X, Acc (factor precision) + block counters
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
@@ -217,6 +221,13 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.stgt.data(), bytes_of(S.stgt), (const void **)&P.stgt},
         {S.fdep.data(), bytes_of(S.fdep), (const void **)&P.fdep},
         {S.bwd_order.data(), bytes_of(S.bwd_order), (const void **)&P.bwd_order},
+        {S.pqueue.data(), bytes_of(S.pqueue), (const void **)&P.pqueue},
+        {S.pchunk.data(), bytes_of(S.pchunk), (const void **)&P.pchunk},
+        {S.psmall.data(), bytes_of(S.psmall), (const void **)&P.psmall},
+        {S.ptiny.data(), bytes_of(S.ptiny), (const void **)&P.ptiny},
+        {S.pdep0.data(), bytes_of(S.pdep0), (const void **)&P.pdep0},
+        {S.ptgt_ptr.data(), bytes_of(S.ptgt_ptr), (const void **)&P.ptgt_ptr},
+        {S.ptgt.data(), bytes_of(S.ptgt), (const void **)&P.ptgt},
     };
     size_t total = 0;
     for (auto &p : pieces) total += (p.bytes + 255) & ~size_t(255);
@@ -246,7 +257,8 @@ size_t plan_bytes(const spc::Symbolic &S) {
            bytes_of(S.perm) + bytes_of(S.dsrc) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
            bytes_of(S.stasks) + bytes_of(S.stiny) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
-           bytes_of(S.fdep) + bytes_of(S.bwd_order);
+           bytes_of(S.fdep) + bytes_of(S.bwd_order) + bytes_of(S.pqueue) + bytes_of(S.pchunk) + bytes_of(S.psmall) + bytes_of(S.ptiny) +
+           bytes_of(S.pdep0) + bytes_of(S.ptgt_ptr) + bytes_of(S.ptgt);
 }
 
 // Brackets one launch with a pair of events (on the launch's stream) when
@@ -291,8 +303,8 @@ struct Prof {
 // factoring the next block overlaps the bulk of the update.
 template <typename T>
 void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double *d_values, T *Lx, T *Linv,
-                    unsigned long long *status, int32_t *hflags, spc::WaitCtl wc, bool bf16, T *pfloor,
-                    hipStream_t st, Prof &prof) {
+                    unsigned long long *status, int32_t *hflags, int32_t *qctr, int32_t *pdep, spc::WaitCtl wc,
+                    bool bf16, T *pfloor, hipStream_t st, Prof &prof) {
     spc::PivotFloor<T> pfl;
     if (bf16) {
         pfl.v = pfloor;
@@ -303,6 +315,13 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         spc::launch_assemble<T>(P, S.nnzA, d_values, Lx, st);
         if (bf16) spc::launch_pivot_floor<T>(P, S.n, d_values, spc::kBf16PivotTheta, pfloor, st);
     });
+    if (!S.pqueue.empty()) {
+        prof.level = -2;
+        prof.run(SPC_K_SMALL_TREES, S.persist_flops, st, [&] {
+            spc::launch_persist_small<T>(P, (int64_t)S.pchunk.size() - 1, S.nsuper, pdep, qctr, Lx, Linv, status, pfl,
+                                         wc, st);
+        });
+    }
     for (int32_t l = 0; l < S.nlevels; ++l) {
         prof.level = l;
         if (S.tiny_ptr[l + 1] > S.tiny_ptr[l])
@@ -393,11 +412,11 @@ int capture_factor(spc_factor f, const double *d_values) {
     Prof none{nullptr};
     const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc,
-                               false, nullptr, f->cap_stream, none);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, f->qctr,
+                               f->pdep, wc, false, nullptr, f->cap_stream, none);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc,
-                              f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, f->cap_stream, none);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, f->qctr,
+                              f->pdep, wc, f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, f->cap_stream, none);
     hipGraph_t g = nullptr;
     const hipError_t e0 = hipGetLastError();
     const hipError_t e1 = hipStreamEndCapture(f->cap_stream, &g);
@@ -432,11 +451,11 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     Prof prof{f};
     const spc::WaitCtl wc{f->deverr, f->spin};
     if (f->precision == SPC_FP64)
-        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, wc, false,
-                               nullptr, st, prof);
+        enqueue_factor<double>(S, P, d_values, (double *)f->Lx, (double *)f->Linv, f->status, f->hflags, f->qctr,
+                               f->pdep, wc, false, nullptr, st, prof);
     else
-        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, wc,
-                              f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, st, prof);
+        enqueue_factor<float>(S, P, d_values, (float *)f->Lx, (float *)f->Linv, f->status, f->hflags, f->qctr,
+                              f->pdep, wc, f->precision == SPC_FP32_BF16UPD, (float *)f->pfloor, st, prof);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(f->ev1, st));
     f->stream = st;
@@ -463,12 +482,17 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
     f->nflags = 4 * (int)sym->S.sblocks.size();  // one per 16-column panel of each block
-    // status words, the device-error word (padded to 8 bytes), hand-over flags
+    // status words, the device-error word and the raised-pivot count,
+    // hand-over flags, the persistent launch's work counter (padded to 8
+    // bytes) and its dependency counters
     if (e == hipSuccess)
-        e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * (nstatus + 1) + sizeof(int32_t) * f->nflags);
+        e = hipMalloc((void **)&f->status, sizeof(unsigned long long) * (nstatus + 1) +
+                                               sizeof(int32_t) * (f->nflags + 2 + (size_t)sym->S.nsuper));
     if (e == hipSuccess) {
         f->deverr = reinterpret_cast<int32_t *>(f->status + nstatus);
         f->hflags = reinterpret_cast<int32_t *>(f->status + nstatus + 1);
+        f->qctr = f->hflags + f->nflags;
+        f->pdep = f->qctr + 2;
     }
     if (e == hipSuccess && precision == SPC_FP32_BF16UPD)
         e = hipMalloc(&f->pfloor, std::max<size_t>(1, (size_t)sym->S.n) * sizeof(float));
@@ -797,7 +821,8 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
                         pick(opts->big_min_k, spc::kBigMinK, kNone, kNone, &tu.big_min_k) &&
                         pick(opts->solve_persist_max, spc::kSolvePersistMax, kNone, 0, &tu.solve_persist_max) &&
                         pick(opts->handover, 1, 1, 0, &tu.handover) &&
-                        pick(opts->delay, spc::kDelay, spc::kDelayMax, spc::kDelay, &tu.delay);
+                        pick(opts->delay, spc::kDelay, spc::kDelayMax, spc::kDelay, &tu.delay) &&
+                        pick(opts->persist, 0, 1, 0, &tu.persist);
         if (!ok) {
             delete s;
             return SPC_INVALID_INPUT;
@@ -1070,7 +1095,7 @@ int spc_factor_kernel_stats(spc_factor f, int kernel_class, spc_kernel_stats *ou
 
 int spc_factor_level_stats(spc_factor f, int level, spc_kernel_stats *out) {
     if (!fac_ok(f)) return SPC_BAD_HANDLE;
-    if (!out || level < -1 || level >= f->sym->S.nlevels) return SPC_INVALID_INPUT;
+    if (!out || level < -2 || level >= f->sym->S.nlevels) return SPC_INVALID_INPUT;
     out->launches = 0;
     out->total_ms = 0.0;
     out->flops = 0.0;

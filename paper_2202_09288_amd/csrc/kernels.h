@@ -30,6 +30,13 @@ struct DevPlan {
     const int32_t *stgt;
     const int32_t *fdep;         // forward contributions per block
     const int32_t *bwd_order;    // task order of the backward sweep
+    const PersistEntry *pqueue;  // persistent launch over the small subtrees
+    const int32_t *pchunk;
+    const SmallTask *psmall;
+    const SmallTask *ptiny;
+    const int32_t *pdep0;
+    const int64_t *ptgt_ptr;
+    const int32_t *ptgt;
 };
 
 // Bounded waits on other workgroups: `err` is the factor's device-error
@@ -106,6 +113,13 @@ void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st);
+
+// The persistent launch over the small subtrees (nchunks chunks of queue
+// entries, nsuper dependency counters in pdep, one work counter): resets the
+// counters, then runs every entry.
+template <typename T>
+void launch_persist_small(const DevPlan &P, int64_t nchunks, int64_t nsuper, int32_t *pdep, int32_t *qctr, T *Lx,
+                          T *Linv, unsigned long long *status, PivotFloor<T> pfl, WaitCtl wc, hipStream_t st);
 
 template <typename T>
 void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,

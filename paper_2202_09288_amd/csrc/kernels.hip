@@ -109,6 +109,19 @@ __device__ __forceinline__ void flag_device_error(int32_t *deverr) {
     __hip_atomic_fetch_or(deverr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bounded waits: poll an int until it holds `want`; after `spin` polls
+// (about a second by default) give up, flag err and go on, so every wave
+// always exits.  Once any wait has given up, the others stop waiting too.
+__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err, int32_t spin) {
+    for (int it = 0; it < spin; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
+        // once any wait has given up, the others stop waiting too
+        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    flag_device_error(err);
+}
+
 template <typename T>
 __global__ void k_assemble(const int64_t *amap, int64_t nnz, const double *values, T *Lx) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -556,22 +569,24 @@ __device__ __forceinline__ int64_t lane_read_i64(int64_t v, int src) {
     return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t ntasks, const int64_t *cbase,
-                                              const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
-                                              unsigned long long *status, const int32_t *status_slot,
-                                              PivotFloor<T> pfl) {
+// One wave's tiny supernode (the body of k_tiny and of the persistent
+// launch).  COH: the panel is read with device-scope loads, for a launch in
+// which other workgroups (on other XCDs) scatter-added into it.
+template <typename T, bool COH>
+__device__ __forceinline__ void tiny_body(const SmallTask &tk, const int64_t *cbase, const int64_t *crel,
+                                          const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
+                                          const int32_t *status_slot, PivotFloor<T> pfl) {
     constexpr int WT = kTinyW, CB = 8;  // CB: update columns per batch of loads
     const int lane = threadIdx.x & 63;
-    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (ti >= ntasks) return;  // the whole wave
-    const SmallTask tk = tasks[ti];
     const int m = tk.m, w = tk.w;
     T *P = Lx + tk.loff;
     const int rc = min(lane, m - 1);
     T r[WT];
 #pragma unroll
-    for (int c = 0; c < WT; ++c) r[c] = P[(int64_t)min(c, w - 1) * m + rc];
+    for (int c = 0; c < WT; ++c) {
+        const T *src = &P[(int64_t)min(c, w - 1) * m + rc];
+        r[c] = COH ? dev_load(src) : *src;
+    }
     // scatter addressing of this lane's row position taken as a column
     const int64_t kpos = tk.roff + min(max(lane, w), m - 1);
     const int64_t my_cb = cbase[kpos], my_cr = crel[kpos];
@@ -648,6 +663,16 @@ __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t nt
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t ntasks, const int64_t *cbase,
+                                              const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
+                                              unsigned long long *status, const int32_t *status_slot,
+                                              PivotFloor<T> pfl) {
+    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ti >= ntasks) return;  // the whole wave
+    tiny_body<T, false>(tasks[ti], cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+}
+
 // ---------------------------------------------------------------------------
 // k_small: one workgroup per small supernode (w <= kSmallW, m <= kSmallM),
 // the whole m x w panel in LDS:
@@ -660,15 +685,27 @@ __global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t nt
 //      the ancestors: C[i][k] goes to cbase[k] + rel[crel[k] + i].
 // Pivots that are not positive and finite lower the status word.
 // ---------------------------------------------------------------------------
+// LDS of one small supernode: A[c][i] = panel entry (row i, column c), the
+// inverse Vt[c][a] = (L^{-1})_ac, and the scatter addresses of its rows.
 template <typename T>
-__global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int64_t *cbase, const int64_t *crel,
-                                               const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
-                                               const int32_t *status_slot, PivotFloor<T> pfl) {
+struct SmallLds {
+    T A[kSmallW][kSmallM + 1];
+    T Vt[kSmallW][kSmallW + 1];
+    int64_t cb[kSmallM], cr[kSmallM];
+};
+
+// One workgroup's small supernode (the body of k_small and of the
+// persistent launch); COH as in tiny_body.
+template <typename T, bool COH>
+__device__ __forceinline__ void small_body(const SmallTask &tk, SmallLds<T> &L, const int64_t *cbase,
+                                           const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
+                                           unsigned long long *status, const int32_t *status_slot,
+                                           PivotFloor<T> pfl) {
     constexpr int MS = kSmallM, WS = kSmallW, LPT = WS * MS / 256, SB = 8;
-    __shared__ T A[WS][MS + 1];   // A[c][i] = panel entry (row i, column c)
-    __shared__ T Vt[WS][WS + 1];  // inverse, Vt[c][a] = (L^{-1})_ac
-    __shared__ int64_t cb[MS], cr[MS];
-    const SmallTask tk = tasks[blockIdx.x];
+    auto &A = L.A;
+    auto &Vt = L.Vt;
+    auto &cb = L.cb;
+    auto &cr = L.cr;
     const int m = tk.m, w = tk.w;
     T *P = Lx + tk.loff;
     const int tid = threadIdx.x;
@@ -677,7 +714,8 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 #pragma unroll
         for (int q = 0; q < LPT; ++q) {
             const int e = tid + 256 * q, i = e % MS, c = e / MS;
-            ld[q] = P[(int64_t)min(c, w - 1) * m + min(i, m - 1)];
+            const T *src = &P[(int64_t)min(c, w - 1) * m + min(i, m - 1)];
+            ld[q] = COH ? dev_load(src) : *src;
         }
         if (tid < MS) {
             const int64_t k = tk.roff + min(max(tid, w), m - 1);
@@ -754,6 +792,79 @@ __global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int
 #pragma unroll
         for (int u = 0; u < SB; ++u)
             if (ok[u]) atomicAdd(&Lx[cb[cc_[u]] + rr[u]], -vv[u]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_small(const SmallTask *tasks, const int64_t *cbase, const int64_t *crel,
+                                               const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
+                                               const int32_t *status_slot, PivotFloor<T> pfl) {
+    __shared__ SmallLds<T> L;
+    small_body<T, false>(tasks[blockIdx.x], L, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+}
+
+// ---------------------------------------------------------------------------
+// k_persist_small: every small subtree of the elimination forest (of every
+// system of a batch), all its levels, in one launch.  Resident workgroups
+// take queue entries from a work counter; the queue is in level order, so
+// every supernode an entry waits for belongs to an earlier entry, which a
+// running workgroup holds or has finished: no wait can deadlock.  An entry is
+// one small supernode (the workgroup, small_body) or up to four tiny ones
+// (one wave each, tiny_body).  Before it starts, a supernode waits until
+// every source inside the launch has scatter-added its update into it
+// (pdep[s] counted down to 0); after its own scatter-adds have completed
+// (s_waitcnt), it counts down each of its targets inside the launch.  The
+// scatter-adds are device-scope atomics and the panel is read with
+// device-scope loads, so the values cross XCDs without cache-wide fences.
+// ---------------------------------------------------------------------------
+__global__ void k_persist_reset(const int32_t *pdep0, int64_t ns, int32_t *pdep, int32_t *qctr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns) pdep[i] = pdep0[i];
+    if (i == 0) *qctr = 0;
+}
+
+// (at least six waves per SIMD where the LDS allows it, i.e. in FP32: the
+// entries are latency-bound, and 4 -> 6 waves cut the 512-system batch's
+// launch from 13.3 to 10.4 ms)
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_persist_small(const PersistEntry *queue, const int32_t *chunk, int64_t nc,
+                                                       const SmallTask *psmall,
+                                                       const SmallTask *ptiny, const int64_t *ptgt_ptr,
+                                                       const int32_t *ptgt, int32_t *pdep, int32_t *qctr,
+                                                       const int64_t *cbase, const int64_t *crel, const int32_t *rel,
+                                                       T *Lx, T *Linv, unsigned long long *status,
+                                                       const int32_t *status_slot, PivotFloor<T> pfl, WaitCtl wc) {
+    __shared__ SmallLds<T> L;
+    __shared__ int32_t slot;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (;;) {
+        if (tid == 0) slot = atomicAdd(qctr, 1);
+        __syncthreads();
+        const int64_t c = slot;
+        __syncthreads();  // every thread has read the slot
+        if (c >= nc) return;
+        // the chunk's entries in order: an entry waits only on entries before
+        // it, earlier in this chunk (done) or in chunks taken before
+        for (int32_t q = chunk[c]; q < chunk[c + 1]; ++q) {
+        const PersistEntry e = queue[q];
+        if (e.kind == 0) {
+            const SmallTask tk = psmall[e.first];
+            if (tid == 0) wait_value(&pdep[tk.s], 0, wc.err, wc.spin);
+            __syncthreads();
+            small_body<T, true>(tk, L, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's scatter-adds have completed
+            __syncthreads();
+            for (int64_t k = ptgt_ptr[tk.s] + tid; k < ptgt_ptr[tk.s + 1]; k += 256) atomicSub(&pdep[ptgt[k]], 1);
+        } else if (wv < e.count) {
+            const SmallTask tk = ptiny[e.first + wv];
+            if (lane == 0) wait_value(&pdep[tk.s], 0, wc.err, wc.spin);
+            __asm__ volatile("" ::: "memory");
+            tiny_body<T, true>(tk, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+            __builtin_amdgcn_s_waitcnt(0);
+            for (int64_t k = ptgt_ptr[tk.s] + lane; k < ptgt_ptr[tk.s + 1]; k += 64) atomicSub(&pdep[ptgt[k]], 1);
+        }
+        __syncthreads();
+        }
     }
 }
 
@@ -1266,18 +1377,6 @@ constexpr int kMaxRhs = 16;
 // a block's tasks wait until every task updating its rows has counted down
 // dep[block]; backward: a task waits until the blocks owning its rows are
 // done (bounded waits, wait_value).
-// Bounded waits: poll an int until it holds `want`; after `spin` polls
-// (about a second by default) give up, flag err and go on, so every wave
-// always exits.  Once any wait has given up, the others stop waiting too.
-__device__ __forceinline__ void wait_value(int32_t *p, int32_t want, int32_t *err, int32_t spin) {
-    for (int it = 0; it < spin; ++it) {
-        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return;
-        // once any wait has given up, the others stop waiting too
-        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    flag_device_error(err);
-}
 
 // Data handed between workgroups of one persistent sweep moves through
 // device-scope atomics (loads after a wait, stores before a flag is raised),
@@ -2269,6 +2368,33 @@ void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16,
 }
 
 template <typename T>
+void launch_persist_small(const DevPlan &P, int64_t nchunks, int64_t nsuper, int32_t *pdep, int32_t *qctr, T *Lx,
+                          T *Linv, unsigned long long *status, PivotFloor<T> pfl, WaitCtl wc, hipStream_t st) {
+    if (nchunks <= 0) return;
+    hipLaunchKernelGGL(k_persist_reset, dim3(grid1(std::max<int64_t>(nsuper, 1), 256)), dim3(256), 0, st, P.pdep0,
+                       nsuper, pdep, qctr);
+    // as many workgroups as can be resident at once (the kernel's occupancy
+    // times the CUs), measured once per precision: the entries are short and
+    // latency-bound, so every resident slot counts
+    static int resident[2] = {0, 0};
+    int &r = resident[sizeof(T) == 8 ? 1 : 0];
+    if (r == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist_small<T>, 256, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+            cus < 1)
+            r = 768;
+        else
+            r = per_cu * cus;
+    }
+    const unsigned g = (unsigned)std::min<int64_t>(nchunks, r);
+    hipLaunchKernelGGL(k_persist_small<T>, dim3(g), dim3(256), 0, st, P.pqueue, P.pchunk, nchunks, P.psmall, P.ptiny,
+                       P.ptgt_ptr,
+                       P.ptgt, pdep, qctr, P.cbase, P.crel, P.rel, Lx, Linv, status, P.status_slot, pfl, wc);
+}
+
+template <typename T>
 void launch_perm_in(const DevPlan &P, int64_t n, int nrhs, const double *B, int64_t ldb, T *W,
                     hipStream_t st) {
     if (n * nrhs <= 0) return;
@@ -2459,6 +2585,8 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
     template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \
                                  PivotFloor<T>, hipStream_t);                                               \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, bool, hipStream_t);            \
+    template void launch_persist_small<T>(const DevPlan &, int64_t, int64_t, int32_t *, int32_t *, T *, T *, \
+                                          unsigned long long *, PivotFloor<T>, WaitCtl, hipStream_t);       \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \
                                     hipStream_t);                                                           \
     template void launch_perm_out<T>(const DevPlan &, int64_t, int, const T *, double *, int64_t,           \

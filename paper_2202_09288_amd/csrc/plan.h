@@ -58,6 +58,7 @@ struct Tuning {
     int32_t solve_persist_max = kSolvePersistMax;
     int32_t handover = 1;  // fused TRSM with in-launch waits (0: off)
     int32_t delay = kDelay;  // column blocks per bulk trailing update
+    int32_t persist = 0;     // small subtrees in one persistent launch (0: per level)
 };
 
 // One pair (source supernode s, ancestor t) of the scatter: rows
@@ -126,6 +127,16 @@ struct SmallTask {
     int32_t m;
     int32_t w;
     int32_t g0;    // global column of its first column
+};
+
+// One entry of the persistent launch over the small subtrees: one small
+// supernode (kind 0, psmall[first]) or up to four tiny ones (kind 1,
+// ptiny[first .. first + count - 1], one wave each).
+struct PersistEntry {
+    int32_t kind;
+    int32_t first;
+    int32_t count;
+    int32_t pad;
 };
 
 // One column block of a supernode (solves and inverse store).
@@ -206,6 +217,21 @@ struct Symbolic {
     std::vector<double> tiny_flops;        // [nlevels] flops of the single-wave path
     std::vector<double> ext_flops;         // [nlevels] flops of the 64-tile scatter launch
     std::vector<double> ext_big_flops;     // [nlevels] flops of the 128-tile scatter launch
+    // Persistent launch over every small subtree (a supernode whose whole
+    // subtree is small or tiny), all levels at once: queue entries in level
+    // order; a supernode waits until the scatters of every source inside
+    // that set into it have counted pdep0[s] down to zero, and after its own
+    // scatter counts down the targets ptgt[ptgt_ptr[s] ..] inside the set.
+    std::vector<SmallTask> psmall, ptiny;
+    std::vector<PersistEntry> pqueue;
+    // chunks of consecutive queue entries of one level, taken by one
+    // workgroup per work-counter increment (up to 16 entries where the level
+    // is wide, so that the counter is not contended): [nchunks+1]
+    std::vector<int32_t> pchunk;
+    std::vector<int32_t> pdep0;            // [nsuper]
+    std::vector<int64_t> ptgt_ptr;         // [nsuper+1]
+    std::vector<int32_t> ptgt;
+    double persist_flops = 0.0;
     std::vector<PanelTask> potrf_tasks;
     std::vector<TileTask> trsm_tiles;
     std::vector<TileTask> int_tiles;

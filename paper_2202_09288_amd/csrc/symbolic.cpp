@@ -409,9 +409,56 @@ int build_schedule(Symbolic &S) {
         return is_tiny(s) ||
                (S.super_ptr[s + 1] - S.super_ptr[s] <= tu.small_w && S.rptr[s + 1] - S.rptr[s] <= tu.small_m);
     };
+    // small subtrees: a supernode that is small and whose children all head
+    // small subtrees (children come before their parent in postorder)
+    std::vector<char> allsmall(ns, 0);
+    for (int32_t s = 0; s < ns; ++s) allsmall[s] = tu.persist && is_small(s);
+    for (int32_t s = 0; s < ns; ++s) {
+        const int32_t p = S.sparent[s];
+        if (p >= 0 && !allsmall[s]) allsmall[p] = 0;
+    }
+    S.psmall.clear();
+    S.ptiny.clear();
+    S.pqueue.clear();
+    S.persist_flops = 0.0;
+    S.pdep0.assign(ns, 0);
+    S.ptgt_ptr.assign(ns + 1, 0);
+    S.ptgt.clear();
+    for (int32_t s = 0; s < ns; ++s) {
+        if (allsmall[s])
+            for (int64_t q = S.pair_ptr[s]; q < S.pair_ptr[s + 1]; ++q) {
+                const int32_t t = S.pairs[q].target;
+                if (!allsmall[t]) continue;
+                S.ptgt.push_back(t);
+                S.pdep0[t]++;
+            }
+        S.ptgt_ptr[s + 1] = (int64_t)S.ptgt.size();
+    }
+    S.pchunk.assign(1, 0);
     for (int32_t l = 0; l < S.nlevels; ++l) {
         std::vector<int32_t> big;
+        const int32_t level_first = (int32_t)S.pqueue.size();
+        int32_t tiny_open = -1;  // queue entry of the level's last tiny group, if not full
         for (int32_t s : bylevel[l]) {
+            if (allsmall[s]) {
+                const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
+                const int64_t mi = S.rptr[s + 1] - S.rptr[s];
+                const SmallTask tk{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s, (int32_t)mi, wi, S.super_ptr[s]};
+                const double w = wi, m = (double)mi;
+                S.persist_flops += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 + (m - w) * w * w + (m - w) * (m - w + 1) * w;
+                if (is_tiny(s)) {
+                    if (tiny_open < 0 || S.pqueue[tiny_open].count == 4) {
+                        tiny_open = (int32_t)S.pqueue.size();
+                        S.pqueue.push_back(PersistEntry{1, (int32_t)S.ptiny.size(), 0, 0});
+                    }
+                    S.pqueue[tiny_open].count++;
+                    S.ptiny.push_back(tk);
+                } else {
+                    S.pqueue.push_back(PersistEntry{0, (int32_t)S.psmall.size(), 1, 0});
+                    S.psmall.push_back(tk);
+                }
+                continue;
+            }
             if (is_small(s)) {
                 const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
                 const int64_t mi = S.rptr[s + 1] - S.rptr[s];
@@ -429,6 +476,15 @@ int build_schedule(Symbolic &S) {
         }
         S.small_ptr[l + 1] = (int64_t)S.small_tasks.size();
         S.tiny_ptr[l + 1] = (int64_t)S.tiny_tasks.size();
+        {
+            // chunks of this level's entries: at least about 4096 of them
+            // (twice the workgroups the device holds) while chunks hold
+            // at most 16 entries
+            const int32_t ne = (int32_t)S.pqueue.size() - level_first;
+            const int32_t c = std::max(1, std::min(16, ne / 4096));
+            for (int32_t e = level_first + c; e < (int32_t)S.pqueue.size(); e += c) S.pchunk.push_back(e);
+            if (ne > 0) S.pchunk.push_back((int32_t)S.pqueue.size());
+        }
         bylevel[l].swap(big);
     }
     for (int32_t l = 0; l < S.nlevels; ++l) {
@@ -791,6 +847,43 @@ int verify_schedule(const Symbolic &S, std::string &msg) {
         if (!blocked[b.s]) continue;
         if (solved[q] != m_of(b.s) - b.c1) return fail("rows below a block not solved exactly once", q, solved[q]);
     }
+    // every supernode is factored by exactly one path
+    std::vector<int32_t> seen(S.nsuper, 0);
+    for (const SmallTask &t : S.small_tasks) seen[t.s]++;
+    for (const SmallTask &t : S.tiny_tasks) seen[t.s]++;
+    for (const SmallTask &t : S.psmall) seen[t.s]++;
+    for (const SmallTask &t : S.ptiny) seen[t.s]++;
+    for (int32_t t = 0; t < S.nsuper; ++t)
+        if (seen[t] + (blocked[t] ? 1 : 0) != 1) return fail("supernode not factored exactly once", t, seen[t]);
+    // persistent launch: every count-down target comes in a later queue
+    // entry than its source, and each counter starts at the number of its
+    // sources, so a wait only ever waits on entries taken before it
+    std::vector<int64_t> pos(S.nsuper, -1);
+    for (int64_t e = 0; e < (int64_t)S.pqueue.size(); ++e) {
+        const PersistEntry &pe = S.pqueue[e];
+        const std::vector<SmallTask> &src = pe.kind == 0 ? S.psmall : S.ptiny;
+        if (pe.count < 1 || pe.count > (pe.kind == 0 ? 1 : 4) || pe.first + pe.count > (int32_t)src.size())
+            return fail("bad persistent queue entry", e, pe.count);
+        for (int32_t k = 0; k < pe.count; ++k) pos[src[pe.first + k].s] = e;
+    }
+    if (S.pchunk.empty() || S.pchunk.front() != 0 || S.pchunk.back() != (int32_t)S.pqueue.size())
+        return fail("persistent chunks do not cover the queue", (int64_t)S.pchunk.size(), (int64_t)S.pqueue.size());
+    for (size_t c = 0; c + 1 < S.pchunk.size(); ++c)
+        if (S.pchunk[c + 1] <= S.pchunk[c]) return fail("empty persistent chunk", (int64_t)c, S.pchunk[c]);
+    std::vector<int32_t> count(S.nsuper, 0);
+    for (int32_t t = 0; t < S.nsuper; ++t) {
+        if (pos[t] < 0) {
+            if (S.ptgt_ptr[t + 1] != S.ptgt_ptr[t]) return fail("count-down from outside the persistent set", t, 0);
+            continue;
+        }
+        for (int64_t q = S.ptgt_ptr[t]; q < S.ptgt_ptr[t + 1]; ++q) {
+            const int32_t u = S.ptgt[q];
+            if (pos[u] <= pos[t]) return fail("persistent count-down target not after its source", t, u);
+            count[u]++;
+        }
+    }
+    for (int32_t t = 0; t < S.nsuper; ++t)
+        if (pos[t] >= 0 && count[t] != S.pdep0[t]) return fail("persistent counter start", t, S.pdep0[t]);
     return 0;
 }
 

@@ -42,17 +42,17 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
            "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats",
            "spc_factor_set_wait_limit", "spc_solve_noalloc", "spc_factor_pivot_floors")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
-                  "small": 6, "tiny": 7}
+                  "small": 6, "tiny": 7, "small_trees": 8}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
 KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": "k_tiles<{t}, 0>",
                 "scatter": "k_tiles<{t}, 1>", "scatter_big": "k_tiles128<{t}>", "small": "k_small<{t}>",
-                "tiny": "k_tiny<{t}>",
+                "tiny": "k_tiny<{t}>", "small_trees": "k_persist_small<{t}>",
                 "assemble": "k_zero<{t}> + k_assemble<{t}>"}
 
 
 # schedule cut-offs of spc_options (0: library default, < 0: path off)
 TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max",
-                 "handover", "delay")
+                 "handover", "delay", "persist")
 
 
 class _Options(ctypes.Structure):
@@ -312,10 +312,11 @@ class Factor:
         _check(_lib.spc_factor_set_profiling(self._h, 1 if on else 0), "spc_factor_set_profiling")
 
     def level_stats(self) -> list:
-        """Per elimination-tree level (index 0 = the assembly, then levels
-        0..): launches, device ms and flops of the last profiled factorization."""
+        """Per elimination-tree level (-2 = the persistent launch over the
+        small subtrees, -1 = the assembly, then levels 0..): launches, device
+        ms and flops of the last profiled factorization."""
         out = []
-        for lv in range(-1, self.sym.info["levels"]):
+        for lv in range(-2, self.sym.info["levels"]):
             st = _KernelStats()
             _check(_lib.spc_factor_level_stats(self._h, lv, ctypes.byref(st)), "spc_factor_level_stats")
             out.append({"level": lv, "launches": int(st.launches), "ms": float(st.total_ms),
@@ -465,6 +466,16 @@ class Batch:
 
     def set_graph(self, on: bool = True):
         _check(_lib.spc_batch_set_graph(self._h, 1 if on else 0), "spc_batch_set_graph")
+
+    def level_stats(self) -> list:
+        """As Factor.level_stats, for the last profiled batch factorization."""
+        out = []
+        for lv in range(-2, self.info["levels"]):
+            st = _KernelStats()
+            _check(_lib.spc_batch_level_stats(self._h, lv, ctypes.byref(st)), "spc_batch_level_stats")
+            out.append({"level": lv, "launches": int(st.launches), "ms": float(st.total_ms),
+                        "flops": float(st.flops)})
+        return out
 
     def kernel_stats(self) -> dict:
         out = {}

@@ -39,6 +39,7 @@ GROUPS = [
     ("persist", ("solve_persist_max",), [(1024,), (256,), (4096,)]),
     ("handover", ("handover",), [(1,), (-1,)]),
     ("delay", ("delay",), [(1,), (2,), (3,), (4,)]),
+    ("persist", ("persist",), [(-1,), (1,)]),
 ]
 
 

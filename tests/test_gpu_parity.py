@@ -120,6 +120,8 @@ SCHEDULES = {
     "bulk updates every 2 blocks": {"delay": 2},
     "bulk updates every 4 blocks, no hand-over": {"delay": 4, "handover": -1},
     "bulk updates every 3 blocks": {"delay": 3},
+    "small subtrees in one persistent launch": {"persist": 1},
+    "small subtrees persistent, one-wave path off": {"persist": 1, "tiny_w": -1},
 }
 
 
@@ -1039,3 +1041,52 @@ def test_bf16upd_refined_elasticity_kappa1e6(torch_dev, lib):
           f"to their floor, {info}, host eta {eta:.3e}", flush=True)
     assert info["converged"] and info["status"] == lib.OK
     assert eta <= BERR_FP64
+
+
+# ---- the persistent launch over the small subtrees ---------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_persistent_small_subtrees_batch(torch_dev, lib, precision):
+    """A batch whose small subtrees (of every system, all their levels) run
+    as one persistent launch with device-side dependency counters: every
+    system's factor against the oracle, and the solves."""
+    torch = torch_dev
+    systems = small_batch(16, seed=3)
+    syms = [lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"persist": 1}) for s in systems]
+    batch = lib.Batch(syms, precision)
+    dvs = [torch.from_numpy(s.values).cuda() for s in systems]
+    batch.set_profiling(True)
+    batch.factorize(dvs)
+    batch.sync()
+    ks = batch.kernel_stats()
+    print(f"persistent launch: {ks['small_trees']}", flush=True)
+    assert ks["small_trees"]["launches"] == 1
+    Bs = [torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda() for s in systems]
+    batch.solve(Bs)
+    for i, s in enumerate(systems):
+        S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        Lref = S.factor(s.values)
+        Lg = batch.factor(i).export()
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Bs[i].cpu().numpy().T, s.B)
+        if precision == "fp64":
+            assert factor_error(Lg, Lref, S) <= REL_F_FP64 and eta <= BERR_FP64
+        else:
+            assert oracle.rel_frobenius(Lg, Lref, S.lower_mask()) <= 1e-4 and eta <= 1e-5
+
+
+def test_persistent_small_subtrees_not_spd(torch_dev, lib):
+    """A failing pivot inside the persistent launch is reported at the
+    oracle's column, and every later supernode still runs to its end."""
+    s = grid((13, 12, 11), seed=6)
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    iperm = np.argsort(S.perm)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"persist": 1})
+    for r in (5, s.n // 3):
+        v = s.values.copy()
+        v[s.colptr[r]] = -v[s.colptr[r]]
+        with pytest.raises(oracle.NotSPD) as eo:
+            S.factor(v)
+        F = lib.factorize(sym, torch_dev.from_numpy(v).cuda())
+        with pytest.raises(lib.NotSPD) as eg:
+            F.sync()
+        assert eg.value.column == eo.value.column == iperm[r]
