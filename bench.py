@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per rate")
     ap.add_argument("--capacity-sweep", action="store_true",
                     help="serving: measure capacity (all requests at once), then sweep 0.25-1.1x of it")
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0,
+                    help="serving: HBM budget for resident factors and work areas (GiB)")
     ap.add_argument("--serving-handover", default="off", choices=["on", "off"],
                     help="serving: the factorizations' in-launch TRSM hand-over (off: no waits inside a launch)")
     return ap.parse_args()
@@ -527,12 +529,14 @@ def bench_serving(args):
 
     def one(rate, count):
         reqs = serving.make_requests(count, rate, seed=args.seed)
-        srv = serving.Server(slots=4, hbm_budget=64 << 30, precision="fp32", tol=1e-12, maxit=100,
-                             handover=args.serving_handover == "on")
+        srv = serving.Server(slots=4, hbm_budget=int(args.serving_budget_gb * (1 << 30)), precision="fp32",
+                             tol=1e-12, maxit=100, handover=args.serving_handover == "on")
         t0 = time.perf_counter()
         srv.run(reqs)
         wall = time.perf_counter() - t0
+        srv.close()
         summ = serving.summarize(reqs, wall)
+        summ["peak_device_bytes"] = srv.peak
         summ["rate_hz"] = rate
         print(f"serving rate {rate}: {summ}", file=sys.stderr, flush=True)
         return summ
@@ -554,8 +558,9 @@ def bench_serving(args):
     best = min(runs, key=lambda r: r["p99_ms"] or 1e30)
     out = head(args, round(best["solves_per_s"], 2), "solves/s", "f32",
                {"workload": "serving: Poisson arrivals, batch size mix + 5% 3D 50^3, 30% re-solves (8 RHS) "
-                            "on resident factors, FP32 + FP64 refinement to 1e-12, 4 slots",
-                "requests_per_rate": args.requests}, None)
+                            "of factors resident when dispatched, FP32 + FP64 refinement to 1e-12, 4 slots, "
+                            "analysis in a 2-thread pool, pooled slots refactorized by graph replay",
+                "requests_per_rate": args.requests, "hbm_budget_gb": args.serving_budget_gb}, None)
     out.update({"runs": runs, "capacity_requests_per_s": capacity})
     print(json.dumps(out), flush=True)
 

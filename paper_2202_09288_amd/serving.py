@@ -7,20 +7,34 @@ request).  The loop admits requests as slots and device memory free up:
   - a slot is a worker thread with its own HIP stream (default priority), so
     the work of requests in different slots overlaps on the device; the
     library calls release the GIL;
-  - admission is by footprint: a factor request needs the factor bytes the
-    analysis reports (plus solve and refinement workspace), and it waits
-    while admitting it would exceed the HBM budget; resident factors that
-    are not in use are evicted (least recently used first) to make room;
-  - the analysis of a pattern is cached (keyed by the pattern), so repeated
-    patterns skip the host analysis;
-  - every solve is FP32 factor + FP64 refinement to the backward-error
-    tolerance, and the result records latency (completion - arrival).
-
-The paper's analyze/factorize/solve phases (Sec. 1-2) are the unit of work;
-keeping factors for repeated solves is the resident-factor cache.
+  - the analysis of a pattern (spc_analyze, on the host) runs in a pool of
+    analysis threads, off the dispatcher: a factor request whose pattern is
+    being analysed waits while the dispatcher admits the requests behind it;
+    the result is cached by pattern, so a known pattern is never analysed
+    again (the paper's analyze-once, factorize-many, Sec. 1-2);
+  - device memory is held in factor slots: a factor, its values buffer and
+    the footprint the analysis reports (panels, plan, solve and refinement
+    work areas).  A factor request gets a new slot, admitted by footprint,
+    while the HBM budget allows; at the budget it takes over the slot of the
+    least recently used idle resident factor of its own pattern
+    (spc_refactorize into it, replayed from the slot's captured HIP graph:
+    the values buffer keeps its address, so a slot's graph is captured once),
+    else idle resident factors of other patterns are evicted, least recently
+    used first, until it fits.  Residency is bounded by the budget alone;
+  - after its request, a factor stays resident: a re-solve picks uniformly
+    among the factors resident when it is dispatched (its `pick` in [0, 1)
+    indexes them), so it never misses while one is resident.  With
+    resolve_policy="fixed" a re-solve instead names its factor request
+    (`target`), and one whose factor was evicted is a miss: that system is
+    factored again, then solved;
+  - every solve is a factor in `precision` plus FP64 refinement to the
+    backward-error tolerance, and each request records its latency
+    (completion - arrival), whether its pattern was new on arrival (cold)
+    and whether it reused a pooled slot.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import hashlib
 import queue
@@ -38,17 +52,21 @@ class Request:
     kind: str                      # "factor" or "resolve"
     system: object = None          # workloads.System for "factor"
     values_scale: float = 1.0      # factor requests scale the system's values
-    target: int = -1               # resolve requests: rid of the factor request
+    target: int = -1               # resolve: the factor request it solves with
+    pick: float = 0.0              # resolve: which resident factor, in [0, 1)
     nrhs: int = 8
+    key: str = ""                  # factor: pattern key
     # filled in by the server
     start: float = -1.0
     done: float = -1.0
     berr: float = float("nan")
     iterations: int = -1
-    factor_key: int = -1
-    miss: bool = False             # resolve whose factor had been evicted
+    miss: bool = False             # fixed-target resolve whose factor had been evicted
+    cold: bool = False             # factor: pattern first seen at this request's arrival
+    pooled: bool = False           # factor: refactorized into an idle slot of its pattern
     status: str = "pending"
     X: object = None               # host solution when keep_solutions
+    L: object = None               # host panels (FP64) when export_factors
 
 
 def pattern_key(s) -> str:
@@ -59,26 +77,41 @@ def pattern_key(s) -> str:
     return h.hexdigest()
 
 
-class Resident:
-    def __init__(self, key, factor, d_values, system, nbytes, scale):
+class Slot:
+    """Device memory of one factor: the factor, its values buffer, and the
+    bytes admitted for it.  owner: the request whose factor it holds while
+    resident, else -1 (idle in its pattern's pool)."""
+
+    def __init__(self, key, sym, nbytes):
         self.key = key
-        self.factor = factor
-        self.d_values = d_values
-        self.system = system
+        self.sym = sym
         self.nbytes = nbytes
-        self.scale = scale
-        self.lock = threading.Lock()
+        self.factor = None
+        self.d_values = None
+        self.owner = -1
+        self.system = None
+        self.scale = 1.0
         self.in_use = 0
+        self.lock = threading.Lock()
+
+    def close(self):
+        if self.factor is not None:
+            self.factor.close()
+            self.factor = None
+        self.d_values = None
 
 
 class Server:
     """Serve a list of requests with arrival times; see module docstring."""
 
     def __init__(self, slots: int = 4, hbm_budget: int = 64 << 30, precision: str = "fp32",
-                 tol: float = 1e-12, maxit: int = 50, keep_solutions: bool = False,
-                 max_resident: int = 64, handover: bool = False):
+                 tol: float = 1e-12, maxit: int = 50, keep_solutions: bool = False, handover: bool = False,
+                 analysis_workers: int = 2, resolve_policy: str = "resident", graph: bool = True,
+                 export_factors: bool = False):
         import torch
         from . import spchol
+        if resolve_policy not in ("resident", "fixed"):
+            raise ValueError("resolve_policy is 'resident' or 'fixed'")
         self.torch = torch
         self.lib = spchol
         self.slots = slots
@@ -87,136 +120,145 @@ class Server:
         self.tol = tol
         self.maxit = maxit
         self.keep_solutions = keep_solutions
-        self.max_resident = max_resident
+        self.export_factors = export_factors
+        self.policy = resolve_policy
+        self.graph = graph
         # in-launch TRSM hand-over (waits inside a launch) for the
         # factorizations; off by default, since the slots' factorizations
         # share the device on several streams
         self.tuning = {"handover": 1 if handover else -1}
         self.sym_cache = {}
-        self.sym_lock = threading.Lock()
-        self.resident = OrderedDict()      # key -> Resident (LRU order)
-        self.res_lock = threading.Lock()
-        self.used = 0                      # bytes admitted or resident
-        self.mem_cv = threading.Condition()
-        self.refactoring = set()           # targets being factored again
+        self.analyzing = {}                # key -> future
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=max(1, analysis_workers))
+        self.lock = threading.RLock()      # resident, free, used, in_use
+        self.resident = OrderedDict()      # owner rid -> Slot (LRU order)
+        self.used = 0                      # bytes held by slots
+        self.peak = 0
+        self.wake = threading.Condition()  # a request finished or an analysis ended
+        self.inflight_factors = 0
+        self.refactoring = set()           # fixed policy: targets being factored again
+        self._factors_pending = False
+        self._by_rid = {}
 
     # ---- memory accounting ------------------------------------------------
     def footprint(self, sym, nrhs: int) -> int:
         i = sym.info
-        fac = i["factor_bytes_fp32"] if self.precision == "fp32" else i["factor_bytes_fp64"]
+        fac = i["factor_bytes_fp32"] if self.precision != "fp64" else i["factor_bytes_fp64"]
         n = i["n"]
-        work = n * 16 * (3 * (4 if self.precision == "fp32" else 8)) + n * 16 * 8 * 7  # solve + refine
+        esz = 8 if self.precision == "fp64" else 4
+        work = n * 16 * 3 * esz + n * 16 * 8 * 7  # solve + refinement work areas
         csr = 2 * i["nnz_a"] * 12 + 8 * n
         vals = i["nnz_a"] * 8 + 2 * n * nrhs * 8
         return int(fac + work + csr + vals)
 
-    def _reserve(self, nbytes: int) -> bool:
-        """Reserve device bytes, evicting idle resident factors (LRU)."""
-        with self.mem_cv:
-            while self.used + nbytes > self.budget:
-                victim = None
-                with self.res_lock:
-                    for k, r in self.resident.items():
-                        if r.in_use == 0:
-                            victim = k
-                            break
-                    if victim is not None:
-                        r = self.resident.pop(victim)
-                if victim is None:
-                    return False
-                r.factor.close()
-                self.used -= r.nbytes
-            self.used += nbytes
-            return True
+    def _free_slot(self, slot):
+        slot.close()
+        self.used -= slot.nbytes
 
-    def _release(self, nbytes: int):
-        with self.mem_cv:
-            self.used -= nbytes
-            self.mem_cv.notify_all()
+    def acquire_slot(self, key, sym, nbytes):
+        """Device memory for a factor of pattern `key`: a new slot while the
+        budget allows; else the least recently used idle resident factor of
+        the same pattern, whose slot is taken over as it is (pooled: no
+        allocation, its graph replays); else new room made by evicting idle
+        resident factors of other patterns, least recently used first.
+        Returns (slot, pooled), or (None, False) if there is no room now."""
+        with self.lock:
+            if nbytes > self.budget:
+                return None, False
+            if self.used + nbytes > self.budget:
+                rid = next((r for r, sl in self.resident.items() if sl.in_use == 0 and sl.key == key), None)
+                if rid is not None:
+                    sl = self.resident.pop(rid)
+                    sl.owner = -1
+                    return sl, True
+            while self.used + nbytes > self.budget:
+                rid = next((r for r, sl in self.resident.items() if sl.in_use == 0), None)
+                if rid is None:
+                    return None, False
+                self._free_slot(self.resident.pop(rid))
+            self.used += nbytes
+            self.peak = max(self.peak, self.used)
+            return Slot(key, sym, nbytes), False
 
     def symbolic(self, s):
+        """The analysis of s's pattern (synchronously; the loop itself uses
+        the analysis pool)."""
         key = pattern_key(s)
-        with self.sym_lock:
+        with self.lock:
             sym = self.sym_cache.get(key)
-            if sym is None:
-                sym = self.lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, self.tuning)
-                self.sym_cache[key] = sym
+        if sym is None:
+            sym = self._analyze(key, s)
         return sym
 
+    def _analyze(self, key, s):
+        sym = self.lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, self.tuning)
+        with self.lock:
+            self.sym_cache.setdefault(key, sym)
+            sym = self.sym_cache[key]
+        return sym
+
+    def _analysis_done(self, key):
+        with self.lock:
+            self.analyzing.pop(key, None)
+        with self.wake:
+            self.wake.notify_all()
+
     # ---- work of one request (runs in a slot thread) ------------------------
-    def _run_factor(self, req: Request, stream, sym, nbytes, hold: bool = False):
+    def _factor_into(self, slot, system, scale, stream):
+        """Factor system (values * scale) into the slot on `stream`."""
         torch = self.torch
-        s = req.system
-        with torch.cuda.stream(stream):
-            dv = torch.from_numpy(s.values * req.values_scale).to("cuda", non_blocking=False)
-            F = self.lib.factorize(sym, dv, self.precision, stream=stream)
+        vals = torch.from_numpy(system.values * scale)
+        if slot.d_values is None:
+            slot.d_values = torch.empty(vals.numel(), dtype=torch.float64, device="cuda")
+        slot.d_values.copy_(vals)
+        if slot.factor is None:
+            slot.factor = self.lib.factorize(slot.sym, slot.d_values, self.precision, stream=stream)
+            slot.factor.set_graph(self.graph)
+        else:
+            slot.factor.refactorize(slot.d_values, stream=stream)
+        slot.factor.sync()
+        slot.system = system
+        slot.scale = scale
+
+    def _solve(self, req, slot, stream, B):
+        torch = self.torch
+        X = torch.zeros_like(B)
+        info = slot.factor.solve_refined(slot.d_values, B, X, tol=self.tol, maxit=self.maxit, stream=stream)
+        stream.synchronize()
+        req.berr = info["berr"]
+        req.iterations = info["iterations"]
+        req.status = "ok" if info["converged"] else "no-convergence"
+        if self.keep_solutions:
+            req.X = X.cpu().numpy().T.copy()
+
+    def _run_factor(self, req, slot, stream):
+        torch = self.torch
+        with slot.lock, torch.cuda.stream(stream):
+            self._factor_into(slot, req.system, req.values_scale, stream)
+            if self.export_factors:
+                req.L = slot.factor.export()
             B = torch.from_numpy(self.rhs(req)).cuda()
-            X = torch.zeros_like(B)
-            F.sync()
-            info = F.solve_refined(dv, B, X, tol=self.tol, maxit=self.maxit, stream=stream)
-            stream.synchronize()
-        req.berr = info["berr"]
-        req.iterations = info["iterations"]
-        req.status = "ok" if info["converged"] else "no-convergence"
-        if self.keep_solutions:
-            req.X = X.cpu().numpy().T.copy()
-        victims = []
-        with self.res_lock:  # never take mem_cv while holding res_lock
-            key = req.target if req.kind == "resolve" else req.rid
-            old = self.resident.get(key)
-            if old is not None and old.in_use > 0:
-                # a user still holds the current one: keep it, drop ours
-                if hold:
-                    old.in_use += 1
-                new = old
-                victims.append(Resident(key, F, dv, s, nbytes, req.values_scale))
-            else:
-                if old is not None:
-                    victims.append(self.resident.pop(key))
-                new = Resident(key, F, dv, s, nbytes, req.values_scale)
-                new.in_use = 1 if hold else 0  # held: not evictable until released
-                self.resident[key] = new
-            req.factor_key = key
-            # cap the number of resident factors
-            while len(self.resident) > self.max_resident:
-                k0 = next((k for k, r in self.resident.items() if r.in_use == 0), None)
-                if k0 is None:
-                    break
-                victims.append(self.resident.pop(k0))
-        for r in victims:
-            r.factor.close()
-            self._release(r.nbytes)
-        return new
+            self._solve(req, slot, stream, B)
+        with self.lock:
+            slot.owner = req.rid
+            slot.in_use -= 1
+            self.resident[req.rid] = slot
+            self.inflight_factors -= 1
 
-    def _run_refactor(self, req: Request, stream, sym, nbytes, tgt: Request):
-        """A re-solve whose factor was evicted: factor the target's system
-        again (it becomes resident under the target's id) and solve."""
-        shadow = Request(rid=tgt.rid, arrival=req.arrival, kind="factor", system=tgt.system,
-                         values_scale=tgt.values_scale, nrhs=req.nrhs)
-        try:
-            res = self._run_factor(shadow, stream, sym, nbytes, hold=True)
-        finally:
-            self.refactoring.discard(tgt.rid)
-        try:
-            self._run_resolve(req, stream, res)
-        finally:
-            with self.res_lock:
-                res.in_use -= 1
-
-    def _run_resolve(self, req: Request, stream, res: Resident):
+    def _run_resolve(self, req, slot, stream):
         torch = self.torch
-        s = res.system
-        with res.lock, torch.cuda.stream(stream):
-            B = torch.from_numpy(self.rhs(req, s)).cuda()
-            X = torch.zeros_like(B)
-            info = res.factor.solve_refined(res.d_values, B, X, tol=self.tol, maxit=self.maxit, stream=stream)
-            stream.synchronize()
-        req.berr = info["berr"]
-        req.iterations = info["iterations"]
-        req.status = "ok" if info["converged"] else "no-convergence"
-        req.factor_key = res.key
-        if self.keep_solutions:
-            req.X = X.cpu().numpy().T.copy()
+        with slot.lock, torch.cuda.stream(stream):
+            if slot.owner != req.target:  # a miss: factor the target's system again
+                tgt = self._by_rid[req.target]
+                self._factor_into(slot, tgt.system, tgt.values_scale, stream)
+            B = torch.from_numpy(self.rhs(req, slot.system)).cuda()
+            self._solve(req, slot, stream, B)
+        with self.lock:
+            if slot.owner != req.target:
+                slot.owner = req.target
+                self.resident[req.target] = slot
+                self.refactoring.discard(req.target)
+            slot.in_use -= 1
 
     @staticmethod
     def rhs(req: Request, system=None):
@@ -228,125 +270,144 @@ class Server:
         u = uniform(stream_key(W_SERVE, 0, P_RHS, req.rid), req.nrhs * system.n)
         return np.ascontiguousarray((2.0 * u - 1.0).reshape(req.nrhs, system.n))
 
+    # ---- dispatch ------------------------------------------------------------
+    def _dispatch_factor(self, req):
+        with self.lock:
+            sym = self.sym_cache.get(req.key)
+            busy = req.key in self.analyzing
+        if sym is None:
+            if not busy:
+                fut = self.pool.submit(self._analyze, req.key, req.system)
+                with self.lock:
+                    self.analyzing[req.key] = fut
+                fut.add_done_callback(lambda _f, k=req.key: self._analysis_done(k))
+            return None
+        slot, pooled = self.acquire_slot(req.key, sym, self.footprint(sym, req.nrhs))
+        if slot is None:
+            return None
+        req.pooled = pooled
+        with self.lock:
+            slot.in_use += 1
+            self.inflight_factors += 1
+        return (req, "factor", slot)
+
+    def _dispatch_resolve(self, req):
+        with self.lock:
+            if self.policy == "resident":
+                if not self.resident:
+                    if self.inflight_factors > 0 or self._factors_pending:
+                        return None  # one will be resident soon
+                    req.status = "no-resident-factor"
+                    return "done"
+                owners = sorted(self.resident)
+                rid = owners[min(int(req.pick * len(owners)), len(owners) - 1)]
+                slot = self.resident[rid]
+                req.target = rid
+                slot.in_use += 1
+                self.resident.move_to_end(rid)
+                return (req, "resolve", slot)
+            slot = self.resident.get(req.target)
+            if slot is not None:
+                slot.in_use += 1
+                self.resident.move_to_end(req.target)
+                return (req, "resolve", slot)
+            tgt = self._by_rid.get(req.target)
+            if tgt is None or tgt.status not in ("ok", "pending"):
+                req.status = "no-resident-factor"
+                return "done"
+            if tgt.done < 0 or req.target in self.refactoring:
+                return None  # its factor request (or another miss on it) is queued or running
+        # evicted: a miss, factored again into a slot of its pattern
+        got = self._dispatch_factor(Request(rid=-1, arrival=req.arrival, kind="factor", system=tgt.system,
+                                            values_scale=tgt.values_scale, key=tgt.key))
+        if got is None:
+            return None
+        _, _, slot = got
+        with self.lock:
+            self.inflight_factors -= 1
+            self.refactoring.add(req.target)
+        req.miss = True
+        return (req, "resolve", slot)
+
     # ---- the loop ------------------------------------------------------------
     def run(self, requests, time_scale: float = 1.0):
         """Serve `requests` (sorted by arrival); returns them with results.
 
         Arrival times are in seconds and replayed in real time divided by
-        time_scale.  Re-solve requests that arrive before any factor is
-        resident wait for one.
+        time_scale.
         """
         torch = self.torch
         todo = queue.Queue()
         finished = []
-        fin_lock = threading.Lock()
-        slot_free = threading.Semaphore(self.slots)
+        free_workers = threading.Semaphore(self.slots)
+        self._by_rid = {r.rid: r for r in requests}
+        for r in requests:
+            if r.kind == "factor" and not r.key:
+                r.key = pattern_key(r.system)
 
-        def worker(idx):
+        def worker():
             stream = torch.cuda.Stream()
             while True:
                 item = todo.get()
                 if item is None:
                     return
-                req, payload = item
+                req, kind, slot = item
                 req.start = time.perf_counter() - t0
                 try:
-                    if req.kind == "factor":
-                        sym, nbytes = payload
-                        self._run_factor(req, stream, sym, nbytes)
-                    elif isinstance(payload, tuple):
-                        _, sym, nbytes, tgt = payload
-                        self._run_refactor(req, stream, sym, nbytes, tgt)
+                    if kind == "factor":
+                        self._run_factor(req, slot, stream)
                     else:
-                        try:
-                            self._run_resolve(req, stream, payload)
-                        finally:
-                            with self.res_lock:
-                                payload.in_use -= 1
+                        self._run_resolve(req, slot, stream)
                 except Exception as e:  # recorded, the loop goes on
                     req.status = f"error: {e}"
-                    if isinstance(payload, tuple):
-                        self._release(payload[-2] if len(payload) == 4 else payload[1])
+                    with self.lock:
+                        slot.in_use = max(0, slot.in_use - 1)
+                        if kind == "factor":
+                            self.inflight_factors -= 1
                 req.done = time.perf_counter() - t0
-                with fin_lock:
-                    finished.append(req)
-                slot_free.release()
+                finished.append(req)
+                free_workers.release()
+                with self.wake:
+                    self.wake.notify_all()
 
-        threads = [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.slots)]
+        threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.slots)]
         for th in threads:
             th.start()
         pending = list(requests)
-        by_rid = {r.rid: r for r in pending}
+        seen = set(self.sym_cache)
         waiting = []
         t0 = time.perf_counter()
         i = 0
         while i < len(pending) or waiting:
             now = time.perf_counter() - t0
             while i < len(pending) and pending[i].arrival / time_scale <= now:
-                waiting.append(pending[i])
+                r = pending[i]
+                if r.kind == "factor":
+                    r.cold = r.key not in seen
+                    seen.add(r.key)
+                waiting.append(r)
                 i += 1
-            if not waiting:
-                nxt = pending[i].arrival / time_scale
-                time.sleep(max(0.0, min(0.01, nxt - now)))
-                continue
-            req = waiting[0]
-            if req.kind == "resolve":
-                with self.res_lock:
-                    res = self.resident.get(req.target)
-                    if res is not None:
-                        res.in_use += 1
-                        self.resident.move_to_end(req.target)
-                if res is None:
-                    tgt = by_rid.get(req.target)
-                    if tgt is not None and tgt.done < 0 and tgt.status == "pending":
-                        # its factor is queued or in flight: serve others first
-                        nxt_req = next((r for r in waiting if r.kind == "factor"), None)
-                        if nxt_req is not None:
-                            waiting.remove(nxt_req)
-                            waiting.insert(0, nxt_req)
-                        else:
-                            time.sleep(0.0005)
-                        continue
-                    if tgt is None or tgt.status != "ok":
-                        req.status = "no-resident-factor"
-                        waiting.pop(0)
-                        with fin_lock:
-                            finished.append(req)
-                        continue
-                    if req.target in self.refactoring:
-                        time.sleep(0.0005)  # another re-solve is refactoring it
-                        continue
-                    # evicted: factor the target's system again (a miss)
-                    req.miss = True
-                    sym = self.symbolic(tgt.system)
-                    nbytes = self.footprint(sym, req.nrhs)
-                    if not self._reserve(nbytes):
-                        with self.mem_cv:
-                            self.mem_cv.wait(timeout=0.01)
-                        continue
-                    slot_free.acquire()
-                    waiting.pop(0)
-                    self.refactoring.add(req.target)
-                    todo.put((req, ("refactor", sym, nbytes, tgt)))
+            self._factors_pending = any(r.kind == "factor" for r in waiting)
+            progressed = False
+            for req in list(waiting):
+                if not free_workers.acquire(blocking=False):
+                    break
+                got = self._dispatch_factor(req) if req.kind == "factor" else self._dispatch_resolve(req)
+                if got is None:
+                    free_workers.release()
                     continue
-                slot_free.acquire()
-                waiting.pop(0)
-                todo.put((req, res))
-                continue
-            sym = self.symbolic(req.system)
-            nbytes = self.footprint(sym, req.nrhs)
-            if nbytes > self.budget:
-                req.status = "rejected: footprint above budget"
-                waiting.pop(0)
-                finished.append(req)
-                continue
-            if not self._reserve(nbytes):
-                with self.mem_cv:
-                    self.mem_cv.wait(timeout=0.01)
-                continue
-            slot_free.acquire()
-            waiting.pop(0)
-            todo.put((req, (sym, nbytes)))
+                waiting.remove(req)
+                progressed = True
+                if got == "done":
+                    free_workers.release()
+                    req.done = time.perf_counter() - t0
+                    finished.append(req)
+                    continue
+                todo.put(got)
+            if not progressed:
+                nxt = pending[i].arrival / time_scale - now if i < len(pending) else 0.01
+                with self.wake:
+                    self.wake.wait(timeout=max(0.0002, min(0.002, nxt)))
         for _ in threads:
             todo.put(None)
         for th in threads:
@@ -354,37 +415,54 @@ class Server:
         return sorted(finished, key=lambda r: r.rid)
 
     def close(self):
-        with self.res_lock:
-            for r in self.resident.values():
-                r.factor.close()
+        with self.lock:
+            for sl in self.resident.values():
+                sl.close()
             self.resident.clear()
-        self.used = 0
+            self.used = 0
+        self.pool.shutdown(wait=True)
+
+
+def _pcts(lat):
+    lat = np.asarray(lat, dtype=np.float64)
+    if not lat.size:
+        return {"count": 0, "p50_ms": None, "p99_ms": None}
+    return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99))}
 
 
 def summarize(reqs, wall: float) -> dict:
     ok = [r for r in reqs if r.status == "ok"]
-    lat = np.array([r.done - r.arrival for r in ok]) * 1e3
+    lat = {r.rid: (r.done - r.arrival) * 1e3 for r in ok}
     solves = sum(r.nrhs for r in ok)
-    return {
+    res = [r for r in reqs if r.kind == "resolve"]
+    out = {
         "requests": len(reqs), "ok": len(ok),
         "failed": sorted({r.status for r in reqs if r.status != "ok"}),
         "misses": sum(r.miss for r in reqs),
-        "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
-        "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
-        "mean_ms": float(lat.mean()) if lat.size else None,
+        "resolve_hit_rate": (sum(not r.miss for r in res if r.status == "ok") / len(res)) if res else None,
+        "p50_ms": float(np.percentile(list(lat.values()), 50)) if lat else None,
+        "p99_ms": float(np.percentile(list(lat.values()), 99)) if lat else None,
+        "mean_ms": float(np.mean(list(lat.values()))) if lat else None,
         "solves_per_s": solves / wall if wall > 0 else None,
         "requests_per_s": len(ok) / wall if wall > 0 else None,
         "max_berr": float(max((r.berr for r in ok), default=float("nan"))),
         "factor_requests": sum(r.kind == "factor" for r in ok),
         "resolve_requests": sum(r.kind == "resolve" for r in ok),
+        "pooled_factor_requests": sum(r.pooled for r in ok if r.kind == "factor"),
+        "cold": _pcts([lat[r.rid] for r in ok if r.kind == "factor" and r.cold]),
+        "warm": _pcts([lat[r.rid] for r in ok if r.kind == "factor" and not r.cold]),
+        "resolve": _pcts([lat[r.rid] for r in ok if r.kind == "resolve"]),
     }
+    return out
 
 
 def make_requests(count: int, rate_hz: float, seed: int = 0, system_fn=None, max_side=None):
     """Requests of the serving mix (workloads.serving_requests): factor
     requests carry their system (built by system_fn(kind, side), cached per
-    pattern), re-solves target an earlier factor request, chosen uniformly
-    from those before it.  max_side clamps grid sides (smaller tests)."""
+    pattern); a re-solve carries its `pick` (which resident factor) and, for
+    the fixed policy, a target chosen with the same pick among the factor
+    requests before it.  max_side clamps grid sides (smaller tests)."""
     from . import workloads as W
     specs = W.serving_requests(count, rate_hz, seed)
     cache = {}
@@ -397,16 +475,18 @@ def make_requests(count: int, rate_hz: float, seed: int = 0, system_fn=None, max
                 side = min(side, max_side[kind])
             key = (kind, side)
             if key not in cache:
-                cache[key] = system_fn(kind, side) if system_fn else W.batch_system(
+                sysm = system_fn(kind, side) if system_fn else W.batch_system(
                     len(cache), kind, side, seed, nrhs=sp["nrhs"], workload=W.W_SERVE)
+                cache[key] = (sysm, pattern_key(sysm))
             scale = 1.0 + 0.5 * ((sp["id"] * 0.6180339887498949) % 1.0)
-            r = Request(rid=sp["id"], arrival=sp["t"], kind="factor", system=cache[key],
-                        values_scale=scale, nrhs=sp["nrhs"])
+            r = Request(rid=sp["id"], arrival=sp["t"], kind="factor", system=cache[key][0],
+                        values_scale=scale, nrhs=sp["nrhs"], key=cache[key][1])
             factors.append(r.rid)
         else:
             if not factors:
                 continue
             tgt = factors[min(int(sp["pick"] * len(factors)), len(factors) - 1)]
-            r = Request(rid=sp["id"], arrival=sp["t"], kind="resolve", target=tgt, nrhs=sp["nrhs"])
+            r = Request(rid=sp["id"], arrival=sp["t"], kind="resolve", target=tgt, pick=sp["pick"],
+                        nrhs=sp["nrhs"])
         out.append(r)
     return out

@@ -621,8 +621,9 @@ def test_serving_alone_equals_in_mix(torch_dev, lib):
     from paper_2202_09288_amd import serving as SV
     reqs_a = SV.make_requests(24, 200.0, 3, max_side={"2d": 48, "3d": 12})
     reqs_b = SV.make_requests(24, 200.0, 3, max_side={"2d": 48, "3d": 12})
-    alone = SV.Server(slots=1, keep_solutions=True).run(reqs_a, time_scale=1.0)
-    mix = SV.Server(slots=4, keep_solutions=True).run(reqs_b, time_scale=1.0)
+    # re-solves name their factor request, so both runs pair the same systems
+    alone = SV.Server(slots=1, keep_solutions=True, resolve_policy="fixed").run(reqs_a, time_scale=1.0)
+    mix = SV.Server(slots=4, keep_solutions=True, resolve_policy="fixed").run(reqs_b, time_scale=1.0)
     assert [r.rid for r in alone] == [r.rid for r in mix]
     systems = {r.rid: r.system for r in alone if r.kind == "factor"}
     scales = {r.rid: r.values_scale for r in alone if r.kind == "factor"}
@@ -653,18 +654,11 @@ def test_serving_admission_budget(torch_dev, lib):
     srv = SV.Server(slots=3)
     one = max(srv.footprint(srv.symbolic(r.system), r.nrhs) for r in reqs if r.kind == "factor")
     srv.budget = int(one * 1.5)
-    peak = []
-    orig = srv._reserve
-
-    def spy(nbytes):
-        ok = orig(nbytes)
-        peak.append(srv.used)
-        return ok
-    srv._reserve = spy
     out = srv.run(reqs)
+    srv.close()
     bad = [(r.rid, r.kind, r.status) for r in out if r.status != "ok"]
     assert not bad, bad
-    assert max(peak) <= srv.budget
+    assert 0 < srv.peak <= srv.budget
     assert all(r.berr <= 1e-12 for r in out)
 
 
@@ -1090,3 +1084,33 @@ def test_persistent_small_subtrees_not_spd(torch_dev, lib):
         with pytest.raises(lib.NotSPD) as eg:
             F.sync()
         assert eg.value.column == eo.value.column == iperm[r]
+
+
+def test_serving_pooled_refactorization(torch_dev, lib):
+    """Serving in FP64 with a budget that holds a few factors: factor
+    requests of a known pattern refactorize an idle slot of that pattern
+    (spc_refactorize, replayed from the slot's graph), and every factor
+    served, pooled or new, matches the oracle's factor of the values it was
+    given; re-solves pick resident factors and never miss."""
+    from paper_2202_09288_amd import serving as SV
+    reqs = SV.make_requests(40, 2000.0, 5, max_side={"2d": 40, "3d": 11})
+    srv = SV.Server(slots=2, precision="fp64", export_factors=True, keep_solutions=True)
+    fps = {r.key: srv.footprint(srv.symbolic(r.system), r.nrhs) for r in reqs if r.kind == "factor"}
+    srv.budget = int(3.5 * max(fps.values()))
+    out = srv.run(reqs)
+    srv.close()
+    summ = SV.summarize(out, 1.0)
+    print(f"pooled serving: {summ}", flush=True)
+    assert summ["ok"] == len(out) and summ["misses"] == 0
+    assert summ["pooled_factor_requests"] > 0
+    refs = {}
+    for r in out:
+        if r.kind != "factor":
+            continue
+        s = r.system
+        if r.key not in refs:
+            refs[r.key] = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        S = refs[r.key]
+        err = factor_error(r.L, S.factor(s.values * r.values_scale), S)
+        assert err <= REL_F_FP64, (r.rid, r.pooled, err)
+    assert srv.peak <= srv.budget
