@@ -47,11 +47,12 @@ def parse():
                     help="target wall time of the oracle's all-cores sample (the one-core sample takes about "
                          "a third of it)")
     ap.add_argument("--workload", default="elast48",
-                    choices=["elast48", "grid3d60", "grid2d64", "batch512", "serving", "copy"],
+                    choices=["elast48", "grid3d60", "grid2d64", "batch512", "serving", "copy", "cpu_tasks"],
                     help="elast48: the headline, 48^3 elasticity, FP64 factor + solve with the FP32 + FP64 "
                          "refinement leg beside it (default); grid3d60: 60^3 7-point FP64 factor + solve; "
                          "grid2d64: small-system latency; batch512: 512 systems in one schedule; "
-                         "serving: request loop")
+                         "serving: request loop; cpu_tasks: the paper's task-parallel host factorization "
+                         "(every strategy) on configurations 1-3, no GPU")
     ap.add_argument("--tuning", default="auto", choices=["auto", "default"],
                     help="schedule cut-offs: the autotuner's cache entry for this workload (auto), else defaults")
     ap.add_argument("--seed", type=int, default=0, help="seed of the synthetic inputs (configs 1-3)")
@@ -176,8 +177,58 @@ def main():
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     modes = {"grid3d60": bench_grid3d, "grid2d64": bench_grid2d, "elast48": bench_elast,
-             "batch512": bench_batch, "serving": bench_serving, "copy": bench_copy}
+             "batch512": bench_batch, "serving": bench_serving, "copy": bench_copy, "cpu_tasks": bench_cpu_tasks}
     modes[args.workload](args)
+
+
+def task_leg(s, strategies, threads=None, reps=1):
+    """The paper's task-parallel left-looking factorization (Sec. 3-4) on
+    the host cores, on the same matrix and analysis: per strategy the best
+    of `reps` wall times and GFLOP/s (sum of squared column counts), with
+    the update-count statistics of Algorithm 1."""
+    from paper_2202_09288_amd import spchol, taskchol
+    threads = threads or max(1, min(16, len(os.sched_getaffinity(0))))
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    plan = taskchol.TaskPlan.from_symbolic(sym, s.colptr, s.rowidx)
+    st = plan.stats()
+    C = plan.update_counts()
+    hist = np.bincount(C)
+    runs = {}
+    for name in strategies:
+        best = None
+        for _ in range(reps):
+            _, info = plan.factor(s.values, name, threads=threads)
+            if best is None or info["seconds"] < best["seconds"]:
+                best = info
+        best["gflops"] = round(st["flops"] / best["seconds"] / 1e9, 3)
+        best["seconds"] = round(best["seconds"], 4)
+        runs[name] = best
+        progress(f"task-parallel host factorization, {name}: {best}")
+    if "nonested" in runs:
+        for v in runs.values():
+            v["speedup_vs_nonested"] = round(runs["nonested"]["seconds"] / v["seconds"], 3)
+    plan.close()
+    return {"threads": threads, "runs": runs,
+            "update_counts": {"nsuper": st["nsuper"], "updates": st["updates"], "max": st["max_updates"],
+                              "opt_d": st["opt_d"], "split_under_opt_d": st["split_opt_d"],
+                              "tasks": {"nonested": st["tasks_nonested"], "nested": st["tasks_nested"],
+                                        "opt_d": st["tasks_opt_d"], "opt_d_cost": st["tasks_opt_d_cost"]},
+                              "histogram_head": [int(x) for x in hist[:16]],
+                              "avg_supernode_cols": round(st["avg_supernode_cols"], 3),
+                              "density": st["density"], "hybrid_choice": st["hybrid_choice"]}}
+
+
+def bench_cpu_tasks(args):
+    """The paper's method on the host: every strategy on configurations 1 and
+    2, the hybrid choice and mt-BLAS on configuration 3; no GPU."""
+    from paper_2202_09288_amd import workloads as W
+    all_s = ["nonested", "nested", "opt_d", "opt_d_cost", "mt_blas", "hybrid"]
+    out = {"workload": "cpu_tasks", "configs": {}}
+    for name, s, strats, reps in (("64^2 2D 5-point", W.grid2d_unit(), all_s, 5),
+                                  ("60^3 3D 7-point", W.grid3d_cond(), all_s, 1),
+                                  ("48^3 elasticity", W.elast48(), ["mt_blas", "hybrid"], 1)):
+        out["configs"][name] = task_leg(s, strats, reps=reps)
+    print(json.dumps(out), flush=True)
 
 
 def bench_copy(args):

@@ -20,8 +20,26 @@ FLAGS = [
 ]
 
 
+TASKLIB = os.path.join(HERE, "libtaskchol.so")
+# the host task-parallel CPU baseline: plain C++ with OpenMP, for any x86-64
+# with AVX2 and FMA (it is built here and run on the GPU machine's host)
+TASK_FLAGS = ["-O3", "-std=c++17", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-Wall"]
+
+
+def build_taskchol(verbose: bool = False) -> str:
+    tmp = TASKLIB + f".tmp{os.getpid()}"
+    cmd = ["g++", *TASK_FLAGS, os.path.join(CSRC, "taskchol.cpp"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, TASKLIB)
+    return TASKLIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libspchol.so; returns its path."""
+    """Compile every source and link libspchol.so (and the host baseline
+    libtaskchol.so); returns the path of libspchol.so."""
+    build_taskchol(verbose)
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
