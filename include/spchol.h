@@ -104,12 +104,16 @@ typedef struct spc_options {
      *                     device-side dependency counters; a negative value
      *                     (the default, 0) launches those supernodes level by
      *                     level, which measured faster on the workloads here.
+     *   ordering          when spc_analyze gets no order (h_perm NULL): 0
+     *                     the identity (default), 1 graph nested dissection,
+     *                     2 minimum degree (see spc_order)
      * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
     int32_t tiny_w, tiny_m, small_w, small_m;
     int32_t big_min, big_min_k, solve_persist_max;
     int32_t handover;
     int32_t delay;
     int32_t persist;
+    int32_t ordering;
 } spc_options;
 
 /* Summary numbers of an analysis. */
@@ -150,6 +154,26 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx,
                 const int32_t *h_perm, const spc_options *opts, spc_symbolic *out);
 
 int spc_symbolic_info(spc_symbolic sym, spc_info *out);
+
+/*
+ * spc_order -- a fill-reducing order of a pattern without coordinates (paper
+ * Sec. 2: the analysis reorders the matrix to reduce fill, with METIS or
+ * AMD; these are this library's own methods).  Host only.
+ *   n, h_colptr, h_rowidx   lower CSC pattern (as for spc_analyze)
+ *   method   0 identity; 1 graph nested dissection: in each connected part a
+ *            breadth-first level structure from a pseudo-peripheral vertex,
+ *            the separator a level with the fewest vertices that leaves at
+ *            least a third of the part on each side (thinned to the vertices
+ *            touching the next level), both sides recursively, then the
+ *            separator; parts of at most 64 vertices by minimum degree;
+ *            2 minimum degree on the elimination graph (exact degrees, ties
+ *            to the lowest index; n <= 10,000)
+ *   h_perm   receives perm[k] = the original index of the k-th pivot, the
+ *            form spc_analyze takes
+ * Errors: SPC_INVALID_INPUT (malformed pattern, unknown method, minimum
+ * degree above its size limit), SPC_OUT_OF_MEMORY.
+ */
+int spc_order(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, int method, int32_t *h_perm);
 
 /* Check the device schedule of an analysis on the host (no device needed),
  * for tests and diagnostics: every 64-column block of the blocked path has

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspchol.so")
-SOURCES = ["symbolic.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["symbolic.cpp", "ordering.cpp", "capi.cpp", "kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

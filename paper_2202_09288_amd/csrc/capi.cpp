@@ -822,13 +822,33 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
                         pick(opts->solve_persist_max, spc::kSolvePersistMax, kNone, 0, &tu.solve_persist_max) &&
                         pick(opts->handover, 1, 1, 0, &tu.handover) &&
                         pick(opts->delay, spc::kDelay, spc::kDelayMax, spc::kDelay, &tu.delay) &&
-                        pick(opts->persist, 0, 1, 0, &tu.persist);
+                        pick(opts->persist, 0, 1, 0, &tu.persist) &&
+                        pick(opts->ordering, 0, 2, 0, &tu.ordering);
         if (!ok) {
             delete s;
             return SPC_INVALID_INPUT;
         }
     }
     int rc;
+    std::vector<int32_t> computed;
+    if (!h_perm && tu.ordering != 0 && n > 0) {
+        if (!h_colptr || !h_rowidx) {
+            delete s;
+            return SPC_INVALID_INPUT;
+        }
+        try {
+            computed.resize(n);
+        } catch (const std::bad_alloc &) {
+            delete s;
+            return SPC_OUT_OF_MEMORY;
+        }
+        rc = spc_order(n, h_colptr, h_rowidx, tu.ordering, computed.data());
+        if (rc != SPC_OK) {
+            delete s;
+            return rc;
+        }
+        h_perm = computed.data();
+    }
     try {
         rc = spc::analyze(n, h_colptr, h_rowidx, h_perm, z, tu, s->S);
     } catch (const std::bad_alloc &) {
@@ -841,6 +861,27 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
         return rc;
     }
     *out = s;
+    return SPC_OK;
+}
+
+int spc_order(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, int method, int32_t *h_perm) {
+    if (n < 0 || (n > 0 && (!h_colptr || !h_rowidx || !h_perm)) || method < 0 || method > 2) return SPC_INVALID_INPUT;
+    if (n == 0) return SPC_OK;
+    if (n > INT32_MAX - 1 || h_colptr[0] != 0) return SPC_INVALID_INPUT;
+    for (int64_t c = 0; c < n; ++c)
+        if (h_colptr[c + 1] < h_colptr[c]) return SPC_INVALID_INPUT;
+    int rc;
+    try {
+        rc = spc::order_graph(n, h_colptr, h_rowidx, method, h_perm);
+    } catch (const std::bad_alloc &) {
+        return SPC_OUT_OF_MEMORY;
+    }
+    if (rc != 0) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      method == 2 && n > 10000 ? "spc_order: minimum degree is for n <= 10000"
+                                               : "spc_order: malformed pattern");
+        return SPC_INVALID_INPUT;
+    }
     return SPC_OK;
 }
 

@@ -59,6 +59,7 @@ struct Tuning {
     int32_t handover = 1;  // fused TRSM with in-launch waits (0: off)
     int32_t delay = kDelay;  // column blocks per bulk trailing update
     int32_t persist = 0;     // small subtrees in one persistent launch (0: per level)
+    int32_t ordering = 0;    // order computed by analyze when none is given (order_graph's method)
 };
 
 // One pair (source supernode s, ancestor t) of the scatter: rows
@@ -267,6 +268,11 @@ struct Symbolic {
     int64_t rows_total() const { return rptr.empty() ? 0 : rptr.back(); }
     int64_t panel_entries() const { return lptr.empty() ? 0 : lptr.back(); }
 };
+
+// A fill-reducing order of a lower-CSC pattern (perm[k] = vertex eliminated
+// k-th): method 0 the identity, 1 graph nested dissection by level
+// structures, 2 minimum degree (n <= 10,000).  0, or -1 for invalid input.
+int order_graph(int64_t n, const int64_t *colptr, const int32_t *rowidx, int method, int32_t *perm);
 
 // Returns 0 or a negative spc_status.
 int analyze(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int32_t *perm,

@@ -40,7 +40,7 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
            "spc_batch_solve", "spc_batch_sync", "spc_batch_last_ms", "spc_batch_info", "spc_free_batch",
            "spc_batch_set_profiling", "spc_batch_kernel_stats", "spc_batch_solve_refined",
            "spc_factor_set_graph", "spc_batch_set_graph", "spc_factor_level_stats", "spc_batch_level_stats",
-           "spc_factor_set_wait_limit", "spc_solve_noalloc", "spc_factor_pivot_floors")
+           "spc_factor_set_wait_limit", "spc_solve_noalloc", "spc_factor_pivot_floors", "spc_order")
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7, "small_trees": 8}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
@@ -52,7 +52,7 @@ KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": 
 
 # schedule cut-offs of spc_options (0: library default, < 0: path off)
 TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max",
-                 "handover", "delay", "persist")
+                 "handover", "delay", "persist", "ordering")
 
 
 class _Options(ctypes.Structure):
@@ -79,6 +79,7 @@ _P = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _lib.spc_analyze.argtypes = [_i64, _P, _P, _P, ctypes.POINTER(_Options), ctypes.POINTER(_P)]
 _lib.spc_symbolic_info.argtypes = [_P, ctypes.POINTER(_Info)]
+_lib.spc_order.argtypes = [_i64, _P, _P, ctypes.c_int, _P]
 _lib.spc_symbolic_verify.argtypes = [_P]
 _lib.spc_symbolic_export.argtypes = [_P, ctypes.c_int, _P]
 _lib.spc_factorize.argtypes = [_P, _P, ctypes.c_int, _P, ctypes.POINTER(_P)]
@@ -493,6 +494,22 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+ORDERINGS = {"natural": 0, "nd": 1, "md": 2}
+
+
+def order(colptr, rowidx, method: str = "nd") -> np.ndarray:
+    """spc_order: a fill-reducing order (perm[k] = original index of the
+    k-th pivot) of a lower-CSC pattern without coordinates."""
+    cp = np.ascontiguousarray(colptr, dtype=np.int64)
+    ri = np.ascontiguousarray(rowidx, dtype=np.int32)
+    n = cp.size - 1
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    rc = _lib.spc_order(n, _np_ptr(cp), _np_ptr(ri), ORDERINGS[method], _np_ptr(perm))
+    if rc != OK:
+        raise SpcError(rc, "spc_order: " + _lib.spc_last_error_message().decode())
+    return perm[:n]
 
 
 def analyze(colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None) -> Symbolic:

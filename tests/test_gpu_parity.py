@@ -1114,3 +1114,25 @@ def test_serving_pooled_refactorization(torch_dev, lib):
         err = factor_error(r.L, S.factor(s.values * r.values_scale), S)
         assert err <= REL_F_FP64, (r.rid, r.pooled, err)
     assert srv.peak <= srv.budget
+
+
+# ---- orderings computed without coordinates ---------------------------------
+
+@pytest.mark.parametrize("method", ["nd", "md"])
+def test_graph_orderings_factor_and_solve(torch_dev, lib, method):
+    """The factor under an order spc_order computes (graph nested dissection,
+    minimum degree) matches the oracle's factor under that order, and the
+    solution, which no order changes, matches the oracle's solution under the
+    coordinate nested dissection of the workload (within kappa u)."""
+    torch = torch_dev
+    s = grid((22, 21, 20), seed=12, nrhs=2) if method == "nd" else grid((60, 61), seed=12, nrhs=2)
+    perm = lib.order(s.colptr, s.rowidx, method)
+    relF, eta, F, S = run_case(torch, lib, s.colptr, s.rowidx, s.values, perm, s.B)
+    print(f"{method}: relF={relF:.2e} eta={eta:.2e}", flush=True)
+    assert relF <= REL_F_FP64 and eta <= BERR_FP64
+    Bt = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    F.solve(Bt)
+    X = Bt.cpu().numpy().T
+    Sc = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Xc = Sc.solve(Sc.factor(s.values), s.B)
+    assert np.max(np.abs(X - Xc)) <= 1e-9 * np.max(np.abs(Xc))
