@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--grid", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-task-baseline", action="store_true",
+                    help="skip the paper's task-parallel host factorization of the headline matrix")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the oracle's all-cores sample (the one-core sample takes about "
                          "a third of it)")
@@ -503,6 +505,10 @@ def bench_elast(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, "48^3 elasticity")
         progress("CPU oracle sample done")
+    if not args.no_task_baseline:
+        # the paper's own method on all host cores, whole matrix: its hybrid
+        # rule's choice and mt-BLAS
+        out["cpu_task_baseline"] = task_leg(s, ["hybrid", "mt_blas"])
     print(json.dumps(out), flush=True)
 
 
