@@ -1797,6 +1797,32 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                     if (PERSIST) shared_store(&X[tk.g0 + oc], a);
                     else X[tk.g0 + oc] = a;
                 }
+            } else if constexpr (NR < kMaxRhs) {
+                // a few right-hand sides: the inverse staged in LDS, each
+                // thread one or two outputs (c, q) as a dot product over the
+                // rows i >= c of the inverse's column c
+#pragma unroll
+                for (int u = 0; u < QW; ++u) {
+                    const int e = tid + 256 * u;
+                    if (e < nb * nb) Vt[e % nb][e / nb] = qv[u];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < (NB * NR + 255) / 256; ++u) {
+                    const int e = tid + 256 * u, c = e / NR, q = e % NR;
+                    if (c < nb && q < nrhs) {
+                        T a0 = T(0), a1 = T(0);
+                        int i = c;
+                        for (; i + 1 < nb; i += 2) {
+                            a0 += Vt[i][c] * tq[i][q];
+                            a1 += Vt[i + 1][c] * tq[i + 1][q];
+                        }
+                        if (i < nb) a0 += Vt[i][c] * tq[i][q];
+                        const T a = a0 + a1;
+                        if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], a);
+                        else X[(tk.g0 + c) * nrhs + q] = a;
+                    }
+                }
             } else {
                 using acc_t = typename Mfma<T>::acc;
 #pragma unroll
@@ -2480,21 +2506,26 @@ void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
     const SolveTask *tk = persist ? P.stasks : P.stasks + t0;
     const int64_t *tp = persist ? P.stgt_ptr : P.stgt_ptr + t0;
     const int32_t *ord = persist ? P.bwd_order : nullptr;
+    // the instantiation for the fewest right-hand sides that holds nrhs
+#define SPC_BWD(NRV)                                                                                          \
+    do {                                                                                                      \
+        if (persist)                                                                                          \
+            hipLaunchKernelGGL((k_solve_bwd<T, NRV, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, \
+                               n, nrhs, tp, P.stgt, sy);                                                      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_solve_bwd<T, NRV, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X,    \
+                               Acc, n, nrhs, tp, P.stgt, sy);                                                 \
+    } while (0)
     if (nrhs == 1) {
-        if (persist)
-            hipLaunchKernelGGL((k_solve_bwd<T, 1, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, n,
-                               nrhs, tp, P.stgt, sy);
-        else
-            hipLaunchKernelGGL((k_solve_bwd<T, 1, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, n,
-                               nrhs, tp, P.stgt, sy);
+        SPC_BWD(1);
+    } else if (nrhs <= 4) {
+        SPC_BWD(4);
+    } else if (nrhs <= 8) {
+        SPC_BWD(8);
     } else {
-        if (persist)
-            hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc,
-                               n, nrhs, tp, P.stgt, sy);
-        else
-            hipLaunchKernelGGL((k_solve_bwd<T, kMaxRhs, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc,
-                               n, nrhs, tp, P.stgt, sy);
+        SPC_BWD(kMaxRhs);
     }
+#undef SPC_BWD
 }
 
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,

@@ -1136,3 +1136,33 @@ def test_graph_orderings_factor_and_solve(torch_dev, lib, method):
     Sc = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
     Xc = Sc.solve(Sc.factor(s.values), s.B)
     assert np.max(np.abs(X - Xc)) <= 1e-9 * np.max(np.abs(Xc))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_few_rhs_instantiations(torch_dev, lib, precision):
+    """Right-hand-side counts that take the 4- and 8-column forms of the
+    backward sweep (and the 16-column one beyond), in the level launches and
+    the persistent top sweep: each column's solution meets the bar of its
+    precision and equals the one-column solve's."""
+    torch = torch_dev
+    s = grid((26, 25, 24), seed=14, nrhs=11)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    assert sym.info["solve_persistent_levels"] > 0
+    F = lib.factorize(sym, torch.from_numpy(s.values).cuda(), precision)
+    F.sync()
+    bar = BERR_FP64 if precision == "fp64" else 1e-5
+    B0 = np.ascontiguousarray(s.B.T)
+    one = np.zeros_like(B0)
+    for q in range(B0.shape[0]):
+        x = torch.from_numpy(B0[q].copy()).cuda()
+        F.solve(x)
+        one[q] = x.cpu().numpy()
+    for nrhs in (2, 3, 4, 5, 8, 11):
+        X = torch.from_numpy(B0[:nrhs].copy()).cuda()
+        F.solve(X)
+        Xh = X.cpu().numpy()
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, Xh.T, s.B[:, :nrhs])
+        diff = np.max(np.abs(Xh - one[:nrhs])) / np.max(np.abs(one[:nrhs]))
+        print(f"{precision} nrhs={nrhs}: eta={eta:.2e}, against one at a time {diff:.2e}", flush=True)
+        assert eta <= bar
+        assert diff <= (1e-12 if precision == "fp64" else 1e-4)
