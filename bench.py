@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--grid", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-fp64", action="store_true",
+                    help="elast48: the plain FP64 steps only, without the FP32 and BF16-update legs (profiling runs)")
     ap.add_argument("--no-task-baseline", action="store_true",
                     help="skip the paper's task-parallel host factorization of the headline matrix")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -470,13 +472,16 @@ def bench_elast(args):
                 "factor_plus_refined_solve_ms": round(f_ms + float(np.median(ref)), 3),
                 "schedule_cutoffs": tun32 or "library defaults"}
 
-    leg32 = refined_leg("fp32")
-    progress(f"FP32 + refinement: {leg32['factor_ms']} ms + {leg32['refined_solve_ms_p50']} ms")
-    try:
-        leg16 = refined_leg("bf16upd")
-    except spchol.NotSPD as e:
-        leg16 = {"status": "not SPD", "detail": str(e)}
-    progress(f"BF16 updates + refinement: {leg16}")
+    if args.only_fp64:
+        leg32 = leg16 = None
+    else:
+        leg32 = refined_leg("fp32")
+        progress(f"FP32 + refinement: {leg32['factor_ms']} ms + {leg32['refined_solve_ms_p50']} ms")
+        try:
+            leg16 = refined_leg("bf16upd")
+        except spchol.NotSPD as e:
+            leg16 = {"status": "not SPD", "detail": str(e)}
+        progress(f"BF16 updates + refinement: {leg16}")
     plain = {"factor_ms": round(fac_mean, 3), "solve_ms_p50": round(float(np.median(sol_ms)), 3),
              "factor_plus_solve_ms": round(fac_mean + float(np.median(sol_ms)), 3)}
     out = head(args, round(value, 2), "GFLOP/s", "f64",
@@ -500,7 +505,8 @@ def bench_elast(args):
                           "rows": level_rows(lv, nprof)},
         "vs_plain_fp64": {"plain_fp64": plain, "fp32_refined": leg32, "bf16upd_refined": leg16,
                           "speedup_factor_plus_solve": round(plain["factor_plus_solve_ms"] /
-                                                             leg32["factor_plus_refined_solve_ms"], 3)},
+                                                             leg32["factor_plus_refined_solve_ms"], 3)
+                          if leg32 else None},
     })
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, "48^3 elasticity")
@@ -544,6 +550,16 @@ def bench_batch(args):
         res[prec] = {"factor_ms": round(float(fac.mean()), 3),
                      "factor_gflops": round(flops / (fac.mean() * 1e-3) / 1e9, 1),
                      "batched_solve_ms_p50": round(float(np.median(sol)), 3)}
+        # one profiled factorization: device time per kernel class and per
+        # etree level of the merged forest (events around every launch)
+        batch.set_profiling(True)
+        batch.factorize(dvs)
+        batch.sync()
+        res[prec]["classes_ms"] = {k: round(v["ms"], 3) for k, v in batch.kernel_stats().items()}
+        res[prec]["factor_levels"] = {
+            "columns": ["etree level (-2: the small-subtree launch, -1: assembly)", "launches", "device ms", "TFLOP/s"],
+            "rows": level_rows(batch.level_stats(), 1)}
+        batch.set_profiling(False)
         if prec == "fp32":
             # FP64 refinement of all systems at once (one merged solve per
             # step, per-system norms and coefficients)

@@ -44,8 +44,8 @@ EXPORTS = ("spc_analyze", "spc_symbolic_info", "spc_symbolic_verify", "spc_symbo
 KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter": 4, "scatter_big": 5,
                   "small": 6, "tiny": 7, "small_trees": 8}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
-KERNEL_NAMES = {"potrf": "k_potrf<{t}>", "trsm": "k_tiles<{t}, 2>", "trailing": "k_tiles<{t}, 0>",
-                "scatter": "k_tiles<{t}, 1>", "scatter_big": "k_tiles128<{t}>", "small": "k_small<{t}>",
+KERNEL_NAMES = {"potrf": "k_potrf<{t}, false>", "trsm": "k_tiles<{t}, 2, false>", "trailing": "k_tiles<{t}, 0, false>",
+                "scatter": "k_tiles<{t}, 1, false>", "scatter_big": "k_tiles128<{t}, false>", "small": "k_small<{t}>",
                 "tiny": "k_tiny<{t}>", "small_trees": "k_persist_small<{t}>",
                 "assemble": "k_zero<{t}> + k_assemble<{t}>"}
 
