@@ -90,7 +90,11 @@ typedef struct spc_options {
      *                     on device flags for its panels; a negative value
      *                     gives every block a TRSM launch of its own (no
      *                     waits inside a launch: for many factorizations
-     *                     sharing the device on several streams).  Default 1.
+     *                     sharing the device on several streams); 2 keeps
+     *                     the hand-over only in steps whose waiting tiles
+     *                     spread over the device (eight or more supernodes,
+     *                     or few waiting tiles beside the step's other
+     *                     tiles), the others get a TRSM launch.  Default 1.
      *   delay             column blocks per bulk trailing update inside a wide
      *                     supernode: the columns beyond a group of `delay`
      *                     64-column blocks receive the group's update once,
@@ -107,6 +111,20 @@ typedef struct spc_options {
      *   ordering          when spc_analyze gets no order (h_perm NULL): 0
      *                     the identity (default), 1 graph nested dissection,
      *                     2 minimum degree (see spc_order)
+     *   group             1 (default): tiny supernodes with w <= 4 and
+     *                     m <= 16 (m <= 32) share a wave, 16 (32) lanes
+     *                     each; a negative value gives each its own wave
+     *   bulk128           1: the bulk trailing updates inside a wide
+     *                     supernode (K = 64 * delay >= 128) run on 128x128
+     *                     tiles in a launch of their own; a negative value
+     *                     (the default, 0) keeps them on 64x64 tiles in the
+     *                     step's trailing launch
+     *   lookahead         1 (with delay >= 2): a group's bulk update reaches
+     *                     only the next group's columns at once; the columns
+     *                     beyond get it in the next group's other steps,
+     *                     beside their column updates and factorizations; a
+     *                     negative value (the default, 0) updates them all
+     *                     at the end of the group
      * Values beyond a kernel's limit give SPC_INVALID_INPUT. */
     int32_t tiny_w, tiny_m, small_w, small_m;
     int32_t big_min, big_min_k, solve_persist_max;
@@ -114,6 +132,9 @@ typedef struct spc_options {
     int32_t delay;
     int32_t persist;
     int32_t ordering;
+    int32_t group;
+    int32_t bulk128;
+    int32_t lookahead;
 } spc_options;
 
 /* Summary numbers of an analysis. */

@@ -214,6 +214,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         {S.int_tiles.data(), bytes_of(S.int_tiles), (const void **)&P.int_tiles},
         {S.ext_tiles.data(), bytes_of(S.ext_tiles), (const void **)&P.ext_tiles},
         {S.ext_tiles_big.data(), bytes_of(S.ext_tiles_big), (const void **)&P.ext_tiles_big},
+        {S.trail_big.data(), bytes_of(S.trail_big), (const void **)&P.trail_big},
         {S.stasks.data(), bytes_of(S.stasks), (const void **)&P.stasks},
         {S.stiny.data(), bytes_of(S.stiny), (const void **)&P.stiny},
         {S.status_slot.data(), bytes_of(S.status_slot), (const void **)&P.status_slot},
@@ -254,7 +255,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
 
 size_t plan_bytes(const spc::Symbolic &S) {
     return bytes_of(S.rows) + bytes_of(S.rel) + bytes_of(S.cbase) + bytes_of(S.crel) + bytes_of(S.amap) +
-           bytes_of(S.perm) + bytes_of(S.dsrc) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) +
+           bytes_of(S.perm) + bytes_of(S.dsrc) + bytes_of(S.potrf_tasks) + bytes_of(S.small_tasks) + bytes_of(S.tiny_tasks) + bytes_of(S.trsm_tiles) + bytes_of(S.trail_big) +
            bytes_of(S.int_tiles) + bytes_of(S.ext_tiles) + bytes_of(S.ext_tiles_big) +
            bytes_of(S.stasks) + bytes_of(S.stiny) + bytes_of(S.status_slot) + bytes_of(S.stgt_ptr) + bytes_of(S.stgt) +
            bytes_of(S.fdep) + bytes_of(S.bwd_order) + bytes_of(S.pqueue) + bytes_of(S.pchunk) + bytes_of(S.psmall) + bytes_of(S.ptiny) +
@@ -326,7 +327,8 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
         prof.level = l;
         if (S.tiny_ptr[l + 1] > S.tiny_ptr[l])
             prof.run(SPC_K_TINY, S.tiny_flops[l], st, [&] {
-                spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_ptr[l + 1], Lx, Linv, status, pfl, st);
+                spc::launch_tiny<T>(P, S.tiny_ptr[l], S.tiny_e16[l], S.tiny_e32[l], S.tiny_ptr[l + 1], Lx, Linv,
+                                    status, pfl, st);
             });
         if (S.small_ptr[l + 1] > S.small_ptr[l])
             prof.run(SPC_K_SMALL, S.small_flops[l], st, [&] {
@@ -347,6 +349,9 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
                     spc::launch_tiles<T>(P, spc::kTilesTrailing, stp.t0, stp.t1, Lx, Linv, status, hflags, wc, bf16,
                                          pfl, st);
                 });
+            if (stp.q1 > stp.q0)
+                prof.run(SPC_K_TRAILING, stp.big_flops, st,
+                         [&] { spc::launch_trail128<T>(P, stp.q0, stp.q1, Lx, bf16, st); });
         }
         if (S.ext_big_ptr[l + 1] > S.ext_big_ptr[l])
             prof.run(SPC_K_SCATTER_BIG, S.ext_big_flops[l], st, [&] {
@@ -820,10 +825,13 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
                         pick(opts->big_min, spc::kBigMin, kNone, kNone, &tu.big_min) &&
                         pick(opts->big_min_k, spc::kBigMinK, kNone, kNone, &tu.big_min_k) &&
                         pick(opts->solve_persist_max, spc::kSolvePersistMax, kNone, 0, &tu.solve_persist_max) &&
-                        pick(opts->handover, 1, 1, 0, &tu.handover) &&
+                        pick(opts->handover, 1, 2, 0, &tu.handover) &&
                         pick(opts->delay, spc::kDelay, spc::kDelayMax, spc::kDelay, &tu.delay) &&
                         pick(opts->persist, 0, 1, 0, &tu.persist) &&
-                        pick(opts->ordering, 0, 2, 0, &tu.ordering);
+                        pick(opts->ordering, 0, 2, 0, &tu.ordering) &&
+                        pick(opts->group, 1, 1, 0, &tu.group) &&
+                        pick(opts->bulk128, 0, 1, 0, &tu.bulk128) &&
+                        pick(opts->lookahead, 0, 1, 0, &tu.lookahead);
         if (!ok) {
             delete s;
             return SPC_INVALID_INPUT;

@@ -23,6 +23,7 @@ struct DevPlan {
     const TileTask *int_tiles;
     const TileTask *ext_tiles;
     const TileTask *ext_tiles_big;
+    const TileTask *trail_big;   // bulk trailing updates on 128x128 tiles
     const SolveTask *stasks;
     const SmallTask *stiny;      // one-wave solve tasks (tiny supernodes)
     const int32_t *status_slot;  // supernode -> status word, or null (one word)
@@ -103,8 +104,10 @@ template <typename T>
 void launch_small(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
                   PivotFloor<T> pfl, hipStream_t st);
 template <typename T>
-void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                 PivotFloor<T> pfl, hipStream_t st);
+// tasks t0..t16-1 in groups of 16 lanes, t16..t32-1 in groups of 32, the
+// rest one wave each
+void launch_tiny(const DevPlan &P, int64_t t0, int64_t t16, int64_t t32, int64_t t1, T *Lx, T *Linv,
+                 unsigned long long *status, PivotFloor<T> pfl, hipStream_t st);
 template <typename T>
 // bf16: (float panels only) the trailing and scatter updates multiply
 // operands rounded to BF16 on BF16 MFMA with FP32 accumulation
@@ -113,6 +116,9 @@ void launch_tiles(const DevPlan &P, int mode, int64_t t0, int64_t t1, T *Lx, T *
 
 template <typename T>
 void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st);
+// The bulk trailing updates trail_big[t0..t1) on 128x128 tiles (in place).
+template <typename T>
+void launch_trail128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st);
 
 // The persistent launch over the small subtrees (nchunks chunks of queue
 // entries, nsuper dependency counters in pdep, one work counter): resets the

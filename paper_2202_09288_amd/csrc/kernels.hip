@@ -663,12 +663,159 @@ __device__ __forceinline__ void tiny_body(const SmallTask &tk, const int64_t *cb
     }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped tiny supernodes (w <= kGroupW, m <= G): G = 16 or 32 lanes per
+// supernode, 64 / G of them per wave, the steps of tiny_body inside each
+// group; values of other rows come from their lanes by ds_bpermute (every
+// lane of the wave takes part in each exchange, so a lane read is always
+// active).  Groups past the end of a launch's list (live false) run on an
+// identity block and store nothing.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t pull32(int32_t v, int src) {
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+__device__ __forceinline__ double lane_pull(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = pull32((int)(b & 0xffffffffll), src), hi = pull32((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_pull(float v, int src) { return __int_as_float(pull32(__float_as_int(v), src)); }
+__device__ __forceinline__ int64_t lane_pull(int64_t v, int src) {
+    const int lo = pull32((int)(v & 0xffffffffll), src), hi = pull32((int)(v >> 32), src);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+template <typename T, int G, bool COH>
+__device__ __forceinline__ void group_body(const SmallTask &tk, bool live, const int64_t *cbase, const int64_t *crel,
+                                           const int32_t *rel, T *Lx, T *Linv, unsigned long long *status,
+                                           const int32_t *status_slot, PivotFloor<T> pfl) {
+    constexpr int WG = kGroupW, CB = 4;
+    static_assert(G == 16 || G == 32, "group of 16 or 32 lanes");
+    const int lane = threadIdx.x & 63, gi = lane & (G - 1), gb = lane - gi;
+    const int m = live ? tk.m : 1, w = live ? tk.w : 1;
+    T *P = Lx + tk.loff;
+    const int rc = min(gi, m - 1);
+    T r[WG];
+#pragma unroll
+    for (int c = 0; c < WG; ++c) {
+        if (live) {
+            const T *src = &P[(int64_t)min(c, w - 1) * m + rc];
+            r[c] = COH ? dev_load(src) : *src;
+        } else {
+            r[c] = gi == c ? T(1) : T(0);
+        }
+    }
+    int64_t my_cb = 0, my_cr = 0;
+    if (live) {
+        const int64_t kpos = tk.roff + min(max(gi, w), m - 1);
+        my_cb = cbase[kpos];
+        my_cr = crel[kpos];
+    }
+    const T flo = (live && pfl.v) ? pfl.v[tk.g0 + min(gi, w - 1)] : T(0);
+    // 1. column Cholesky (columns past w are padding: left alone)
+    int bad = -1, boosted = 0;
+    T rdg[WG];
+#pragma unroll
+    for (int c = 0; c < WG; ++c) {
+        const bool on = c < w;
+        T d = lane_pull(r[c], gb + c);
+        if (pfl.v) {
+            const T fc = lane_pull(flo, gb + c);
+            if (on && d < fc) {
+                d = fc;
+                ++boosted;
+            }
+        }
+        if (on && bad < 0 && !finite_pos(d)) bad = c;
+        const T rs = rsqrt_nr(on ? d : T(1));
+        rdg[c] = rs;
+        const T lic = (gi == c) ? d * rs : r[c] * rs;
+        if (on) r[c] = lic;
+#pragma unroll
+        for (int c2 = c + 1; c2 < WG; ++c2) {
+            const T lk = lane_pull(lic, gb + c2);
+            if (on) r[c2] -= lic * lk;
+        }
+    }
+    if (live && gi == 0 && bad >= 0)
+        atomicMin(status + (status_slot ? status_slot[tk.s] : 0), (unsigned long long)(tk.g0 + bad));
+    if (live && gi == 0 && boosted) atomicAdd(pfl.count, boosted);
+    if (live && gi < m)
+#pragma unroll
+        for (int c = 0; c < WG; ++c)
+            if (c < w && c <= gi) P[(int64_t)c * m + gi] = r[c];
+    // 2. inverse of the diagonal triangle, column gi
+    {
+        T y[WG];
+#pragma unroll
+        for (int a = 0; a < WG; ++a) {
+            T v = (a == gi) ? T(1) : T(0);
+#pragma unroll
+            for (int k = 0; k < a; ++k) v -= lane_pull(r[k], gb + a) * y[k];
+            y[a] = a < w ? v * rdg[a] : T(0);
+        }
+        T *Vi = Linv + tk.ioff;
+        if (live && gi < w)
+#pragma unroll
+            for (int a = 0; a < WG; ++a)
+                if (a < w) Vi[gi * w + a] = y[a];
+    }
+    // 3. update of the rows below, scatter-added into the ancestors
+#pragma unroll
+    for (int k0 = 0; k0 < G; k0 += CB) {
+        int32_t rv[CB];
+        int64_t cbk[CB];
+        T acc[CB];
+        bool ok[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int k = k0 + u, kc = min(max(k, w), m - 1);
+            cbk[u] = lane_pull(my_cb, gb + kc);
+            const int64_t crk = lane_pull(my_cr, gb + kc);
+            ok[u] = live && k >= w && k < m && gi >= k && gi < m;
+            rv[u] = ok[u] ? rel[crk + gi] : 0;
+            T a = T(0);
+#pragma unroll
+            for (int j = 0; j < WG; ++j) {
+                const T lk = lane_pull(r[j], gb + kc);
+                if (j < w) a += r[j] * lk;
+            }
+            acc[u] = a;
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+            if (ok[u]) atomicAdd(&Lx[cbk[u] + rv[u]], -acc[u]);
+    }
+}
+
+// The tiny supernodes of one level: tasks [0, n16) in groups of 16 lanes
+// (16 per workgroup), [n16, n32) in groups of 32 (8 per workgroup), the
+// rest one wave each (4 per workgroup); the workgroups of the three parts
+// follow each other.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t ntasks, const int64_t *cbase,
-                                              const int64_t *crel, const int32_t *rel, T *Lx, T *Linv,
-                                              unsigned long long *status, const int32_t *status_slot,
+__global__ __launch_bounds__(256) void k_tiny(const SmallTask *tasks, int64_t n16, int64_t n32, int64_t ntasks,
+                                              const int64_t *cbase, const int64_t *crel, const int32_t *rel, T *Lx,
+                                              T *Linv, unsigned long long *status, const int32_t *status_slot,
                                               PivotFloor<T> pfl) {
-    const int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t b = blockIdx.x;
+    const int64_t b16 = (n16 + 15) / 16, b32 = (n32 - n16 + 7) / 8;
+    if (b < b16) {
+        const int64_t gi = b * 16 + wv * 4 + (lane >> 4);
+        const bool live = gi < n16;
+        group_body<T, 16, false>(tasks[live ? gi : 0], live, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+        return;
+    }
+    b -= b16;
+    if (b < b32) {
+        const int64_t gi = n16 + b * 8 + wv * 2 + (lane >> 5);
+        const bool live = gi < n32;
+        group_body<T, 32, false>(tasks[live ? gi : n16], live, cbase, crel, rel, Lx, Linv, status, status_slot,
+                                 pfl);
+        return;
+    }
+    b -= b32;
+    const int64_t ti = n32 + b * 4 + wv;
     if (ti >= ntasks) return;  // the whole wave
     tiny_body<T, false>(tasks[ti], cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
 }
@@ -855,13 +1002,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             __builtin_amdgcn_s_waitcnt(0);  // this thread's scatter-adds have completed
             __syncthreads();
             for (int64_t k = ptgt_ptr[tk.s] + tid; k < ptgt_ptr[tk.s + 1]; k += 256) atomicSub(&pdep[ptgt[k]], 1);
-        } else if (wv < e.count) {
-            const SmallTask tk = ptiny[e.first + wv];
-            if (lane == 0) wait_value(&pdep[tk.s], 0, wc.err, wc.spin);
+        } else if (e.kind == 1) {
+            if (wv < e.count) {
+                const SmallTask tk = ptiny[e.first + wv];
+                if (lane == 0) wait_value(&pdep[tk.s], 0, wc.err, wc.spin);
+                __asm__ volatile("" ::: "memory");
+                tiny_body<T, true>(tk, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+                __builtin_amdgcn_s_waitcnt(0);
+                for (int64_t k = ptgt_ptr[tk.s] + lane; k < ptgt_ptr[tk.s + 1]; k += 64)
+                    atomicSub(&pdep[ptgt[k]], 1);
+            }
+        } else {
+            // kind 2 (3): up to 16 (8) tiny supernodes in groups of 16 (32)
+            // lanes; each group's first lane waits for its own supernode
+            const int G = e.kind == 2 ? 16 : 32;
+            const int gi = wv * (64 / G) + lane / G, gl = lane & (G - 1);
+            const bool live = gi < e.count;
+            const SmallTask tk = ptiny[e.first + (live ? gi : 0)];
+            if (live && gl == 0) wait_value(&pdep[tk.s], 0, wc.err, wc.spin);
             __asm__ volatile("" ::: "memory");
-            tiny_body<T, true>(tk, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+            if (e.kind == 2)
+                group_body<T, 16, true>(tk, live, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
+            else
+                group_body<T, 32, true>(tk, live, cbase, crel, rel, Lx, Linv, status, status_slot, pfl);
             __builtin_amdgcn_s_waitcnt(0);
-            for (int64_t k = ptgt_ptr[tk.s] + lane; k < ptgt_ptr[tk.s + 1]; k += 64) atomicSub(&pdep[ptgt[k]], 1);
+            if (live)
+                for (int64_t k = ptgt_ptr[tk.s] + gl; k < ptgt_ptr[tk.s + 1]; k += G) atomicSub(&pdep[ptgt[k]], 1);
         }
         __syncthreads();
         }
@@ -1188,13 +1354,16 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
 
 // ---------------------------------------------------------------------------
 // k_tiles128: the scatter update on 128x128 tiles for the large supernodes
-// (same operation as k_tiles in MODE_SCATTER).  8 waves in a 2x4 grid of
-// 64x32 sub-tiles, each a 4x2 set of 16x16x4 MFMA blocks, so two waves share
-// each SIMD and hide each other's MFMA latency; K staged through LDS 16 at a
-// time with the next chunk in registers while the current one is consumed.
-// The epilogue goes through LDS in four passes of 32 columns.
+// (same operation as k_tiles in MODE_SCATTER), or, with TRAIL, the bulk
+// trailing update inside a wide supernode (as MODE_TRAILING without the
+// next block's factorization: P[i][j] -= C for i >= j, j < jmax, in place).
+// 8 waves in a 2x4 grid of 64x32 sub-tiles, each a 4x2 set of 16x16x4 MFMA
+// blocks, so two waves share each SIMD and hide each other's MFMA latency; K
+// staged through LDS 16 at a time with the next chunk in registers while the
+// current one is consumed.  The epilogue goes through LDS in four passes of
+// 32 columns.
 // ---------------------------------------------------------------------------
-template <typename T, bool BF = false>
+template <typename T, bool BF = false, bool TRAIL = false>
 __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const int64_t *cbase, const int64_t *crel,
                                                   const int32_t *rel, T *Lx) {
     constexpr int TM = 128, KB = 16, PADA = 4, CPT = 8, NT = 512;
@@ -1221,7 +1390,7 @@ __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const i
     const bool col_ok = tk.j0 + lr < tk.jmax;
     const T *pa = P + min<int64_t>(tk.i0 + lr, m - 1);
     const T *pb = P + min(tk.j0 + lr, tk.jmax - 1);
-    if (tid < TM) {
+    if (!TRAIL && tid < TM) {
         const int64_t k = tk.aux + min(tk.j0 + tid, tk.jmax - 1);
         cb[tid] = cbase[k];
         cr[tid] = crel[k];
@@ -1312,11 +1481,18 @@ __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const i
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         int32_t rv[CPT];
+        T old[CPT];
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             const int c = 32 * pass + cq * CPT + cc;
             const int64_t gj = min(tk.j0 + c, tk.jmax - 1);
-            rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
+            if constexpr (TRAIL) {
+                old[cc] = P[gj * m + min<int64_t>(gi, m - 1)];
+                rv[cc] = 0;
+            } else {
+                rv[cc] = rel[cr[c] + max(min<int64_t>(gi, m - 1), gj)];
+                old[cc] = T(0);
+            }
         }
         if (wc == 32 * pass)
 #pragma unroll
@@ -1333,7 +1509,10 @@ __global__ __launch_bounds__(512) void k_tiles128(const TileTask *tasks, const i
                 const int c = 32 * pass + cq * CPT + cc;
                 const int64_t gj = tk.j0 + c;
                 if (gj >= tk.jmax || gj > gi) continue;
-                atomicAdd(&Lx[cb[c] + rv[cc]], -Cs[c & 31][r]);
+                if constexpr (TRAIL)
+                    P[gj * m + gi] = old[cc] - Cs[c & 31][r];
+                else
+                    atomicAdd(&Lx[cb[c] + rv[cc]], -Cs[c & 31][r]);
             }
         }
         __syncthreads();
@@ -2336,10 +2515,12 @@ void launch_potrf(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsi
 }
 
 template <typename T>
-void launch_tiny(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, T *Linv, unsigned long long *status,
-                 PivotFloor<T> pfl, hipStream_t st) {
+void launch_tiny(const DevPlan &P, int64_t t0, int64_t t16, int64_t t32, int64_t t1, T *Lx, T *Linv,
+                 unsigned long long *status, PivotFloor<T> pfl, hipStream_t st) {
     if (t1 <= t0) return;
-    hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(256), 0, st, P.tiny_tasks + t0, t1 - t0,
+    const int64_t n16 = t16 - t0, n32 = t32 - t0, nt = t1 - t0;
+    const int64_t blocks = (n16 + 15) / 16 + (n32 - n16 + 7) / 8 + (nt - n32 + 3) / 4;
+    hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)blocks), dim3(256), 0, st, P.tiny_tasks + t0, n16, n32, nt,
                        P.cbase, P.crel, P.rel, Lx, Linv, status, P.status_slot, pfl);
 }
 
@@ -2391,6 +2572,20 @@ void launch_tiles128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16,
     }
     hipLaunchKernelGGL((k_tiles128<T, false>), dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
                        P.ext_tiles_big + t0, P.cbase, P.crel, P.rel, Lx);
+}
+
+template <typename T>
+void launch_trail128(const DevPlan &P, int64_t t0, int64_t t1, T *Lx, bool bf16, hipStream_t st) {
+    if (t1 <= t0) return;
+    if constexpr (std::is_same<T, float>::value) {
+        if (bf16) {
+            hipLaunchKernelGGL((k_tiles128<T, true, true>), dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
+                               P.trail_big + t0, P.cbase, P.crel, P.rel, Lx);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_tiles128<T, false, true>), dim3((unsigned)(t1 - t0)), dim3(512), 0, st,
+                       P.trail_big + t0, P.cbase, P.crel, P.rel, Lx);
 }
 
 template <typename T>
@@ -2613,9 +2808,10 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
                                   int32_t *, WaitCtl, bool, PivotFloor<T>, hipStream_t);                    \
     template void launch_small<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,         \
                                   PivotFloor<T>, hipStream_t);                                              \
-    template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, T *, T *, unsigned long long *,          \
-                                 PivotFloor<T>, hipStream_t);                                               \
+    template void launch_tiny<T>(const DevPlan &, int64_t, int64_t, int64_t, int64_t, T *, T *,             \
+                                 unsigned long long *, PivotFloor<T>, hipStream_t);                         \
     template void launch_tiles128<T>(const DevPlan &, int64_t, int64_t, T *, bool, hipStream_t);            \
+    template void launch_trail128<T>(const DevPlan &, int64_t, int64_t, T *, bool, hipStream_t);            \
     template void launch_persist_small<T>(const DevPlan &, int64_t, int64_t, int32_t *, int32_t *, T *, T *, \
                                           unsigned long long *, PivotFloor<T>, WaitCtl, hipStream_t);       \
     template void launch_perm_in<T>(const DevPlan &, int64_t, int, const double *, int64_t, T *,            \

@@ -22,6 +22,9 @@ constexpr int kSmallW = 32;
 constexpr int kSmallM = 128;
 constexpr int kTinyW = 8;
 constexpr int kTinyM = 64;
+// Tiny supernodes with w <= kGroupW and m <= 16 (32) share a wave, four
+// (two) to a wave, 16 (32) lanes each.
+constexpr int kGroupW = 4;
 // Width of the column blocks a supernode is cut into, for the panel
 // factorization and for the triangular solves alike; each block's diagonal
 // triangle gets an explicit inverse in the inverse store.
@@ -56,10 +59,13 @@ struct Tuning {
     int32_t small_w = kSmallW, small_m = kSmallM;
     int32_t big_min = kBigMin, big_min_k = kBigMinK;
     int32_t solve_persist_max = kSolvePersistMax;
-    int32_t handover = 1;  // fused TRSM with in-launch waits (0: off)
+    int32_t handover = 1;  // fused TRSM with in-launch waits (0: off, 2: where the waits spread over the XCDs)
     int32_t delay = kDelay;  // column blocks per bulk trailing update
     int32_t persist = 0;     // small subtrees in one persistent launch (0: per level)
     int32_t ordering = 0;    // order computed by analyze when none is given (order_graph's method)
+    int32_t group = 1;       // tiny supernodes of 16 / 32 rows share a wave (0: one wave each)
+    int32_t bulk128 = 0;     // bulk trailing updates (K >= 128) on 128x128 tiles in a launch of their own
+    int32_t lookahead = 0;   // bulk update beyond the next group spread over that group's steps (delay >= 2)
 };
 
 // One pair (source supernode s, ancestor t) of the scatter: rows
@@ -131,8 +137,9 @@ struct SmallTask {
 };
 
 // One entry of the persistent launch over the small subtrees: one small
-// supernode (kind 0, psmall[first]) or up to four tiny ones (kind 1,
-// ptiny[first .. first + count - 1], one wave each).
+// supernode (kind 0, psmall[first]) or tiny ones, ptiny[first .. first +
+// count - 1]: up to four, one wave each (kind 1), up to 16 in groups of 16
+// lanes (kind 2), up to 8 in groups of 32 lanes (kind 3).
 struct PersistEntry {
     int32_t kind;
     int32_t first;
@@ -198,16 +205,21 @@ struct Symbolic {
         int64_t f0, f1;   // POTRF tasks
         int64_t p0, p1;   // TRSM tiles
         int64_t t0, tm, t1;  // trailing tiles: next block's columns, then the rest
-        double potrf_flops, trsm_flops, look_flops, rest_flops;  // algorithmic flops of its launches
+        int64_t q0, q1;      // bulk trailing tiles on 128x128 (trail_big), a launch after the trailing one
+        double potrf_flops, trsm_flops, look_flops, rest_flops, big_flops;  // algorithmic flops of its launches
     };
     std::vector<int64_t> level_step_ptr;   // [nlevels+1]
     std::vector<Step> steps;
     std::vector<int64_t> ext_tile_ptr;     // [nlevels+1] external tiles (64)
     std::vector<int64_t> ext_big_ptr;      // [nlevels+1] external tiles (128)
+    std::vector<TileTask> trail_big;       // bulk trailing tiles (128), by step
     std::vector<int64_t> small_ptr;        // [nlevels+1] into small_tasks
     std::vector<SmallTask> small_tasks;    // supernodes of the single-workgroup path
     std::vector<int64_t> tiny_ptr;         // [nlevels+1] into tiny_tasks
     std::vector<SmallTask> tiny_tasks;     // supernodes of the single-wave path
+    // per level, tiny_tasks[tiny_ptr[l] .. tiny_e16[l]) go in groups of 16
+    // lanes, [tiny_e16[l] .. tiny_e32[l]) in groups of 32, the rest one wave each
+    std::vector<int64_t> tiny_e16, tiny_e32;  // [nlevels]
     // Scatter addressing per row position k >= w_s of R_s (pair p of k,
     // target t): cbase = lptr[t] + (rows[k] - first column of t) * m_t is
     // column rows[k] of t's panel; crel = rel_off(p) - i0(p), so row

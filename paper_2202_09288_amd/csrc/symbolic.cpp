@@ -319,6 +319,7 @@ int build_schedule(Symbolic &S) {
     S.int_tiles.clear();
     S.ext_tiles.clear();
     S.ext_tiles_big.clear();
+    S.trail_big.clear();
     S.ext_flops.clear();
     S.ext_big_flops.clear();
     S.sblocks.clear();
@@ -401,9 +402,18 @@ int build_schedule(Symbolic &S) {
     S.tiny_ptr.assign(S.nlevels + 1, 0);
     S.tiny_tasks.clear();
     S.tiny_flops.assign(S.nlevels, 0.0);
+    S.tiny_e16.assign(S.nlevels, 0);
+    S.tiny_e32.assign(S.nlevels, 0);
     const Tuning &tu = S.tune;
     auto is_tiny = [&](int32_t s) {
         return S.super_ptr[s + 1] - S.super_ptr[s] <= tu.tiny_w && S.rptr[s + 1] - S.rptr[s] <= tu.tiny_m;
+    };
+    // lanes per tiny supernode: 16 or 32 (groups sharing a wave), else 64
+    auto group_of = [&](int32_t s) {
+        const int32_t w = S.super_ptr[s + 1] - S.super_ptr[s];
+        const int64_t m = S.rptr[s + 1] - S.rptr[s];
+        if (!tu.group || w > kGroupW) return 64;
+        return m <= 16 ? 16 : (m <= 32 ? 32 : 64);
     };
     auto is_small = [&](int32_t s) {
         return is_tiny(s) ||
@@ -438,7 +448,13 @@ int build_schedule(Symbolic &S) {
     for (int32_t l = 0; l < S.nlevels; ++l) {
         std::vector<int32_t> big;
         const int32_t level_first = (int32_t)S.pqueue.size();
-        int32_t tiny_open = -1;  // queue entry of the level's last tiny group, if not full
+        // the level's tiny tasks by lanes (16, 32, 64): per-level path (lt)
+        // and persistent launch (pt)
+        std::vector<SmallTask> lt[3], pt[3];
+        auto lanes_slot = [&](int32_t s) {
+            const int g = group_of(s);
+            return g == 16 ? 0 : (g == 32 ? 1 : 2);
+        };
         for (int32_t s : bylevel[l]) {
             if (allsmall[s]) {
                 const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
@@ -447,12 +463,7 @@ int build_schedule(Symbolic &S) {
                 const double w = wi, m = (double)mi;
                 S.persist_flops += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 + (m - w) * w * w + (m - w) * (m - w + 1) * w;
                 if (is_tiny(s)) {
-                    if (tiny_open < 0 || S.pqueue[tiny_open].count == 4) {
-                        tiny_open = (int32_t)S.pqueue.size();
-                        S.pqueue.push_back(PersistEntry{1, (int32_t)S.ptiny.size(), 0, 0});
-                    }
-                    S.pqueue[tiny_open].count++;
-                    S.ptiny.push_back(tk);
+                    pt[lanes_slot(s)].push_back(tk);
                 } else {
                     S.pqueue.push_back(PersistEntry{0, (int32_t)S.psmall.size(), 1, 0});
                     S.psmall.push_back(tk);
@@ -463,9 +474,12 @@ int build_schedule(Symbolic &S) {
                 const int32_t wi = S.super_ptr[s + 1] - S.super_ptr[s];
                 const int64_t mi = S.rptr[s + 1] - S.rptr[s];
                 const bool tiny = is_tiny(s);
-                (tiny ? S.tiny_tasks : S.small_tasks)
-                    .push_back(SmallTask{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s, (int32_t)mi, wi,
-                                         S.super_ptr[s]});
+                const SmallTask tk{S.lptr[s], S.rptr[s], S.inv_off[first_blk[s]], s, (int32_t)mi, wi, S.super_ptr[s]};
+                if (tiny) {
+                    lt[lanes_slot(s)].push_back(tk);
+                } else {
+                    S.small_tasks.push_back(tk);
+                }
                 // POTRF + TRSM + SYRK of the rows below (LAPACK counts)
                 const double w = wi, m = (double)mi;
                 (tiny ? S.tiny_flops : S.small_flops)[l] += w * w * w / 3.0 + w * w / 2.0 + w / 6.0 +
@@ -475,7 +489,24 @@ int build_schedule(Symbolic &S) {
             }
         }
         S.small_ptr[l + 1] = (int64_t)S.small_tasks.size();
+        S.tiny_tasks.insert(S.tiny_tasks.end(), lt[0].begin(), lt[0].end());
+        S.tiny_e16[l] = (int64_t)S.tiny_tasks.size();
+        S.tiny_tasks.insert(S.tiny_tasks.end(), lt[1].begin(), lt[1].end());
+        S.tiny_e32[l] = (int64_t)S.tiny_tasks.size();
+        S.tiny_tasks.insert(S.tiny_tasks.end(), lt[2].begin(), lt[2].end());
         S.tiny_ptr[l + 1] = (int64_t)S.tiny_tasks.size();
+        // the level's persistent tiny entries (the supernodes of one level
+        // do not depend on each other, so their order inside it is free):
+        // kind 2 holds up to 16 in groups of 16 lanes, kind 3 up to 8 in
+        // groups of 32, kind 1 up to 4, one wave each
+        for (int k = 0; k < 3; ++k) {
+            const int32_t kind = k == 0 ? 2 : (k == 1 ? 3 : 1), cap = k == 0 ? 16 : (k == 1 ? 8 : 4);
+            for (size_t i = 0; i < pt[k].size(); i += cap) {
+                const int32_t cnt = (int32_t)std::min<size_t>(cap, pt[k].size() - i);
+                S.pqueue.push_back(PersistEntry{kind, (int32_t)S.ptiny.size(), cnt, 0});
+                S.ptiny.insert(S.ptiny.end(), pt[k].begin() + i, pt[k].begin() + i + cnt);
+            }
+        }
         {
             // chunks of this level's entries: at least about 4096 of them
             // (twice the workgroups the device holds) while chunks hold
@@ -493,12 +524,76 @@ int build_schedule(Symbolic &S) {
             int64_t w = S.super_ptr[s + 1] - S.super_ptr[s];
             maxb = std::max(maxb, (w + kNB - 1) / kNB);
         }
+        // handover 2: a step takes the hand-over only where its waiting
+        // tiles spread over the XCDs: eight or more supernodes get one, or
+        // the tiles that wait (all on their diagonal tile's XCD) are at most
+        // 1.5 of the launch's mean share per XCD; otherwise block b+1's
+        // column is updated without waits and gets a TRSM launch of its own
+        // The bulk update at the end of a group (step b, K = the group's
+        // columns) covers the columns beyond block b+1 on 64x64 tiles.  With
+        // lookahead (delay >= 2) only the next group's columns get it in
+        // step b; the columns beyond the next group are updated in the
+        // next group's other steps (its tiles dealt round-robin over steps
+        // b+1 .. b+delay-1), beside their column updates and
+        // factorizations.  Those columns are next written by the next
+        // group's own bulk update (step b+delay), a later launch, and no
+        // step in between reads them, so the result is the same.
+        std::vector<std::vector<TileTask>> rest_at(maxb);
+        std::vector<double> rest_fl(maxb, 0.0);
+        {
+            const int64_t d = tu.delay;
+            const bool spread = tu.lookahead && d >= 2;
+            for (int32_t s : bylevel[l]) {
+                const int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+                for (int64_t b = 0; b * kNB < w; ++b) {
+                    const int64_t c1 = std::min<int64_t>(b * kNB + kNB, w), cx = std::min<int64_t>(c1 + kNB, w);
+                    if (c1 >= w) continue;
+                    const int64_t k0 = (b - b % d) * kNB, kd = c1 - k0;
+                    const bool close = b % d == d - 1 || cx >= w;
+                    if (!close || (tu.bulk128 && kd >= kTileBig)) continue;
+                    const int64_t cn = spread ? std::min<int64_t>(w, c1 + d * kNB) : w;
+                    int64_t t = 0;
+                    for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTile)
+                        for (int64_t i0 = j0; i0 < m; i0 += kTile) {
+                            const int64_t at = j0 < cn ? b : b + 1 + (t++ % (d - 1));
+                            rest_at[at].push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
+                                                           (int32_t)j0, (int32_t)k0, (int32_t)c1, (int32_t)w, -1, -1,
+                                                           0});
+                            // flops: SYRK on a diagonal tile, GEMM below it
+                            const double r = (double)(std::min<int64_t>(i0 + kTile, m) - i0),
+                                         c = (double)(std::min<int64_t>(j0 + kTile, w) - j0);
+                            rest_fl[at] += i0 == j0 ? (double)kd * (c * (c + 1) + 2.0 * (r - c) * c)
+                                                    : 2.0 * (double)kd * r * c;
+                        }
+                }
+            }
+        }
+        std::vector<char> fuse_step(maxb, 0);
+        for (int64_t b = 0; b < maxb; ++b) {
+            if (tu.handover == 1) {
+                fuse_step[b] = 1;
+                continue;
+            }
+            if (tu.handover != 2) continue;
+            int64_t B = 0, nsup = 0;
+            for (int32_t s : bylevel[l]) {
+                const int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
+                const int64_t c1 = std::min<int64_t>(b * kNB + kNB, w), cx = std::min<int64_t>(c1 + kNB, w);
+                if (b * kNB >= w || c1 >= w) continue;
+                ++nsup;
+                B += (m - cx + kTile - 1) / kTile;
+            }
+            const int64_t R = (int64_t)rest_at[b].size();
+            fuse_step[b] = nsup >= 8 || 8 * B <= 3 * (R + B) / 2;
+        }
         for (int64_t b = 0; b < maxb; ++b) {
             Symbolic::Step st;
             st.potrf_flops = 0.0;
             st.trsm_flops = 0.0;
             st.look_flops = 0.0;
             st.rest_flops = 0.0;
+            st.big_flops = 0.0;
+            st.q0 = (int64_t)S.trail_big.size();
             st.f0 = (int64_t)S.potrf_tasks.size();
             st.p0 = (int64_t)S.trsm_tiles.size();
             st.t0 = (int64_t)S.int_tiles.size();
@@ -522,7 +617,8 @@ int build_schedule(Symbolic &S) {
             // pattern take other tiles, else no-op entries (s = -1).
             const int64_t gb = b - b % tu.delay;  // first block of b's group
             const bool bulk = b % tu.delay == tu.delay - 1;
-            std::vector<TileTask> diag, rest, below;
+            std::vector<TileTask> diag, rest(rest_at[b]), below;
+            st.rest_flops += rest_fl[b];
             std::vector<int32_t> below_diag;  // diagonal tile of each waiting tile (index into diag)
             for (int32_t s : bylevel[l]) {
                 int64_t w = S.super_ptr[s + 1] - S.super_ptr[s], m = S.rptr[s + 1] - S.rptr[s];
@@ -538,8 +634,8 @@ int build_schedule(Symbolic &S) {
                 const bool close = bulk || cx >= w;
                 // block b+1 gets its TRSM from this step's tiles below its
                 // diagonal; block b got it from step b-1's
-                const bool fuse_next = tu.handover && c1 < w && cx - c1 == kNB;
-                const bool fused_here = tu.handover && b > 0 && c1 - c0 == kNB;
+                const bool fuse_next = fuse_step[b] && c1 < w && cx - c1 == kNB;
+                const bool fused_here = b > 0 && fuse_step[b - 1] && c1 - c0 == kNB;
                 const int32_t gnext = (int32_t)(S.super_ptr[s] + c1);
                 // flop counts: POTRF nb^3/3 + nb^2/2 + nb/6, TRSM r nb^2,
                 // SYRK k n(n+1), GEMM 2 m n k
@@ -548,9 +644,12 @@ int build_schedule(Symbolic &S) {
                     st.look_flops += nx * nx * nx / 3.0 + nx * nx / 2.0 + nx / 6.0;
                 st.look_flops += nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd;
                 if (fuse_next) st.look_flops += (double)(m - cx) * nx * nx;
-                if (close)
-                    st.rest_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
-                                     (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
+                // the bulk update on 128x128 tiles in a launch of its own
+                // (K of the group at least 128)
+                const bool to128 = tu.bulk128 && c1 - k0 >= kTileBig;
+                if (close && to128)
+                    st.big_flops += tot * (tot + 1) * kd + 2.0 * (double)(m - w) * tot * kd -
+                                    (nx * (nx + 1) * kd + 2.0 * ((double)(m - c1) - nx) * nx * kd);
                 // block 0 gets a POTRF task; block b+1 is factored by the
                 // workgroup of its diagonal tile in step b's column update
                 if (b == 0) {
@@ -569,13 +668,13 @@ int build_schedule(Symbolic &S) {
                 const int32_t di = (int32_t)diag.size();
                 diag.push_back(TileTask{S.lptr[s], S.inv_off[blk + 1], s, (int32_t)m, (int32_t)c1, (int32_t)c1,
                                         (int32_t)k0, (int32_t)c1, (int32_t)w, gnext, fuse_next ? blk + 1 : -1, 0});
-                if (close)
-                    // trailing update of the columns beyond block b+1:
-                    // rows [j0, m), K = [k0, c1)
-                    for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTile)
-                        for (int64_t i0 = j0; i0 < m; i0 += kTile)
-                            rest.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0, (int32_t)j0,
-                                                    (int32_t)k0, (int32_t)c1, (int32_t)w, -1, -1, 0});
+                if (close && to128)
+                    for (int64_t j0 = c1 + kTile; j0 < w; j0 += kTileBig)
+                        for (int64_t i0 = j0; i0 < m; i0 += kTileBig)
+                            S.trail_big.push_back(TileTask{S.lptr[s], S.rptr[s], s, (int32_t)m, (int32_t)i0,
+                                                           (int32_t)j0, (int32_t)k0, (int32_t)c1, (int32_t)w, -1,
+                                                           -1, 0});
+                // (the columns beyond block b+1 otherwise: rest_at)
                 // block b+1's columns below its diagonal tile
                 for (int64_t i0 = c1 + kTile; i0 < m; i0 += kTile) {
                     const TileTask tt{S.lptr[s], fuse_next ? S.inv_off[blk + 1] : S.rptr[s], s, (int32_t)m,
@@ -644,6 +743,7 @@ int build_schedule(Symbolic &S) {
             st.f1 = (int64_t)S.potrf_tasks.size();
             st.p1 = (int64_t)S.trsm_tiles.size();
             st.t1 = (int64_t)S.int_tiles.size();
+            st.q1 = (int64_t)S.trail_big.size();
             S.steps.push_back(st);
         }
         S.level_step_ptr[l + 1] = (int64_t)S.steps.size();
@@ -855,6 +955,19 @@ int verify_schedule(const Symbolic &S, std::string &msg) {
     for (const SmallTask &t : S.ptiny) seen[t.s]++;
     for (int32_t t = 0; t < S.nsuper; ++t)
         if (seen[t] + (blocked[t] ? 1 : 0) != 1) return fail("supernode not factored exactly once", t, seen[t]);
+    // the per-level tiny lists: groups of 16 lanes, then of 32, then one
+    // wave each, every supernode within its part's limits
+    for (int32_t l = 0; l < S.nlevels; ++l) {
+        const int64_t a = S.tiny_ptr[l], b = S.tiny_e16[l], c = S.tiny_e32[l], d = S.tiny_ptr[l + 1];
+        if (!(a <= b && b <= c && c <= d)) return fail("tiny lists out of order", l, b);
+        for (int64_t q = a; q < c; ++q) {
+            const SmallTask &t = S.tiny_tasks[q];
+            if (t.w > kGroupW || t.m > (q < b ? 16 : 32)) return fail("supernode does not fit its lane group", t.s, t.m);
+        }
+        for (int64_t q = a; q < d; ++q)
+            if (S.tiny_tasks[q].w > kTinyW || S.tiny_tasks[q].m > kTinyM)
+                return fail("supernode beyond the one-wave limits", S.tiny_tasks[q].s, S.tiny_tasks[q].m);
+    }
     // persistent launch: every count-down target comes in a later queue
     // entry than its source, and each counter starts at the number of its
     // sources, so a wait only ever waits on entries taken before it
@@ -862,9 +975,17 @@ int verify_schedule(const Symbolic &S, std::string &msg) {
     for (int64_t e = 0; e < (int64_t)S.pqueue.size(); ++e) {
         const PersistEntry &pe = S.pqueue[e];
         const std::vector<SmallTask> &src = pe.kind == 0 ? S.psmall : S.ptiny;
-        if (pe.count < 1 || pe.count > (pe.kind == 0 ? 1 : 4) || pe.first + pe.count > (int32_t)src.size())
+        const int32_t cap = pe.kind == 0 ? 1 : (pe.kind == 1 ? 4 : (pe.kind == 2 ? 16 : 8));
+        if (pe.kind < 0 || pe.kind > 3 || pe.count < 1 || pe.count > cap || pe.first < 0 ||
+            pe.first + pe.count > (int32_t)src.size())
             return fail("bad persistent queue entry", e, pe.count);
-        for (int32_t k = 0; k < pe.count; ++k) pos[src[pe.first + k].s] = e;
+        for (int32_t k = 0; k < pe.count; ++k) {
+            const SmallTask &t = src[pe.first + k];
+            // a group entry's supernodes fit their groups
+            if (pe.kind >= 2 && (t.w > kGroupW || t.m > (pe.kind == 2 ? 16 : 32)))
+                return fail("supernode does not fit its lane group", t.s, t.m);
+            pos[t.s] = e;
+        }
     }
     if (S.pchunk.empty() || S.pchunk.front() != 0 || S.pchunk.back() != (int32_t)S.pqueue.size())
         return fail("persistent chunks do not cover the queue", (int64_t)S.pchunk.size(), (int64_t)S.pqueue.size());

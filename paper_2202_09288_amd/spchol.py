@@ -52,7 +52,7 @@ KERNEL_NAMES = {"potrf": "k_potrf<{t}, false>", "trsm": "k_tiles<{t}, 2, false>"
 
 # schedule cut-offs of spc_options (0: library default, < 0: path off)
 TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k", "solve_persist_max",
-                 "handover", "delay", "persist", "ordering")
+                 "handover", "delay", "persist", "ordering", "group", "bulk128", "lookahead")
 
 
 class _Options(ctypes.Structure):

@@ -37,9 +37,12 @@ GROUPS = [
     ("small", ("small_w", "small_m"), [(32, 128), (16, 64), (32, 64), (-1, -1)]),
     ("big", ("big_min", "big_min_k"), [(256, 128), (128, 64), (512, 128), (256, 256), (-1, -1)]),
     ("persist", ("solve_persist_max",), [(1024,), (256,), (4096,)]),
-    ("handover", ("handover",), [(1,), (-1,)]),
     ("delay", ("delay",), [(1,), (2,), (3,), (4,)]),
+    ("handover", ("handover",), [(1,), (-1,), (2,)]),
+    ("lookahead", ("lookahead",), [(-1,), (1,)]),
     ("persist", ("persist",), [(-1,), (1,)]),
+    ("group", ("group",), [(1,), (-1,)]),
+    ("bulk128", ("bulk128",), [(-1,), (1,)]),
 ]
 
 

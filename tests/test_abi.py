@@ -117,7 +117,7 @@ def test_info_and_export():
 
 
 @pytest.mark.parametrize("field,value", [("tiny_w", 9), ("tiny_m", 65), ("small_w", 33), ("small_m", 129),
-                                         ("handover", 2)])
+                                         ("handover", 3), ("group", 2), ("bulk128", 2), ("lookahead", 2)])
 def test_cutoffs_beyond_kernel_limits_rejected(field, value):
     s = W.laplacian((6, 5), "5pt", 88, 0, unit=False, shift=1e-2, nrhs=1)
     with pytest.raises(spchol.SpcError) as e:

@@ -122,6 +122,15 @@ SCHEDULES = {
     "bulk updates every 3 blocks": {"delay": 3},
     "small subtrees in one persistent launch": {"persist": 1},
     "small subtrees persistent, one-wave path off": {"persist": 1, "tiny_w": -1},
+    "hand-over where its waits spread": {"handover": 2},
+    "hand-over where its waits spread, bulk every 3 blocks": {"delay": 3, "handover": 2},
+    "tiny supernodes one wave each": {"group": -1},
+    "bulk every 3 blocks, far columns in the next group's steps": {"delay": 3, "lookahead": 1},
+    "bulk every 2 blocks, far columns in the next group's steps, hand-over where it spreads":
+        {"delay": 2, "lookahead": 1, "handover": 2},
+    "bulk updates every 3 blocks on 128-tiles": {"delay": 3, "bulk128": 1},
+    "bulk updates every 2 blocks on 128-tiles, hand-over where it spreads": {"delay": 2, "bulk128": 1, "handover": 2},
+    "small subtrees persistent, tiny one wave each": {"persist": 1, "group": -1},
 }
 
 

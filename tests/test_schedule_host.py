@@ -14,7 +14,10 @@ from paper_2202_09288_amd import spchol  # noqa: E402  (conftest builds it when 
 
 TUNINGS = [None, {"handover": -1}, {"tiny_w": -1, "small_w": -1}, {"big_min": 1, "big_min_k": 1},
            {"tiny_w": 4, "tiny_m": 32, "small_w": 16, "small_m": 64}, {"delay": 2}, {"delay": 3},
-           {"delay": 4, "handover": -1}, {"persist": 1}, {"persist": 1, "tiny_w": 4, "tiny_m": 32}]
+           {"delay": 4, "handover": -1}, {"persist": 1}, {"persist": 1, "tiny_w": 4, "tiny_m": 32},
+           {"group": -1}, {"persist": 1, "group": -1}, {"handover": 2}, {"delay": 3, "handover": 2},
+           {"delay": 3, "bulk128": 1}, {"delay": 2, "bulk128": 1, "handover": 2},
+           {"delay": 3, "lookahead": 1}, {"delay": 4, "lookahead": 1, "handover": 2}]
 
 
 @pytest.mark.parametrize("dims", [(20, 20, 20), (30, 24, 28), (37, 23), (200, 150), (12, 9, 11)])

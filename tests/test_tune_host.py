@@ -30,6 +30,6 @@ def test_committed_cache_entries_are_valid_options():
 
 def test_candidate_groups_start_at_defaults():
     defaults = {"tiny_w": 8, "tiny_m": 64, "small_w": 32, "small_m": 128, "big_min": 256, "big_min_k": 128,
-                "solve_persist_max": 1024, "handover": 1, "delay": 1, "persist": -1}
+                "solve_persist_max": 1024, "handover": 1, "delay": 1, "persist": -1, "group": 1, "bulk128": -1, "lookahead": -1}
     for _, fields, cands in tune.GROUPS:
         assert tuple(defaults[f] for f in fields) == cands[0]
