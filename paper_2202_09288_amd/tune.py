@@ -140,9 +140,11 @@ def measure(systems, nrhs: int, tuning: dict, precision: str, reps: int, torch):
     return float(np.mean(fac[1:])), float(np.mean(sol[1:])), worst
 
 
-def tune(systems, nrhs: int, precision: str = "fp64", reps: int = 5, log=print) -> dict:
-    """Coordinate descent over GROUPS from the defaults; returns the best
-    setting with its times and every trial."""
+def tune(systems, nrhs: int, precision: str = "fp64", reps: int = 5, log=print, passes: int = 2) -> dict:
+    """Coordinate descent over GROUPS from the defaults (a second pass goes
+    over the groups again from the best setting, since some cut-offs pay
+    only together, e.g. the bulk-update depth and the hand-over rule);
+    returns the best setting with its times and every trial."""
     import torch
     torch.cuda.set_device(0)
     best = {}
@@ -156,14 +158,23 @@ def tune(systems, nrhs: int, precision: str = "fp64", reps: int = 5, log=print) 
         return (f + s) if ok else float("inf"), f, s
 
     cost, fbest, sbest = run(best)
-    for name, fields, cands in GROUPS:
-        log(f"group {name}")
-        for vals in cands[1:]:
-            trial = dict(best)
-            trial.update(dict(zip(fields, vals)))
-            c, f, s = run(trial)
-            if c < cost:
-                cost, fbest, sbest, best = c, f, s, trial
+    tried = {json.dumps(best, sort_keys=True)}
+    for p in range(passes):
+        changed = False
+        for name, fields, cands in GROUPS:
+            log(f"pass {p + 1}, group {name}")
+            for vals in cands:
+                trial = dict(best)
+                trial.update(dict(zip(fields, vals)))
+                key = json.dumps(trial, sort_keys=True)
+                if key in tried:
+                    continue
+                tried.add(key)
+                c, f, s = run(trial)
+                if c < cost:
+                    cost, fbest, sbest, best, changed = c, f, s, trial, True
+        if not changed:
+            break
     return {"tuning": best, "factor_ms": fbest, "solve_ms": sbest, "precision": precision, "nrhs": nrhs,
             "trials": trials}
 
@@ -173,12 +184,13 @@ def main(argv=None):
     ap.add_argument("--workload", default="grid3d60", choices=["grid3d60", "grid2d64", "elast48", "batch512"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16upd"])
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--passes", type=int, default=2, help="passes of coordinate descent over the groups")
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args(argv)
     systems, nrhs = workload(a.workload)
     key = cache_key(systems, a.precision, nrhs)
     print(f"tuning {a.workload} ({key})", flush=True)
-    res = tune(systems, nrhs, a.precision, a.reps, log=lambda m: print(m, flush=True))
+    res = tune(systems, nrhs, a.precision, a.reps, log=lambda m: print(m, flush=True), passes=a.passes)
     res["workload"] = a.workload
     save(key, res, a.out)
     print(json.dumps({k: v for k, v in res.items() if k != "trials"}), flush=True)
