@@ -41,7 +41,7 @@ enum spc_status {
     SPC_NOT_SPD = -2,         /* a pivot was not positive and finite */
     SPC_OUT_OF_MEMORY = -3,   /* device or host allocation failed */
     SPC_NO_CONVERGENCE = -4,  /* refinement did not reach the tolerance */
-    SPC_DEVICE_ERROR = -5,    /* a HIP call failed */
+    SPC_DEVICE_ERROR = -5,    /* a HIP call failed, or a device-side wait gave up */
     SPC_BAD_HANDLE = -6,      /* NULL or already released handle */
     SPC_NO_DEVICE = -7        /* no usable gfx950 device */
 };

@@ -45,7 +45,7 @@ KERNEL_CLASSES = {"assemble": 0, "potrf": 1, "trsm": 2, "trailing": 3, "scatter"
                   "small": 6, "tiny": 7, "small_trees": 8}
 # kernel behind each class (as rocprofv3 names it, precision filled in)
 KERNEL_NAMES = {"potrf": "k_potrf<{t}, false>", "trsm": "k_tiles<{t}, 2, false>", "trailing": "k_tiles<{t}, 0, false>",
-                "scatter": "k_tiles<{t}, 1, false>", "scatter_big": "k_tiles128<{t}, false>", "small": "k_small<{t}>",
+                "scatter": "k_tiles<{t}, 1, false>", "scatter_big": "k_tiles128<{t}, false, false>", "small": "k_small<{t}>",
                 "tiny": "k_tiny<{t}>", "small_trees": "k_persist_small<{t}>",
                 "assemble": "k_zero<{t}> + k_assemble<{t}>"}
 
