@@ -33,3 +33,33 @@ def test_candidate_groups_start_at_defaults():
                 "solve_persist_max": 1024, "handover": 1, "delay": 1, "persist": -1, "group": 1, "bulk128": -1, "lookahead": -1}
     for _, fields, cands in tune.GROUPS:
         assert tuple(defaults[f] for f in fields) == cands[0]
+
+
+def test_second_pass_finds_settings_that_pay_together(monkeypatch):
+    """Coordinate descent with a second pass: a cost where the deeper bulk
+    update pays only once the hand-over rule has changed, which the first
+    pass (bulk depth before hand-over) cannot see; no setting is timed
+    twice, and a rejected trial (backward error above the bar) never wins."""
+    import torch
+
+    def cost(t):
+        c = 10.0
+        if t.get("handover") == 2:
+            c -= 1.0
+            if t.get("delay") == 2:
+                c -= 3.0
+        return c
+
+    def fake_measure(systems, nrhs, tuning, precision, reps, torch_mod):
+        if tuning.get("group") == -1:
+            return 0.5, 0.0, 1.0  # fastest, but its backward error is rejected
+        return cost(tuning), 0.0, 1e-16
+
+    monkeypatch.setattr(tune, "measure", fake_measure)
+    monkeypatch.setattr(torch.cuda, "set_device", lambda *_: None)
+    res = tune.tune([None], 1, "fp64", log=lambda *_: None)
+    assert res["tuning"] == {"handover": 2, "delay": 2}
+    assert res["factor_ms"] == 6.0
+    keys = [json.dumps(t["tuning"], sort_keys=True) for t in res["trials"]]
+    assert len(keys) == len(set(keys))
+    assert any(not t["ok"] for t in res["trials"])
