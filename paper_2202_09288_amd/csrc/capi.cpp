@@ -137,6 +137,30 @@ int record_error(hipError_t e, const char *what, int line) {
 
 bool sym_ok(spc_symbolic s) { return s && s->magic == kSymMagic; }
 
+// Host-synchronous copies on a non-blocking stream of the calling thread's
+// own (one per thread and device, kept for the process): the legacy default
+// stream is never used, so these copies neither wait for other threads'
+// blocking streams nor collide with a graph capture running in another
+// thread (the HIP runtime refuses legacy-stream work while any capture is
+// in progress).  Callers synchronize the stream that produced the data
+// first.
+constexpr int kMaxDevices = 64;
+hipError_t copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+    thread_local hipStream_t streams[kMaxDevices] = {};
+    if (bytes == 0) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipMemcpyAsync(dst, src, bytes, kind, streams[dev]);
+    if (e == hipSuccess) e = hipStreamSynchronize(streams[dev]);
+    return e;
+}
+
 // The factor whose storage, status words and device-error word a handle
 // uses: itself, or for a view into a batch, the batch's merged factor.
 spc_factor_s *owner_of(spc_factor_s *f) { return f->batch ? f->batch->F : f; }
@@ -149,7 +173,7 @@ spc::WaitCtl wait_of(spc_factor_s *f) {
 // have drained), else SPC_OK.
 int check_deverr(spc_factor_s *f) {
     int32_t v = 0;
-    HIP_TRY(hipMemcpy(&v, owner_of(f)->deverr, sizeof(v), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(&v, owner_of(f)->deverr, sizeof(v), hipMemcpyDeviceToHost));
     if (v == 0) return SPC_OK;
     std::snprintf(g_last_error, sizeof(g_last_error),
                   "a wait on another workgroup gave up after its poll limit; the factor and the solves since "
@@ -241,7 +265,7 @@ int ensure_device_plan(spc_symbolic_s *sym, int device) {
         *p.dst = (const char *)base + off;
         off += (p.bytes + 255) & ~size_t(255);
     }
-    hipError_t e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
+    hipError_t e = copy_sync(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
         return record_error(e, "plan upload", __LINE__);
@@ -412,7 +436,7 @@ int capture_factor(spc_factor f, const double *d_values) {
     const spc::DevPlan &P = f->sym->dev.plan;
     drop_graph(f);
     if (!f->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal));
+    HIP_TRY(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeRelaxed));
     spc::launch_status_reset(f->status, f->nstatus, f->deverr, f->hflags, f->nflags, f->cap_stream);
     Prof none{nullptr};
     const spc::WaitCtl wc{f->deverr, f->spin};
@@ -538,11 +562,11 @@ int ensure_csr(spc_symbolic_s *sym) {
     void *base = nullptr;
     HIP_TRY(hipMalloc(&base, b0 + b1 + b2 + 256));
     char *c = (char *)base;
-    hipError_t e = hipMemcpy(c, S.csr_ptr.data(), bytes_of(S.csr_ptr), hipMemcpyHostToDevice);
+    hipError_t e = copy_sync(c, S.csr_ptr.data(), bytes_of(S.csr_ptr), hipMemcpyHostToDevice);
     if (e == hipSuccess && !S.csr_val.empty())
-        e = hipMemcpy(c + b0, S.csr_val.data(), bytes_of(S.csr_val), hipMemcpyHostToDevice);
+        e = copy_sync(c + b0, S.csr_val.data(), bytes_of(S.csr_val), hipMemcpyHostToDevice);
     if (e == hipSuccess && !S.csr_col.empty())
-        e = hipMemcpy(c + b0 + b1, S.csr_col.data(), bytes_of(S.csr_col), hipMemcpyHostToDevice);
+        e = copy_sync(c + b0 + b1, S.csr_col.data(), bytes_of(S.csr_col), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
         return record_error(e, "csr upload", __LINE__);
@@ -1080,7 +1104,7 @@ int spc_sync(spc_factor f, int64_t *bad_pivot) {
     int rc = check_deverr(f);
     if (rc) return rc;
     unsigned long long v = 0;
-    HIP_TRY(hipMemcpy(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(&v, f->status, sizeof(v), hipMemcpyDeviceToHost));
     if (v != ~0ull) {
         if (bad_pivot) *bad_pivot = (int64_t)v - f->status_col_off;
         return SPC_NOT_SPD;
@@ -1095,10 +1119,10 @@ int spc_factor_export(spc_factor f, double *h_dst) {
     HIP_TRY(hipStreamSynchronize(f->batch ? f->batch->F->stream : f->stream));
     int64_t cnt = S.panel_entries();
     if (f->precision == SPC_FP64) {
-        HIP_TRY(hipMemcpy(h_dst, f->Lx, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(copy_sync(h_dst, f->Lx, cnt * sizeof(double), hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tmp(cnt);
-        HIP_TRY(hipMemcpy(tmp.data(), f->Lx, cnt * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(copy_sync(tmp.data(), f->Lx, cnt * sizeof(float), hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < cnt; ++i) h_dst[i] = tmp[i];
     }
     for (int32_t s = 0; s < S.nsuper; ++s) {
@@ -1212,7 +1236,7 @@ int spc_factor_pivot_floors(spc_factor f, int64_t *raised) {
     if (o->precision != SPC_FP32_BF16UPD) return SPC_OK;
     HIP_TRY(hipStreamSynchronize(o->stream));
     int32_t v = 0;
-    HIP_TRY(hipMemcpy(&v, o->deverr + 1, sizeof(v), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(&v, o->deverr + 1, sizeof(v), hipMemcpyDeviceToHost));
     *raised = v;
     return SPC_OK;
 }
@@ -1272,7 +1296,7 @@ int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_bat
     b->meta_bytes = 2 * sizeof(double *) * count + sizeof(int64_t) * (2 * count + 1);
     if (rc == SPC_OK && hipMalloc(&b->meta, b->meta_bytes) != hipSuccess) rc = SPC_OUT_OF_MEMORY;
     if (rc == SPC_OK &&
-        hipMemcpy((char *)b->meta + sizeof(double *) * count + sizeof(int64_t) * count, b->col_off.data(),
+        copy_sync((char *)b->meta + sizeof(double *) * count + sizeof(int64_t) * count, b->col_off.data(),
                   sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice) != hipSuccess)
         rc = SPC_DEVICE_ERROR;
     if (rc) {
@@ -1376,7 +1400,7 @@ int spc_batch_solve_refined(spc_batch b, const double *const *d_B, double *const
             std::fill(seg.begin() + b->col_off[i], seg.begin() + b->col_off[i + 1], (int32_t)i);
         int32_t *d = nullptr;
         HIP_TRY(hipMalloc((void **)&d, n * sizeof(int32_t)));
-        hipError_t e = hipMemcpy(d, seg.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+        hipError_t e = copy_sync(d, seg.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(d);
             return record_error(e, "row systems upload", __LINE__);
@@ -1437,7 +1461,7 @@ int spc_batch_sync(spc_batch b, int64_t *bad_system, int64_t *bad_pivot) {
     int rc = check_deverr(b->F);
     if (rc) return rc;
     std::vector<unsigned long long> v(b->count);
-    HIP_TRY(hipMemcpy(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(v.data(), b->F->status, sizeof(unsigned long long) * b->count, hipMemcpyDeviceToHost));
     for (int i = 0; i < b->count; ++i)
         if (v[i] != ~0ull) {
             if (bad_system) *bad_system = i;
