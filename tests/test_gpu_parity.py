@@ -1146,6 +1146,54 @@ def test_serving_pooled_refactorization(torch_dev, lib):
     assert srv.peak <= srv.budget
 
 
+def test_graph_capture_beside_other_threads(torch_dev, lib):
+    """One thread captures factorization graphs (a new factor with graph
+    replay on, each first refactorization captures) while two others
+    factorize, synchronize, solve and export on streams of their own: no
+    call fails (host copies never go through the legacy stream, which the
+    runtime refuses while another thread captures), and every factor matches
+    the oracle's."""
+    import threading
+    torch = torch_dev
+    systems = [grid((23, 21), seed=40 + i, nrhs=2) for i in range(3)]
+    refs = []
+    for s in systems:
+        S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+        refs.append((S, S.factor(s.values)))
+    errors, worst = [], [0.0]
+
+    def work(i, capture):
+        try:
+            s = systems[i]
+            S, Lref = refs[i]
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+                dv = torch.from_numpy(s.values).cuda()
+                for _ in range(12):
+                    F = lib.factorize(sym, dv, stream=st)
+                    if capture:
+                        F.set_graph(True)
+                        F.refactorize(dv, stream=st)  # captures, then replays
+                    F.sync()
+                    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+                    F.solve(B, stream=st)
+                    st.synchronize()
+                    worst[0] = max(worst[0], factor_error(F.export(), Lref, S))
+                    F.close()
+        except Exception as e:  # recorded, checked below
+            errors.append(f"thread {i}: {e}")
+
+    threads = [threading.Thread(target=work, args=(i, i == 0)) for i in range(3)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    print(f"capture beside other threads: errors {errors}, worst factor error {worst[0]:.2e}", flush=True)
+    assert not errors
+    assert worst[0] <= REL_F_FP64
+
+
 # ---- orderings computed without coordinates ---------------------------------
 
 @pytest.mark.parametrize("method", ["nd", "md"])
