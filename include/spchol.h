@@ -155,6 +155,7 @@ typedef struct spc_info {
     int64_t solve_persistent_levels; /* top levels run as one persistent launch per sweep */
     int64_t solve_block_tasks;/* row tasks of the block solve kernels */
     int64_t solve_tiny_tasks; /* tiny supernodes solved one wave each */
+    int64_t updates_total;    /* sum of |U_s|: (source, ancestor) update pairs */
 } spc_info;
 
 /*
@@ -216,6 +217,9 @@ int spc_symbolic_verify(spc_symbolic sym);
  *   6 rows int32[rows_total]     row lists R_s (sorted; first w_s are cols(s))
  *   7 lptr int64[nsuper+1]       panel offsets (m_s*w_s entries each)
  *   8 level int32[nsuper]        0 for leaves, else 1 + max over children
+ *   9 uptr int64[nsuper+1]       offsets of the update lists U_s
+ *  10 ulist int32[updates_total] U_s: every supernode d < s with a row of R_d
+ *                                among cols(s), ascending (Sec. 3, Listing 1)
  * Returns SPC_INVALID_INPUT for an unknown `which`. */
 int spc_symbolic_export(spc_symbolic sym, int which, void *h_dst);
 

@@ -938,6 +938,7 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     out->solve_persistent_levels = S.nslevels - S.solve_split;
     out->solve_block_tasks = (int64_t)S.stasks.size();
     out->solve_tiny_tasks = (int64_t)S.stiny.size();
+    out->updates_total = (int64_t)S.pairs.size();
     return SPC_OK;
 }
 
@@ -967,6 +968,22 @@ int spc_symbolic_export(spc_symbolic sym, int which, void *h_dst) {
     case 6: return put(S.rows);
     case 7: return put(S.lptr);
     case 8: return put(S.level);
+    case 9:
+    case 10: {
+        // the update lists U_t (Sec. 3, Listing 1: every earlier supernode
+        // whose rows meet t's columns), ascending, as the transpose of the
+        // scatter pairs (source s -> ancestor t)
+        const int32_t ns = S.nsuper;
+        std::vector<int64_t> uptr(ns + 1, 0);
+        for (const spc::UpdatePair &q : S.pairs) uptr[q.target + 1]++;
+        for (int32_t t = 0; t < ns; ++t) uptr[t + 1] += uptr[t];
+        if (which == 9) return put(uptr);
+        std::vector<int32_t> ulist(S.pairs.size());
+        std::vector<int64_t> fill(uptr.begin(), uptr.end() - 1);
+        for (int32_t src = 0; src < ns; ++src)  // ascending sources: each list comes out sorted
+            for (int64_t k = S.pair_ptr[src]; k < S.pair_ptr[src + 1]; ++k) ulist[fill[S.pairs[k].target]++] = src;
+        return put(ulist);
+    }
     default: return SPC_INVALID_INPUT;
     }
 }

@@ -63,7 +63,7 @@ class _Info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n", "nnz_a", "nsuper", "nnz_l", "panel_entries", "flops", "levels", "rows_total",
         "max_width", "max_rows", "factor_bytes_fp64", "factor_bytes_fp32", "solve_levels",
-        "solve_persistent_levels", "solve_block_tasks", "solve_tiny_tasks")]
+        "solve_persistent_levels", "solve_block_tasks", "solve_tiny_tasks", "updates_total")]
 
 
 class _KernelStats(ctypes.Structure):
@@ -206,7 +206,8 @@ _EXPORT_ARRAYS = {"perm": (0, np.int32, "n"), "parent": (1, np.int32, "n"),
                   "colcount": (2, np.int32, "n"), "super_ptr": (3, np.int32, "ns1"),
                   "sparent": (4, np.int32, "ns"), "rptr": (5, np.int64, "ns1"),
                   "rows": (6, np.int32, "rows_total"), "lptr": (7, np.int64, "ns1"),
-                  "level": (8, np.int32, "ns")}
+                  "level": (8, np.int32, "ns"), "uptr": (9, np.int64, "ns1"),
+                  "ulist": (10, np.int32, "updates_total")}
 
 
 class Symbolic:
@@ -260,7 +261,7 @@ class Symbolic:
             which, dt, sz = _EXPORT_ARRAYS[name]
             i = self.info
             count = {"n": i["n"], "ns": i["nsuper"], "ns1": i["nsuper"] + 1,
-                     "rows_total": i["rows_total"]}[sz]
+                     "rows_total": i["rows_total"], "updates_total": i["updates_total"]}[sz]
             a = np.zeros(max(count, 1), dtype=dt)
             _check(_lib.spc_symbolic_export(self._h, which, _np_ptr(a)), "spc_symbolic_export")
             self._cache[name] = a[:count]

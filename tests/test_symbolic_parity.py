@@ -13,7 +13,7 @@ from paper_2202_09288_amd import workloads as W
 
 from paper_2202_09288_amd import spchol  # noqa: E402  (conftest builds it when missing)
 
-NAMES = ("perm", "parent", "colcount", "super_ptr", "sparent", "rptr", "rows", "lptr", "level")
+NAMES = ("perm", "parent", "colcount", "super_ptr", "sparent", "rptr", "rows", "lptr", "level", "uptr", "ulist")
 
 
 def compare(colptr, rowidx, perm, z):
@@ -29,6 +29,7 @@ def compare(colptr, rowidx, perm, z):
     assert L.info["nsuper"] == S.nsuper
     assert L.info["levels"] == S.sizes["nlevels"]
     assert L.info["panel_entries"] == S.sizes["panel_entries"]
+    assert L.info["updates_total"] == S.sizes["updates_total"]
     return S, L
 
 
