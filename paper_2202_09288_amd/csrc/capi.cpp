@@ -650,7 +650,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     if (rc) return rc;
     spc::launch_zero<unsigned long long>(umax, 3 * K + ns, st);
     if (T.seg) spc::launch_seg_norm_inf_A(T.rp, T.vm, T.values, T.seg, n, umax + 3 * K, st);
-    else spc::launch_norm_inf_A(T.rp, T.vm, T.values, n, umax + 3 * K, st);
+    else spc::launch_norm_inf_A(T.rp, T.vm, T.values, n, T.nnz, umax + 3 * K, st);
     colmax(Bw, umax + 2 * K);
 
     std::vector<unsigned long long> hb(3 * K + ns);

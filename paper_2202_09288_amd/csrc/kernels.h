@@ -156,7 +156,7 @@ void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,
                  const double *X, const double *B, double *Y, int64_t n, int64_t nnz, int nrhs, int64_t ld,
                  hipStream_t st);
-void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
+void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n, int64_t nnz,
                        unsigned long long *out, hipStream_t st);
 void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned long long *out, hipStream_t st);
 void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st);

@@ -2282,16 +2282,33 @@ __global__ __launch_bounds__(256) void k_spmv(const int64_t *rowptr, const int32
         for (int q = 0; q < nrhs; ++q) Y[i + q * ld] = B ? B[i + q * ld] - acc[q] : acc[q];
 }
 
-// out = max_i sum_j |a_ij| (as the bit pattern of a non-negative double)
-__global__ void k_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
-                             unsigned long long *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double sum = 0.0;
-    if (i < n)
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) sum += fabs(values[valmap[e]]);
-    sum = abs_key(sum);
-    for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sum));
+// out = max_i sum_j |a_ij| (as the bit pattern of a non-negative double):
+// LPR lanes per row as in k_spmv (so a group's loads are contiguous), rows
+// taken grid-stride by a capped grid, one atomic per workgroup
+template <int LPR>
+__global__ __launch_bounds__(256) void k_norm_inf_A(const int64_t *rowptr, const int64_t *valmap,
+                                                    const double *values, int64_t n, unsigned long long *out) {
+    __shared__ double wmax[4];
+    const int j = threadIdx.x % LPR;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / LPR);
+    double mx = 0.0;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;; i += stride) {
+        // every lane takes part in the shuffles: the loop ends for a whole
+        // wave at once (i advances by the same stride in all its groups)
+        if (__builtin_amdgcn_ballot_w64(i < n) == 0) break;
+        double sum = 0.0;
+        if (i < n)
+            for (int64_t e = rowptr[i] + j; e < rowptr[i + 1]; e += LPR) sum += fabs(values[valmap[e]]);
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        mx = fmax(mx, abs_key(sum));  // NaN as +Inf
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(out, (unsigned long long)__double_as_longlong(fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]))));
 }
 
 // out[q] = max_i |V[i, q]| (bit patterns), grid.y = q, 256 threads: one
@@ -2742,10 +2759,16 @@ void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *va
         hipLaunchKernelGGL(k_spmv<32>, dim3(grid1(n * 32, 256)), dim3(256), 0, st, rowptr, colidx, valmap, values,
                            X, B, Y, n, nrhs, ld);
 }
-void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n,
+void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const double *values, int64_t n, int64_t nnz,
                        unsigned long long *out, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_norm_inf_A, dim3(grid1(n, 256)), dim3(256), 0, st, rowptr, valmap, values, n, out);
+    const int64_t avg = (nnz + n - 1) / n;
+    const unsigned g4 = (unsigned)std::min<int64_t>(grid1(n * 4, 256), 1024);
+    const unsigned g32 = (unsigned)std::min<int64_t>(grid1(n * 32, 256), 1024);
+    if (avg <= 8)
+        hipLaunchKernelGGL(k_norm_inf_A<4>, dim3(g4), dim3(256), 0, st, rowptr, valmap, values, n, out);
+    else
+        hipLaunchKernelGGL(k_norm_inf_A<32>, dim3(g32), dim3(256), 0, st, rowptr, valmap, values, n, out);
 }
 static unsigned red_grid(int64_t n) {
     int64_t g = (n + 255) / 256;

@@ -1194,6 +1194,28 @@ def test_graph_capture_beside_other_threads(torch_dev, lib):
     assert worst[0] <= REL_F_FP64
 
 
+@pytest.mark.parametrize("case", ["grid7", "elasticity27"])
+def test_device_backward_error_matches_host(torch_dev, lib, case):
+    """The backward error the refinement computes on the device (FP64
+    residual, matrix and vector infinity norms: the short-row and the
+    long-row lane groups) equals the oracle's host definition of the same
+    solution, per right-hand side maximum, to a relative 1e-6."""
+    torch = torch_dev
+    s = grid((14, 13, 12), seed=21, nrhs=3) if case == "grid7" else \
+        W.elasticity27((7, 6, 5), 21, 0, kappa=1e4, nrhs=3, power_iters=5)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv, "fp32")
+    F.sync()
+    B = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    X = torch.zeros_like(B)
+    info = F.solve_refined(dv, B, X, tol=0.0, maxit=0)  # the plain FP32 solve, measured in FP64
+    eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+    print(f"{case}: device berr {info['berr']:.6e}, host eta {eta:.6e}", flush=True)
+    assert eta > 1e-12  # an FP32 solve: far from the FP64 level, so the two norms are tested
+    assert abs(info["berr"] - eta) <= 1e-6 * eta
+
+
 # ---- orderings computed without coordinates ---------------------------------
 
 @pytest.mark.parametrize("method", ["nd", "md"])
