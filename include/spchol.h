@@ -91,10 +91,11 @@ typedef struct spc_options {
      *                     gives every block a TRSM launch of its own (no
      *                     waits inside a launch: for many factorizations
      *                     sharing the device on several streams); 2 keeps
-     *                     the hand-over only in steps whose waiting tiles
-     *                     spread over the device (eight or more supernodes,
-     *                     or few waiting tiles beside the step's other
-     *                     tiles), the others get a TRSM launch.  Default 1.
+     *                     the hand-over only in steps where few tiles wait
+     *                     (eight or more supernodes, or the waiting tiles at
+     *                     most 1.5 of a launch's mean share per XCD beside
+     *                     the step's other tiles), the others get a TRSM
+     *                     launch.  Default 1.
      *   delay             column blocks per bulk trailing update inside a wide
      *                     supernode: the columns beyond a group of `delay`
      *                     64-column blocks receive the group's update once,
@@ -201,10 +202,12 @@ int spc_order(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, int m
  * for tests and diagnostics: every 64-column block of the blocked path has
  * the rows below its diagonal solved exactly once (by a TRSM launch, or by
  * the hand-over tiles of the step before, spc_options.handover), and every
- * tile that waits inside a trailing launch comes after the tile it waits for
- * at a launch index congruent to it mod 8, so both run on one XCD and the
- * wait cannot deadlock.  Returns SPC_OK, or SPC_INVALID_INPUT with the first
- * violation in spc_last_error_message(); SPC_BAD_HANDLE for a bad handle. */
+ * tile that waits inside a trailing launch comes after the diagonal tile of
+ * its block and carries the task that tile runs: the block's factorization
+ * is claimed by the first of those workgroups to start, so a wait is only
+ * ever on a running workgroup.  Returns SPC_OK, or SPC_INVALID_INPUT with the
+ * first violation in spc_last_error_message(); SPC_BAD_HANDLE for a bad
+ * handle. */
 int spc_symbolic_verify(spc_symbolic sym);
 
 /* Export one symbolic array to host memory for inspection.

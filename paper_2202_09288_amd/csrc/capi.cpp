@@ -510,7 +510,7 @@ int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus 
     hipError_t e = hipMalloc(&f->Lx, bytes);
     size_t inv_bytes = std::max<size_t>(1, (size_t)sym->S.inv_off.back()) * esz;
     if (e == hipSuccess) e = hipMalloc(&f->Linv, inv_bytes);
-    f->nflags = 4 * (int)sym->S.sblocks.size();  // one per 16-column panel of each block
+    f->nflags = spc::kFlagsPerBlock * (int)sym->S.sblocks.size();  // panel flags and claim of each block
     // status words, the device-error word and the raised-pivot count,
     // hand-over flags, the persistent launch's work counter (padded to 8
     // bytes) and its dependency counters

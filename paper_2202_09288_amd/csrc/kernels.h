@@ -58,6 +58,9 @@ struct PivotFloor {
 // theta: the unit roundoff of BF16 (8 significant bits), 2^-8.
 constexpr double kBf16PivotTheta = 1.0 / 256.0;
 
+// Hand-over words per 64-column block: the flags of its four 16-column
+// panels, then the claim of its factorization.
+constexpr int kFlagsPerBlock = 5;
 // Polls of a bounded wait by default: about a second.
 constexpr int32_t kSpinDefault = 1 << 20;
 

@@ -1043,7 +1043,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 //                  then factors that block (potrf_lds); a tile below it
 //                  with a flag then solves X L^T = P - C for its rows,
 //                  following the block's panels as they are handed out,
-//                  and stores X instead.
+//                  and stores X instead.  The block's factorization is
+//                  claimed by whichever of these workgroups comes first.
 //   MODE_SCATTER:  A, B = panel rows i0.., j0..; C (i >= j) scatter-added
 //                  atomically into the ancestors: C[i][j] goes to
 //                  cbase[j] + rel[crel[j] + i].
@@ -1063,10 +1064,21 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
     __shared__ T ABs[2][KB][TM + 4];  // A and B chunks, one buffer
     __shared__ T Cs[TM][TM + 1];
     __shared__ int64_t cb[TM], cr[TM];
+    __shared__ int claimed;
     T(*As)[TM + 4] = ABs[0];
     T(*Bs)[TM + 4] = ABs[1];
-    const TileTask tk = tasks[blockIdx.x];
-    if (MODE == MODE_TRAILING && tk.s < 0) return;  // a no-op entry of the launch layout
+    const TileTask own = tasks[blockIdx.x];
+    if (MODE == MODE_TRAILING && own.s < 0) return;  // a no-op entry of the launch layout
+    // the claim of the next block's factorization (see below): thread 0 of
+    // the diagonal tile's workgroup takes it at its start and reads the
+    // outcome only before factoring, so the atomic's round trip overlaps the
+    // tile's update
+    int32_t *const claim = (MODE == MODE_TRAILING && own.flag >= 0) ? hflags + kFlagsPerBlock * own.flag + 4 : nullptr;
+    int32_t ticket = 0;
+    // one tile task (the whole body; its returns end that task); defer: the
+    // diagonal tile's own task, which factors the block only if its ticket
+    // won the claim
+    auto body = [&](const TileTask tk, bool defer) {
     const int64_t m = tk.m;
     T *P = Lx + tk.loff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1248,6 +1260,11 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
                 const int64_t gj = tk.j0 + cg * CPT + cc;
                 if (gj < tk.jmax) P[gj * m + gi] = nv[cc];
             }
+        if (defer) {
+            if (tid == 0) claimed = ticket == 0;
+            __syncthreads();
+            if (!claimed) return;  // a tile below took the factorization
+        }
         __syncthreads();
         // LDS for the factorization: the tile buffers, free now (cb and cr
         // hold no scatter addresses in this mode)
@@ -1267,7 +1284,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
         // that no tile waits in vain)
         potrf_lds<T, BF>(A, rdg, Tf, T32, flags, nb2, P, m, tk.j0, Linv + tk.aux,
                          status + (status_slot ? status_slot[tk.s] : 0), wctl.err, tk.blk,
-                         tk.flag >= 0 ? hflags + 4 * tk.flag : nullptr, pfl);
+                         tk.flag >= 0 ? hflags + kFlagsPerBlock * tk.flag : nullptr, pfl);
         return;
     }
     if (MODE == MODE_TRAILING && tk.flag >= 0) {
@@ -1283,7 +1300,7 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
         __syncthreads();
         const T *Vi = Linv + tk.aux;                        // (L^{-1})_{jk} at Vi[k * TM + j]
         const T *Lb = P + (int64_t)tk.j0 * m + tk.j0;       // block-local L[i][k] at Lb[k * m + i]
-        int32_t *pf = hflags + 4 * tk.flag;
+        int32_t *pf = hflags + kFlagsPerBlock * tk.flag;
         const int w16 = wave * 16, l16 = lane & 15, lk4 = lane >> 4;
         bool ok = true;
 #pragma unroll
@@ -1350,6 +1367,39 @@ __global__ __launch_bounds__(256, 3) void k_tiles(const TileTask *tasks, const i
             if (gj <= gi) atomicAdd(&Lx[cb[c] + rv[cc]], -v);
         }
     }
+    };
+    if (MODE == MODE_TRAILING && own.flag >= 0) {
+        // The factorization of the next block (its diagonal tile's update,
+        // POTRF and the panels handed out) is one job that the first
+        // workgroup of the hand-over to arrive claims: the diagonal tile's,
+        // or, if that one has not started yet, a tile below it, which does
+        // the job before its own work.  A tile that waits for the panels
+        // thus always waits for a workgroup that is running and never waits
+        // itself, whatever the dispatch order, the XCDs or other launches.
+        // The claim word is cleared with the factorization's status.  The
+        // diagonal tile starts at once and looks at its ticket before it
+        // factors; a tile below first reads the word and takes a ticket
+        // only while nobody has (the diagonal tile, first in the launch,
+        // nearly always has).
+        if (own.i0 == own.j0) {
+            if (threadIdx.x == 0) ticket = __hip_atomic_fetch_add(claim, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            body(own, true);
+            return;
+        }
+        if (threadIdx.x == 0)
+            claimed = dev_load(claim) == 0 &&
+                      __hip_atomic_fetch_add(claim, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        __syncthreads();
+        const bool mine = claimed;
+        __syncthreads();
+        if (mine) {
+            TileTask d = own;
+            d.i0 = d.j0;
+            body(d, false);
+            __syncthreads();
+        }
+    }
+    body(own, false);
 }
 
 // ---------------------------------------------------------------------------

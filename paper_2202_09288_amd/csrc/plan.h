@@ -59,7 +59,7 @@ struct Tuning {
     int32_t small_w = kSmallW, small_m = kSmallM;
     int32_t big_min = kBigMin, big_min_k = kBigMinK;
     int32_t solve_persist_max = kSolvePersistMax;
-    int32_t handover = 1;  // fused TRSM with in-launch waits (0: off, 2: where the waits spread over the XCDs)
+    int32_t handover = 1;  // fused TRSM with in-launch waits (0: off, 2: only where few tiles wait)
     int32_t delay = kDelay;  // column blocks per bulk trailing update
     int32_t persist = 0;     // small subtrees in one persistent launch (0: per level)
     int32_t ordering = 0;    // order computed by analyze when none is given (order_graph's method)
@@ -103,12 +103,14 @@ struct TileTask {
                     // workgroup (i0 = j0) factors the block after updating it
     int32_t flag;   // trailing tiles of the next block's columns, when that
                     // block is a full kNB wide: its block id q, which owns
-                    // the flag words 4q..4q+3, one per 16-column panel.  The
-                    // diagonal tile's workgroup hands out each panel (its L
-                    // and the inverse of its diagonal triangle, inside the
-                    // inverse at aux) as soon as it is factored; each tile
-                    // below follows panel by panel with the block's TRSM on
-                    // its own rows.  -1 otherwise.
+                    // the hand-over words 5q..5q+4 (one flag per 16-column
+                    // panel, then the claim of the block's factorization).
+                    // The workgroup that claims it (the diagonal tile's, or
+                    // the first tile below to arrive) hands out each panel
+                    // (its L and the inverse of its diagonal triangle,
+                    // inside the inverse at aux) as soon as it is factored;
+                    // each tile below follows panel by panel with the
+                    // block's TRSM on its own rows.  -1 otherwise.
     int32_t pad;
 };
 
@@ -294,7 +296,8 @@ int build_schedule(Symbolic &S);
 // Host check of a schedule's invariants: every block of the blocked path
 // has the rows below it solved exactly once (TRSM launch or hand-over
 // tiles), and every tile that waits inside a trailing launch comes after its
-// diagonal tile at a launch index congruent to it mod 8.  0, or -1 with msg.
+// diagonal tile and carries the task that tile runs (which it runs itself
+// when it claims the block's factorization).  0, or -1 with msg.
 int verify_schedule(const Symbolic &S, std::string &msg);
 // Disjoint union of analyses with a schedule over the whole forest; the
 // offsets of each part (columns, panel entries, inverse store, caller
