@@ -124,8 +124,10 @@ class Server:
         self.policy = resolve_policy
         self.graph = graph
         # in-launch TRSM hand-over (waits inside a launch) for the
-        # factorizations; off by default, since the slots' factorizations
-        # share the device on several streams
+        # factorizations: safe beside the other slots' work (a wait is only
+        # on a running workgroup), but off by default, since its waiting
+        # tiles hold CUs that the other slots could use (2,000 requests at
+        # 466/s: p50 5.4 / p99 310 ms with it, 5.0 / 209 ms without)
         self.tuning = {"handover": 1 if handover else -1}
         self.sym_cache = {}
         self.analyzing = {}                # key -> future
