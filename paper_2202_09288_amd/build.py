@@ -22,7 +22,7 @@ FLAGS = [
 
 TASKLIB = os.path.join(HERE, "libtaskchol.so")
 # the host task-parallel CPU baseline: plain C++ with OpenMP, for any x86-64
-# with AVX2 and FMA (it is built here and run on the GPU machine's host)
+# with AVX2 and FMA (built once, run on the host of the GPU machine)
 TASK_FLAGS = ["-O3", "-std=c++17", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-Wall"]
 
 
