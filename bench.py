@@ -38,7 +38,8 @@ FP32_PEAK_TFLOPS = 157.3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--solves", type=int, default=200, help="solves timed for the solve p50/p99 (headline, 60^3)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--grid", type=int, default=60)
@@ -275,6 +276,20 @@ def head(args, value, unit, dtype, config, ms_per_step, higher=True):
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
+def solve_times(F, B0, Bw, count, stream, torch):
+    """Device ms of `count` solves of the resident factor (events around
+    each solve on the library's stream; the right-hand sides are restored
+    outside the timed interval)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    for e0, e1 in evs:
+        Bw.copy_(B0)
+        e0.record(stream)
+        F.solve(Bw)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+
+
 def timed(fn, steps, warmup, torch):
     """Device time per call of fn() (events on the current stream), ms."""
     for _ in range(warmup):
@@ -432,8 +447,10 @@ def bench_elast(args):
     fac_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     sol_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
     berr64 = host_backward_error(s.n, s.colptr, s.rowidx, s.values, Bw.cpu().numpy().T, s.B)
+    # solve latency over more samples than the steps: the p50/p99 reported
+    sol_ms = solve_times(F, B0, Bw, args.solves, stream, torch)
     nprof = max(1, min(args.steps, 2))
-    progress(f"plain FP64: {args.steps} steps, factor {fac_ms.mean():.2f} ms")
+    progress(f"plain FP64: {args.steps} steps, factor {fac_ms.mean():.2f} ms, {args.solves} solves")
     prof, lv = profiled_pass(F, step, nprof)
     roofline = roofline_of(prof, nprof, "fp64", "elast48", spchol.KERNEL_NAMES)
     F.close()
@@ -496,6 +513,7 @@ def bench_elast(args):
         "factor_ms_p50": round(float(np.median(fac_ms)), 3),
         "solve_ms_p50": round(float(np.percentile(sol_ms, 50)), 3),
         "solve_ms_p99": round(float(np.percentile(sol_ms, 99)), 3),
+        "solves_timed": int(sol_ms.size),
         "berr": berr64, "berr_ok": bool(berr64 <= 1e-12),
         "frac_of_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
         "analyze_s": round(t_analyze, 2),
@@ -684,6 +702,7 @@ def bench_grid3d(args):
 
     X = Bw.cpu().numpy().T
     berr = host_backward_error(s.n, s.colptr, s.rowidx, s.values, X, s.B)
+    sol_ms = solve_times(F, B0, Bw, args.solves, stream, torch)
 
     nprof = max(1, min(args.steps, 3))
     prof, lv_ms = profiled_pass(F, lambda: step([torch.cuda.Event(enable_timing=True) for _ in range(3)]), nprof)
@@ -716,6 +735,7 @@ def bench_grid3d(args):
         "factor_ms_p50": round(float(np.median(fac_ms)), 3),
         "solve_ms_p50": round(float(np.percentile(sol_ms, 50)), 3),
         "solve_ms_p99": round(float(np.percentile(sol_ms, 99)), 3),
+        "solves_timed": int(sol_ms.size),
         "berr": berr,
         "berr_ok": bool(berr <= 1e-12),
         "frac_of_peak": round(value / (peak * 1e3), 4),
