@@ -1,10 +1,10 @@
 """Host checks of the device schedule (spc_symbolic_verify, no device): every
 64-column block of the blocked path gets the rows below its diagonal solved
 exactly once, by a TRSM launch or by the tiles of the step before that take
-its TRSM inside the trailing launch, and every tile that waits inside a
-launch sits after the tile it waits for at a launch index congruent to it mod
-8 (one XCD: the wait cannot deadlock, whatever other launches hold the
-device).  The schedule is the one the GPU parity tests run."""
+its TRSM inside the trailing launch; every tile that waits inside a launch
+sits after its block's diagonal tile and carries the task that tile runs
+(it runs it itself when it claims the block's factorization).  The schedule
+is the one the GPU parity tests run."""
 import numpy as np
 import pytest
 
