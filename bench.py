@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--solves", type=int, default=200, help="solves timed for the solve p50/p99 (headline, 60^3)")
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--grid", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
