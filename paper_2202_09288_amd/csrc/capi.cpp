@@ -399,25 +399,34 @@ void enqueue_solve(const spc::Symbolic &S, const spc::DevPlan &P, const T *Lx, c
                    T *Acc, int32_t *sync, spc::WaitCtl wc, int nrhs, hipStream_t st) {
     const int64_t n = S.n, nb = (int64_t)S.sblocks.size(), nt = (int64_t)S.stasks.size();
     const spc::SolveSync sy = spc::make_solve_sync(sync, nb, wc);
-    spc::launch_zero<T>(Acc, n * nrhs, st);
-    spc::launch_solve_reset(P, nb, sy, st);
     const int32_t split = S.solve_split;
+    // the persistent sweeps' hand-over buffers: Acc (unused until the
+    // backward sweep) for the forward one, Y (spent by then) for the
+    // backward one
+    const bool persist = split < S.nslevels;
+    if (persist) spc::launch_fill_unset<T>(Acc, n * nrhs, st);
+    else spc::launch_zero<T>(Acc, n * nrhs, st);
+    spc::launch_solve_reset(P, nb, sy, st);
     // below solve_split the tiny supernodes of a level have their own
     // (one-wave) launch beside the level's task launch
     const int32_t tsplit = S.solve_split;
     for (int32_t l = 0; l < split; ++l) {
         if (l < tsplit)
             spc::launch_solve_tiny_fwd<T>(P, S.stiny_ptr[l], S.stiny_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, st);
-        spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, n, nrhs, sy, false, st);
+        spc::launch_solve_fwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, Y, X, nullptr, n, nrhs, sy, false,
+                                 st);
     }
-    if (split < S.nslevels) {
-        spc::launch_solve_fwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, Y, X, n, nrhs, sy, true, st);
-        spc::launch_solve_bwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, X, Acc, n, nrhs, sy, true, st);
+    if (persist) {
+        spc::launch_solve_fwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, Y, X, Acc, n, nrhs, sy, true, st);
+        spc::launch_fill_unset<T>(Y, n * nrhs, st);
+        spc::launch_zero<T>(Acc, n * nrhs, st);
+        spc::launch_solve_bwd<T>(P, S.stask_ptr[split], nt, Lx, Linv, X, Acc, Y, n, nrhs, sy, true, st);
     }
     for (int32_t l = split - 1; l >= 0; --l) {
         if (l < tsplit)
             spc::launch_solve_tiny_bwd<T>(P, S.stiny_ptr[l], S.stiny_ptr[l + 1], Lx, Linv, X, n, nrhs, st);
-        spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, n, nrhs, sy, false, st);
+        spc::launch_solve_bwd<T>(P, S.stask_ptr[l], S.stask_ptr[l + 1], Lx, Linv, X, Acc, nullptr, n, nrhs, sy, false,
+                                 st);
     }
 }
 

@@ -141,8 +141,10 @@ void launch_solve_reset(const DevPlan &P, int64_t nblocks, SolveSync sy, hipStre
 // persist, over the tasks of levels solve_split.. in one persistent launch
 // (t0 = first task of that range, t1 = all tasks; needs launch_solve_reset
 // first).
+// H (forward) and XB (backward): the persistent sweeps' hand-over buffers,
+// n x nrhs like Y, every entry unset (launch_fill_unset) before the sweep.
 template <typename T>
-void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
+void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X, T *H,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);
 // One-wave solve sweeps over the tiny supernodes t0..t1-1 of one level.
 template <typename T>
@@ -152,8 +154,10 @@ template <typename T>
 void launch_solve_tiny_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, int64_t n,
                            int nrhs, hipStream_t st);
 template <typename T>
-void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
+void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc, T *XB,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st);
+template <typename T>
+void launch_fill_unset(T *p, int64_t count, hipStream_t st);
 
 // refinement (FP64)
 void launch_spmv(const int64_t *rowptr, const int32_t *colidx, const int64_t *valmap, const double *values,

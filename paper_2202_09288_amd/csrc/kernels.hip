@@ -1623,6 +1623,39 @@ __device__ __forceinline__ void shared_store(T *p, T v) {
 __device__ __forceinline__ void release_own() { __builtin_amdgcn_s_waitcnt(0); }
 __device__ __forceinline__ void acquire_after_wait() {}
 
+// Hand-over buffers between consecutive blocks of a supernode: filled with
+// a signalling-NaN pattern before the sweep, which no arithmetic result
+// takes (a NaN that arithmetic yields is quiet), so a reader polls the
+// value itself and the writer needs no flag after it.
+template <typename T>
+struct Unset;
+template <>
+struct Unset<double> {
+    using bits_t = unsigned long long;
+    static constexpr bits_t bits = 0x7ff5a5a5a5a5a5a5ull;
+};
+template <>
+struct Unset<float> {
+    using bits_t = unsigned int;
+    static constexpr bits_t bits = 0x7fa5a5a5u;
+};
+template <typename T>
+__device__ __forceinline__ bool is_unset(T v) {
+    return __builtin_bit_cast(typename Unset<T>::bits_t, v) == Unset<T>::bits;
+}
+// Bounded wait for a handed-over value (0 once a wait gave up).
+template <typename T>
+__device__ __forceinline__ T wait_handed(const T *p, int32_t *err, int32_t spin) {
+    for (int it = 0; it < spin; ++it) {
+        const T v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!is_unset(v)) return v;
+        if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return T(0);
+        __builtin_amdgcn_s_sleep(1);
+    }
+    flag_device_error(err);
+    return T(0);
+}
+
 // Next task of a workgroup: the persistent grid takes it from the work
 // counter (through `order` when given), the level-launch grid takes its
 // own index once.  Returns -1 when there is none.
@@ -1646,9 +1679,13 @@ __device__ __forceinline__ int64_t next_task(int pass, const int32_t *order, int
 // part of Linv, its target blocks) is loaded before it waits.
 // A persistent task's rows fall in at most 256 blocks (one per row), so
 // each thread holds at most one target block to count down.
+// Persistent sweep, inside a supernode: the first task of block q - 1 puts
+// its sums for q's rows into H (as values, not subtracted from Y) instead
+// of counting q down, and q's tasks take y_q = Y - H once those values are
+// there (hand bits).
 template <typename T, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64_t ntasks, const int32_t *rows,
-                                                   const T *Lx, const T *Linv, T *Y, T *X, int64_t n,
+                                                   const T *Lx, const T *Linv, T *Y, T *X, T *H, int64_t n,
                                                    const int64_t *tgt_ptr, const int32_t *tgt, SolveSync sy) {
     constexpr int NB = kNB, QW = NB / 4;
     __shared__ T yq[NB];
@@ -1683,7 +1720,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
         }
         if (tid < NB) {
             const T *py = &Y[tk.g0 + min(tid, nb - 1)];
-            const T yv = PERSIST ? shared_load(py) : *py;
+            T yv = PERSIST ? shared_load(py) : *py;
+            if (PERSIST && (tk.hand & kHandIn) && tid < nb) yv -= wait_handed(&H[tk.g0 + tid], sy.err, sy.spin);
             yq[tid] = tid < nb ? yv : T(0);
         }
         __syncthreads();
@@ -1714,12 +1752,14 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
                 a2 += pv[k + 2] * xq[k + 2];
                 a3 += pv[k + 3] * xq[k + 3];
             }
-            atomicAdd(&Y[gr], -((a0 + a1) + (a2 + a3)));
+            const T v = (a0 + a1) + (a2 + a3);
+            if (PERSIST && (tk.hand & kHandOut) && tid < (tk.hand >> 8)) shared_store(&H[gr], v);
+            else atomicAdd(&Y[gr], -v);
         }
         if (PERSIST) {
             release_own();
             __syncthreads();
-            if (my_tgt >= 0) atomicSub(&sy.dep[my_tgt], 1);
+            if (my_tgt >= 0 && !((tk.hand & kHandOut) && my_tgt == tk.blk + 1)) atomicSub(&sy.dep[my_tgt], 1);
         }
     }
 }
@@ -1731,7 +1771,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
 template <typename T, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, int64_t ntasks,
                                                          const int32_t *rows, const T *Lx, const T *Linv, T *Y,
-                                                         T *X, int64_t n, int nrhs, const int64_t *tgt_ptr,
+                                                         T *X, T *H, int64_t n, int nrhs, const int64_t *tgt_ptr,
                                                          const int32_t *tgt, SolveSync sy) {
     constexpr int NB = kNB, NR = kMaxRhs, YPT = NB * NR / 256, KS = NB / 4;
     using acc_t = typename Mfma<T>::acc;
@@ -1783,6 +1823,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 #pragma unroll
         for (int u = 0; u < YPT; ++u) {
             const int e = tid + 256 * u, i = e / NR, q = e % NR;
+            if (PERSIST && (tk.hand & kHandIn) && i < nb && q < nrhs)
+                yv[u] -= wait_handed(&H[(tk.g0 + i) * nrhs + q], sy.err, sy.spin);
             yq[i][q] = (i < nb && q < nrhs) ? yv[u] : T(0);
         }
         __syncthreads();
@@ -1809,13 +1851,18 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = 64 * wave + 16 * tt + Mfma<T>::row(lane, v), q = lane & 15;
-                if (tk.r0 + rr < tk.r1 && q < nrhs) atomicAdd(&Y[grs[rr] * nrhs + q], -acc[v]);
+                if (tk.r0 + rr < tk.r1 && q < nrhs) {
+                    if (PERSIST && (tk.hand & kHandOut) && rr < (tk.hand >> 8))
+                        shared_store(&H[grs[rr] * nrhs + q], acc[v]);
+                    else
+                        atomicAdd(&Y[grs[rr] * nrhs + q], -acc[v]);
+                }
             }
         }
         if (PERSIST) {
             release_own();
             __syncthreads();
-            if (my_tgt >= 0) atomicSub(&sy.dep[my_tgt], 1);
+            if (my_tgt >= 0 && !((tk.hand & kHandOut) && my_tgt == tk.blk + 1)) atomicSub(&sy.dep[my_tgt], 1);
         }
         __syncthreads();
     }
@@ -1833,12 +1880,14 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
 // rows are ready, which keeps that exchange off the chain of blocks.
 // Rows below the block belong to ancestors, whose x is final before the
 // block's tasks read it (level order, or the done flags of the persistent
-// sweep).
+// sweep).  Persistent sweep, inside a supernode: the task finishing block
+// q also puts x_q into XB, and the first task of block q - 1 (whose first
+// rows are q's) polls XB for those rows instead of q's done flag (hand bits).
 template <typename T, int NR, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64_t ntasks, const int32_t *order,
                                                    const int32_t *rows, const T *Lx, const T *Linv, T *X, T *Acc,
-                                                   int64_t n, int nrhs, const int64_t *tgt_ptr, const int32_t *tgt,
-                                                   SolveSync sy) {
+                                                   T *XB, int64_t n, int nrhs, const int64_t *tgt_ptr,
+                                                   const int32_t *tgt, SolveSync sy) {
     constexpr int NB = kNB, QW = 16, RG = 64;
     constexpr int XR = 256 * (NR + 1), SM = 4 * NB * NR, VT = NR == 1 ? 0 : NB * (NB + 1);
     constexpr int SH = XR > SM ? (XR > VT ? XR : VT) : (SM > VT ? SM : VT);
@@ -1914,16 +1963,20 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                                                  __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        // rows of the next block of the supernode: their x come through XB
+        const bool handed = PERSIST && (tk.hand & kHandOut) && tid < (tk.hand >> 8);
         if (PERSIST) {
-            if (my_tgt >= 0) wait_value(&sy.done[my_tgt], 1, sy.err, sy.spin);
+            if (my_tgt >= 0 && !((tk.hand & kHandOut) && my_tgt == tk.blk + 1))
+                wait_value(&sy.done[my_tgt], 1, sy.err, sy.spin);
             __syncthreads();
             acquire_after_wait();
         }
         T xv[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-            const T *px = &X[gr * nrhs + min(q, nrhs - 1)];
-            xv[q] = PERSIST ? shared_load(px) : *px;
+            const int64_t e = gr * nrhs + min(q, nrhs - 1);
+            xv[q] = handed ? (q < nrhs ? wait_handed(&XB[e], sy.err, sy.spin) : T(0))
+                           : (PERSIST ? shared_load(&X[e]) : X[e]);
         }
 #pragma unroll
         for (int q = 0; q < NR; ++q) xr[tid][q] = (rown < tk.r1 && q < nrhs) ? xv[q] : T(0);
@@ -2023,8 +2076,12 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                 a += __shfl_xor(a, 1);
                 a += __shfl_xor(a, 2);
                 if ((tid & 3) == 0 && oc < nb) {
-                    if (PERSIST) shared_store(&X[tk.g0 + oc], a);
-                    else X[tk.g0 + oc] = a;
+                    if (PERSIST) {
+                        shared_store(&X[tk.g0 + oc], a);
+                        if (tk.hand & kHandIn) shared_store(&XB[tk.g0 + oc], a);
+                    } else {
+                        X[tk.g0 + oc] = a;
+                    }
                 }
             } else if constexpr (NR < kMaxRhs) {
                 // a few right-hand sides: the inverse staged in LDS, each
@@ -2048,8 +2105,12 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                         }
                         if (i < nb) a0 += Vt[i][c] * tq[i][q];
                         const T a = a0 + a1;
-                        if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], a);
-                        else X[(tk.g0 + c) * nrhs + q] = a;
+                        if (PERSIST) {
+                            shared_store(&X[(tk.g0 + c) * nrhs + q], a);
+                            if (tk.hand & kHandIn) shared_store(&XB[(tk.g0 + c) * nrhs + q], a);
+                        } else {
+                            X[(tk.g0 + c) * nrhs + q] = a;
+                        }
                     }
                 }
             } else {
@@ -2072,8 +2133,12 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const SolveTask *tasks, int64
                 for (int v = 0; v < 4; ++v) {
                     const int c = 16 * g + Mfma<T>::row(k, v), q = k & 15;
                     if (c < nb && q < nrhs) {
-                        if (PERSIST) shared_store(&X[(tk.g0 + c) * nrhs + q], xa[v]);
-                        else X[(tk.g0 + c) * nrhs + q] = xa[v];
+                        if (PERSIST) {
+                            shared_store(&X[(tk.g0 + c) * nrhs + q], xa[v]);
+                            if (tk.hand & kHandIn) shared_store(&XB[(tk.g0 + c) * nrhs + q], xa[v]);
+                        } else {
+                            X[(tk.g0 + c) * nrhs + q] = xa[v];
+                        }
                     }
                 }
             }
@@ -2286,6 +2351,13 @@ __global__ void k_solve_reset(const int32_t *fdep, int64_t nblocks, SolveSync sy
         sy.cnt[i] = 0;
     }
     if (i < 2) sy.queue[i] = 0;
+}
+
+// The hand-over buffers of a solve: every entry unset.
+template <typename T>
+__global__ void k_fill_unset(T *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = __builtin_bit_cast(T, Unset<T>::bits);
 }
 
 // |v| for the maxima of refinement, with NaN mapped to +Inf: fmax drops a
@@ -2709,7 +2781,13 @@ void launch_solve_reset(const DevPlan &P, int64_t nblocks, SolveSync sy, hipStre
 }
 
 template <typename T>
-void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X,
+void launch_fill_unset(T *p, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_unset<T>, dim3(grid1(count, 256)), dim3(256), 0, st, p, count);
+}
+
+template <typename T>
+void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *Y, T *X, T *H,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st) {
     if (t1 <= t0) return;
     const int64_t nt = t1 - t0;
@@ -2718,16 +2796,17 @@ void launch_solve_fwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
     const int64_t *tp = P.stgt_ptr + t0;
     if (nrhs == 1) {
         if (persist)
-            hipLaunchKernelGGL((k_solve_fwd<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, tp, P.stgt, sy);
+            hipLaunchKernelGGL((k_solve_fwd<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, H, n, tp, P.stgt,
+                               sy);
         else
-            hipLaunchKernelGGL((k_solve_fwd<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, tp, P.stgt,
+            hipLaunchKernelGGL((k_solve_fwd<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, H, n, tp, P.stgt,
                                sy);
     } else {
         if (persist)
-            hipLaunchKernelGGL((k_solve_fwd_multi<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, nrhs,
+            hipLaunchKernelGGL((k_solve_fwd_multi<T, true>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, H, n, nrhs,
                                tp, P.stgt, sy);
         else
-            hipLaunchKernelGGL((k_solve_fwd_multi<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, n, nrhs,
+            hipLaunchKernelGGL((k_solve_fwd_multi<T, false>), g, b, 0, st, tk, nt, P.rows, Lx, Linv, Y, X, H, n, nrhs,
                                tp, P.stgt, sy);
     }
 }
@@ -2759,7 +2838,7 @@ void launch_solve_tiny_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx
 }
 
 template <typename T>
-void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc,
+void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, const T *Linv, T *X, T *Acc, T *XB,
                       int64_t n, int nrhs, SolveSync sy, bool persist, hipStream_t st) {
     if (t1 <= t0) return;
     const int64_t nt = t1 - t0;
@@ -2773,10 +2852,10 @@ void launch_solve_bwd(const DevPlan &P, int64_t t0, int64_t t1, const T *Lx, con
     do {                                                                                                      \
         if (persist)                                                                                          \
             hipLaunchKernelGGL((k_solve_bwd<T, NRV, true>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X, Acc, \
-                               n, nrhs, tp, P.stgt, sy);                                                      \
+                               XB, n, nrhs, tp, P.stgt, sy);                                                  \
         else                                                                                                  \
             hipLaunchKernelGGL((k_solve_bwd<T, NRV, false>), g, b, 0, st, tk, nt, ord, P.rows, Lx, Linv, X,    \
-                               Acc, n, nrhs, tp, P.stgt, sy);                                                 \
+                               Acc, XB, n, nrhs, tp, P.stgt, sy);                                             \
     } while (0)
     if (nrhs == 1) {
         SPC_BWD(1);
@@ -2891,9 +2970,10 @@ template void launch_zero<unsigned long long>(unsigned long long *, int64_t, hip
                                     hipStream_t);                                                           \
     template void launch_perm_out<T>(const DevPlan &, int64_t, int, const T *, double *, int64_t,           \
                                      hipStream_t);                                                          \
-    template void launch_solve_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
+    template void launch_fill_unset<T>(T *, int64_t, hipStream_t);                                         \
+    template void launch_solve_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *, T *, \
                                       int64_t, int, SolveSync, bool, hipStream_t);                          \
-    template void launch_solve_bwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *,     \
+    template void launch_solve_bwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *, T *, \
                                       int64_t, int, SolveSync, bool, hipStream_t);                          \
     template void launch_solve_tiny_fwd<T>(const DevPlan &, int64_t, int64_t, const T *, const T *, T *, T *, \
                                            int64_t, int, hipStream_t);                                      \

@@ -171,7 +171,16 @@ struct SolveTask {
     int32_t ntasks;  // tasks of the block
     int32_t blk;
     int32_t first;   // 1 for the block's first task
+    // Persistent sweeps, hand-over between blocks q - 1 and q of one
+    // supernode: bit 0 on every task of q (forward: the sums of q - 1's
+    // first task for q's rows come through the hand-over buffer; backward,
+    // on q's first task: x_q goes out through it too); bit 1 on the first
+    // task of q - 1, whose first (hand >> 8) rows are q's (forward: their
+    // sums go out through the buffer; backward: their x come in through it).
+    int32_t hand;
+    int32_t pad;
 };
+constexpr int32_t kHandIn = 1, kHandOut = 2;
 
 struct Symbolic {
     Tuning tune;

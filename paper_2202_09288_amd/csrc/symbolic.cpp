@@ -844,6 +844,8 @@ int build_schedule(Symbolic &S) {
                 tk.r1 = (int32_t)r1;
                 tk.blk = q;
                 tk.first = cnt == 0;
+                tk.hand = 0;
+                tk.pad = 0;
                 S.stasks.push_back(tk);
                 ++cnt;
                 r = r1;
@@ -877,6 +879,25 @@ int build_schedule(Symbolic &S) {
                 }
             }
             S.stgt_ptr[t + 1] = (int64_t)S.stgt.size();
+        }
+        // hand-over inside a supernode: the first task of block q - 1 covers
+        // q's rows first (its rows start right below q - 1), so in the
+        // persistent sweeps it passes q's sums (forward) and takes x_q
+        // (backward) through buffers polled for a value, which spares the
+        // counter or flag round trip on the chain from block to block
+        {
+            std::vector<int64_t> first_of(nb, -1);
+            for (int64_t t = tp0; t < nt; ++t)
+                if (S.stasks[t].first) first_of[S.stasks[t].blk] = t;
+            for (int64_t q = 1; q < nb; ++q) {
+                const SolveBlock &B = S.sblocks[q];
+                if (B.c0 == 0 || first_of[q] < 0 || first_of[q - 1] < 0) continue;
+                SolveTask &prev = S.stasks[first_of[q - 1]];
+                prev.hand |= kHandOut | ((B.c1 - B.c0) << 8);
+                for (int64_t t = first_of[q]; t < first_of[q] + S.stasks[first_of[q]].ntasks; ++t)
+                    S.stasks[t].hand |= kHandIn;
+                S.fdep[q]--;
+            }
         }
         // backward order: levels from the top; inside a level, each block's
         // other tasks and then its first task, which finishes the block (it
@@ -1009,6 +1030,46 @@ int verify_schedule(const Symbolic &S, std::string &msg) {
     }
     for (int32_t t = 0; t < S.nsuper; ++t)
         if (pos[t] >= 0 && count[t] != S.pdep0[t]) return fail("persistent counter start", t, S.pdep0[t]);
+    // persistent solves: a hand-over goes from the first task of block q - 1
+    // to every task of block q of the same supernode, over exactly q's rows,
+    // which come first in that task; each forward counter starts at the
+    // (task, block) contributions of the persistent tasks that do not come
+    // through a hand-over
+    {
+        const int64_t nt = (int64_t)S.stasks.size(), tp0 = S.stask_ptr[S.solve_split];
+        std::vector<int32_t> want(nb, 0);
+        for (int64_t t = 0; t < nt; ++t) {
+            const SolveTask &k = S.stasks[t];
+            if (t < tp0) {
+                if (k.hand) return fail("hand-over outside the persistent sweeps", t, k.hand);
+                continue;
+            }
+            const bool out = (k.hand & kHandOut) != 0;
+            if (out) {
+                const int64_t q = k.blk + 1;
+                if (!k.first || q >= nb || S.sblocks[q].s != S.sblocks[k.blk].s || k.r0 != S.sblocks[q].c0 ||
+                    (k.hand >> 8) != S.sblocks[q].c1 - S.sblocks[q].c0)
+                    return fail("hand-over not over the next block's rows", t, k.hand);
+            }
+            if ((k.hand & kHandIn) != 0) {
+                const SolveBlock &B = S.sblocks[k.blk];
+                if (B.c0 == 0) return fail("hand-over into a supernode's first block", t, k.blk);
+            }
+            for (int64_t e = S.stgt_ptr[t]; e < S.stgt_ptr[t + 1]; ++e)
+                if (!(out && S.stgt[e] == k.blk + 1)) want[S.stgt[e]]++;
+        }
+        std::vector<char> hands_out(nb, 0);
+        for (int64_t t = tp0; t < nt; ++t)
+            if (S.stasks[t].first && (S.stasks[t].hand & kHandOut)) hands_out[S.stasks[t].blk] = 1;
+        for (int64_t t = tp0; t < nt; ++t) {
+            const SolveTask &k = S.stasks[t];
+            const bool in = (k.hand & kHandIn) != 0;
+            if (in != (k.blk > 0 && S.sblocks[k.blk].c0 > 0 && hands_out[k.blk - 1]))
+                return fail("hand-over flags of two blocks disagree", t, k.blk);
+        }
+        for (int64_t q = 0; q < nb; ++q)
+            if (want[q] != S.fdep[q]) return fail("forward counter start", q, S.fdep[q]);
+    }
     return 0;
 }
 
