@@ -418,9 +418,11 @@ def bench_elast(args):
     stream = torch.cuda.current_stream()
 
     # ---- plain FP64: the timed steps
+    progress(f"analysis done ({t_analyze:.1f} s)")
     F = spchol.factorize(sym, dv, "fp64")
     F.sync()
     F.set_graph(args.graph == "on")
+    progress("first FP64 factorization done")
 
     def step(ev=None):
         Bw.copy_(B0)
@@ -436,6 +438,7 @@ def bench_elast(args):
     for _ in range(args.warmup):
         step()
     F.sync()
+    progress(f"{args.warmup} warmup steps done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()

@@ -1766,7 +1766,9 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
 
 // Several right-hand sides (up to kMaxRhs): the update of the task's rows
 // is the product (rows x 64) (64 x 16) on 16x16x4 MFMA blocks, wave w
-// taking rows 64 w .. 64 w + 63; the A operand comes straight from the
+// taking the 16-row tiles w, w + 4, w + 8 and w + 12 in that order (so the
+// first 64 rows, handed over to the next block in the persistent sweep, are
+// done first, by all four waves); the A operand comes straight from the
 // panel, the B operand (x_q) from LDS.
 template <typename T, bool PERSIST>
 __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, int64_t ntasks,
@@ -1800,7 +1802,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
         grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-            const int64_t row = min<int64_t>(tk.r0 + 64 * wave + 16 * tt + (lane & 15), m - 1);
+            const int64_t row = min<int64_t>(tk.r0 + 16 * (4 * tt + wave) + (lane & 15), m - 1);
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
                 av[tt][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
@@ -1850,7 +1852,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks,
                 acc = Mfma<T>::run(av[tt][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = 64 * wave + 16 * tt + Mfma<T>::row(lane, v), q = lane & 15;
+                const int rr = 16 * (4 * tt + wave) + Mfma<T>::row(lane, v), q = lane & 15;
                 if (tk.r0 + rr < tk.r1 && q < nrhs) {
                     if (PERSIST && (tk.hand & kHandOut) && rr < (tk.hand >> 8))
                         shared_store(&H[grs[rr] * nrhs + q], acc[v]);
