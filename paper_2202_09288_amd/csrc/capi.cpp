@@ -389,7 +389,8 @@ void enqueue_factor(const spc::Symbolic &S, const spc::DevPlan &P, const double 
     }
 }
 
-// Y holds the permuted right-hand sides on entry; X receives the solution.
+// Y holds the permuted right-hand sides on entry (and is overwritten); X
+// receives the solution.
 // sync points to kSolveSyncInts(blocks) words of workspace.  Each sweep runs
 // one launch per wide block-tree level, and the narrow levels at the top
 // (levels solve_split..) as one persistent launch per sweep, which removes
