@@ -157,6 +157,8 @@ typedef struct spc_info {
     int64_t solve_block_tasks;/* row tasks of the block solve kernels */
     int64_t solve_tiny_tasks; /* tiny supernodes solved one wave each */
     int64_t updates_total;    /* sum of |U_s|: (source, ancestor) update pairs */
+    int64_t solve_handovers;  /* pairs of consecutive blocks of a supernode that the
+                                 persistent solve sweeps hand over directly */
 } spc_info;
 
 /*

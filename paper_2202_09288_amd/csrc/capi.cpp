@@ -949,6 +949,9 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     out->solve_block_tasks = (int64_t)S.stasks.size();
     out->solve_tiny_tasks = (int64_t)S.stiny.size();
     out->updates_total = (int64_t)S.pairs.size();
+    out->solve_handovers = 0;
+    for (const spc::SolveTask &t : S.stasks)
+        if (t.first && (t.hand & spc::kHandOut)) out->solve_handovers++;
     return SPC_OK;
 }
 

@@ -63,7 +63,8 @@ class _Info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n", "nnz_a", "nsuper", "nnz_l", "panel_entries", "flops", "levels", "rows_total",
         "max_width", "max_rows", "factor_bytes_fp64", "factor_bytes_fp32", "solve_levels",
-        "solve_persistent_levels", "solve_block_tasks", "solve_tiny_tasks", "updates_total")]
+        "solve_persistent_levels", "solve_block_tasks", "solve_tiny_tasks", "updates_total",
+        "solve_handovers")]
 
 
 class _KernelStats(ctypes.Structure):

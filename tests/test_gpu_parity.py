@@ -1266,3 +1266,53 @@ def test_solve_few_rhs_instantiations(torch_dev, lib, precision):
         print(f"{precision} nrhs={nrhs}: eta={eta:.2e}, against one at a time {diff:.2e}", flush=True)
         assert eta <= bar
         assert diff <= (1e-12 if precision == "fp64" else 1e-4)
+
+
+def handover_cases():
+    """A grid whose top supernodes span many column blocks, and one dense
+    supernode of 10 blocks with a ragged last one."""
+    g = grid((40, 38, 36), seed=21, nrhs=16)
+    n = 611
+    rng = np.random.default_rng(6)
+    Xd = rng.standard_normal((n, n))
+    A = Xd @ Xd.T + n * np.eye(n)
+    r, c = np.tril_indices(n)
+    colptr, rowidx, values = W.lower_csc(n, r, c, A[r, c])
+    return [("grid-40x38x36", g.colptr, g.rowidx, g.values, g.perm, g.B),
+            ("dense-611", colptr, rowidx, values, np.arange(n, dtype=np.int32), rng.standard_normal((n, 16)))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_block_handover(torch_dev, lib, precision):
+    """Solves whose every level is persistent (blocks of a supernode hand
+    over through the polled buffers) meet the precision's bar for 1, 3, 4, 8
+    and 16 right-hand sides (every instantiation), twice in a row (the
+    buffers are set again per solve), and agree with the level launches,
+    which hand nothing over."""
+    torch = torch_dev
+    bar = BERR_FP64 if precision == "fp64" else 1e-5
+    for name, colptr, rowidx, values, perm, B in handover_cases():
+        n = len(colptr) - 1
+        levels = lib.Symbolic(colptr, rowidx, perm, 0.05, {"solve_persist_max": -1})
+        every = lib.Symbolic(colptr, rowidx, perm, 0.05, {"solve_persist_max": 1 << 30})
+        assert levels.info["solve_handovers"] == 0 and every.info["solve_handovers"] > 0
+        dv = torch.from_numpy(values).cuda()
+        Fl = lib.factorize(levels, dv, precision)
+        Fe = lib.factorize(every, dv, precision)
+        Fl.sync()
+        Fe.sync()
+        for q in (1, 3, 4, 8, 16):
+            B0 = np.ascontiguousarray(B[:, :q].T)
+            Xl = torch.from_numpy(B0.copy()).cuda()
+            Fl.solve(Xl)
+            ref = Xl.cpu().numpy()
+            for rep in range(2):
+                Xe = torch.from_numpy(B0.copy()).cuda()
+                Fe.solve(Xe)
+                Xh = Xe.cpu().numpy()
+                eta = oracle.backward_error(n, colptr, rowidx, values, Xh.T, B[:, :q])
+                diff = np.max(np.abs(Xh - ref)) / np.max(np.abs(ref))
+                print(f"block hand-over {name} {precision} nrhs={q} rep={rep}: eta={eta:.2e}, "
+                      f"against the level launches {diff:.2e}", flush=True)
+                assert eta <= bar
+                assert diff <= (1e-10 if precision == "fp64" else 1e-3)

@@ -51,3 +51,20 @@ def test_schedule_invariants_headline_grid():
 def test_schedule_invariants_elasticity():
     s = W.elasticity27((6, 5, 7), 88, 0, kappa=1e6, nrhs=1, power_iters=5)
     spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05).verify()
+
+
+def test_solve_handovers_counted():
+    """Consecutive column blocks of a supernode hand over directly only in
+    the persistent solve sweeps: one dense supernode of 10 blocks has 9
+    hand-overs when every solve level is persistent and none when none is."""
+    n = 611
+    r, c = np.tril_indices(n)
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    colptr, rowidx, v = W.lower_csc(n, r, c, A[r, c])
+    perm = np.arange(n, dtype=np.int32)
+    every = spchol.Symbolic(colptr, rowidx, perm, 0.05, {"solve_persist_max": 1 << 30})
+    every.verify()
+    assert every.info["nsuper"] == 1 and every.info["solve_handovers"] == 9
+    assert spchol.Symbolic(colptr, rowidx, perm, 0.05, {"solve_persist_max": -1}).info["solve_handovers"] == 0
