@@ -1769,9 +1769,12 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const SolveTask *tasks, int64
 // taking the 16-row tiles w, w + 4, w + 8 and w + 12 in that order (so the
 // first 64 rows, handed over to the next block in the persistent sweep, are
 // done first, by all four waves); the A operand comes straight from the
-// panel, the B operand (x_q) from LDS.
+// panel, the B operand (x_q) from LDS.  Two workgroups per CU (the FP64
+// form then keeps 256 registers with a spill of two): the persistent sweep
+// runs twice as many resident workgroups, so the tasks waiting on a block
+// leave room for the ones on the chain.
 template <typename T, bool PERSIST>
-__global__ __launch_bounds__(256) void k_solve_fwd_multi(const SolveTask *tasks, int64_t ntasks,
+__global__ __launch_bounds__(256, 2) void k_solve_fwd_multi(const SolveTask *tasks, int64_t ntasks,
                                                          const int32_t *rows, const T *Lx, const T *Linv, T *Y,
                                                          T *X, T *H, int64_t n, int nrhs, const int64_t *tgt_ptr,
                                                          const int32_t *tgt, SolveSync sy) {
