@@ -635,7 +635,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     const int64_t K = (int64_t)C * ns;  // (column, system) slots
     // workspace: 7 vectors of n x C (leading dimension n), then scalars
     const size_t vec = ((size_t)n * C * sizeof(double) + 255) & ~size_t(255);
-    const size_t scal = (size_t)(7 * K + ns) * sizeof(double);
+    const size_t scal = (size_t)(9 * K + ns) * sizeof(double);
     int rc = ensure_bytes((void **)&T.f->refine, &T.f->refine_bytes, 7 * vec + scal);
     if (rc) return rc;
     char *base = (char *)T.f->refine;
@@ -645,6 +645,8 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     unsigned long long *umax = (unsigned long long *)(base + 7 * vec);  // r[K], x[K], b[K], |A|[ns]
     double *dots = (double *)(umax + 3 * K + ns);                          // [K]
     double *coef = dots + K;                                               // alpha[K], -alpha[K], beta[K]
+    double *rho = coef + 3 * K;                                            // [K] r.z of the current step
+    double *frz = rho + K;                                                 // [K] 1 for a converged slot
     auto colmax = [&](const double *V, unsigned long long *out) {
         if (T.seg) spc::launch_seg_colmax(V, T.seg, n, q, n, ns, out, st);
         else spc::launch_colmax(V, n, q, n, out, st);
@@ -664,18 +666,17 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     colmax(Bw, umax + 2 * K);
 
     std::vector<unsigned long long> hb(3 * K + ns);
-    std::vector<double> hdot(K), hcoef(3 * K);
-    std::vector<double> eta_hist, rho(K, 0.0), eta_s(ns);
-    std::vector<char> frozen(K, 0), done(ns, 0);
+    std::vector<double> eta_hist, eta_s(ns), frozen(K, 0.0);
+    std::vector<char> done(ns, 0);
     bool cg = false, cg_started = false;
     int it = 0;
-    auto dot = [&](const double *U, const double *V) -> int {
+    // dot products per slot into dots, left on the device: the CG
+    // coefficients are formed there too, so a step synchronizes only for
+    // its backward errors
+    auto dot = [&](const double *U, const double *V) {
         spc::launch_zero<double>(dots, K, st);
         if (T.seg) spc::launch_seg_coldot(U, V, T.seg, n, q, n, ns, dots, st);
         else spc::launch_coldot(U, V, n, q, n, dots, st);
-        HIP_TRY(hipMemcpyAsync(hdot.data(), dots, K * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        return SPC_OK;
     };
     for (;;) {
         spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, T.nnz, q, n, st);  // T = b - A x
@@ -701,7 +702,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
                 if (std::isnan(e) || !std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(bn) ||
                     !std::isfinite(normA))
                     e = INFINITY;
-                frozen[j] = e <= tol;
+                frozen[j] = e <= tol ? 1.0 : 0.0;
                 eta_s[sg] = std::max(eta_s[sg], e);
                 eta = std::max(eta, e);
             }
@@ -735,30 +736,21 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
             rc = spc_solve(T.f, Zv, q, n, st);
             if (rc) return rc;
             spc::launch_copy_cols(Zv, n, Pv, n, n, q, st);
-            if ((rc = dot(Rv, Zv))) return rc;
-            for (int64_t j = 0; j < K; ++j) rho[j] = hdot[j];
+            dot(Rv, Zv);
+            HIP_TRY(hipMemcpyAsync(rho, dots, K * sizeof(double), hipMemcpyDeviceToDevice, st));
             cg_started = true;
         }
+        HIP_TRY(hipMemcpyAsync(frz, frozen.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
         spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Pv, nullptr, Qv, n, T.nnz, q, n, st);  // q = A p
-        if ((rc = dot(Pv, Qv))) return rc;
-        for (int64_t j = 0; j < K; ++j) {
-            const double a = (!frozen[j] && hdot[j] > 0.0 && std::isfinite(rho[j] / hdot[j])) ? rho[j] / hdot[j] : 0.0;
-            hcoef[j] = a;
-            hcoef[K + j] = -a;
-        }
-        HIP_TRY(hipMemcpyAsync(coef, hcoef.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
+        dot(Pv, Qv);
+        spc::launch_cg_coef(dots, rho, frz, coef, K, true, st);  // alpha = rho / p.q
         axpby(coef, 0.0, Pv, nullptr, 1.0, Xw);      // x += alpha p
         axpby(coef + K, 0.0, Qv, nullptr, 1.0, Rv);  // r -= alpha q
         spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
         rc = spc_solve(T.f, Zv, q, n, st);  // z = M^{-1} r
         if (rc) return rc;
-        if ((rc = dot(Rv, Zv))) return rc;
-        for (int64_t j = 0; j < K; ++j) {
-            const double bt = (rho[j] != 0.0 && std::isfinite(hdot[j] / rho[j])) ? hdot[j] / rho[j] : 0.0;
-            hcoef[2 * K + j] = frozen[j] ? 0.0 : bt;
-            if (!frozen[j]) rho[j] = hdot[j];
-        }
-        HIP_TRY(hipMemcpyAsync(coef + 2 * K, hcoef.data() + 2 * K, K * sizeof(double), hipMemcpyHostToDevice, st));
+        dot(Rv, Zv);
+        spc::launch_cg_coef(dots, rho, frz, coef, K, false, st);  // beta = r.z / rho, rho = r.z
         axpby(nullptr, 1.0, Zv, coef + 2 * K, 0.0, Pv);  // p = z + beta p
     }
     spc::launch_copy_cols(Xw, n, X, ld, n, q, st);

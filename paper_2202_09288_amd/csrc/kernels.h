@@ -167,6 +167,10 @@ void launch_norm_inf_A(const int64_t *rowptr, const int64_t *valmap, const doubl
                        unsigned long long *out, hipStream_t st);
 void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned long long *out, hipStream_t st);
 void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st);
+// The conjugate-gradient coefficients of K slots on the device (alpha, or
+// beta with the update of rho); frozen[j] != 0 marks a converged slot.
+void launch_cg_coef(const double *dots, double *rho, const double *frozen, double *coef, int64_t K, bool alpha,
+                    hipStream_t st);
 void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
                   int nrhs, int64_t ld, hipStream_t st);
 void launch_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, int nrhs, hipStream_t st);

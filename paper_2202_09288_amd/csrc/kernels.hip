@@ -2479,6 +2479,27 @@ __global__ void k_axpby(const double *a, double a0, const double *X, const doubl
         Y[i + q * ld] = (bq == 0.0) ? aq * X[i + q * ld] : aq * X[i + q * ld] + bq * Y[i + q * ld];
 }
 
+// Conjugate-gradient coefficients per (column, system) slot j < K, formed
+// on the device so that a step needs no host round trip.  alpha: coef[j] =
+// rho[j] / dots[j] and coef[K + j] = -coef[j]; beta: coef[2K + j] =
+// dots[j] / rho[j], then rho[j] = dots[j].  A frozen slot (its column has
+// met the tolerance) and a quotient that is not finite give 0, and a frozen
+// slot keeps its rho.
+__global__ void k_cg_coef(const double *dots, double *rho, const double *frozen, double *coef, int64_t K, int alpha) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    const bool fz = frozen[j] != 0.0;
+    if (alpha) {
+        const double a = (!fz && dots[j] > 0.0 && isfinite(rho[j] / dots[j])) ? rho[j] / dots[j] : 0.0;
+        coef[j] = a;
+        coef[K + j] = -a;
+    } else {
+        const double bt = (rho[j] != 0.0 && isfinite(dots[j] / rho[j])) ? dots[j] / rho[j] : 0.0;
+        coef[2 * K + j] = fz ? 0.0 : bt;
+        if (!fz) rho[j] = dots[j];
+    }
+}
+
 // copy n x q between leading dimensions
 __global__ void k_copy_cols(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n) {
     const int q = blockIdx.y;
@@ -2915,6 +2936,11 @@ void launch_colmax(const double *V, int64_t n, int nrhs, int64_t ld, unsigned lo
 void launch_coldot(const double *U, const double *V, int64_t n, int nrhs, int64_t ld, double *out, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return;
     hipLaunchKernelGGL(k_coldot, dim3(std::min(red_grid(n), 128u), nrhs), dim3(256), 0, st, U, V, n, ld, out);
+}
+void launch_cg_coef(const double *dots, double *rho, const double *frozen, double *coef, int64_t K, bool alpha,
+                    hipStream_t st) {
+    if (K <= 0) return;
+    hipLaunchKernelGGL(k_cg_coef, dim3(grid1(K, 256)), dim3(256), 0, st, dots, rho, frozen, coef, K, alpha ? 1 : 0);
 }
 void launch_axpby(const double *a, double a0, const double *X, const double *b, double b0, double *Y, int64_t n,
                   int nrhs, int64_t ld, hipStream_t st) {
