@@ -329,7 +329,11 @@ typedef struct spc_refine_info {
  * device: r = b - A x (FP64 sparse product with the original A), d = solve(r)
  * in the factor's precision, x += d (FP64), until the backward error
  *   max_k ||b_k - A x_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf) <= tol
- * or maxit steps.  d_values must be the values the factor was built from.
+ * or maxit steps.  Once a step cuts that error less than tenfold, conjugate
+ * gradients preconditioned by the factor's solve continue from x; after a
+ * refined solve that switched, the next ones with the same factorization
+ * start with them (a new factorization starts over with the classical
+ * steps).  d_values must be the values the factor was built from.
  *   d_B  device double n x nrhs (ld), not modified
  *   d_X  device double n x nrhs (ld), receives the solution
  * Returns SPC_NO_CONVERGENCE (with info filled) when tol is not reached.

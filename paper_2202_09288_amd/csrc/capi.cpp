@@ -73,6 +73,9 @@ struct spc_factor_s {
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
     size_t refine_bytes = 0;
+    // a refined solve with this factorization switched to CG, so the next
+    // ones start there (cleared by every factorization)
+    std::atomic<bool> refine_cg{false};
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // status words (one per system of a batch) and, for a view into a
@@ -472,6 +475,7 @@ int capture_factor(spc_factor f, const double *d_values) {
 int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
     const spc::Symbolic &S = f->sym->S;
     const spc::DevPlan &P = f->sym->dev.plan;
+    f->refine_cg = false;
     (void)hipGetLastError();  // report only the launches below
     if (f->use_graph && !f->profiling) {
         if (!f->gexec || f->graph_values != d_values) {
@@ -627,6 +631,9 @@ struct RefineTarget {
 // different systems do not mix).  Stops when every eta <= tol or after
 // maxit steps of either kind.  res[s] receives system s's result; its
 // iteration count is the step at which all its columns first met tol.
+// Once a refined solve with a factorization has switched to CG, the next
+// ones with it start with CG: the classical step would only show again
+// that the factor is too weak for it.
 int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64_t ld, double tol, int maxit,
                  hipStream_t st, RefineResult *res) {
     const int64_t n = T.n;
@@ -668,7 +675,8 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     std::vector<unsigned long long> hb(3 * K + ns);
     std::vector<double> eta_hist, eta_s(ns), frozen(K, 0.0);
     std::vector<char> done(ns, 0);
-    bool cg = false, cg_started = false;
+    std::atomic<bool> &start_cg = owner_of(T.f)->refine_cg;  // per factorization (a batch's for a view)
+    bool cg = start_cg, cg_started = false;
     int it = 0;
     // dot products per slot into dots, left on the device: the CG
     // coefficients are formed there too, so a step synchronizes only for
@@ -720,7 +728,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         // over: its rate bound (sqrt(k) - 1) / (sqrt(k) + 1), with
         // k <= (1 + rho) / (1 - rho), is then well below rho, which pays for
         // its second SpMV and its dot products.
-        if (!cg && h >= 2 && !(eta_hist[h - 1] <= 0.1 * eta_hist[h - 2])) cg = true;
+        if (!cg && h >= 2 && !(eta_hist[h - 1] <= 0.1 * eta_hist[h - 2])) cg = start_cg = true;
         ++it;
         if (!cg) {
             spc::launch_copy_cols(Tv, n, Zv, n, n, q, st);

@@ -1316,3 +1316,29 @@ def test_solve_block_handover(torch_dev, lib, precision):
                       f"against the level launches {diff:.2e}", flush=True)
                 assert eta <= bar
                 assert diff <= (1e-10 if precision == "fp64" else 1e-3)
+
+
+def test_refined_starts_with_cg_after_a_switch(torch_dev, lib):
+    """After a refined solve that switched to CG (kappa = 1e8 elasticity in
+    FP32), the next one with the same factorization starts with CG: it meets
+    1e-12 in no more steps; a new factorization starts over and meets it
+    again."""
+    torch = torch_dev
+    s = W.elasticity27((7, 6, 5), 88, 1, kappa=1e8, nrhs=4, power_iters=50)
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv, "fp32")
+    F.sync()
+    B0 = torch.from_numpy(np.ascontiguousarray(s.B.T)).cuda()
+    steps = []
+    for rep in range(3):
+        if rep == 2:
+            F.refactorize(dv)
+            F.sync()
+        X = torch.zeros_like(B0)
+        info = F.solve_refined(dv, B0, X, tol=1e-12, maxit=200)
+        eta = oracle.backward_error(s.n, s.colptr, s.rowidx, s.values, X.cpu().numpy().T, s.B)
+        print(f"refined solve {rep}: {info}, eta={eta:.2e}", flush=True)
+        assert info["converged"] and eta <= 1e-12
+        steps.append(info["iterations"])
+    assert steps[1] <= steps[0]
