@@ -136,6 +136,17 @@ typedef struct spc_options {
     int32_t group;
     int32_t bulk128;
     int32_t lookahead;
+    /* Device-memory budget in bytes for each factorization of this analysis
+     * (the footprint spc_symbolic_info reports as factor_bytes_fp64 or
+     * factor_bytes_fp32, by precision; a batch is held to the smallest
+     * positive budget among its members, over the merged footprint).  A
+     * factorization or batch that would exceed it is refused with
+     * SPC_OUT_OF_MEMORY before anything is allocated, and
+     * spc_last_error_message names both sizes.  0 or negative: no budget
+     * (default).  Admission by footprint is the memory side of the paper's
+     * per-phase analysis (Sec. 2: the symbolic phase fixes the storage of
+     * L before any numeric work). */
+    int64_t hbm_budget;
 } spc_options;
 
 /* Summary numbers of an analysis. */

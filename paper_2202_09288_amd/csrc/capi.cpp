@@ -42,6 +42,7 @@ struct spc_symbolic_s {
     void *csr_base = nullptr;
     const int64_t *d_csr_ptr = nullptr, *d_csr_val = nullptr;
     const int32_t *d_csr_col = nullptr;
+    int64_t hbm_budget = 0;  // bytes per factorization; <= 0: none
     std::mutex mu;
 };
 
@@ -289,6 +290,14 @@ size_t plan_bytes(const spc::Symbolic &S) {
            bytes_of(S.pdep0) + bytes_of(S.ptgt_ptr) + bytes_of(S.ptgt);
 }
 
+// Device bytes of one factor (panels and block inverses at esz bytes per
+// entry) plus the device plan: the footprint the budget and
+// spc_symbolic_info use.
+int64_t factor_footprint(const spc::Symbolic &S, int64_t esz) {
+    const int64_t entries = S.panel_entries() + (S.inv_off.empty() ? 0 : S.inv_off.back());
+    return entries * esz + (int64_t)plan_bytes(S);
+}
+
 // Brackets one launch with a pair of events (on the launch's stream) when
 // profiling is on.
 struct Prof {
@@ -507,6 +516,15 @@ int run_factor(spc_factor f, const double *d_values, hipStream_t st) {
 
 int create_factor(spc_symbolic sym, int precision, spc_factor *out, int nstatus = 1) {
     if (precision != SPC_FP64 && precision != SPC_FP32 && precision != SPC_FP32_BF16UPD) return SPC_INVALID_INPUT;
+    if (sym->hbm_budget > 0) {
+        const int64_t need = factor_footprint(sym->S, precision == SPC_FP64 ? 8 : 4);
+        if (need > sym->hbm_budget) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "factorization needs %lld device bytes, over the budget of %lld", (long long)need,
+                          (long long)sym->hbm_budget);
+            return SPC_OUT_OF_MEMORY;
+        }
+    }
     int dev = -1;
     int rc = check_device(&dev);
     if (rc) return rc;
@@ -870,6 +888,7 @@ int spc_analyze(int64_t n, const int64_t *h_colptr, const int32_t *h_rowidx, con
             delete s;
             return SPC_INVALID_INPUT;
         }
+        s->hbm_budget = opts->hbm_budget;
     }
     int rc;
     std::vector<int32_t> computed;
@@ -941,9 +960,8 @@ int spc_symbolic_info(spc_symbolic sym, spc_info *out) {
     out->rows_total = S.rows_total();
     out->max_width = S.max_w;
     out->max_rows = S.max_m;
-    const int64_t entries = S.panel_entries() + (S.inv_off.empty() ? 0 : S.inv_off.back());
-    out->factor_bytes_fp64 = (int64_t)(entries * 8 + plan_bytes(S));
-    out->factor_bytes_fp32 = (int64_t)(entries * 4 + plan_bytes(S));
+    out->factor_bytes_fp64 = factor_footprint(S, 8);
+    out->factor_bytes_fp32 = factor_footprint(S, 4);
     out->solve_levels = S.nslevels;
     out->solve_persistent_levels = S.nslevels - S.solve_split;
     out->solve_block_tasks = (int64_t)S.stasks.size();
@@ -1316,6 +1334,10 @@ int spc_batch_create(int count, const spc_symbolic *syms, int precision, spc_bat
         rc = spc::merge(parts, b->merged->S, b->col_off, b->panel_off, b->inv_base, b->val_off);
     } catch (const std::bad_alloc &) {
         rc = SPC_OUT_OF_MEMORY;
+    }
+    for (int i = 0; i < count; ++i) {
+        const int64_t bud = syms[i]->hbm_budget;
+        if (bud > 0 && (b->merged->hbm_budget <= 0 || bud < b->merged->hbm_budget)) b->merged->hbm_budget = bud;
     }
     if (rc == SPC_OK) rc = create_factor(b->merged, precision, &b->F, count);
     if (rc == SPC_OK && hipMalloc((void **)&b->vbuf, std::max<int64_t>(1, b->val_off[count]) * sizeof(double)) !=

@@ -56,7 +56,8 @@ TUNING_FIELDS = ("tiny_w", "tiny_m", "small_w", "small_m", "big_min", "big_min_k
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("amalg_z", ctypes.c_double)] + [(k, ctypes.c_int32) for k in TUNING_FIELDS]
+    _fields_ = [("amalg_z", ctypes.c_double)] + [(k, ctypes.c_int32) for k in TUNING_FIELDS] + [
+        ("hbm_budget", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -214,7 +215,7 @@ _EXPORT_ARRAYS = {"perm": (0, np.int32, "n"), "parent": (1, np.int32, "n"),
 class Symbolic:
     """spc_analyze: host-only symbolic analysis of a lower-CSC pattern."""
 
-    def __init__(self, colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None):
+    def __init__(self, colptr, rowidx, perm=None, amalg_z: float = 0.05, tuning=None, hbm_budget: int = 0):
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
@@ -225,7 +226,7 @@ class Symbolic:
             raise ValueError("rowidx is shorter than colptr[n]")
         if self._perm is not None and self._perm.size != n:
             raise ValueError(f"perm must have n = {n} entries")
-        opts = _Options(amalg_z=float(amalg_z))
+        opts = _Options(amalg_z=float(amalg_z), hbm_budget=int(hbm_budget))
         self.tuning = dict(tuning or {})
         for k, v in self.tuning.items():
             if k not in TUNING_FIELDS:

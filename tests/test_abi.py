@@ -162,3 +162,26 @@ def test_cutoffs_shape_the_schedule():
             assert np.array_equal(other.export(name), base.export(name))
     with pytest.raises(ValueError):
         spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, {"tile": 3})
+
+
+def test_hbm_budget_refuses_before_the_device():
+    """A factorization over the analysis's device budget is refused with
+    SPC_OUT_OF_MEMORY before any allocation (no device needed), with both
+    sizes in the error message; a budget at the footprint is not refused by
+    the budget check."""
+    s = W.laplacian((6, 5, 4), "7pt", 1, 0, unit=False, shift=1e-2, nrhs=1)
+    sym = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, hbm_budget=1000)
+    need = {1: sym.info["factor_bytes_fp32"], 0: sym.info["factor_bytes_fp64"]}
+    assert need[1] > 1000 and need[0] > need[1]
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the budget check comes first
+    for prec in (spchol.FP64, spchol.FP32, spchol.FP32_BF16UPD):
+        h = ctypes.c_void_p()
+        rc = spchol._lib.spc_factorize(sym.handle, dummy, prec, None, ctypes.byref(h))
+        assert rc == spchol.OUT_OF_MEMORY and not h.value
+        msg = spchol._lib.spc_last_error_message().decode()
+        assert str(need[0 if prec == 0 else 1]) in msg and "1000" in msg
+    # at the FP32 footprint: FP32 passes the budget check, FP64 does not
+    sym2 = spchol.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, hbm_budget=need[1])
+    h = ctypes.c_void_p()
+    assert spchol._lib.spc_factorize(sym2.handle, dummy, spchol.FP64, None,
+                                     ctypes.byref(h)) == spchol.OUT_OF_MEMORY

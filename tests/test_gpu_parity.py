@@ -1342,3 +1342,37 @@ def test_refined_starts_with_cg_after_a_switch(torch_dev, lib):
         assert info["converged"] and eta <= 1e-12
         steps.append(info["iterations"])
     assert steps[1] <= steps[0]
+
+
+def test_hbm_budget_factor_and_batch(torch_dev, lib):
+    """The analysis's device budget: a factorization at exactly its footprint
+    runs and matches the oracle, one byte less is refused with
+    SPC_OUT_OF_MEMORY; a batch is held to its members' smallest budget over
+    the merged footprint."""
+    torch = torch_dev
+    s = grid((9, 7, 11), nrhs=2)
+    need = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05).info["factor_bytes_fp64"]
+    sym = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, hbm_budget=need)
+    dv = torch.from_numpy(s.values).cuda()
+    F = lib.factorize(sym, dv, "fp64")
+    F.sync()
+    S = oracle.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)
+    Lref = S.factor(s.values)
+    assert factor_error(F.export(), Lref, S) <= REL_F_FP64
+    tight = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, hbm_budget=need - 1)
+    with pytest.raises(lib.SpcError) as e:
+        lib.factorize(tight, dv, "fp64")
+    assert e.value.status == lib.OUT_OF_MEMORY
+    # FP32 needs less than the FP64 footprint
+    F32 = lib.factorize(tight, dv, "fp32")
+    F32.sync()
+    # two members that each fit alone, merged over the smaller budget
+    with pytest.raises(lib.SpcError) as e:
+        lib.Batch([sym, lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05)], "fp64")
+    assert e.value.status == lib.OUT_OF_MEMORY
+    roomy = lib.Symbolic(s.colptr, s.rowidx, s.perm, 0.05, hbm_budget=3 * need)
+    batch = lib.Batch([roomy, roomy], "fp64")
+    batch.factorize([dv, dv])
+    batch.sync()
+    for i in range(2):
+        assert factor_error(batch.factor(i).export(), Lref, S) <= REL_F_FP64
