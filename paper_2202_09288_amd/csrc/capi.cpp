@@ -74,6 +74,8 @@ struct spc_factor_s {
     size_t work_bytes = 0;
     double *refine = nullptr;   // refinement vectors (FP64)
     size_t refine_bytes = 0;
+    void *refine_host = nullptr;  // pinned: the maxima read back each step, the converged flags sent down
+    size_t refine_host_bytes = 0;
     // a refined solve with this factorization switched to CG, so the next
     // ones start there (cleared by every factorization)
     std::atomic<bool> refine_cg{false};
@@ -690,8 +692,19 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
     else spc::launch_norm_inf_A(T.rp, T.vm, T.values, n, T.nnz, umax + 3 * K, st);
     colmax(Bw, umax + 2 * K);
 
-    std::vector<unsigned long long> hb(3 * K + ns);
-    std::vector<double> eta_hist, eta_s(ns), frozen(K, 0.0);
+    // the per-step copies go through pinned host memory (no staging)
+    const size_t host_need = (3 * K + ns) * sizeof(unsigned long long) + K * sizeof(double);
+    if (T.f->refine_host_bytes < host_need) {
+        if (T.f->refine_host) HIP_TRY(hipHostFree(T.f->refine_host));
+        T.f->refine_host = nullptr;
+        T.f->refine_host_bytes = 0;
+        HIP_TRY(hipHostMalloc(&T.f->refine_host, host_need, hipHostMallocDefault));
+        T.f->refine_host_bytes = host_need;
+    }
+    unsigned long long *hb = (unsigned long long *)T.f->refine_host;  // r[K], x[K], b[K], |A|[ns]
+    double *frozen = (double *)(hb + 3 * K + ns);                       // [K]
+    std::fill(frozen, frozen + K, 0.0);
+    std::vector<double> eta_hist, eta_s(ns);
     std::vector<char> done(ns, 0);
     std::atomic<bool> &start_cg = owner_of(T.f)->refine_cg;  // per factorization (a batch's for a view)
     bool cg = start_cg, cg_started = false;
@@ -709,8 +722,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         spc::launch_zero<unsigned long long>(umax, 2 * K, st);
         colmax(Tv, umax);
         colmax(Xw, umax + K);
-        HIP_TRY(hipMemcpyAsync(hb.data(), umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                               st));
+        HIP_TRY(hipMemcpyAsync(hb, umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if ((rc = check_deverr(T.f))) return rc;
         double eta = 0.0;
@@ -755,6 +767,9 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
             axpby(nullptr, 1.0, Zv, nullptr, 1.0, Xw);  // x += d
             continue;
         }
+        // frozen is next written after the next step's synchronization,
+        // so this copy from it has finished by then
+        HIP_TRY(hipMemcpyAsync(frz, frozen, K * sizeof(double), hipMemcpyHostToDevice, st));
         if (!cg_started) {
             // r = b - A x, z = M^{-1} r, p = z, rho = r.z
             spc::launch_copy_cols(Tv, n, Rv, n, n, q, st);
@@ -765,19 +780,22 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
             dot(Rv, Zv);
             HIP_TRY(hipMemcpyAsync(rho, dots, K * sizeof(double), hipMemcpyDeviceToDevice, st));
             cg_started = true;
+        } else {
+            // the preconditioner solve of the last step's residual comes
+            // after that step's convergence check, so the step that
+            // converges makes none
+            spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
+            rc = spc_solve(T.f, Zv, q, n, st);  // z = M^{-1} r
+            if (rc) return rc;
+            dot(Rv, Zv);
+            spc::launch_cg_coef(dots, rho, frz, coef, K, false, st);  // beta = r.z / rho, rho = r.z
+            axpby(nullptr, 1.0, Zv, coef + 2 * K, 0.0, Pv);  // p = z + beta p
         }
-        HIP_TRY(hipMemcpyAsync(frz, frozen.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
         spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Pv, nullptr, Qv, n, T.nnz, q, n, st);  // q = A p
         dot(Pv, Qv);
         spc::launch_cg_coef(dots, rho, frz, coef, K, true, st);  // alpha = rho / p.q
         axpby(coef, 0.0, Pv, nullptr, 1.0, Xw);      // x += alpha p
         axpby(coef + K, 0.0, Qv, nullptr, 1.0, Rv);  // r -= alpha q
-        spc::launch_copy_cols(Rv, n, Zv, n, n, q, st);
-        rc = spc_solve(T.f, Zv, q, n, st);  // z = M^{-1} r
-        if (rc) return rc;
-        dot(Rv, Zv);
-        spc::launch_cg_coef(dots, rho, frz, coef, K, false, st);  // beta = r.z / rho, rho = r.z
-        axpby(nullptr, 1.0, Zv, coef + 2 * K, 0.0, Pv);  // p = z + beta p
     }
     spc::launch_copy_cols(Xw, n, X, ld, n, q, st);
     HIP_TRY(hipGetLastError());
@@ -1243,6 +1261,7 @@ void spc_free_factor(spc_factor f) {
         spc_batch_s *b = f->batch;
         if (f->work) (void)hipFree(f->work);
         if (f->refine) (void)hipFree(f->refine);
+        if (f->refine_host) (void)hipHostFree(f->refine_host);
         spc_symbolic_s *s = f->sym;
         f->magic = kDead;
         delete f;
@@ -1257,6 +1276,7 @@ void spc_free_factor(spc_factor f) {
     if (f->status) (void)hipFree(f->status);
     if (f->work) (void)hipFree(f->work);
     if (f->refine) (void)hipFree(f->refine);
+    if (f->refine_host) (void)hipHostFree(f->refine_host);
     if (f->ev0) (void)hipEventDestroy(f->ev0);
     if (f->ev1) (void)hipEventDestroy(f->ev1);
     for (hipEvent_t e : f->prof_ev) (void)hipEventDestroy(e);
