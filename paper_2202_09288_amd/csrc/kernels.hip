@@ -1795,28 +1795,46 @@ __global__ __launch_bounds__(256, 2) void k_solve_fwd_multi(const SolveTask *tas
         const T *Q = Linv + tk.ioff;
         // x = Linv y on MFMA as well: wave w the rows 16 w .. 16 w + 15 of x,
         // lane bringing Linv[16 w + lane % 16][4 s + lane / 16]
-        // K-steps of 4 columns that reach the block's nb columns, and the
-        // row tiles of 16 that reach the task's rows: the clamped operands
-        // beyond them only ever meet zeros, so narrow blocks and short tasks
-        // skip their loads and products (same for every lane of a wave)
+        // Level launches: K-steps of 4 columns that reach the block's nb
+        // columns, and the row tiles of 16 that reach the task's rows; the
+        // clamped operands beyond them only ever meet zeros, so the narrow
+        // blocks and short tasks of the bottom levels skip their loads and
+        // products (same for every lane of a wave).  The persistent sweep,
+        // of mostly full blocks, keeps the unconditional form.
         const int ksn = (nb + 3) >> 2;
         const int64_t nrows = tk.r1 - tk.r0;
         T qv[KS], yv[YPT], av[4][KS];
+        if constexpr (PERSIST) {
 #pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2) {
-            const int i = 16 * wave + (lane & 15), c = 4 * s2 + (lane >> 4);
-            const T v = s2 < ksn ? Q[min(i, nb - 1) + (int64_t)min(c, nb - 1) * nb] : T(0);
-            qv[s2] = (c <= i && i < nb) ? v : T(0);
+            for (int s2 = 0; s2 < KS; ++s2) {
+                const int i = 16 * wave + (lane & 15), c = 4 * s2 + (lane >> 4);
+                const T v = Q[min(i, nb - 1) + (int64_t)min(c, nb - 1) * nb];
+                qv[s2] = (c <= i && i < nb) ? v : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) {
+                const int i = 16 * wave + (lane & 15), c = 4 * s2 + (lane >> 4);
+                const T v = s2 < ksn ? Q[min(i, nb - 1) + (int64_t)min(c, nb - 1) * nb] : T(0);
+                qv[s2] = (c <= i && i < nb) ? v : T(0);
+            }
         }
         grs[tid] = rows[tk.roff + min<int64_t>(tk.r0 + tid, m - 1)];
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
             const int64_t row = min<int64_t>(tk.r0 + 16 * (4 * tt + wave) + (lane & 15), m - 1);
-            const bool live = 16 * (4 * tt + wave) < nrows;
+            if constexpr (PERSIST) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                av[tt][ks] = live && ks < ksn ? P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row]
-                                              : T(0);
+                for (int ks = 0; ks < KS; ++ks)
+                    av[tt][ks] = P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row];
+            } else {
+                const bool live = 16 * (4 * tt + wave) < nrows;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    av[tt][ks] = live && ks < ksn
+                                     ? P[(int64_t)(tk.c0 + min(4 * ks + (lane >> 4), nb - 1)) * m + row]
+                                     : T(0);
+            }
         }
         int32_t my_tgt = -1;
         if (PERSIST) {
@@ -1845,7 +1863,7 @@ __global__ __launch_bounds__(256, 2) void k_solve_fwd_multi(const SolveTask *tas
             acc_t xa = {0, 0, 0, 0};
 #pragma unroll
             for (int s2 = 0; s2 < KS; ++s2)
-                if (s2 < ksn) xa = Mfma<T>::run(qv[s2], yq[4 * s2 + (lane >> 4)][lane & 15], xa);
+                if (PERSIST || s2 < ksn) xa = Mfma<T>::run(qv[s2], yq[4 * s2 + (lane >> 4)][lane & 15], xa);
 #pragma unroll
             for (int v = 0; v < 4; ++v) xq[16 * wave + Mfma<T>::row(lane, v)][lane & 15] = xa[v];
         }
@@ -1858,11 +1876,13 @@ __global__ __launch_bounds__(256, 2) void k_solve_fwd_multi(const SolveTask *tas
         // rows of x_q beyond nb are zero, so the clamped columns contribute nothing
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-            if (16 * (4 * tt + wave) >= nrows) continue;  // no row of this tile is the task's
+            if constexpr (!PERSIST) {
+                if (16 * (4 * tt + wave) >= nrows) continue;  // no row of this tile is the task's
+            }
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
-                if (ks < ksn) acc = Mfma<T>::run(av[tt][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
+                if (PERSIST || ks < ksn) acc = Mfma<T>::run(av[tt][ks], xq[4 * ks + (lane >> 4)][lane & 15], acc);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = 16 * (4 * tt + wave) + Mfma<T>::row(lane, v), q = lane & 15;
