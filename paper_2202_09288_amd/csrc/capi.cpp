@@ -717,33 +717,52 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         if (T.seg) spc::launch_seg_coldot(U, V, T.seg, n, q, n, ns, dots, st);
         else spc::launch_coldot(U, V, n, q, n, dots, st);
     };
+    std::vector<double> e_slot(K, 0.0);
     for (;;) {
-        spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, T.nnz, q, n, st);  // T = b - A x
-        spc::launch_zero<unsigned long long>(umax, 2 * K, st);
-        colmax(Tv, umax);
-        colmax(Xw, umax + K);
-        HIP_TRY(hipMemcpyAsync(hb, umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if ((rc = check_deverr(T.f))) return rc;
+        // Once CG runs, its recursive residual r tracks b - A x to rounding,
+        // so a step's backward error is first estimated from r; the true
+        // residual (one more SpMV) is taken before any column counts as
+        // converged and at the step limit, so every reported backward error
+        // is the true one.  After a true residual, r is replaced by it.
+        bool est = cg_started;
         double eta = 0.0;
-        std::fill(eta_s.begin(), eta_s.end(), 0.0);
-        for (int k = 0; k < q; ++k)
-            for (int sg = 0; sg < ns; ++sg) {
-                const int64_t j = (int64_t)k * ns + sg;
-                const double normA = bits_to_double(hb[3 * K + sg]);
-                const double rn = bits_to_double(hb[j]), xn = bits_to_double(hb[K + j]),
-                             bn = bits_to_double(hb[2 * K + j]);
-                const double den = normA * xn + bn;
-                double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
-                // a NaN or Inf anywhere (the maxima carry NaN as +Inf) is
-                // never converged
-                if (std::isnan(e) || !std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(bn) ||
-                    !std::isfinite(normA))
-                    e = INFINITY;
-                frozen[j] = e <= tol ? 1.0 : 0.0;
-                eta_s[sg] = std::max(eta_s[sg], e);
-                eta = std::max(eta, e);
+        for (;;) {
+            if (!est) spc::launch_spmv(T.rp, T.ci, T.vm, T.values, Xw, Bw, Tv, n, T.nnz, q, n, st);  // T = b - A x
+            spc::launch_zero<unsigned long long>(umax, 2 * K, st);
+            colmax(est ? Rv : Tv, umax);
+            colmax(Xw, umax + K);
+            HIP_TRY(hipMemcpyAsync(hb, umax, (3 * K + ns) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if ((rc = check_deverr(T.f))) return rc;
+            eta = 0.0;
+            std::fill(eta_s.begin(), eta_s.end(), 0.0);
+            bool newly = false;
+            for (int k = 0; k < q; ++k)
+                for (int sg = 0; sg < ns; ++sg) {
+                    const int64_t j = (int64_t)k * ns + sg;
+                    const double normA = bits_to_double(hb[3 * K + sg]);
+                    const double rn = bits_to_double(hb[j]), xn = bits_to_double(hb[K + j]),
+                                 bn = bits_to_double(hb[2 * K + j]);
+                    const double den = normA * xn + bn;
+                    double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+                    // a NaN or Inf anywhere (the maxima carry NaN as +Inf) is
+                    // never converged
+                    if (std::isnan(e) || !std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(bn) ||
+                        !std::isfinite(normA))
+                        e = INFINITY;
+                    e_slot[j] = e;
+                    if (e <= tol && frozen[j] == 0.0) newly = true;
+                    eta_s[sg] = std::max(eta_s[sg], e);
+                    eta = std::max(eta, e);
+                }
+            if (est && (newly || it >= maxit)) {
+                est = false;  // confirm on the true residual
+                continue;
             }
+            break;
+        }
+        if (cg_started && !est) spc::launch_copy_cols(Tv, n, Rv, n, n, q, st);  // residual replacement
+        for (int64_t j = 0; j < (int64_t)q * ns; ++j) frozen[j] = e_slot[j] <= tol ? 1.0 : 0.0;
         for (int sg = 0; sg < ns; ++sg) {
             res[sg].berr = eta_s[sg];
             res[sg].converged = eta_s[sg] <= tol;
@@ -757,7 +776,7 @@ int refine_chunk(const RefineTarget &T, const double *B, double *X, int q, int64
         // I - M^{-1} A.  Once a step contracts it by less than 10x, CG takes
         // over: its rate bound (sqrt(k) - 1) / (sqrt(k) + 1), with
         // k <= (1 + rho) / (1 - rho), is then well below rho, which pays for
-        // its second SpMV and its dot products.
+        // its dot products and its true residuals near convergence.
         if (!cg && h >= 2 && !(eta_hist[h - 1] <= 0.1 * eta_hist[h - 2])) cg = start_cg = true;
         ++it;
         if (!cg) {
